@@ -1,0 +1,560 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test names the passage it pins.  None of these re-types an oracle
+formula: they check identities (adjoint definition, reverse product rule),
+closed forms (normal equations), conservation, continuous steady states,
+special cases (one subdomain = global 4D-Var, J = sum of local J), and brute
+force on tiny inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import custom_problem, problem
+from oracle import brute, dd, ddmaps, lbfgs, local, model
+
+
+def _grid(p):
+    return model.Grid.of(p)
+
+
+# --- P1: the rest state is an exact fixed point ------------------------------
+def test_rest_state_is_fixed_point():
+    """All tendencies of EquU/EquV/EquH vanish at h = const, u = v = 0 (Sec. 7)."""
+    p = problem("c1")
+    g = _grid(p)
+    Z = np.stack([np.full((p.nlat, p.nlon), p.h_ref), np.zeros((p.nlat, p.nlon)),
+                  np.zeros((p.nlat, p.nlon))])
+    assert np.all(model.increment(g, Z) == 0.0)
+    tr = model.forward(g, Z, 5)
+    assert np.all(tr == Z[None])
+    maps = ddmaps.build(p)
+    for s in (0, 3, 5):
+        b = maps.boxes[s]
+        geo = local.LocalGeometry(g, maps, s)
+        zb = local.restrict_global(maps, s, np.repeat(Z[None], p.nsteps + 1, 0))
+        ring = local.ring_from_trajs(maps, s, {k: local.restrict_global(
+            maps, k, np.repeat(Z[None], p.nsteps + 1, 0)) for k in range(len(maps.boxes))})
+        lt = local.forward(geo, zb[0], ring)
+        assert np.all(lt == zb[0][None]), b
+
+
+# --- P2: mass conservation of the flux form ----------------------------------
+@pytest.mark.parametrize("name", ["c1", "small"])
+def test_mass_conservation(name):
+    """Flux-form continuity (EquH) conserves sum_j cos(theta_j) h_ij exactly."""
+    p = problem(name)
+    g = _grid(p)
+    tr = model.forward(g, p.xb0, p.nsteps)
+    m = np.array([model.mass(g, z) for z in tr])
+    assert np.max(np.abs(m - m[0])) / m[0] <= 1e-13
+    # the total increment of h is exactly mass-neutral, level by level
+    for z in tr[::3]:
+        H = model.increment(g, z)[0]
+        assert abs(np.sum(g.cos[:, None] * H)) <= 1e-13 * np.sum(g.cos[:, None] * np.abs(z[0]))
+
+
+# --- the discrete U, V, H approximate the continuous SWE --------------------
+def _tc2(nlat, omega, alpha):
+    """Solid-body rotation about an axis tilted by alpha (steady for alpha=0,
+    or for any alpha when omega = 0)."""
+    nlon = 2 * nlat
+    a, gr = 6.37122e6, 9.80616
+    g = model.Grid(nlat, nlon, 10.0, a, gr, omega)
+    u0 = 2 * math.pi * a / (12 * 86400.0)
+    th = g.theta[:, None] * np.ones((1, nlon))
+    la = (np.arange(nlon) * g.dlon)[None, :] * np.ones((nlat, 1))
+    u = u0 * (np.cos(th) * math.cos(alpha) + np.cos(la) * np.sin(th) * math.sin(alpha))
+    v = -u0 * np.sin(la) * math.sin(alpha)
+    mu = -np.cos(la) * np.cos(th) * math.sin(alpha) + np.sin(th) * math.cos(alpha)
+    h = 2.94e4 / gr - (a * omega * u0 + u0 ** 2 / 2) * mu ** 2 / gr
+    return g, np.stack([h, u, v])
+
+
+@pytest.mark.parametrize("omega,alpha", [(7.292e-5, 0.0), (0.0, math.pi / 4), (0.0, 0.3)])
+def test_steady_flow_second_order(omega, alpha):
+    """Williamson-type solid-body rotation is a steady solution of EquU/EquV/EquH.
+
+    The discrete increment must vanish at second order in the grid spacing:
+    halving the spacing divides the residual (relative to the pressure-gradient
+    term) by about four.  A wrong sign or factor in any advection, metric,
+    Coriolis or pressure term leaves an O(1) residual instead.
+    """
+    res = []
+    for nlat in (32, 64, 128):
+        g, Z = _tc2(nlat, omega, alpha)
+        F = model.increment(g, Z)
+        h = Z[0]
+        # compare on |latitude| < 60 deg: towards the poles the 1/cos(theta)
+        # factors turn the centred-difference error at a fixed number of rows
+        # from the pole into a first-order one
+        band = np.abs(g.theta) < math.pi / 3
+        scale = np.linalg.norm((g.sig_lat * g.gravity * (np.roll(h, -1, 0) - np.roll(h, 1, 0)))[band])
+        res.append(max(np.linalg.norm(F[k][band]) for k in range(3)) / scale)
+    assert res[0] < 0.05
+    assert 3.0 < res[0] / res[1] < 5.0 and 3.0 < res[1] / res[2] < 5.0, res
+
+
+def test_time_integration_second_order():
+    """Leapfrog with a forward-Euler half increment is second order in dt."""
+    p = problem("c1")
+    T = 20 * p.dt
+    out = []
+    for k in (1, 2, 4):
+        g = model.Grid(p.nlat, p.nlon, p.dt / k, p.radius, p.gravity, p.omega)
+        out.append(model.forward(g, p.truth0, 20 * k)[-1])
+    e1 = np.linalg.norm(out[0] - out[1])
+    e2 = np.linalg.norm(out[1] - out[2])
+    assert 3.0 < e1 / e2 < 5.0
+    assert T > 0
+
+
+def test_brute_force_increment():
+    """Vectorised increment equals a per-cell loop transcription on tiny grids."""
+    for name in ("tiny1", "c1"):
+        p = problem(name)
+        g = _grid(p)
+        for Z in (p.truth0, p.xb0):
+            F = model.increment(g, Z)
+            Fb = np.array(brute.increment(p, Z.tolist()))
+            assert np.max(np.abs(F - Fb)) <= 1e-15 * np.max(np.abs(F)) + 1e-300
+
+
+# --- P3 / P4: dot-product tests (adjoint definition, eq. Eq_propAdj) --------
+def test_global_dot_product(rng):
+    p = problem("c1")
+    g = _grid(p)
+    tr = model.forward(g, p.xb0, p.nsteps)
+    dx = rng.standard_normal(p.xb0.shape)
+    y = rng.standard_normal(tr.shape)
+    lhs = np.sum(model.tlm(g, tr, dx) * y)
+    rhs = np.sum(dx * model.adjoint(g, tr, y))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_single_step_dot_product(rng):
+    """Per-step transposes (reverse product rule, eq. adjProd)."""
+    p = problem("c1")
+    g = _grid(p)
+    for Z in (p.truth0, p.xb0):
+        dZ = rng.standard_normal(Z.shape)
+        lam = rng.standard_normal(Z.shape)
+        lhs = np.sum(model.increment_tl(g, Z, dZ) * lam)
+        rhs = np.sum(dZ * model.increment_ad(g, Z, lam))
+        assert abs(lhs - rhs) <= 1e-14 * abs(lhs)
+    # startup step alone: trajectory with one step
+    tr = model.forward(g, p.xb0, 1)
+    dx = rng.standard_normal(p.xb0.shape)
+    y = rng.standard_normal(tr.shape)
+    lhs = np.sum(model.tlm(g, tr, dx) * y)
+    rhs = np.sum(dx * model.adjoint(g, tr, y))
+    assert abs(lhs - rhs) <= 1e-14 * abs(lhs)
+
+
+SPAN_CFG = dict(index=110, nlat=16, nlon=32, nsteps=8, bands=3, pieces=1, ntime=2,
+                overlap_cells=2, overlap_steps=1, obs_frac=0.1, obs_every=2)
+MIXED_CFG = dict(index=111, nlat=24, nlon=32, brick=(3, 2, 6, 18), ntime=2,
+                 nsteps=8, overlap_cells=2, overlap_steps=2, obs_frac=0.1, obs_every=2)
+
+
+def _local_setup(p):
+    g = _grid(p)
+    maps = ddmaps.build(p)
+    bg, trajs = dd.background(p, maps)
+    rings, _ = dd.exchange(maps, trajs)
+    return g, maps, trajs, rings
+
+
+@pytest.mark.parametrize("which", ["c1", "small", "span", "mixed"])
+def test_local_dot_product(rng, which):
+    """Local sweep control -> all levels, boxes with rings, seams and poles."""
+    p = {"span": lambda: custom_problem(SPAN_CFG), "mixed": lambda: custom_problem(MIXED_CFG)}.get(
+        which, lambda: problem(which))()
+    g, maps, trajs, rings = _local_setup(p)
+    for s in range(len(maps.boxes)):
+        geo = local.LocalGeometry(g, maps, s)
+        x = trajs[s][0] + 0.3 * p.sigma_b[:, None, None] * rng.standard_normal(trajs[s][0].shape)
+        lt = local.forward(geo, x, rings[s])
+        dx = rng.standard_normal(x.shape)
+        y = rng.standard_normal(lt.shape)
+        lhs = np.sum(local.tlm(geo, lt, rings[s], dx) * y)
+        rhs = np.sum(dx * local.adjoint(geo, lt, rings[s], y))
+        assert abs(lhs - rhs) <= 1e-13 * abs(lhs), s
+        # one step
+        P = geo.pad(x, rings[s][0])
+        dP = geo.pad(dx, None)
+        lam = rng.standard_normal(x.shape)
+        lhs = np.sum(local.increment_tl(geo, P, dP) * lam)
+        rhs = np.sum(dx * local.increment_ad(geo, P, lam))
+        assert abs(lhs - rhs) <= 1e-14 * abs(lhs)
+
+
+# --- P6: TLM against finite differences of the forward ----------------------
+def test_tlm_matches_finite_differences(rng):
+    p = problem("small")
+    g, maps, trajs, rings = _local_setup(p)
+    s = 4
+    geo = local.LocalGeometry(g, maps, s)
+    x = trajs[s][0]
+    dx = p.sigma_b[:, None, None] * rng.standard_normal(x.shape)
+    lt = local.forward(geo, x, rings[s])
+    tl = local.tlm(geo, lt, rings[s], dx)
+    errs = []
+    for eps in (1e-1, 5e-2):
+        fd = (local.forward(geo, x + eps * dx, rings[s]) - local.forward(geo, x - eps * dx, rings[s])) / (2 * eps)
+        errs.append(np.linalg.norm(fd - tl) / np.linalg.norm(tl))
+    assert errs[0] < 1e-4
+    assert 3.0 < errs[0] / errs[1] < 5.0   # O(eps^2)
+
+
+# --- P5: gradient of the full local functional vs finite differences -------
+@pytest.mark.parametrize("which", ["c1", "span"])
+def test_local_gradient_finite_differences(rng, which):
+    """Discretize-then-optimize (Sec. 1): the gradient is that of the discrete J."""
+    p = problem("c1") if which == "c1" else custom_problem(SPAN_CFG)
+    g, maps, trajs, rings = _local_setup(p)
+    sb = p.sigma_b[:, None, None]
+    for s in range(len(maps.boxes)):
+        xb = trajs[s][0]
+        x = xb + 0.5 * sb * rng.standard_normal(xb.shape)
+        nb = {k: trajs[k] for k in maps.neighbors[s]}
+        J, gr = local.cost_grad(p, maps, s, x, xb, rings[s], nb)
+        d = sb * rng.standard_normal(xb.shape)
+        an = np.sum(gr * d)
+        errs = []
+        for eps in (1e-3, 5e-4):
+            Jp = local.cost_grad(p, maps, s, x + eps * d, xb, rings[s], nb, with_grad=False)
+            Jm = local.cost_grad(p, maps, s, x - eps * d, xb, rings[s], nb, with_grad=False)
+            errs.append(abs((Jp - Jm) / (2 * eps) - an) / abs(an))
+        assert errs[1] < 1e-6, (s, errs)
+
+
+def test_global_gradient_finite_differences(rng):
+    p = problem("c1")
+    sb = p.sigma_b[:, None, None]
+    x = p.xb0 + 0.5 * sb * rng.standard_normal(p.xb0.shape)
+    J, gr = model.cost_grad(p, x)
+    d = sb * rng.standard_normal(x.shape)
+    an = np.sum(gr * d)
+    eps = 5e-4
+    fd = (model.cost_grad(p, x + eps * d, False) - model.cost_grad(p, x - eps * d, False)) / (2 * eps)
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+# --- P12: brute-force Jacobian of a tiny box vs adjoint rows ----------------
+def test_bruteforce_jacobian_tiny_box():
+    p = problem("tiny2")
+    g, maps, trajs, rings = _local_setup(p)
+    s = 5
+    geo = local.LocalGeometry(g, maps, s)
+    x = trajs[s][0]
+    lt = local.forward(geo, x, rings[s])
+    n_in = x.size
+    n_out = lt.size
+    Jfd = np.empty((n_out, n_in))
+    for i in range(n_in):
+        e = np.zeros(n_in)
+        e[i] = 1e-3 * p.sigma_b[i // (x.size // 3)]
+        xp = local.forward(geo, x + e.reshape(x.shape), rings[s])
+        xm = local.forward(geo, x - e.reshape(x.shape), rings[s])
+        Jfd[:, i] = ((xp - xm) / (2 * e[i])).ravel()
+    Jad = np.empty_like(Jfd)
+    for j in range(n_out):
+        y = np.zeros(n_out)
+        y[j] = 1.0
+        Jad[j] = local.adjoint(geo, lt, rings[s], y.reshape(lt.shape)).ravel()
+    assert np.max(np.abs(Jad - Jfd)) <= 1e-6 * np.max(np.abs(Jad))
+
+
+# --- P8: one subdomain reproduces global 4D-Var -----------------------------
+def test_one_subdomain_equals_global(rng):
+    """With P = Q = 1 the local functional is the global one (eq. min3sec)."""
+    p = problem("tiny1")
+    maps = ddmaps.build(p)
+    assert len(maps.boxes) == 1 and (maps.halo_src[0] < 0).all()
+    for _ in range(3):
+        x = p.xb0 + p.sigma_b[:, None, None] * rng.standard_normal(p.xb0.shape)
+        Jg, gg = model.cost_grad(p, x)
+        Jl, gl = local.cost_grad(p, maps, 0, x, p.xb0, None, {})
+        assert abs(Jg - Jl) <= 1e-14 * Jg
+        assert np.max(np.abs(gg - gl)) <= 1e-13 * np.max(np.abs(gg))
+    # a bigger single box too
+    cfg = dict(synth.CONFIGS["c1"], bands=1, pieces=1, ntime=1, overlap_cells=0,
+               overlap_steps=0, index=112)
+    p = custom_problem(cfg)
+    maps = ddmaps.build(p)
+    x = p.xb0 + p.sigma_b[:, None, None] * rng.standard_normal(p.xb0.shape)
+    Jg, gg = model.cost_grad(p, x)
+    Jl, gl = local.cost_grad(p, maps, 0, x, p.xb0, None, {})
+    assert abs(Jg - Jl) <= 1e-14 * Jg
+    assert np.linalg.norm(gg - gl) <= 1e-13 * np.linalg.norm(gg)
+
+
+# --- P9: J = sum of the extended local functionals (eq. restJ) --------------
+@pytest.mark.parametrize("which", ["c1", "mixed", "span"])
+def test_cost_is_sum_of_local_costs(rng, which):
+    """With one time interval and rings/targets from the global trajectory of x,
+    the weighted local functionals sum to the global one at any x."""
+    base = {"c1": synth.CONFIGS["c1"], "mixed": MIXED_CFG, "span": SPAN_CFG}[which]
+    cfg = dict(base, ntime=1, index=base["index"] + 50)
+    p = custom_problem(cfg)
+    g = _grid(p)
+    maps = ddmaps.build(p)
+    x = p.xb0 + p.sigma_b[:, None, None] * rng.standard_normal(p.xb0.shape)
+    gt = model.forward(g, x, p.nsteps)
+    trajs = {b.sub: local.restrict_global(maps, b.sub, gt) for b in maps.boxes}
+    xb0 = p.xb0[None]
+    total = 0.0
+    for b in maps.boxes:
+        ring = local.ring_from_trajs(maps, b.sub, trajs)
+        xbs = local.restrict_global(maps, b.sub, xb0)[0]
+        J, parts = local.cost_grad(p, maps, b.sub, trajs[b.sub][0], xbs, ring,
+                                   {k: trajs[k] for k in maps.neighbors[b.sub]},
+                                   with_grad=False, parts=True)
+        assert parts[2] == 0.0   # overlap copies agree exactly
+        total += J
+    Jg = model.cost_grad(p, x, with_grad=False)
+    assert abs(total - Jg) <= 1e-13 * Jg
+
+
+# --- P11: background is the minimizer without observations -----------------
+def test_background_minimizer_without_obs():
+    p = problem("c1")
+    p = p.replace(obs_step=p.obs_step[:0], obs_cell=p.obs_cell[:0], obs_field=p.obs_field[:0],
+                  obs_value=p.obs_value[:0], obs_sigma=p.obs_sigma[:0], obs_noise=p.obs_noise[:0])
+    cfg_q1 = p.replace(time_edges=np.array([0, p.nsteps], dtype=np.int32))
+    for q in (p, cfg_q1):
+        maps = ddmaps.build(q)
+        bg, trajs = dd.background(q, maps)
+        rings, _ = dd.exchange(maps, trajs)
+        for s in range(len(maps.boxes)):
+            nb = {k: trajs[k] for k in maps.neighbors[s]}
+            if q is p:
+                qq = q.replace(mu_overlap=0.0)
+            else:
+                qq = q     # one interval: the local model reproduces the background
+            J, gr = local.cost_grad(qq, maps, s, trajs[s][0], trajs[s][0], rings[s], nb)
+            assert J == 0.0 and np.all(gr == 0.0)
+
+
+# --- P7: normal equations closed form on a tiny linearized case -------------
+def _dense_tlm(step_fn, n_in):
+    cols = []
+    for i in range(n_in):
+        e = np.zeros(n_in)
+        e[i] = 1.0
+        cols.append(step_fn(e).ravel())
+    return np.array(cols).T
+
+
+def test_normal_equations_global():
+    """delta x* = (B^-1 + G^T R^-1 G)^-1 G^T R^-1 d (eqs. line5and7, line6and7)
+    equals the L-BFGS minimizer of the linearized J built from TLM/adjoint, and
+    grad J(x_b) = -G^T R^-1 d."""
+    p = problem("tiny1")
+    g = _grid(p)
+    tr = model.forward(g, p.xb0, p.nsteps)
+    n = p.xb0.size
+    Mfull = _dense_tlm(lambda e: model.tlm(g, tr, e.reshape(p.xb0.shape)), n)
+    rows = (p.obs_step.astype(np.int64) * n + p.obs_field.astype(np.int64) * (n // 3)
+            + p.obs_cell.astype(np.int64))
+    G = Mfull[rows]
+    Rinv = p.lambda_obs / p.obs_sigma ** 2
+    Binv = np.repeat(1.0 / p.sigma_b ** 2, n // 3)
+    d = p.obs_value - tr.ravel()[rows]
+    A = np.diag(Binv) + G.T @ (Rinv[:, None] * G)
+    rhs = G.T @ (Rinv * d)
+    dx_star = np.linalg.solve(A, rhs)
+    # gradient identity at the background
+    _, gb = model.cost_grad(p, p.xb0)
+    assert np.max(np.abs(gb.ravel() + rhs)) <= 1e-12 * np.max(np.abs(rhs))
+    # L-BFGS on the linearized functional, in xi = dx / sigma_b
+
+    sb = np.repeat(p.sigma_b, n // 3)
+
+    def fun(xi):
+        dx = sb * xi
+        Gd = (model.tlm(g, tr, dx.reshape(p.xb0.shape)).ravel())[rows]
+        r = Gd - d
+        J = 0.5 * np.sum(Binv * dx * dx) + 0.5 * np.sum(Rinv * r * r)
+        forcing = np.zeros(tr.size)
+        np.add.at(forcing, rows, Rinv * r)
+        gr = Binv * dx + model.adjoint(g, tr, forcing.reshape(tr.shape)).ravel()
+        return J, sb * gr
+
+    res = lbfgs.minimize(fun, np.zeros(n), m=8, max_iter=500, grad_rtol=1e-13)
+    dx_l = sb * res["x"]
+    assert np.linalg.norm(dx_l - dx_star) <= 1e-8 * np.linalg.norm(dx_star)
+
+
+def test_normal_equations_local():
+    """Same closed form for one subdomain of a 2x2x2 decomposition: obs and
+    overlap penalties act as weighted observations of the local trajectory,
+    so the Gauss-Newton normal matrix is B^-1 + M^T W M with M the dense TLM."""
+    p = problem("tiny2")
+    g, maps, trajs, rings = _local_setup(p)
+    s = 6
+    b = maps.boxes[s]
+    geo = local.LocalGeometry(g, maps, s)
+    xb = trajs[s][0]
+    lt = local.forward(geo, xb, rings[s])
+    n = xb.size
+    M = _dense_tlm(lambda e: local.tlm(geo, lt, rings[s], e.reshape(xb.shape)), n)
+    nb = {k: trajs[k] for k in maps.neighbors[s]}
+    J0, g0 = local.cost_grad(p, maps, s, xb, xb, rings[s], nb)
+    # weights of the squared residuals, entry by entry of the local trajectory
+    W = np.zeros(lt.size)
+    flat_idx = np.arange(lt.size).reshape(b.nlev, 3, -1)
+    _, csp = local.weights(p, maps, s)
+    for o in maps.obs_bin[s]:
+        cell = int(p.obs_cell[o])
+        loc = int(maps.box_index(b, cell // p.nlon, cell % p.nlon))
+        k = int(p.obs_step[o])
+        w = 1.0 / (csp[loc] * maps.time_count[k])
+        W[flat_idx[k - b.lev0, int(p.obs_field[o]), loc]] += p.lambda_obs * w / p.obs_sigma[o] ** 2
+    gr_, gc_ = maps.box_cells_global(b)
+    for sp in maps.neighbors[s]:
+        bp = maps.boxes[int(sp)]
+        mine = np.nonzero(maps.box_index(bp, gr_, gc_) >= 0)[0]
+        for lev in range(max(b.lev0, bp.lev0), min(b.lev0 + b.nlev, bp.lev0 + bp.nlev)):
+            for f in range(3):
+                W[flat_idx[lev - b.lev0, f, mine]] += p.mu_overlap / p.sigma_b[f] ** 2
+    Binv = (local.weights(p, maps, s)[0][None, :] / (p.sigma_b ** 2)[:, None]).ravel()
+    A = np.diag(Binv) + M.T @ (W[:, None] * M)
+    dx_star = np.linalg.solve(A, -g0.ravel())
+    sb = np.repeat(p.sigma_b, n // 3)
+
+    def quad(xi):
+        dx = sb * xi
+        Md = local.tlm(geo, lt, rings[s], dx.reshape(xb.shape)).ravel()
+        Hd = Binv * dx + local.adjoint(geo, lt, rings[s], (W * Md).reshape(lt.shape)).ravel()
+        return g0.ravel() @ dx + 0.5 * dx @ Hd, sb * (g0.ravel() + Hd)
+
+    res = lbfgs.minimize(quad, np.zeros(n), m=8, max_iter=1000, grad_rtol=1e-12)
+    assert np.linalg.norm(sb * res["x"] - dx_star) <= 1e-8 * np.linalg.norm(dx_star)
+    # the Gauss-Newton matrix predicts the change of the true gradient for a
+    # small step (the residual-times-curvature term is second order here)
+    dprobe = 1e-3 * sb * np.linspace(-1, 1, n)
+    _, g1 = local.cost_grad(p, maps, s, xb + dprobe.reshape(xb.shape), xb, rings[s], nb)
+    pred = A @ dprobe
+    assert np.linalg.norm((g1 - g0).ravel() - pred) <= 1e-2 * np.linalg.norm(pred)
+
+
+# --- P10: map invariants -----------------------------------------------------
+@pytest.mark.parametrize("which", ["c1", "c2", "small", "span", "mixed", "c3"])
+def test_map_invariants(which):
+    if which == "span":
+        p = synth.make_spec(SPAN_CFG)
+    elif which == "mixed":
+        p = synth.make_spec(MIXED_CFG)
+    else:
+        p = synth.make_spec(which)
+    maps = ddmaps.build(p)
+    nl, nn = p.nlat, p.nlon
+    # every cell is in exactly one core
+    cnt = np.zeros((nl, nn), int)
+    for b in maps.boxes[:maps.nspace]:
+        cnt[b.core_row0:b.core_row1, b.core_col0:b.core_col1] += 1
+    assert (cnt == 1).all()
+    # box sizes: core + 2 o per side, clipped at the poles (eqs. Eq-r, nlocx)
+    o = p.overlap_cells
+    for b in maps.boxes:
+        exp_ny = min(nl, b.core_row1 + o) - max(0, b.core_row0 - o)
+        assert b.ny == exp_ny
+        assert b.nx == (nn if b.span else b.core_col1 - b.core_col0 + 2 * o)
+    # ring sources: the (pole-mapped) neighbour cell, inside the source core
+    half = nn // 2
+    for b in maps.boxes:
+        ny, nx = b.ny, b.nx
+        for k in range(b.nring):
+            if k < nx:
+                r, c = -1, k
+            elif k < 2 * nx:
+                r, c = ny, k - nx
+            elif k < 2 * nx + ny:
+                r, c = k - 2 * nx, -1
+            else:
+                r, c = k - 2 * nx - ny, nx
+            grow, gcol = b.row0 + r, (b.col0 + c) % nn
+            sign = 1
+            if grow < 0:
+                grow, gcol, sign = 0, (gcol + half) % nn, -1
+            elif grow >= nl:
+                grow, gcol, sign = nl - 1, (gcol + half) % nn, -1
+            src = int(maps.halo_src[b.sub][k])
+            off = int(maps.halo_off[b.sub][k])
+            assert int(maps.halo_sign[b.sub][k]) == sign
+            if src < 0:
+                assert b.span
+                assert off // nx == grow - b.row0 and off % nx == gcol
+            else:
+                sb = maps.boxes[src]
+                assert sb.interval == b.interval
+                assert sb.core_row0 <= grow < sb.core_row1 and sb.core_col0 <= gcol < sb.core_col1
+                assert off // sb.nx == grow - sb.row0
+                assert (sb.col0 + off % sb.nx) % nn == gcol
+    # overlap neighbour sets are symmetric and exactly the intersecting boxes
+    for b in maps.boxes:
+        for sp in maps.neighbors[b.sub]:
+            assert b.sub in set(maps.neighbors[int(sp)].tolist())
+    # partition of unity: counts equal the number of boxes containing each point
+    cover = np.zeros((nl, nn), int)
+    for b in maps.boxes[:maps.nspace]:
+        rows = np.arange(b.row0, b.row0 + b.ny)
+        cols = (b.col0 + np.arange(b.nx)) % nn
+        cover[np.ix_(rows, cols)] += 1
+    assert (cover == maps.cover_sp).all()
+    # observation bins: each observation lands in every box containing it
+    for o in range(0, p.nobs, max(1, p.nobs // 200)):
+        cell = int(p.obs_cell[o])
+        k = int(p.obs_step[o])
+        hits = [b.sub for b in maps.boxes if b.lev0 <= k < b.lev0 + b.nlev and
+                maps.box_index(b, cell // nn, cell % nn) >= 0]
+        got = [s for s in range(len(maps.boxes)) if o in set(maps.obs_bin[s].tolist())]
+        assert hits == got
+        assert len(hits) == maps.cover_sp[cell // nn, cell % nn] * maps.time_count[k]
+
+
+def test_box_sizes_at_benchmark_configs():
+    """Extended sizes from the problem-size arithmetic (eqs. Eq-r, nlocx)."""
+    p = synth.make_spec("c5")
+    maps = ddmaps.build(p)
+    assert len(maps.boxes) == 2048
+    sizes = {(b.ny, b.nx) for b in maps.boxes}
+    assert sizes == {(68, 136), (72, 136)}
+    assert sorted({b.nlev for b in maps.boxes}) == [30, 34]
+    local_pt_steps = sum(b.ny * b.nx * (b.nlev - 1) for b in maps.boxes)
+    # 32 polar + 224 interior boxes per interval; 2 intervals of 29 steps, 6 of 33
+    assert local_pt_steps == (32 * 68 + 224 * 72) * 136 * (2 * 29 + 6 * 33) == 637272064
+    assert p.nobs == 999999
+
+
+# --- L-BFGS on a known quadratic and the DD outer loop ------------------------
+def test_lbfgs_quadratic(rng):
+    n = 40
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    bvec = rng.standard_normal(n)
+    res = lbfgs.minimize(lambda x: (0.5 * x @ A @ x - bvec @ x, A @ x - bvec), np.zeros(n),
+                         max_iter=300, grad_rtol=1e-9)
+    assert res["status"] == "converged"
+    xs = np.linalg.solve(A, bvec)
+    assert np.linalg.norm(res["x"] - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_dd_solve_improves_on_background():
+    """Alg. 1 on the smallest configuration: the analysis is closer to the truth
+    than the background, and the gather reproduces the controls' partition of
+    unity."""
+    p = problem("tiny2")
+    xa, rep = dd.solve(p, max_outer=2, max_iter=30)
+    assert rep["outer"] >= 1
+    e_b = np.linalg.norm((p.xb0 - p.truth0) / p.sigma_b[:, None, None])
+    e_a = np.linalg.norm((xa - p.truth0) / p.sigma_b[:, None, None])
+    assert e_a < e_b
+    maps = ddmaps.build(p)
+    # gather of the background trajectory returns the background
+    bg, trajs = dd.background(p, maps)
+    np.testing.assert_allclose(dd.gather(p, maps, trajs, 0), p.xb0, rtol=1e-15, atol=0)
