@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Benchmark: batched local cost + gradient of space-time DD 4D-Var on one GPU.
+
+One step = one evaluation of every subdomain's regularized local functional
+and its gradient (background term, forward sweep, observation and overlap
+misfits, adjoint sweep, FP64 reductions) through dd4dvar_local_cost_grad.
+
+Default workload: SWE on a 1024 x 2048 lat-lon grid, 200 steps, 16 x 16
+spatial pieces x 8 time intervals (2048 subdomains), overlap 4 cells / 4
+steps, 999,999 observations every 10 steps; FP32 state sweeps with FP64
+costs and gradients.  Inputs are seeded and synthetic (twin experiment); the
+truth run that produces the observation values runs on the GPU library.
+
+Prints one JSON line.  Extra fields: the plain per-subdomain FP64 path
+(one launch per subdomain per step) and the batched FP64 path, the FP32
+error against FP64, phase timings, and the oracle timed on host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def gpu_truth_forward(spec, x0, steps):
+    """Truth trajectory at the observation steps, run by the GPU library."""
+    import torch
+    from paper_2205_06649_amd.context import Context
+    one = spec.replace(band_lat_edges=np.array([0, spec.nlat], np.int32),
+                       band_npieces=np.array([1], np.int32),
+                       piece_lon_edges=np.array([0, spec.nlon], np.int32),
+                       time_edges=np.array([0, spec.nsteps], np.int32),
+                       overlap_cells=0, overlap_steps=0, xb0=x0,
+                       obs_step=spec.obs_step[:0], obs_cell=spec.obs_cell[:0],
+                       obs_field=spec.obs_field[:0], obs_value=np.zeros(0),
+                       obs_sigma=spec.obs_sigma[:0], obs_noise=spec.obs_noise[:0])
+    ctx = Context(one, "fp64")
+    traj = ctx.forward_global(torch.from_numpy(np.ascontiguousarray(x0)).cuda())
+    out = traj[list(steps)].cpu().numpy()
+    del traj
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def algorithmic_bytes(ctx, prec_bytes):
+    """Compulsory HBM bytes of one evaluation, per sweep (no re-reads).
+
+    Forward launch at level n, per active cell: read Z^n and Z^{n-1}, write
+    Z^{n+1} (3 fields each) + frozen ring values of level n.  Adjoint launch at
+    level n, per cell: read Z^n, lambda^{n+1}, lambda^{n+2}, write lambda^n
+    (when they exist), the overlap target where covered, the coverage byte,
+    ring values, 20 B per observation entry; level 0 reads x, x_b (FP64) and
+    writes the FP64 gradient instead of lambda^0.
+    """
+    from paper_2205_06649_amd import _lib as L
+    b = prec_bytes
+    tcount = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_TIME_COUNT, 0)
+    fwd = adj = 0.0
+    pts = 0
+    for s, inf in enumerate(ctx.info):
+        ny, nx, lev0, nlev = int(inf[1]), int(inf[3]), int(inf[4]), int(inf[5])
+        ncell = ny * nx
+        L_ = nlev - 1
+        pts += ncell * L_
+        nfrozen = int(np.count_nonzero(L.dd4dvar_plan_get_map(ctx.plan, L.MAP_HALO_SRC, s) >= 0))
+        cover = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_COVER, s).astype(np.int64)
+        nobs = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_OBS_BIN, s).size
+        # forward: init + L steps
+        fwd += ncell * (24 + 3 * b)
+        for n in range(L_):
+            fwd += ncell * 3 * b * (3 if n >= 1 else 2) + nfrozen * 3 * b
+        # adjoint: levels L..0
+        for n in range(L_, -1, -1):
+            nvec = 1 + (n + 1 <= L_) + (n + 2 <= L_) + (n > 0)
+            covered = int(np.count_nonzero(cover * tcount[lev0 + n] - 1 > 0))
+            adj += ncell * (nvec * 3 * b + 1) + covered * 3 * b + nfrozen * 3 * b
+            if n == 0:
+                adj += ncell * 72
+        adj += nobs * 20
+    return fwd, adj, pts
+
+
+def time_evals(ctx, x, steps, warmup):
+    import torch
+    J = torch.empty(ctx.nsub, dtype=torch.float64, device="cuda")
+    g = torch.empty(ctx.ctrl_len, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        ctx.cost_grad(x, J, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.cost_grad(x, J, g)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, J, g
+
+
+def cpu_baseline(spec, budget_s=20.0):
+    """The FP64 oracle timed on host cores over a bounded sample: whole local
+    cost+gradient evaluations of first-interval subdomains of the workload."""
+    from oracle import ddmaps, local, model
+    g = model.Grid.of(spec)
+    maps = ddmaps.build(spec.replace(obs_value=np.zeros(spec.nobs)))
+    sample = [b.sub for b in maps.boxes if b.interval == 0 and b.ny == max(bb.ny for bb in maps.boxes)]
+    lmax = max(maps.boxes[s].nlev for s in sample) - 1
+    steps = sorted({int(k) for k in spec.obs_step if k <= lmax})
+    truth = model.forward_at(g, spec.truth0, steps)
+    pos = {k: i for i, k in enumerate(steps)}
+    vals = np.full(spec.nobs, np.nan)
+    sel = spec.obs_step <= lmax
+    idx = np.array([pos[int(k)] for k in spec.obs_step[sel]])
+    vals[sel] = (truth.reshape(len(steps), 3, -1)[idx, spec.obs_field[sel].astype(int),
+                                                     spec.obs_cell[sel]]
+                 + spec.obs_sigma[sel] * spec.obs_noise[sel])
+    prob = spec.replace(obs_value=vals)   # later steps are never read by the sample
+    bg = model.forward(g, spec.xb0, lmax)
+    trajs = {}
+    rng = np.random.default_rng(1)
+    done = 0
+    pts = 0
+    t_total = 0.0
+    for s in sample:
+        b = maps.boxes[s]
+        need = set(maps.neighbors[s].tolist()) | set(int(k) for k in maps.halo_src[s] if k >= 0)
+        for k in need:
+            if k not in trajs:
+                trajs[k] = local.restrict_global(maps, k, bg)
+        trajs.setdefault(s, local.restrict_global(maps, s, bg))
+        ring = local.ring_from_trajs(maps, s, trajs)
+        xb = trajs[s][0]
+        x = xb + 0.3 * spec.sigma_b[:, None, None] * rng.standard_normal(xb.shape)
+        t0 = time.perf_counter()
+        local.cost_grad(prob, maps, s, x, xb, ring, {k: trajs[k] for k in maps.neighbors[s]})
+        t_total += time.perf_counter() - t0
+        pts += b.ny * b.nx * (b.nlev - 1)
+        done += 1
+        if t_total >= budget_s:
+            break
+    return dict(value=pts / t_total, unit="local grid-point-steps/s", cores=1, kind="oracle",
+                sample=f"{done} full local cost+gradient evaluations of first-interval "
+                       f"{maps.boxes[sample[0]].ny}x{maps.boxes[sample[0]].nx}x"
+                       f"{maps.boxes[sample[0]].nlev - 1}-step subdomains of the same workload "
+                       f"(NumPy FP64, one process, {t_total:.1f} s)",
+                seconds=t_total)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c5")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the whole path runs in-device on a single MI355X; "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        return 2
+
+    import torch
+    import synth
+    from paper_2205_06649_amd.context import Context
+
+    t0 = time.perf_counter()
+    spec = synth.make_spec(args.config)
+    log(f"spec {args.config}: {spec.nlat}x{spec.nlon}x{spec.nsteps}, nobs={spec.nobs} "
+        f"({time.perf_counter() - t0:.1f}s)")
+    prob = synth.finish_spec(spec, gpu_truth_forward)
+    log(f"truth run + observations done ({time.perf_counter() - t0:.1f}s)")
+
+    ctx = Context(prob, "fp32")
+    log(f"fp32 context: {ctx.nsub} subdomains ({time.perf_counter() - t0:.1f}s)")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2205)
+    xb = ctx.background_controls()
+    sb = torch.tensor(prob.sigma_b, dtype=torch.float64, device="cuda")
+    scale = torch.cat([sb[f].expand(int(inf[1]) * int(inf[3])) for inf in ctx.info for f in range(3)])
+    x = xb + 0.3 * scale * torch.randn(ctx.ctrl_len, generator=gen, dtype=torch.float64, device="cuda")
+
+    ms, J32, g32 = time_evals(ctx, x, args.steps, args.warmup)
+    fwd_b, adj_b, pts = algorithmic_bytes(ctx, 4)
+    log(f"fp32 batched: {ms:.3f} ms/eval")
+    ctx.set_timing(True)
+    for _ in range(3):
+        ctx.cost_grad(x, J32, g32)
+    tm = ctx.get_timing()
+    ctx.set_timing(False)
+    calls = tm["calls"]
+    fwd_ms, adj_ms = tm["fwd_ms"] / calls, tm["adj_ms"] / calls
+    adj_launch_ms = tm["adj_ms"] / tm["adj_launches"]
+    achieved = adj_b / (adj_ms * 1e-3) / 1e9
+    J32h, g32h = J32.cpu().numpy(), g32.cpu().numpy()
+    del ctx
+    torch.cuda.empty_cache()
+
+    result = {
+        "metric": "fwd+adjoint grid-point-steps/s",
+        "value": pts / (ms * 1e-3),
+        "unit": "local grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"SWE on the sphere {prob.nlat}x{prob.nlon}, {prob.nsteps} steps, "
+                        f"{ctx.nsub if False else len(J32h)} subdomains "
+                        f"({int(len(prob.band_npieces))}x{int(prob.band_npieces[0])} space x "
+                        f"{len(prob.time_edges) - 1} time), overlap {prob.overlap_cells} cells/"
+                        f"{prob.overlap_steps} steps, {prob.nobs} obs; batched FP32 state, "
+                        f"FP64 cost/gradient",
+            "local_point_steps_per_eval": int(pts),
+            "global_point_steps_per_eval": int(prob.nlat * prob.nlon * prob.nsteps),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_adj (adjoint step, all subdomains per launch)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": adj_b / tm["adj_launches"] * calls,
+            "avg_launch_ms": adj_launch_ms,
+        },
+        "phases_ms": {"forward_sweep": fwd_ms, "adjoint_sweep": adj_ms,
+                      "reduce": tm["reduce_ms"] / calls},
+        "forward_sweep_GBs": fwd_b / (fwd_ms * 1e-3) / 1e9,
+        "whole_eval_algorithmic_GBs": (fwd_b + adj_b) / (ms * 1e-3) / 1e9,
+        "global_point_steps_per_s": prob.nlat * prob.nlon * prob.nsteps / (ms * 1e-3),
+    }
+
+    if not args.no_fp64:
+        ctx64 = Context(prob, "fp64")
+        ms64, J64, g64 = time_evals(ctx64, x, max(2, args.steps // 4), 2)
+        J64h, g64h = J64.cpu().numpy(), g64.cpu().numpy()
+        ctx64.set_exec_mode(1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx64.cost_grad(x)
+        torch.cuda.synchronize()
+        ms_plain = (time.perf_counter() - t1) * 1e3
+        del ctx64
+        torch.cuda.empty_cache()
+        result["fp64_batched_ms"] = ms64
+        result["fp64_plain_per_subdomain_ms"] = ms_plain
+        result["speedup_vs_plain_fp64"] = ms_plain / ms
+        result["speedup_vs_batched_fp64"] = ms64 / ms
+        result["fp32_vs_fp64_rel_err"] = {
+            "J_max": float(np.max(np.abs(J32h - J64h) / np.abs(J64h))),
+            "grad_norm": float(np.linalg.norm(g32h - g64h) / np.linalg.norm(g64h)),
+        }
+        log(f"fp64 batched {ms64:.2f} ms, plain {ms_plain:.1f} ms")
+
+    if not args.no_cpu:
+        log("timing the oracle on host cores")
+        result["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
+        result["cpu_baseline"]["host_cpu"] = _cpu_model()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,263 @@
+/*
+ * dd4dvar.h -- C ABI of the MI355X space-time domain-decomposed 4D-Var engine.
+ *
+ * The library evaluates, for every space-time subdomain Delta_j x Omega_i of
+ * a shallow-water-on-the-sphere problem, the regularized local 4D-Var
+ * functional of the paper's local 4D-Var DA definition (eq. eq:cost:parallel1:
+ * background term + observation misfit + overlap penalty) and its gradient,
+ * all subdomains at once on one GPU, and runs the DD-4DVar outer loop
+ * (Alg. 1) around it.
+ *
+ * Conventions shared by every call
+ *   - Every call returns dd4dvar_status (0 = OK).  Nothing aborts and no C++
+ *     exception crosses the ABI.  On failure, dd4dvar_last_error() describes
+ *     the cause.
+ *   - Fields are ordered (h, u, v).  Grid arrays are [field][lat][lon] with
+ *     longitude fastest and latitude running south to north; a cell index is
+ *     lat * nlon + lon.  h is the full fluid depth in metres.
+ *   - Pointers named *_dev are device pointers owned by the caller (for
+ *     example torch tensors); they must stay valid until the work queued on
+ *     the given stream has completed.  Pointers without the suffix are host
+ *     pointers, read before the call returns.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls marked "asynchronous" only enqueue work on that stream.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *   - Packed control layout (FP64): the subdomains' controls concatenated in
+ *     subdomain order, each [3][ny][nx] over its extended box, starting at
+ *     the ctrl_offset reported by dd4dvar_plan_subdomain_info.
+ *   - Packed trajectory layout (FP64): per subdomain [nlev][3][ny][nx],
+ *     starting at traj_offset.
+ */
+#ifndef DD4DVAR_H
+#define DD4DVAR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dd4dvar_ctx dd4dvar_ctx;    /* owns all device memory */
+typedef struct dd4dvar_plan dd4dvar_plan;  /* host-only maps */
+
+typedef enum {
+  DD4DVAR_OK = 0,
+  DD4DVAR_E_INVALID = 1,       /* bad descriptor or argument; nothing was done */
+  DD4DVAR_E_NOMEM = 2,         /* device or host allocation failed */
+  DD4DVAR_E_DEVICE = 3,        /* a HIP call failed; last_error holds its text */
+  DD4DVAR_E_NONFINITE = 4,     /* NaN/Inf met in a cost or gradient */
+  DD4DVAR_E_NOTCONVERGED = 5,  /* iteration cap hit; outputs are still written */
+  DD4DVAR_E_STATE = 6          /* call order violated (e.g. adjoint before forward) */
+} dd4dvar_status;
+
+typedef enum { DD4DVAR_FP64 = 0, DD4DVAR_FP32_STATE = 1 } dd4dvar_precision;
+
+/* Grid and model (Sec. 7: SWE on the sphere, unstaggered centred scheme with
+ * p = q = 1 and alpha = 0; leapfrog in time with a forward-Euler half
+ * increment at the start of every local interval).  nlon must be even (the
+ * row beyond a pole is the same row shifted by nlon/2 with u, v negated).
+ * dlambda = 2 pi / nlon, dtheta = pi / nlat, cell-centred latitudes.
+ * lambda_obs and mu_overlap are lambda of eq. min3sec and mu of
+ * eq. eq:cost:parallel1.  precision selects the storage/arithmetic type of the
+ * state sweeps (FP32_STATE stores h - h_ref); costs, gradients and all
+ * reductions are FP64 in both modes.  weight_mode 0 weights squared terms by
+ * 1/(number of boxes covering the point) (restriction weights of Def.
+ * defrestrfun); 1 uses unit weights. */
+typedef struct {
+  int32_t nlat, nlon, nsteps;
+  double dt, radius, gravity, omega, h_ref;
+  double lambda_obs, mu_overlap;
+  int32_t precision;
+  int32_t weight_mode;
+} dd4dvar_model_desc;
+
+/* Space-time partition DD(Delta x Omega) (Def. domdecom, eqs. Eq-r, nlocx).
+ * band_lat_edges: [n_bands+1], 0 .. nlat strictly increasing.
+ * band_npieces:   [n_bands], >= 1.
+ * piece_lon_edges: per band npieces+1 edges 0 .. nlon, concatenated.
+ * time_edges:     [n_time+1], 0 .. nsteps strictly increasing.
+ * Each core grows by overlap_cells on every side (clipped at the poles,
+ * wrapped in longitude; a band of one piece spans the circle) and each
+ * interval by overlap_steps on each side (clipped to [0, nsteps], closed).
+ * Requires overlap_cells <= every core height and multi-piece core width,
+ * core width + 2 overlap_cells < nlon, overlap_steps <= every interval. */
+typedef struct {
+  int32_t n_bands;
+  const int32_t* band_lat_edges;
+  const int32_t* band_npieces;
+  const int32_t* piece_lon_edges;
+  int32_t n_time;
+  const int32_t* time_edges;
+  int32_t overlap_cells, overlap_steps;
+} dd4dvar_partition_desc;
+
+/* Background and observations (DA problem setup, Sec. 2).  xb0 is the
+ * background initial state [3][nlat][nlon]; sigma_b the per-field background
+ * standard deviations (diagonal B); each observation is one field at one
+ * cell at one model step with its own standard deviation (diagonal R).
+ * Observations must be finite and unique per (step, cell, field). */
+typedef struct {
+  const double* xb0;
+  const double* sigma_b;
+  int64_t nobs;
+  const int32_t* obs_step;
+  const int32_t* obs_cell;
+  const int8_t* obs_field;
+  const double* obs_value;
+  const double* obs_sigma;
+} dd4dvar_data_desc;
+
+/* ---- host-only planning (no GPU needed) -------------------------------- */
+
+/* Validates the descriptors and builds every index map (boxes, halo sources,
+ * coverage counts, overlap neighbours, observation bins).  Copies all inputs.
+ * Returns E_INVALID for bad descriptors, E_NOMEM on allocation failure. */
+dd4dvar_status dd4dvar_plan_create(const dd4dvar_model_desc* model,
+                                   const dd4dvar_partition_desc* part,
+                                   const dd4dvar_data_desc* data,
+                                   dd4dvar_plan** out);
+void dd4dvar_plan_destroy(dd4dvar_plan* plan);
+
+/* Number of subdomains and total packed control / trajectory lengths. */
+dd4dvar_status dd4dvar_plan_sizes(const dd4dvar_plan* plan, int32_t* nsub,
+                                  int64_t* ctrl_len, int64_t* traj_len);
+
+/* out[10] = {row0, ny, col0, nx, step0, nlev, ctrl_offset, traj_offset,
+ *            spans_all_lon, nring} of subdomain s (s = interval * nspace +
+ * piece, pieces band-major).  The box covers global rows row0..row0+ny-1 and
+ * columns (col0 + c) mod nlon, c < nx; levels step0..step0+nlev-1. */
+dd4dvar_status dd4dvar_plan_subdomain_info(const dd4dvar_plan* plan, int32_t s,
+                                           int64_t out[10]);
+
+/* Integer maps for bit-exact checks.  kind:
+ *   0 HALO_SRC   per s, [nring]: source subdomain of each ring position, -1
+ *                when the position wraps inside the box.  Ring positions:
+ *                south row (box row -1, cols 0..nx-1), north row (row ny),
+ *                west column (col -1, rows 0..ny-1), east column (col nx).
+ *   1 HALO_OFF   per s, [nring]: cell offset in the source box (or in the box
+ *                itself for internal positions)
+ *   2 HALO_SIGN  per s, [nring]: +1, or -1 across a pole (applies to u, v)
+ *   3 COVER      per s, [ny*nx]: number of extended spatial boxes covering
+ *                each box cell
+ *   4 TIME_COUNT global, [nsteps+1]: number of extended intervals per level
+ *   5 NEIGHBORS  per s: sorted subdomains whose extended space-time box
+ *                intersects that of s
+ *   6 OBS_BIN    per s: sorted indices of the observations inside s
+ *   7 HALO_GCELL per s, [nring]: global cell read by each frozen position
+ * With buf == NULL the required length is stored in *len; otherwise *len is
+ * the capacity of buf (E_INVALID if too small) and receives the length. */
+dd4dvar_status dd4dvar_plan_get_map(const dd4dvar_plan* plan, int32_t kind,
+                                    int32_t s, int64_t* len, int32_t* buf);
+
+/* Last error of a context, or of the calling thread's last plan/create call
+ * when ctx is NULL.  The string stays valid until the next call. */
+const char* dd4dvar_last_error(const dd4dvar_ctx* ctx);
+
+/* ---- device context ------------------------------------------------------ */
+
+/* Builds the plan, allocates the device arena on the current HIP device,
+ * copies the inputs, runs the background model over the whole window in FP64
+ * (Alg. 1, first step) and fills the frozen halo rings, overlap targets and
+ * per-subdomain backgrounds from it.  Synchronous. */
+dd4dvar_status dd4dvar_create(const dd4dvar_model_desc* model,
+                              const dd4dvar_partition_desc* part,
+                              const dd4dvar_data_desc* data, void* stream,
+                              dd4dvar_ctx** out);
+void dd4dvar_destroy(dd4dvar_ctx* ctx);
+
+/* The plan owned by a context (valid until dd4dvar_destroy). */
+const dd4dvar_plan* dd4dvar_ctx_plan(const dd4dvar_ctx* ctx);
+
+/* Packed FP64 background controls x^b_s: the background trajectory at each
+ * subdomain's first level on its box (eq. funrestr).  Asynchronous. */
+dd4dvar_status dd4dvar_background_controls(dd4dvar_ctx* ctx, double* x_dev,
+                                           void* stream);
+
+/* The hot path.  For every subdomain s (or those listed in sub_ids, a host
+ * array of nsub ids; NULL = all): J_s(x_s) of eq. eq:cost:parallel1 and its
+ * gradient, from the packed FP64 controls x_dev.  Writes J_dev[s] (FP64, one
+ * per subdomain, entries of unlisted subdomains untouched) and grad_dev
+ * (packed FP64).  Runs the forward sweep, the observation and overlap misfits
+ * and the adjoint sweep; the local trajectories are kept for
+ * dd4dvar_adjoint_integrate.  Asynchronous. */
+dd4dvar_status dd4dvar_local_cost_grad(dd4dvar_ctx* ctx, int32_t nsub,
+                                       const int32_t* sub_ids,
+                                       const double* x_dev, double* J_dev,
+                                       double* grad_dev, void* stream);
+
+/* Forward model.  scope 0: the whole grid from x_dev = [3][nlat][nlon] over
+ * all nsteps, traj_dev = [nsteps+1][3][nlat][nlon] (required), FP64 always.
+ * scope 1: every subdomain's restricted model (eq. restricted) from packed
+ * controls x_dev with its frozen halo ring, in the context precision;
+ * traj_dev (nullable) receives the packed FP64 trajectories.  Asynchronous. */
+dd4dvar_status dd4dvar_forward_integrate(dd4dvar_ctx* ctx, int32_t scope,
+                                         const double* x_dev, double* traj_dev,
+                                         void* stream);
+
+/* Adjoint model of the last scope-1 forward (adjoint definition of Sec. 2,
+ * run step by step in reverse, eq. adjProd).  forcing_dev: packed FP64
+ * trajectory-shaped forcing, or NULL for the cost forcing (observation and
+ * overlap misfits at the stored trajectory).  adj0_dev receives the packed
+ * FP64 adjoint at each subdomain's first level (no background term).
+ * scope must be 1.  E_STATE if no scope-1 forward ran.  Asynchronous. */
+dd4dvar_status dd4dvar_adjoint_integrate(dd4dvar_ctx* ctx, int32_t scope,
+                                         const double* forcing_dev,
+                                         double* adj0_dev, void* stream);
+
+/* Exchange (Alg. 1): integrates every subdomain from the packed controls
+ * x_dev, then refreshes the frozen halo rings from the owners' trajectories
+ * and the overlap targets from the neighbours' trajectories.  Asynchronous. */
+dd4dvar_status dd4dvar_exchange(dd4dvar_ctx* ctx, const double* x_dev,
+                                void* stream);
+
+/* Partition-of-unity gather (eq. rest) of the subdomains' trajectories from
+ * the last scope-1 forward at one global level into out_dev [3][nlat][nlon]
+ * (FP64).  Asynchronous. */
+dd4dvar_status dd4dvar_gather(dd4dvar_ctx* ctx, int32_t level, double* out_dev,
+                              void* stream);
+
+/* Selects how local_cost_grad launches its kernels: 0 = all subdomains per
+ * launch (default), 1 = one launch per subdomain per step (plain baseline). */
+dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode);
+
+/* Phase timing of local_cost_grad, for measurement: when on, every call
+ * records HIP events on its stream around the forward sweep, the adjoint
+ * sweep and the final reduction.  dd4dvar_get_timing waits for them and
+ * returns, summed over the calls since the last query, out[6] = {forward ms,
+ * adjoint ms, reduction ms, forward launches, adjoint launches, calls}, then
+ * clears the record. */
+dd4dvar_status dd4dvar_set_timing(dd4dvar_ctx* ctx, int32_t on);
+dd4dvar_status dd4dvar_get_timing(dd4dvar_ctx* ctx, double out[6]);
+
+/* ---- DD-4DVar solve (Alg. 1) --------------------------------------------- */
+typedef struct {
+  int32_t lbfgs_m;      /* stored pairs (8) */
+  int32_t max_iter;     /* L-BFGS iterations per local solve */
+  int32_t max_outer;    /* outer DD sweeps */
+  int32_t max_ls;       /* Armijo trials per iteration (30) */
+  double grad_rtol;     /* stop a local solve at |g| <= grad_rtol |g0| */
+  double outer_tol;     /* stop when max_s |xi_s - xi_s_prev|_inf < outer_tol */
+  double armijo_c1;     /* 1e-4 */
+} dd4dvar_solve_opts;
+
+typedef struct {
+  int32_t outer_iters, total_evals, lbfgs_iters;
+  double J_final;            /* sum over subdomains of the final local J */
+  double gnorm_ratio_max;    /* max_s |g_s| / |g_s,0| at the end */
+  double seconds;
+} dd4dvar_solve_report;
+
+/* Runs Alg. 1 from x_init_dev (packed controls, NULL = background): batched
+ * L-BFGS over all subdomains in xi = (x - x^b_s) / sigma_b, then forward,
+ * exchange and the outer stop test; finally the partition-of-unity gather of
+ * level 0 into xa_host [3][nlat][nlon].  x_out_dev (nullable) receives the
+ * final packed controls.  Synchronous.  E_NOTCONVERGED when max_outer was
+ * reached without meeting outer_tol (outputs are written). */
+dd4dvar_status dd4dvar_solve(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* opts,
+                             const double* x_init_dev, double* x_out_dev,
+                             double* xa_host, dd4dvar_solve_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DD4DVAR_H */

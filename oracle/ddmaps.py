@@ -191,29 +191,38 @@ def build(prob) -> DDMaps:
             return True
         return ((b.col0 - a.col0) % nlon < a.nx) or ((a.col0 - b.col0) % nlon < b.nx)
 
+    # boxes of one interval share the spatial pieces, so the spatial test is
+    # done once per pair of pieces and the temporal one once per pair of
+    # intervals
+    smeet = [[i2 for i2 in range(nspace) if spatial_meet(boxes[i], boxes[i2])]
+             for i in range(nspace)]
+    tmeet = []
+    for j in range(ntime):
+        a = boxes[j * nspace]
+        tmeet.append([j2 for j2 in range(ntime)
+                      if not (a.lev0 > boxes[j2 * nspace].lev0 + boxes[j2 * nspace].nlev - 1
+                              or boxes[j2 * nspace].lev0 > a.lev0 + a.nlev - 1)])
     neighbors = []
     for a in boxes:
-        nb = []
-        for b in boxes:
-            if b.sub == a.sub:
-                continue
-            if a.lev0 > b.lev0 + b.nlev - 1 or b.lev0 > a.lev0 + a.nlev - 1:
-                continue
-            if spatial_meet(a, b):
-                nb.append(b.sub)
+        nb = [j2 * nspace + i2 for j2 in tmeet[a.interval] for i2 in smeet[a.piece]
+              if j2 * nspace + i2 != a.sub]
         neighbors.append(np.array(sorted(nb), dtype=np.int32))
 
-    # observation bins
+    # observation bins: candidates by level range (observations sorted by
+    # step), then the in-box test
     ostep = np.asarray(prob.obs_step, dtype=np.int64)
     ocell = np.asarray(prob.obs_cell, dtype=np.int64)
-    orow, ocol = ocell // nlon, ocell % nlon
+    order = np.argsort(ostep, kind="stable")
+    ssorted = ostep[order]
     obs_bin = []
     for bx in boxes:
-        inlev = (ostep >= bx.lev0) & (ostep <= bx.lev0 + bx.nlev - 1)
-        r = orow - bx.row0
-        c = (ocol - bx.col0) % nlon
+        lo = np.searchsorted(ssorted, bx.lev0, side="left")
+        hi = np.searchsorted(ssorted, bx.lev0 + bx.nlev - 1, side="right")
+        cand = order[lo:hi]
+        r = ocell[cand] // nlon - bx.row0
+        c = (ocell[cand] % nlon - bx.col0) % nlon
         inbox = (r >= 0) & (r < bx.ny) & (c < bx.nx)
-        obs_bin.append(np.nonzero(inlev & inbox)[0].astype(np.int64))
+        obs_bin.append(np.sort(cand[inbox]).astype(np.int64))
 
     return DDMaps(nlat=nlat, nlon=nlon, nsteps=nt, nspace=nspace, ntime=ntime,
                   boxes=boxes, owner=owner, cover_sp=cover_sp, time_count=time_count,

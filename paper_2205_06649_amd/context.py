@@ -1,0 +1,152 @@
+"""Device context wrapper: torch tensors for device memory and streams.
+
+Thin layer over the C ABI (argument marshalling only).  torch provides the
+device buffers and the current HIP stream; every computation runs in
+libdd4dvar.so.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib as L
+from .descriptors import Descriptors
+
+PRECISIONS = {"fp64": L.DD4DVAR_FP64, "fp32": L.DD4DVAR_FP32_STATE}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the dd4dvar engine needs a HIP device")
+    return torch
+
+
+class Context:
+    def __init__(self, prob, precision="fp64", device="cuda:0"):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.prob = prob
+        self.precision = precision
+        torch.cuda.set_device(self.device)
+        self.desc = Descriptors(prob, PRECISIONS[precision])
+        self.handle = L.dd4dvar_create(self.desc.model, self.desc.part, self.desc.data,
+                                       self._stream())
+        self.plan = L.dd4dvar_ctx_plan(self.handle)
+        self.nsub, self.ctrl_len, self.traj_len = L.dd4dvar_plan_sizes(self.plan)
+        self.info = [L.dd4dvar_plan_subdomain_info(self.plan, s) for s in range(self.nsub)]
+
+    # -- plumbing -----------------------------------------------------------
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.dd4dvar_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self, n):
+        return self.torch.empty(int(n), dtype=self.torch.float64, device=self.device)
+
+    @staticmethod
+    def ptr(t):
+        return None if t is None else t.data_ptr()
+
+    def set_exec_mode(self, mode):
+        L.dd4dvar_set_exec_mode(self.handle, mode)
+
+    def set_timing(self, on):
+        L.dd4dvar_set_timing(self.handle, on)
+
+    def get_timing(self):
+        return L.dd4dvar_get_timing(self.handle)
+
+    # -- C ABI calls --------------------------------------------------------
+    def background_controls(self):
+        x = self.empty(self.ctrl_len)
+        L.dd4dvar_background_controls(self.handle, x.data_ptr(), self._stream())
+        return x
+
+    def cost_grad(self, x, J=None, grad=None, sub_ids=None):
+        if J is None:
+            J = self.torch.full((self.nsub,), float("nan"), dtype=self.torch.float64,
+                                device=self.device)
+        if grad is None:
+            grad = self.torch.zeros(self.ctrl_len, dtype=self.torch.float64, device=self.device)
+        L.dd4dvar_local_cost_grad(self.handle, x.data_ptr(), J.data_ptr(), grad.data_ptr(),
+                                  self._stream(), sub_ids=sub_ids)
+        return J, grad
+
+    def forward(self, x, with_traj=True):
+        traj = self.empty(self.traj_len) if with_traj else None
+        L.dd4dvar_forward_integrate(self.handle, 1, x.data_ptr(), self.ptr(traj), self._stream())
+        return traj
+
+    def forward_global(self, x0):
+        p = self.prob
+        traj = self.empty((p.nsteps + 1) * 3 * p.nlat * p.nlon)
+        L.dd4dvar_forward_integrate(self.handle, 0, x0.data_ptr(), traj.data_ptr(), self._stream())
+        return traj.view(p.nsteps + 1, 3, p.nlat, p.nlon)
+
+    def adjoint(self, forcing=None):
+        out = self.empty(self.ctrl_len)
+        L.dd4dvar_adjoint_integrate(self.handle, 1, self.ptr(forcing), out.data_ptr(),
+                                    self._stream())
+        return out
+
+    def exchange(self, x):
+        L.dd4dvar_exchange(self.handle, x.data_ptr(), self._stream())
+
+    def gather(self, level):
+        p = self.prob
+        out = self.empty(3 * p.nlat * p.nlon)
+        L.dd4dvar_gather(self.handle, level, out.data_ptr(), self._stream())
+        return out.view(3, p.nlat, p.nlon)
+
+    def solve(self, lbfgs_m=8, max_iter=50, max_outer=5, max_ls=30, grad_rtol=0.0,
+              outer_tol=1e-6, armijo_c1=1e-4, x_init=None, want_controls=False):
+        p = self.prob
+        opts = L.dd4dvar_solve_opts(lbfgs_m=lbfgs_m, max_iter=max_iter, max_outer=max_outer,
+                                    max_ls=max_ls, grad_rtol=grad_rtol, outer_tol=outer_tol,
+                                    armijo_c1=armijo_c1)
+        xa = np.empty((3, p.nlat, p.nlon))
+        xo = self.empty(self.ctrl_len) if want_controls else None
+        st, rep = L.dd4dvar_solve(self.handle, opts, self.ptr(x_init), self.ptr(xo), xa)
+        return xa, rep, st, xo
+
+    # -- layout helpers (host side) -----------------------------------------
+    def unpack_ctrl(self, x):
+        a = x.detach().cpu().numpy() if hasattr(x, "detach") else np.asarray(x)
+        out = []
+        for inf in self.info:
+            ny, nx, off = int(inf[1]), int(inf[3]), int(inf[6])
+            out.append(a[off:off + 3 * ny * nx].reshape(3, ny, nx))
+        return out
+
+    def pack_ctrl(self, parts):
+        a = np.empty(self.ctrl_len)
+        for inf, v in zip(self.info, parts):
+            ny, nx, off = int(inf[1]), int(inf[3]), int(inf[6])
+            a[off:off + 3 * ny * nx] = np.asarray(v).ravel()
+        return self.torch.from_numpy(a).to(self.device)
+
+    def unpack_traj(self, t):
+        a = t.detach().cpu().numpy() if hasattr(t, "detach") else np.asarray(t)
+        out = []
+        for inf in self.info:
+            ny, nx, nlev, off = int(inf[1]), int(inf[3]), int(inf[5]), int(inf[7])
+            out.append(a[off:off + nlev * 3 * ny * nx].reshape(nlev, 3, ny, nx))
+        return out
+
+    def pack_traj(self, parts):
+        a = np.empty(self.traj_len)
+        for inf, v in zip(self.info, parts):
+            ny, nx, nlev, off = int(inf[1]), int(inf[3]), int(inf[5]), int(inf[7])
+            a[off:off + nlev * 3 * ny * nx] = np.asarray(v).ravel()
+        return self.torch.from_numpy(a).to(self.device)

@@ -1,0 +1,735 @@
+// Device context of the DD 4D-Var engine: arena layout, uploads, the
+// background run, and the C ABI entry points that enqueue the sweeps.
+//
+// All subdomains live in device memory for the whole run (the paper keeps
+// every work array resident on the device before processing; here all of
+// them share one GPU).  Per subdomain s:
+//   state     [nlev][3][ny][nx]  T     (h stored as h - h_ref)
+//   targets   [nlev][3][ny][nx]  T     (mean neighbour trajectory)
+//   ring      [nlev][3][nring]   T     (frozen halo, signs applied)
+//   adjoint   [3 slots][3][ny][nx] T   (rolling levels of the adjoint sweep)
+// plus FP64 background controls, per-cell coverage counts (uint8), the
+// observation lists binned per (256-cell tile, level), and FP64 per-tile
+// cost accumulators.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "launch.h"
+#include "plan.h"
+
+using namespace dd4dvar;
+
+namespace dd4dvar {
+dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* opts, const double* x_init,
+                          double* x_out, double* xa_host, dd4dvar_solve_report* rep);
+}
+
+struct DeviceArrays {
+  std::vector<void*> owned;
+  ~DeviceArrays() {
+    for (void* p : owned) (void)hipFree(p);
+  }
+};
+
+struct dd4dvar_ctx {
+  dd4dvar_plan plan;
+  std::string err;
+  int device = 0;
+  int prec = 0;
+  int exec_mode = 0;
+  bool have_forward = false;
+  int ntiles = 0, maxlev = 0, ring_blocks = 1, nsub = 0;
+  std::vector<SubDev> subs;
+  std::vector<int2> tiles;
+  SubDev* d_subs = nullptr;
+  int2* d_tiles = nullptr;
+  void *traj = nullptr, *ring = nullptr, *targ = nullptr, *adj = nullptr;
+  void *rows = nullptr, *cosx = nullptr;
+  RowCoef<double>* rows64 = nullptr;
+  double* cosx64 = nullptr;
+  uint8_t* cover = nullptr;
+  int32_t* tcount = nullptr;
+  int32_t *obs_ptr = nullptr, *obs_code = nullptr;
+  double *obs_val = nullptr, *obs_q = nullptr;
+  double *jpart = nullptr, *jc = nullptr, *jconst = nullptr;
+  int32_t *nbr_idx = nullptr, *hsrc = nullptr, *hoff = nullptr, *hsign = nullptr, *hgcell = nullptr;
+  double* xb = nullptr;
+  int32_t *cptr = nullptr, *cpiece = nullptr;
+  int32_t* d_ids = nullptr;
+  uint32_t* nonfinite = nullptr;
+  // the whole grid as one box (FP64), for background and global runs
+  SubDev gsub{};
+  int gtiles = 0;
+  SubDev* d_gsub = nullptr;
+  int2* d_gtiles = nullptr;
+  double st = 0, stg = 0;
+  // optional phase timing: events recorded around the sweeps of each
+  // local_cost_grad on the caller's stream
+  bool timing = false;
+  struct Mark {
+    hipEvent_t ev[4];
+    int nfwd, nadj;
+  };
+  std::vector<Mark> marks;
+  DeviceArrays mem;
+  ~dd4dvar_ctx() {
+    for (Mark& m : marks)
+      for (hipEvent_t e : m.ev) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+struct DevError {
+  dd4dvar_status st;
+  std::string msg;
+};
+
+void chk(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      throw DevError{DD4DVAR_E_NOMEM, std::string(what) + ": " + hipGetErrorString(e)};
+    throw DevError{DD4DVAR_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+  }
+}
+
+template <typename P>
+P* dalloc(dd4dvar_ctx* c, size_t count) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  chk(hipMalloc(&p, count * sizeof(P)), "hipMalloc");
+  c->mem.owned.push_back(p);
+  return static_cast<P*>(p);
+}
+
+template <typename P>
+P* upload(dd4dvar_ctx* c, const std::vector<P>& v, hipStream_t st) {
+  P* d = dalloc<P>(c, v.size());
+  if (!v.empty()) chk(hipMemcpyAsync(d, v.data(), v.size() * sizeof(P), hipMemcpyHostToDevice, st), "upload");
+  return d;
+}
+
+template <typename T>
+Dom<T> local_dom(const dd4dvar_ctx* c) {
+  Dom<T> D{};
+  D.subs = c->d_subs;
+  D.tiles = c->d_tiles;
+  D.traj = static_cast<T*>(c->traj);
+  D.ring = static_cast<T*>(c->ring);
+  D.targ = static_cast<T*>(c->targ);
+  D.adj = static_cast<T*>(c->adj);
+  D.rows = static_cast<const RowCoef<T>*>(c->rows);
+  D.cosx = static_cast<const T*>(c->cosx);
+  D.cover = c->cover;
+  D.tcount = c->tcount;
+  D.obs_ptr = c->obs_ptr;
+  D.obs_code = c->obs_code;
+  D.obs_val = c->obs_val;
+  D.obs_q = c->obs_q;
+  D.jpart = c->jpart;
+  D.nbr_idx = c->nbr_idx;
+  D.hsrc = c->hsrc;
+  D.hoff = c->hoff;
+  D.hsign = c->hsign;
+  D.hgcell = c->hgcell;
+  D.st = T(c->st);
+  D.stg = T(c->stg);
+  D.h0 = T(c->plan.model.h_ref);
+  D.mu = c->plan.model.mu_overlap;
+  for (int f = 0; f < 3; ++f) D.isb2[f] = 1.0 / (c->plan.sigma_b[f] * c->plan.sigma_b[f]);
+  D.nlon = c->plan.model.nlon;
+  D.half = c->plan.model.nlon / 2;
+  D.maxlev = c->maxlev;
+  D.weight_mode = c->plan.model.weight_mode;
+  return D;
+}
+
+Dom<double> global_dom(const dd4dvar_ctx* c, double* traj) {
+  Dom<double> D{};
+  D.subs = c->d_gsub;
+  D.tiles = c->d_gtiles;
+  D.traj = traj;
+  D.rows = c->rows64;
+  D.cosx = c->cosx64;
+  D.st = c->st;
+  D.stg = c->stg;
+  D.h0 = c->plan.model.h_ref;
+  D.nlon = c->plan.model.nlon;
+  D.half = c->plan.model.nlon / 2;
+  D.weight_mode = c->plan.model.weight_mode;
+  return D;
+}
+
+template <typename T>
+void fill_rows(const dd4dvar_model_desc& m, std::vector<RowCoef<T>>& rows, std::vector<T>& cosx) {
+  const double dth = M_PI / m.nlat, dla = 2.0 * M_PI / m.nlon;
+  const double sl = m.dt / (m.radius * dla), st = m.dt / (m.radius * dth);
+  rows.resize(m.nlat);
+  cosx.resize(m.nlat + 2);
+  std::vector<double> c(m.nlat);
+  for (int j = 0; j < m.nlat; ++j) {
+    const double th = -M_PI / 2 + (j + 0.5) * dth;
+    c[j] = std::cos(th);
+    RowCoef<T>& r = rows[j];
+    r.a1 = T(sl / c[j]);
+    r.a2 = T(sl * m.gravity / c[j]);
+    r.a3 = T(st / c[j]);
+    r.cf = T(2.0 * m.dt * 2.0 * m.omega * std::sin(th));
+    r.ct = T(2.0 * m.dt * std::tan(th) / m.radius);
+    r.c = T(c[j]);
+  }
+  cosx[0] = T(c[0]);
+  for (int j = 0; j < m.nlat; ++j) cosx[j + 1] = T(c[j]);
+  cosx[m.nlat + 1] = T(c[m.nlat - 1]);
+}
+
+// Global forward run (FP64) of x (device [3][ncell], full h) into traj
+// ([nsteps+1][3][ncell], h stored as an anomaly).
+void global_forward(dd4dvar_ctx* c, const double* x, double* traj, hipStream_t st) {
+  Dom<double> G = global_dom(c, traj);
+  launch_init<double>(G, x, 0, c->gtiles, st);
+  for (int n = 0; n < c->plan.model.nsteps; ++n) launch_fwd<double>(G, n, 0, c->gtiles, st);
+  chk(hipGetLastError(), "global forward launch");
+}
+
+template <typename T>
+void local_forward(dd4dvar_ctx* c, const double* x, hipStream_t st) {
+  Dom<T> D = local_dom<T>(c);
+  if (c->exec_mode == 0) {
+    launch_init<T>(D, x, 0, c->ntiles, st);
+    for (int n = 0; n + 1 < c->maxlev; ++n) launch_fwd<T>(D, n, 0, c->ntiles, st);
+  } else {
+    for (const SubDev& S : c->subs) {
+      launch_init<T>(D, x, S.tile0, S.ntile, st);
+      for (int n = 0; n + 1 < S.nlev; ++n) launch_fwd<T>(D, n, S.tile0, S.ntile, st);
+    }
+  }
+  chk(hipGetLastError(), "forward launch");
+  c->have_forward = true;
+}
+
+template <typename T>
+void local_adjoint(dd4dvar_ctx* c, int mode, const double* x, const double* forcing, double* out,
+                   const std::vector<int32_t>* ids, hipStream_t st) {
+  Dom<T> D = local_dom<T>(c);
+  if (!ids && c->exec_mode == 0) {
+    for (int n = c->maxlev - 1; n >= 0; --n)
+      launch_adj<T>(D, n, 0, c->ntiles, mode, x, c->xb, forcing, out, st);
+  } else {
+    auto run = [&](const SubDev& S) {
+      for (int n = S.nlev - 1; n >= 0; --n)
+        launch_adj<T>(D, n, S.tile0, S.ntile, mode, x, c->xb, forcing, out, st);
+    };
+    if (ids)
+      for (int32_t s : *ids) run(c->subs[s]);
+    else
+      for (const SubDev& S : c->subs) run(S);
+  }
+  chk(hipGetLastError(), "adjoint launch");
+}
+
+void mark(dd4dvar_ctx* c, int which, hipStream_t st) {
+  if (!c->timing) return;
+  if (which == 0) {
+    dd4dvar_ctx::Mark m{};
+    for (hipEvent_t& e : m.ev) chk(hipEventCreate(&e), "hipEventCreate");
+    c->marks.push_back(m);
+  }
+  chk(hipEventRecord(c->marks.back().ev[which], st), "hipEventRecord");
+}
+
+template <typename T>
+void cost_grad_impl(dd4dvar_ctx* c, const std::vector<int32_t>* ids, const double* x, double* J,
+                    double* grad, hipStream_t st) {
+  Dom<T> D = local_dom<T>(c);
+  mark(c, 0, st);
+  if (ids) {
+    for (int32_t s : *ids) {
+      const SubDev& S = c->subs[s];
+      launch_init<T>(D, x, S.tile0, S.ntile, st);
+      for (int n = 0; n + 1 < S.nlev; ++n) launch_fwd<T>(D, n, S.tile0, S.ntile, st);
+    }
+    chk(hipGetLastError(), "forward launch");
+    c->have_forward = true;
+  } else {
+    local_forward<T>(c, x, st);
+  }
+  mark(c, 1, st);
+  local_adjoint<T>(c, 0, x, nullptr, grad, ids, st);
+  mark(c, 2, st);
+  if (ids) {
+    // the id list lives in pageable host memory owned by the caller's frame:
+    // wait for the copy before returning
+    chk(hipMemcpyAsync(c->d_ids, ids->data(), ids->size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
+        "ids upload");
+    chk(hipStreamSynchronize(st), "ids upload sync");
+    launch_reduce_j(c->d_subs, int(ids->size()), c->d_ids, c->jpart, c->jconst, J, c->nonfinite, st);
+  } else {
+    launch_reduce_j(c->d_subs, c->nsub, nullptr, c->jpart, c->jconst, J, c->nonfinite, st);
+  }
+  chk(hipGetLastError(), "reduce launch");
+  mark(c, 3, st);
+  if (c->timing) {
+    int nf = 0, na = 0;
+    if (!ids && c->exec_mode == 0) {
+      nf = c->maxlev;
+      na = c->maxlev;
+    } else {
+      for (const SubDev& S : c->subs)
+        if (!ids || std::find(ids->begin(), ids->end(), int32_t(&S - c->subs.data())) != ids->end()) {
+          nf += S.nlev;
+          na += S.nlev;
+        }
+    }
+    c->marks.back().nfwd = nf;
+    c->marks.back().nadj = na;
+  }
+}
+
+template <typename T>
+void exchange_impl(dd4dvar_ctx* c, const double* x, hipStream_t st) {
+  local_forward<T>(c, x, st);
+  Dom<T> D = local_dom<T>(c);
+  launch_ring_from_local<T>(D, c->nsub, c->ring_blocks, st);
+  for (int n = 0; n < c->maxlev; ++n) launch_targets_from_local<T>(D, n, c->ntiles, c->jc, st);
+  launch_reduce_jconst(c->d_subs, c->nsub, c->jc, 0.5 * c->plan.model.mu_overlap, c->jconst, st);
+  chk(hipGetLastError(), "exchange launch");
+}
+
+template <typename T>
+void background_impl(dd4dvar_ctx* c, hipStream_t st) {
+  const dd4dvar_model_desc& m = c->plan.model;
+  const int64_t ncell = int64_t(m.nlat) * m.nlon;
+  double* x0 = nullptr;
+  double* bg = nullptr;
+  chk(hipMalloc(&x0, size_t(3 * ncell) * sizeof(double)), "hipMalloc background");
+  hipError_t e = hipMalloc(&bg, size_t(m.nsteps + 1) * 3 * ncell * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipFree(x0);
+    chk(e, "hipMalloc background trajectory");
+  }
+  try {
+    chk(hipMemcpyAsync(x0, c->plan.xb0.data(), size_t(3 * ncell) * sizeof(double),
+                       hipMemcpyHostToDevice, st), "upload xb0");
+    global_forward(c, x0, bg, st);
+    Dom<T> D = local_dom<T>(c);
+    for (int n = 0; n < c->maxlev; ++n) launch_from_global<T>(D, bg, ncell, c->xb, n, c->ntiles, st);
+    launch_ring_from_global<T>(D, c->nsub, c->ring_blocks, bg, ncell, st);
+    launch_fill(c->jconst, c->nsub, 0.0, st);
+    chk(hipGetLastError(), "background launch");
+    chk(hipStreamSynchronize(st), "background sync");
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(x0);
+    (void)hipFree(bg);
+    throw;
+  }
+  chk(hipFree(x0), "hipFree");
+  chk(hipFree(bg), "hipFree");
+}
+
+void build_device(dd4dvar_ctx* c, hipStream_t st) {
+  const dd4dvar_plan& P = c->plan;
+  const dd4dvar_model_desc& m = P.model;
+  c->prec = m.precision;
+  c->nsub = P.nsub;
+  const size_t tsz = c->prec == DD4DVAR_FP64 ? sizeof(double) : sizeof(float);
+  chk(hipGetDevice(&c->device), "hipGetDevice");
+
+  // subdomain table and tiles
+  int64_t ring_off = 0, adj_off = 0;
+  int tile = 0, maxring = 0;
+  c->maxlev = 0;
+  c->subs.resize(P.nsub);
+  for (int s = 0; s < P.nsub; ++s) {
+    const BoxInfo& b = P.boxes[s];
+    SubDev& S = c->subs[s];
+    S.row0 = b.row0; S.ny = b.ny; S.col0 = b.col0; S.nx = b.nx;
+    S.lev0 = b.lev0; S.nlev = b.nlev;
+    S.span = b.span; S.pole_s = b.pole_s; S.pole_n = b.pole_n;
+    S.ncell = int32_t(b.ncell());
+    S.nring = b.nring;
+    S.tile0 = tile;
+    S.ntile = int32_t((b.ncell() + kTile - 1) / kTile);
+    S.nbr0 = int32_t(P.nbr_ptr[s]);
+    S.nbr1 = int32_t(P.nbr_ptr[s + 1]);
+    S.pad_ = 0;
+    S.traj_off = b.traj_off;
+    S.ring_off = ring_off;
+    S.adj_off = adj_off;
+    S.ctrl_off = b.ctrl_off;
+    S.cell_off = P.cell_ptr[s];
+    S.hmap_off = P.ring_ptr[s];
+    ring_off += int64_t(b.nlev) * 3 * b.nring;
+    adj_off += int64_t(9) * b.ncell();
+    tile += S.ntile;
+    c->maxlev = std::max(c->maxlev, b.nlev);
+    maxring = std::max(maxring, b.nring);
+  }
+  c->ntiles = tile;
+  c->ring_blocks = (maxring + 255) / 256;
+  c->tiles.resize(tile);
+  for (int s = 0; s < P.nsub; ++s)
+    for (int t = 0; t < c->subs[s].ntile; ++t) c->tiles[c->subs[s].tile0 + t] = make_int2(s, t);
+
+  // whole-grid box
+  SubDev& G = c->gsub;
+  G = SubDev{};
+  G.row0 = 0; G.ny = m.nlat; G.col0 = 0; G.nx = m.nlon;
+  G.lev0 = 0; G.nlev = m.nsteps + 1; G.span = 1; G.pole_s = 1; G.pole_n = 1;
+  G.ncell = m.nlat * m.nlon;
+  G.nring = 0;
+  G.ntile = (G.ncell + kTile - 1) / kTile;
+  c->gtiles = G.ntile;
+  std::vector<int2> gt(G.ntile);
+  for (int t = 0; t < G.ntile; ++t) gt[t] = make_int2(0, t);
+
+  // coefficient tables
+  const double dth = M_PI / m.nlat;
+  c->st = m.dt / (m.radius * dth);
+  c->stg = c->st * m.gravity;
+  std::vector<RowCoef<double>> r64;
+  std::vector<double> c64;
+  fill_rows<double>(m, r64, c64);
+
+  // coverage (uint8) and observation bins per (tile, level)
+  std::vector<uint8_t> cover(P.cover_box.size());
+  for (size_t i = 0; i < cover.size(); ++i) {
+    if (P.cover_box[i] > 255) throw DevError{DD4DVAR_E_INVALID, "coverage count above 255"};
+    cover[i] = uint8_t(P.cover_box[i]);
+  }
+  const int64_t nkeys = int64_t(tile) * c->maxlev;
+  std::vector<int32_t> optr(nkeys + 1, 0);
+  const int nlon = m.nlon;
+  auto key_of = [&](int s, int64_t k, int* loc_out) {
+    const BoxInfo& b = P.boxes[s];
+    const int64_t cell = P.obs_cell[k];
+    const int row = int(cell / nlon), col = int(cell % nlon);
+    int cc = col - b.col0;
+    if (cc < 0) cc += nlon;
+    const int loc = (row - b.row0) * b.nx + cc;
+    *loc_out = loc;
+    return int64_t(c->subs[s].tile0 + loc / kTile) * c->maxlev + (P.obs_step[k] - b.lev0);
+  };
+  for (int s = 0; s < P.nsub; ++s)
+    for (int64_t q = P.obs_ptr[s]; q < P.obs_ptr[s + 1]; ++q) {
+      int loc;
+      optr[key_of(s, P.obs_idx[q], &loc) + 1] += 1;
+    }
+  for (int64_t k = 0; k < nkeys; ++k) optr[k + 1] += optr[k];
+  const int64_t nent = optr[nkeys];
+  std::vector<int32_t> ocode(nent);
+  std::vector<double> oval(nent), oq(nent);
+  {
+    std::vector<int32_t> fillp(optr.begin(), optr.end() - 1);
+    for (int s = 0; s < P.nsub; ++s) {
+      const BoxInfo& b = P.boxes[s];
+      for (int64_t q = P.obs_ptr[s]; q < P.obs_ptr[s + 1]; ++q) {
+        const int64_t k = P.obs_idx[q];
+        int loc;
+        const int64_t key = key_of(s, k, &loc);
+        const int32_t pos = fillp[key]++;
+        const int f = P.obs_field[k];
+        ocode[pos] = loc * 4 + f;
+        oval[pos] = f == 0 ? P.obs_value[k] - m.h_ref : P.obs_value[k];
+        double w = 1.0;
+        if (m.weight_mode == 0)
+          w = 1.0 / (double(P.cover_box[P.cell_ptr[s] + loc]) * double(P.time_count[P.obs_step[k]]));
+        oq[pos] = m.lambda_obs * w / (P.obs_sigma[k] * P.obs_sigma[k]);
+        (void)b;
+      }
+    }
+  }
+
+  // coverage CSR per global cell for the gather
+  const int64_t ncell = int64_t(m.nlat) * m.nlon;
+  std::vector<int32_t> cptr(ncell + 1, 0);
+  for (int64_t g = 0; g < ncell; ++g) cptr[g + 1] = cptr[g] + P.cover_sp[g];
+  std::vector<int32_t> cpiece(cptr[ncell]);
+  {
+    std::vector<int32_t> f(cptr.begin(), cptr.end() - 1);
+    for (int i = 0; i < P.nspace; ++i) {
+      const BoxInfo& b = P.boxes[i];
+      for (int r = 0; r < b.ny; ++r)
+        for (int cc = 0; cc < b.nx; ++cc) {
+          int col = b.col0 + cc;
+          if (col >= nlon) col -= nlon;
+          const int64_t g = int64_t(b.row0 + r) * nlon + col;
+          cpiece[f[g]++] = i;
+        }
+    }
+  }
+
+  // uploads
+  c->d_subs = upload(c, c->subs, st);
+  c->d_tiles = upload(c, c->tiles, st);
+  c->d_gsub = upload(c, std::vector<SubDev>{G}, st);
+  c->d_gtiles = upload(c, gt, st);
+  c->rows64 = upload(c, r64, st);
+  c->cosx64 = upload(c, c64, st);
+  if (c->prec == DD4DVAR_FP64) {
+    c->rows = c->rows64;
+    c->cosx = c->cosx64;
+  } else {
+    std::vector<RowCoef<float>> r32;
+    std::vector<float> c32;
+    fill_rows<float>(m, r32, c32);
+    c->rows = upload(c, r32, st);
+    c->cosx = upload(c, c32, st);
+  }
+  c->cover = upload(c, cover, st);
+  c->tcount = upload(c, P.time_count, st);
+  c->obs_ptr = upload(c, optr, st);
+  c->obs_code = upload(c, ocode, st);
+  c->obs_val = upload(c, oval, st);
+  c->obs_q = upload(c, oq, st);
+  c->nbr_idx = upload(c, P.nbr_idx, st);
+  c->hsrc = upload(c, P.halo_src, st);
+  c->hoff = upload(c, P.halo_off, st);
+  c->hsign = upload(c, P.halo_sign, st);
+  c->hgcell = upload(c, P.halo_gcell, st);
+  c->cptr = upload(c, cptr, st);
+  c->cpiece = upload(c, cpiece, st);
+  c->jpart = dalloc<double>(c, tile);
+  c->jc = dalloc<double>(c, tile);
+  c->jconst = dalloc<double>(c, P.nsub);
+  c->xb = dalloc<double>(c, P.ctrl_total);
+  c->d_ids = dalloc<int32_t>(c, P.nsub);
+  c->nonfinite = dalloc<uint32_t>(c, 1);
+  chk(hipMemsetAsync(c->nonfinite, 0, sizeof(uint32_t), st), "memset");
+  // large arenas
+  c->traj = dalloc<char>(c, size_t(P.traj_total) * tsz);
+  c->targ = dalloc<char>(c, size_t(P.traj_total) * tsz);
+  c->ring = dalloc<char>(c, size_t(std::max<int64_t>(ring_off, 1)) * tsz);
+  c->adj = dalloc<char>(c, size_t(std::max<int64_t>(adj_off, 1)) * tsz);
+  chk(hipMemsetAsync(c->ring, 0, size_t(std::max<int64_t>(ring_off, 1)) * tsz, st), "memset ring");
+  chk(hipMemsetAsync(c->targ, 0, size_t(P.traj_total) * tsz, st), "memset targets");
+  chk(hipStreamSynchronize(st), "upload sync");
+
+  if (c->prec == DD4DVAR_FP64) background_impl<double>(c, st);
+  else background_impl<float>(c, st);
+}
+
+dd4dvar_status fail(dd4dvar_ctx* c, dd4dvar_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else set_thread_error(msg);
+  return s;
+}
+
+#define API_GUARD(ctx, ...)                                    \
+  try {                                                        \
+    __VA_ARGS__                                                \
+  } catch (const DevError& e) {                                \
+    return fail(ctx, e.st, e.msg);                             \
+  } catch (const std::bad_alloc&) {                            \
+    return fail(ctx, DD4DVAR_E_NOMEM, "host allocation failed"); \
+  }
+
+}  // namespace
+
+extern "C" {
+
+dd4dvar_status dd4dvar_create(const dd4dvar_model_desc* model, const dd4dvar_partition_desc* part,
+                              const dd4dvar_data_desc* data, void* stream, dd4dvar_ctx** out) {
+  if (!out) return fail(nullptr, DD4DVAR_E_INVALID, "null output pointer");
+  *out = nullptr;
+  dd4dvar_ctx* c = new (std::nothrow) dd4dvar_ctx();
+  if (!c) return fail(nullptr, DD4DVAR_E_NOMEM, "host allocation failed");
+  std::string err;
+  dd4dvar_status s = build_plan(model, part, data, &c->plan, &err);
+  if (s != DD4DVAR_OK) {
+    delete c;
+    return fail(nullptr, s, err);
+  }
+  try {
+    build_device(c, static_cast<hipStream_t>(stream));
+  } catch (const DevError& e) {
+    delete c;
+    return fail(nullptr, e.st, e.msg);
+  } catch (const std::bad_alloc&) {
+    delete c;
+    return fail(nullptr, DD4DVAR_E_NOMEM, "host allocation failed");
+  }
+  set_thread_error("");
+  *out = c;
+  return DD4DVAR_OK;
+}
+
+void dd4dvar_destroy(dd4dvar_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  delete ctx;
+}
+
+const dd4dvar_plan* dd4dvar_ctx_plan(const dd4dvar_ctx* ctx) { return ctx ? &ctx->plan : nullptr; }
+
+const char* dd4dvar_last_error(const dd4dvar_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : thread_error();
+}
+
+dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode) {
+  if (!ctx || (mode != 0 && mode != 1)) return fail(ctx, DD4DVAR_E_INVALID, "bad exec mode");
+  ctx->exec_mode = mode;
+  return DD4DVAR_OK;
+}
+
+dd4dvar_status dd4dvar_set_timing(dd4dvar_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(ctx, DD4DVAR_E_INVALID, "null context");
+  ctx->timing = on != 0;
+  return DD4DVAR_OK;
+}
+
+dd4dvar_status dd4dvar_get_timing(dd4dvar_ctx* ctx, double out[6]) {
+  if (!ctx || !out) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  API_GUARD(ctx, {
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (dd4dvar_ctx::Mark& m : ctx->marks) {
+      chk(hipEventSynchronize(m.ev[3]), "hipEventSynchronize");
+      float a = 0, b = 0, d = 0;
+      chk(hipEventElapsedTime(&a, m.ev[0], m.ev[1]), "elapsed");
+      chk(hipEventElapsedTime(&b, m.ev[1], m.ev[2]), "elapsed");
+      chk(hipEventElapsedTime(&d, m.ev[2], m.ev[3]), "elapsed");
+      acc[0] += a;
+      acc[1] += b;
+      acc[2] += d;
+      acc[3] += m.nfwd;
+      acc[4] += m.nadj;
+      acc[5] += 1;
+      for (hipEvent_t e : m.ev) (void)hipEventDestroy(e);
+    }
+    ctx->marks.clear();
+    std::memcpy(out, acc, sizeof(acc));
+    return DD4DVAR_OK;
+  })
+}
+
+dd4dvar_status dd4dvar_background_controls(dd4dvar_ctx* ctx, double* x_dev, void* stream) {
+  if (!ctx || !x_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  API_GUARD(ctx, {
+    chk(hipMemcpyAsync(x_dev, ctx->xb, size_t(ctx->plan.ctrl_total) * sizeof(double),
+                       hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
+        "copy background controls");
+    return DD4DVAR_OK;
+  })
+}
+
+dd4dvar_status dd4dvar_local_cost_grad(dd4dvar_ctx* ctx, int32_t nsub, const int32_t* sub_ids,
+                                       const double* x_dev, double* J_dev, double* grad_dev,
+                                       void* stream) {
+  if (!ctx || !x_dev || !J_dev || !grad_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  std::vector<int32_t> ids;
+  if (sub_ids) {
+    if (nsub < 0 || nsub > ctx->nsub) return fail(ctx, DD4DVAR_E_INVALID, "bad nsub");
+    ids.assign(sub_ids, sub_ids + nsub);
+    std::vector<char> seen(ctx->nsub, 0);
+    for (int32_t s : ids) {
+      if (s < 0 || s >= ctx->nsub || seen[s]) return fail(ctx, DD4DVAR_E_INVALID, "bad subdomain id");
+      seen[s] = 1;
+    }
+    if (ids.empty()) return DD4DVAR_OK;
+  }
+  API_GUARD(ctx, {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (ctx->prec == DD4DVAR_FP64)
+      cost_grad_impl<double>(ctx, sub_ids ? &ids : nullptr, x_dev, J_dev, grad_dev, st);
+    else
+      cost_grad_impl<float>(ctx, sub_ids ? &ids : nullptr, x_dev, J_dev, grad_dev, st);
+    return DD4DVAR_OK;
+  })
+}
+
+dd4dvar_status dd4dvar_forward_integrate(dd4dvar_ctx* ctx, int32_t scope, const double* x_dev,
+                                         double* traj_dev, void* stream) {
+  if (!ctx || !x_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  if (scope != 0 && scope != 1) return fail(ctx, DD4DVAR_E_INVALID, "scope must be 0 or 1");
+  if (scope == 0 && !traj_dev) return fail(ctx, DD4DVAR_E_INVALID, "global scope needs traj_dev");
+  API_GUARD(ctx, {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (scope == 0) {
+      const dd4dvar_model_desc& m = ctx->plan.model;
+      const int64_t plane = int64_t(m.nlat) * m.nlon;
+      global_forward(ctx, x_dev, traj_dev, st);
+      launch_add_href(traj_dev, m.nsteps + 1, plane, m.h_ref, st);
+      chk(hipGetLastError(), "global forward");
+      return DD4DVAR_OK;
+    }
+    if (ctx->prec == DD4DVAR_FP64) {
+      local_forward<double>(ctx, x_dev, st);
+      if (traj_dev) launch_traj_out<double>(local_dom<double>(ctx), traj_dev, 0, ctx->ntiles, st);
+    } else {
+      local_forward<float>(ctx, x_dev, st);
+      if (traj_dev) launch_traj_out<float>(local_dom<float>(ctx), traj_dev, 0, ctx->ntiles, st);
+    }
+    chk(hipGetLastError(), "trajectory output");
+    return DD4DVAR_OK;
+  })
+}
+
+dd4dvar_status dd4dvar_adjoint_integrate(dd4dvar_ctx* ctx, int32_t scope, const double* forcing_dev,
+                                         double* adj0_dev, void* stream) {
+  if (!ctx || !adj0_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  if (scope != 1) return fail(ctx, DD4DVAR_E_INVALID, "only scope 1 is supported");
+  if (!ctx->have_forward) return fail(ctx, DD4DVAR_E_STATE, "adjoint before any forward");
+  API_GUARD(ctx, {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int mode = forcing_dev ? 1 : 2;
+    if (ctx->prec == DD4DVAR_FP64)
+      local_adjoint<double>(ctx, mode, nullptr, forcing_dev, adj0_dev, nullptr, st);
+    else
+      local_adjoint<float>(ctx, mode, nullptr, forcing_dev, adj0_dev, nullptr, st);
+    return DD4DVAR_OK;
+  })
+}
+
+dd4dvar_status dd4dvar_exchange(dd4dvar_ctx* ctx, const double* x_dev, void* stream) {
+  if (!ctx || !x_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  API_GUARD(ctx, {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (ctx->prec == DD4DVAR_FP64) exchange_impl<double>(ctx, x_dev, st);
+    else exchange_impl<float>(ctx, x_dev, st);
+    return DD4DVAR_OK;
+  })
+}
+
+dd4dvar_status dd4dvar_gather(dd4dvar_ctx* ctx, int32_t level, double* out_dev, void* stream) {
+  if (!ctx || !out_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  if (level < 0 || level > ctx->plan.model.nsteps) return fail(ctx, DD4DVAR_E_INVALID, "bad level");
+  if (!ctx->have_forward) return fail(ctx, DD4DVAR_E_STATE, "gather before any forward");
+  API_GUARD(ctx, {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t ncell = int64_t(ctx->plan.model.nlat) * ctx->plan.model.nlon;
+    if (ctx->prec == DD4DVAR_FP64)
+      launch_gather<double>(local_dom<double>(ctx), ctx->plan.nspace, ctx->plan.ntime, level, ncell,
+                            ctx->cptr, ctx->cpiece, out_dev, st);
+    else
+      launch_gather<float>(local_dom<float>(ctx), ctx->plan.nspace, ctx->plan.ntime, level, ncell,
+                           ctx->cptr, ctx->cpiece, out_dev, st);
+    chk(hipGetLastError(), "gather launch");
+    return DD4DVAR_OK;
+  })
+}
+
+dd4dvar_status dd4dvar_solve(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* opts,
+                             const double* x_init_dev, double* x_out_dev, double* xa_host,
+                             dd4dvar_solve_report* report) {
+  if (!ctx || !opts || !xa_host) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  API_GUARD(ctx, { return solve_impl(ctx, opts, x_init_dev, x_out_dev, xa_host, report); })
+}
+
+}  // extern "C"
+
+namespace dd4dvar {
+dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts*, const double*, double*,
+                          double*, dd4dvar_solve_report*) {
+  ctx->err = "solve is not available in this build";
+  return DD4DVAR_E_INVALID;
+}
+}  // namespace dd4dvar

@@ -1,0 +1,266 @@
+// Exchange between subdomains in device memory ("Exchange u_ji between
+// adjacent subdomains", Alg. 1) and the partition-of-unity gather (eq. rest).
+//
+// * Halo rings: every frozen ring position of subdomain s reads, at each of
+//   its levels, the core owner of the (pole-mapped) cell in the same time
+//   interval, with u and v negated across a pole.
+// * Overlap targets: for every (level, cell) of s covered by K other extended
+//   space-time boxes, the mean of their trajectories there and, once per
+//   subdomain, the constant sum_{s'} (T_{s'} - mean)^2 / sigma_b^2, so that
+//   sum_{s'} (Z - T_{s'})^2 = K (Z - mean)^2 + constant.
+// * Before any local solve both come from the global background run.
+#include "kernels.h"
+#include "launch.h"
+
+namespace dd4dvar {
+
+namespace {
+__device__ __forceinline__ double block_sum2(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < int(blockDim.x >> 6); ++i) r += sh[i];
+  return r;
+}
+}  // namespace
+
+// targets (and backgrounds at level 0) from the global FP64 trajectory, whose
+// h is stored as h - h_ref
+template <typename T>
+__global__ __launch_bounds__(kTile) void k_from_global(Dom<T> D, const double* __restrict__ bg,
+                                                       int64_t gplane, double* __restrict__ xb,
+                                                       int n) {
+  const int2 wt = D.tiles[blockIdx.x];
+  const SubDev S = D.subs[wt.x];
+  if (n >= S.nlev) return;
+  const int m = wt.y * kTile + threadIdx.x;
+  if (m >= S.ncell) return;
+  const int r = m / S.nx, c = m - r * S.nx;
+  int gcol = S.col0 + c;
+  if (gcol >= D.nlon) gcol -= D.nlon;
+  const int64_t g = int64_t(S.row0 + r) * D.nlon + gcol;
+  const double* B = bg + int64_t(S.lev0 + n) * 3 * gplane;
+  const int64_t plane = S.ncell;
+  T* Tg = D.targ + S.traj_off + int64_t(n) * 3 * plane;
+  Tg[m] = T(B[g]);
+  Tg[plane + m] = T(B[gplane + g]);
+  Tg[2 * plane + m] = T(B[2 * gplane + g]);
+  if (n == 0) {
+    double* xo = xb + S.ctrl_off;
+    xo[m] = B[g] + double(D.h0);
+    xo[plane + m] = B[gplane + g];
+    xo[2 * plane + m] = B[2 * gplane + g];
+  }
+}
+
+template <typename T>
+__global__ void k_ring_from_global(Dom<T> D, const double* __restrict__ bg, int64_t gplane) {
+  const SubDev S = D.subs[blockIdx.x];
+  const int k = blockIdx.y * blockDim.x + threadIdx.x;
+  if (k >= S.nring) return;
+  const int src = D.hsrc[S.hmap_off + k];
+  if (src < 0) return;
+  const int64_t g = D.hgcell[S.hmap_off + k];
+  const T sg = T(D.hsign[S.hmap_off + k]);
+  for (int n = 0; n < S.nlev; ++n) {
+    const double* B = bg + int64_t(S.lev0 + n) * 3 * gplane;
+    T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
+    R[k] = T(B[g]);
+    R[S.nring + k] = sg * T(B[gplane + g]);
+    R[2 * S.nring + k] = sg * T(B[2 * gplane + g]);
+  }
+}
+
+template <typename T>
+__global__ void k_ring_from_local(Dom<T> D) {
+  const SubDev S = D.subs[blockIdx.x];
+  const int k = blockIdx.y * blockDim.x + threadIdx.x;
+  if (k >= S.nring) return;
+  const int src = D.hsrc[S.hmap_off + k];
+  if (src < 0) return;
+  const SubDev P = D.subs[src];
+  const int64_t off = D.hoff[S.hmap_off + k];
+  const T sg = T(D.hsign[S.hmap_off + k]);
+  for (int n = 0; n < S.nlev; ++n) {   // same interval: same levels
+    const T* Z = D.traj + P.traj_off + int64_t(n) * 3 * P.ncell;
+    T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
+    R[k] = Z[off];
+    R[S.nring + k] = sg * Z[P.ncell + off];
+    R[2 * S.nring + k] = sg * Z[2 * P.ncell + off];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int n,
+                                                              double* __restrict__ jc) {
+  __shared__ double red[kTile / 64];
+  const int w = blockIdx.x;
+  const int2 wt = D.tiles[w];
+  const SubDev S = D.subs[wt.x];
+  if (n >= S.nlev) return;                 // uniform over the block
+  const int m = wt.y * kTile + threadIdx.x;
+  double jloc = 0.0;
+  if (m < S.ncell) {
+    const int K = int(D.cover[S.cell_off + m]) * D.tcount[S.lev0 + n] - 1;
+    if (K > 0) {
+      const int r = m / S.nx, c = m - r * S.nx;
+      const int grow = S.row0 + r;
+      int gcol = S.col0 + c;
+      if (gcol >= D.nlon) gcol -= D.nlon;
+      const int gl = S.lev0 + n;
+      double sh = 0, su = 0, sv = 0;
+      int cnt = 0;
+      for (int q = S.nbr0; q < S.nbr1; ++q) {
+        const SubDev P = D.subs[D.nbr_idx[q]];
+        if (gl < P.lev0 || gl >= P.lev0 + P.nlev) continue;
+        const int rr = grow - P.row0;
+        if (rr < 0 || rr >= P.ny) continue;
+        int cc = gcol - P.col0;
+        if (cc < 0) cc += D.nlon;
+        if (cc >= P.nx) continue;
+        const T* Z = D.traj + P.traj_off + int64_t(gl - P.lev0) * 3 * P.ncell + int64_t(rr) * P.nx + cc;
+        sh += double(Z[0]);
+        su += double(Z[P.ncell]);
+        sv += double(Z[2 * P.ncell]);
+        ++cnt;
+      }
+      const double inv = cnt > 0 ? 1.0 / double(cnt) : 0.0;
+      const double mh = sh * inv, mu = su * inv, mv = sv * inv;
+      double dh = 0, du = 0, dv = 0;
+      for (int q = S.nbr0; q < S.nbr1; ++q) {
+        const SubDev P = D.subs[D.nbr_idx[q]];
+        if (gl < P.lev0 || gl >= P.lev0 + P.nlev) continue;
+        const int rr = grow - P.row0;
+        if (rr < 0 || rr >= P.ny) continue;
+        int cc = gcol - P.col0;
+        if (cc < 0) cc += D.nlon;
+        if (cc >= P.nx) continue;
+        const T* Z = D.traj + P.traj_off + int64_t(gl - P.lev0) * 3 * P.ncell + int64_t(rr) * P.nx + cc;
+        const double a = double(Z[0]) - mh, b = double(Z[P.ncell]) - mu, e = double(Z[2 * P.ncell]) - mv;
+        dh += a * a;
+        du += b * b;
+        dv += e * e;
+      }
+      const int64_t plane = S.ncell;
+      T* Tg = D.targ + S.traj_off + int64_t(n) * 3 * plane;
+      Tg[m] = T(mh);
+      Tg[plane + m] = T(mu);
+      Tg[2 * plane + m] = T(mv);
+      jloc = dh * D.isb2[0] + du * D.isb2[1] + dv * D.isb2[2];
+    }
+  }
+  const double tot = block_sum2(jloc, red);
+  if (threadIdx.x == 0) jc[w] = (n == 0) ? tot : jc[w] + tot;
+}
+
+__global__ void k_reduce_jconst(const SubDev* __restrict__ subs, int nsub, const double* __restrict__ jc,
+                                double half_mu, double* __restrict__ jconst) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsub) return;
+  const SubDev S = subs[s];
+  double acc = 0.0;
+  for (int t = 0; t < S.ntile; ++t) acc += jc[S.tile0 + t];
+  jconst[s] = half_mu * acc;
+}
+
+template <typename T>
+__global__ void k_gather(Dom<T> D, int nspace, int ntime, int level, int64_t ncell,
+                         const int32_t* __restrict__ cptr, const int32_t* __restrict__ cpiece,
+                         double* __restrict__ out) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= ncell) return;
+  const int row = int(g / D.nlon), col = int(g - int64_t(row) * D.nlon);
+  double ah = 0, au = 0, av = 0;
+  int cnt = 0;
+  for (int q = cptr[g]; q < cptr[g + 1]; ++q) {
+    const int p = cpiece[q];
+    for (int j = 0; j < ntime; ++j) {
+      const SubDev S = D.subs[j * nspace + p];
+      if (level < S.lev0 || level >= S.lev0 + S.nlev) continue;
+      int cc = col - S.col0;
+      if (cc < 0) cc += D.nlon;
+      const T* Z = D.traj + S.traj_off + int64_t(level - S.lev0) * 3 * S.ncell +
+                   int64_t(row - S.row0) * S.nx + cc;
+      ah += double(Z[0]);
+      au += double(Z[S.ncell]);
+      av += double(Z[2 * S.ncell]);
+      ++cnt;
+    }
+  }
+  const double inv = 1.0 / double(cnt);
+  out[g] = ah * inv + double(D.h0);
+  out[ncell + g] = au * inv;
+  out[2 * ncell + g] = av * inv;
+}
+
+__global__ void k_add_href(double* traj, int64_t nlev, int64_t plane, double h0) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nlev * plane) return;
+  const int64_t n = i / plane, g = i - n * plane;
+  traj[n * 3 * plane + g] += h0;
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---- launchers --------------------------------------------------------------
+template <typename T>
+void launch_from_global(const Dom<T>& D, const double* bg, int64_t gplane, double* xb, int level,
+                        int ntiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_from_global<T>, dim3(ntiles), dim3(kTile), 0, st, D, bg, gplane, xb, level);
+}
+// grid.y covers the largest ring; positions beyond a box's own ring exit
+template <typename T>
+void launch_ring_from_global(const Dom<T>& D, int nsub, int ring_blocks, const double* bg,
+                             int64_t gplane, hipStream_t st) {
+  hipLaunchKernelGGL(k_ring_from_global<T>, dim3(nsub, ring_blocks), dim3(256), 0, st, D, bg,
+                     gplane);
+}
+template <typename T>
+void launch_ring_from_local(const Dom<T>& D, int nsub, int ring_blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_ring_from_local<T>, dim3(nsub, ring_blocks), dim3(256), 0, st, D);
+}
+template <typename T>
+void launch_targets_from_local(const Dom<T>& D, int level, int ntiles, double* jc, hipStream_t st) {
+  hipLaunchKernelGGL(k_targets_from_local<T>, dim3(ntiles), dim3(kTile), 0, st, D, level, jc);
+}
+void launch_reduce_jconst(const SubDev* subs, int nsub, const double* jc, double half_mu,
+                          double* jconst, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_jconst, dim3((nsub + 255) / 256), dim3(256), 0, st, subs, nsub, jc,
+                     half_mu, jconst);
+}
+template <typename T>
+void launch_gather(const Dom<T>& D, int nspace, int ntime, int level, int64_t ncell,
+                   const int32_t* cptr, const int32_t* cpiece, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather<T>, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, st, D, nspace,
+                     ntime, level, ncell, cptr, cpiece, out);
+}
+void launch_add_href(double* traj, int64_t nlev, int64_t plane, double h0, hipStream_t st) {
+  const int64_t n = nlev * plane;
+  hipLaunchKernelGGL(k_add_href, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, traj, nlev,
+                     plane, h0);
+}
+void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+}
+
+#define DD4DVAR_INST(T)                                                                          \
+  template void launch_from_global<T>(const Dom<T>&, const double*, int64_t, double*, int, int,  \
+                                      hipStream_t);                                              \
+  template void launch_ring_from_global<T>(const Dom<T>&, int, int, const double*, int64_t,      \
+                                           hipStream_t);                                         \
+  template void launch_ring_from_local<T>(const Dom<T>&, int, int, hipStream_t);                 \
+  template void launch_targets_from_local<T>(const Dom<T>&, int, int, double*, hipStream_t);     \
+  template void launch_gather<T>(const Dom<T>&, int, int, int, int64_t, const int32_t*,          \
+                                 const int32_t*, double*, hipStream_t);
+DD4DVAR_INST(float)
+DD4DVAR_INST(double)
+#undef DD4DVAR_INST
+
+}  // namespace dd4dvar

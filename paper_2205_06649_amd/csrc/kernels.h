@@ -1,0 +1,66 @@
+// Device data structures shared by the HIP kernels and the host engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace dd4dvar {
+
+constexpr int kTile = 256;  // cells per work tile = threads per workgroup
+
+// One subdomain (or the whole grid) as the kernels see it.
+struct SubDev {
+  int32_t row0, ny, col0, nx;
+  int32_t lev0, nlev;        // first global level, number of levels
+  int32_t span, pole_s, pole_n;
+  int32_t ncell, nring, tile0, ntile;
+  int32_t nbr0, nbr1;        // neighbour list range
+  int32_t pad_;
+  int64_t traj_off;          // state arena (and packed FP64 trajectory) offset
+  int64_t ring_off;          // ring arena offset, level stride 3*nring
+  int64_t adj_off;           // adjoint arena offset: 3 slots x 3 x ncell
+  int64_t ctrl_off;          // packed control offset
+  int64_t cell_off;          // per-cell coverage offset
+  int64_t hmap_off;          // halo map offset
+};
+
+// Per-row coefficients of the discrete increment.
+template <typename T>
+struct RowCoef {
+  T a1;   // sigma_lon / cos
+  T a2;   // sigma_lon * g / cos
+  T a3;   // sigma_lat / cos
+  T cf;   // 2 dt f
+  T ct;   // 2 dt tan / a
+  T c;    // cos
+};
+
+template <typename T>
+struct Dom {
+  const SubDev* subs;
+  const int2* tiles;         // (subdomain, tile within subdomain)
+  T* traj;                   // [nlev][3][ncell] per subdomain, h stored as h - h_ref
+  T* ring;                   // [nlev][3][nring] per subdomain, signs applied
+  T* targ;                   // mean overlap target, traj layout
+  T* adj;                    // rolling adjoint levels
+  const RowCoef<T>* rows;    // [nlat]
+  const T* cosx;             // [nlat+2]: cos of rows -1..nlat (pole-mapped)
+  const uint8_t* cover;      // spatial coverage count per box cell
+  const int32_t* tcount;     // temporal coverage count per global level
+  const int32_t* obs_ptr;    // CSR over (tile, level)
+  const int32_t* obs_code;   // local cell * 4 + field
+  const double* obs_val;     // value (h as anomaly)
+  const double* obs_q;       // lambda * w_o / sigma_o^2
+  double* jpart;             // per-tile cost accumulator
+  const int32_t* nbr_idx;
+  const int32_t* hsrc;
+  const int32_t* hoff;
+  const int32_t* hsign;
+  const int32_t* hgcell;
+  T st, stg, h0;
+  double mu;
+  double isb2[3];            // 1 / sigma_b^2
+  int32_t nlon, half, maxlev, weight_mode;
+};
+
+}  // namespace dd4dvar

@@ -1,0 +1,42 @@
+// Kernel launchers (defined in sweep.hip and exchange.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace dd4dvar {
+
+template <typename T>
+void launch_init(const Dom<T>& D, const double* x, int tile_base, int ntiles, hipStream_t st);
+template <typename T>
+void launch_fwd(const Dom<T>& D, int n, int tile_base, int ntiles, hipStream_t st);
+template <typename T>
+void launch_adj(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, const double* x,
+                const double* xb, const double* forcing, double* out, hipStream_t st);
+void launch_reduce_j(const SubDev* subs, int count, const int32_t* ids, const double* jpart,
+                     const double* jconst, double* J, uint32_t* nonfinite, hipStream_t st);
+template <typename T>
+void launch_traj_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hipStream_t st);
+
+// exchange.hip
+template <typename T>
+void launch_from_global(const Dom<T>& D, const double* bg, int64_t gplane, double* xb,
+                        int level, int ntiles, hipStream_t st);
+template <typename T>
+void launch_ring_from_global(const Dom<T>& D, int nsub, int ring_blocks, const double* bg,
+                             int64_t gplane, hipStream_t st);
+template <typename T>
+void launch_ring_from_local(const Dom<T>& D, int nsub, int ring_blocks, hipStream_t st);
+template <typename T>
+void launch_targets_from_local(const Dom<T>& D, int level, int ntiles, double* jc,
+                               hipStream_t st);
+void launch_reduce_jconst(const SubDev* subs, int nsub, const double* jc, double half_mu,
+                          double* jconst, hipStream_t st);
+template <typename T>
+void launch_gather(const Dom<T>& D, int nspace, int ntime, int level, int64_t ncell,
+                   const int32_t* cptr, const int32_t* cpiece, double* out, hipStream_t st);
+void launch_add_href(double* traj, int64_t nlev, int64_t plane, double h0, hipStream_t st);
+void launch_fill(double* p, int64_t n, double v, hipStream_t st);
+
+}  // namespace dd4dvar
