@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the whole path runs in-device on a single MI355X; "
@@ -205,6 +207,13 @@ def main():
     adj_launch_ms = tm["adj_ms"] / tm["adj_launches"]
     achieved = adj_b / (adj_ms * 1e-3) / 1e9
     J32h, g32h = J32.cpu().numpy(), g32.cpu().numpy()
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        a.fill_(1.0)
+        b = a.clone()
+        torch.cuda.synchronize()
+        log(f"copy probe: {a.numel() * 4} bytes read and written by one clone")
+        del a, b
     del ctx
     torch.cuda.empty_cache()
 
@@ -223,7 +232,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"SWE on the sphere {prob.nlat}x{prob.nlon}, {prob.nsteps} steps, "
-                        f"{ctx.nsub if False else len(J32h)} subdomains "
+                        f"{len(J32h)} subdomains "
                         f"({int(len(prob.band_npieces))}x{int(prob.band_npieces[0])} space x "
                         f"{len(prob.time_edges) - 1} time), overlap {prob.overlap_cells} cells/"
                         f"{prob.overlap_steps} steps, {prob.nobs} obs; batched FP32 state, "

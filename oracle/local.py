@@ -59,7 +59,7 @@ class LocalGeometry:
     def pad(self, Zb, ring_level):
         """Padded (3, ny+2, nx+2) array: box + ring (already signed) + wraps."""
         b = self.box
-        P = np.zeros((3, b.ny + 2, b.nx + 2))
+        P = np.zeros((3, b.ny + 2, b.nx + 2), dtype=Zb.dtype)
         P[:, 1:-1, 1:-1] = Zb
         Pf = P.reshape(3, -1)
         Zf = Zb.reshape(3, -1)
@@ -207,7 +207,7 @@ def forward(geo: LocalGeometry, x, ring):
     applied) or None when the box has no frozen positions.
     """
     L = geo.box.nlev - 1
-    traj = np.empty((L + 1,) + x.shape)
+    traj = np.empty((L + 1,) + x.shape, dtype=x.dtype)
     traj[0] = x
 
     def rl(n):
@@ -270,7 +270,7 @@ def ring_from_trajs(maps, s, trajs):
     src = maps.halo_src[s]
     off = maps.halo_off[s]
     sgn = maps.halo_sign[s].astype(np.float64)
-    ring = np.zeros((b.nlev, 3, b.nring))
+    ring = np.zeros((b.nlev, 3, b.nring), dtype=next(iter(trajs.values())).dtype)
     for k in np.nonzero(src >= 0)[0]:
         t = trajs[int(src[k])].reshape(b.nlev, 3, -1)
         ring[:, 0, k] = t[:, 0, off[k]]
@@ -289,14 +289,23 @@ def weights(prob, maps, s):
     return 1.0 / csp, csp
 
 
-def cost_grad(prob, maps, s, x, xb, ring, nbr_trajs, with_grad=True, parts=False):
+def cost_grad(prob, maps, s, x, xb, ring, nbr_trajs, with_grad=True, parts=False,
+              dtype=np.float64):
     """Local functional J_s(x) and its gradient (eq. eq:cost:parallel1).
 
     x, xb      : [3][ny][nx] control and background at level S_j
     ring       : [nlev][3][nring] frozen halo values (or None)
     nbr_trajs  : dict s' -> box trajectory of every overlap neighbour s'
+                 (levels from the neighbour's first level on; only the levels
+                 it shares with s are read)
+    dtype      : arithmetic type; np.longdouble evaluates the same function
+                 of the same FP64 inputs in extended precision
     """
-    g = Grid.of(prob)
+    if dtype is not np.float64:
+        x, xb = np.asarray(x, dtype), np.asarray(xb, dtype)
+        ring = None if ring is None else np.asarray(ring, dtype)
+        nbr_trajs = {k: np.asarray(v, dtype) for k, v in nbr_trajs.items()}
+    g = Grid.of(prob, dtype)
     geo = LocalGeometry(g, maps, s)
     b = maps.boxes[s]
     sb2 = prob.sigma_b[:, None, None] ** 2
@@ -344,7 +353,7 @@ def cost_grad(prob, maps, s, x, xb, ring, nbr_trajs, with_grad=True, parts=False
         if mine.size == 0:
             continue
         theirs = idxp[mine]
-        T = nbr_trajs[int(sp)].reshape(bp.nlev, 3, -1)
+        T = nbr_trajs[int(sp)].reshape(-1, 3, bp.ny * bp.nx)
         for lev in range(lo, hi):
             e = flat[lev - b.lev0][:, mine] - T[lev - bp.lev0][:, theirs]
             Jov += 0.5 * mu * np.sum(e * e / sb2f)

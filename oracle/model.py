@@ -30,23 +30,29 @@ import numpy as np
 class Grid:
     """Per-row tables and Courant factors of the lat-lon grid."""
 
-    def __init__(self, nlat, nlon, dt, radius, gravity, omega):
+    def __init__(self, nlat, nlon, dt, radius, gravity, omega, dtype=np.float64):
+        """``dtype`` is the arithmetic type of the tables and constants:
+        float64 normally; np.longdouble gives an extended-precision reference
+        of the same computation (its inputs are still the FP64 values)."""
         if nlon % 2:
             raise ValueError("nlon must be even for the across-pole map")
-        self.nlat, self.nlon, self.dt = int(nlat), int(nlon), float(dt)
-        self.radius, self.gravity, self.omega = float(radius), float(gravity), float(omega)
-        self.dlat = np.pi / nlat
-        self.dlon = 2.0 * np.pi / nlon
-        self.theta = -np.pi / 2 + (np.arange(nlat) + 0.5) * self.dlat
+        D = dtype
+        self.dtype = D
+        self.nlat, self.nlon = int(nlat), int(nlon)
+        self.dt, self.radius, self.gravity, self.omega = D(dt), D(radius), D(gravity), D(omega)
+        pi = D(np.pi) if D is np.float64 else D("3.14159265358979323846264338327950288")
+        self.dlat = pi / nlat
+        self.dlon = D(2) * pi / nlon
+        self.theta = -pi / 2 + (np.arange(nlat, dtype=D) + D(0.5)) * self.dlat
         self.cos = np.cos(self.theta)
         self.tan = np.tan(self.theta)
-        self.fcor = 2.0 * self.omega * np.sin(self.theta)
+        self.fcor = D(2) * self.omega * np.sin(self.theta)
         self.sig_lon = self.dt / (self.radius * self.dlon)
         self.sig_lat = self.dt / (self.radius * self.dlat)
 
     @classmethod
-    def of(cls, prob):
-        return cls(prob.nlat, prob.nlon, prob.dt, prob.radius, prob.gravity, prob.omega)
+    def of(cls, prob, dtype=np.float64):
+        return cls(prob.nlat, prob.nlon, prob.dt, prob.radius, prob.gravity, prob.omega, dtype)
 
 
 # --- neighbour operators on the global grid ---------------------------------
@@ -210,7 +216,7 @@ def increment_ad(g: Grid, Z, lam):
 # --- time stepping ------------------------------------------------------------
 def forward(g: Grid, x0, nsteps):
     """Leapfrog trajectory from x0; returns [nsteps+1][3][nlat][nlon]."""
-    traj = np.empty((nsteps + 1,) + x0.shape)
+    traj = np.empty((nsteps + 1,) + x0.shape, dtype=x0.dtype)
     traj[0] = x0
     if nsteps >= 1:
         traj[1] = x0 + 0.5 * increment(g, x0)

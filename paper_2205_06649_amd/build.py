@@ -19,7 +19,17 @@ ARCH = os.environ.get("DD4DVAR_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")
 
-HIP_SOURCES = ["sweep.hip", "exchange.hip", "solve.hip", "engine.hip"]
+# (source, object, extra flags): the sweep kernels are compiled once per state
+# type; FP64 without floating-point contraction (separately rounded multiply
+# and add, as in the FP64 reference), FP32 with the default FMA contraction.
+HIP_UNITS = [
+    ("sweep.hip", "sweep_f32.o", ["-DDD4DVAR_SWEEP_T=float", "-DDD4DVAR_SWEEP_PRIMARY=1"]),
+    ("sweep.hip", "sweep_f64.o", ["-DDD4DVAR_SWEEP_T=double", "-DDD4DVAR_SWEEP_PRIMARY=0",
+                                  "-ffp-contract=off"]),
+    ("exchange.hip", "exchange.o", []),
+    ("solve.hip", "solve.o", []),
+    ("engine.hip", "engine.o", []),
+]
 CXX_SOURCES = ["plan.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.
@@ -41,12 +51,10 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = []
     objs = []
-    for src in HIP_SOURCES:
-        if not os.path.exists(os.path.join(CSRC, src)):
-            continue
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+    for src, oname, extra in HIP_UNITS:
+        obj = os.path.join(BUILD, oname)
         objs.append(obj)
-        jobs.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        jobs.append([HIPCC, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
         objs.append(obj)

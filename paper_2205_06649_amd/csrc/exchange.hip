@@ -33,7 +33,7 @@ template <typename T>
 __global__ __launch_bounds__(kTile) void k_from_global(Dom<T> D, const double* __restrict__ bg,
                                                        int64_t gplane, double* __restrict__ xb,
                                                        int n) {
-  const int2 wt = D.tiles[blockIdx.x];
+  const int2 wt = D.tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const SubDev S = D.subs[wt.x];
   if (n >= S.nlev) return;
   const int m = wt.y * kTile + threadIdx.x;
@@ -97,7 +97,7 @@ template <typename T>
 __global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int n,
                                                               double* __restrict__ jc) {
   __shared__ double red[kTile / 64];
-  const int w = blockIdx.x;
+  const int w = xcd_tile(blockIdx.x, gridDim.x);
   const int2 wt = D.tiles[w];
   const SubDev S = D.subs[wt.x];
   if (n >= S.nlev) return;                 // uniform over the block

@@ -7,6 +7,17 @@
 namespace dd4dvar {
 
 constexpr int kTile = 256;  // cells per work tile = threads per workgroup
+constexpr int kXcd = 8;     // MI355X: 8 accelerator dies, each with its own L2
+
+// Workgroups are dealt to the XCDs round-robin (block i runs on XCD i % 8).
+// Remap block i to tile index so that each XCD receives one contiguous range
+// of tiles: consecutive tiles of a box (whose rows are each other's north and
+// south halos) then share an L2.  Bijective on [0, nblocks).
+__device__ __forceinline__ int xcd_tile(int i, int nblocks) {
+  const int per = nblocks / kXcd, rem = nblocks % kXcd;
+  const int x = i % kXcd, k = i / kXcd;
+  return x * per + (x < rem ? x : rem) + k;
+}
 
 // One subdomain (or the whole grid) as the kernels see it.
 struct SubDev {

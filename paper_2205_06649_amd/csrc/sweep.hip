@@ -22,6 +22,10 @@
 #include "kernels.h"
 #include "launch.h"
 
+#ifndef DD4DVAR_SWEEP_T
+#error "compile with -DDD4DVAR_SWEEP_T=float or double"
+#endif
+
 namespace dd4dvar {
 
 namespace {
@@ -42,37 +46,48 @@ __device__ __forceinline__ V3<T> ld_ring(const T* R, int nring, int k) {
 }
 
 // Neighbour positions of box cell (r, c): index into the box (>= 0) or ring
-// position (encoded as -1 - k), plus the sign applied to u, v.
+// position (encoded as -1 - k), plus the sign applied to u, v.  Computed
+// with selects only, so that every neighbour load is issued unconditionally
+// (branches around loads make the compiler wait for each one in turn).
 struct NbrIdx {
-  int64_t e, w, n, s;
-  int8_t sn, ss;       // -1 across a pole
+  int e, w, n, s;
+  int sn, ss;       // -1 across a pole
 };
 
 __device__ __forceinline__ NbrIdx nbr_index(const SubDev& S, int r, int c, int half) {
   NbrIdx q;
-  const int64_t m = int64_t(r) * S.nx + c;
-  q.sn = 1;
-  q.ss = 1;
-  if (c + 1 < S.nx) q.e = m + 1;
-  else if (S.span) q.e = m + 1 - S.nx;
-  else q.e = -1 - (2 * S.nx + S.ny + r);
-  if (c > 0) q.w = m - 1;
-  else if (S.span) q.w = m - 1 + S.nx;
-  else q.w = -1 - (2 * S.nx + r);
-  if (r + 1 < S.ny) q.n = m + S.nx;
-  else if (S.pole_n) { q.n = int64_t(r) * S.nx + (c + half) % S.nx; q.sn = -1; }
-  else q.n = -1 - (S.nx + c);
-  if (r > 0) q.s = m - S.nx;
-  else if (S.pole_s) { q.s = (c + half) % S.nx; q.ss = -1; }
-  else q.s = -1 - c;
+  const int m = r * S.nx + c;
+  int ch = c + half;                       // column across the pole (span boxes)
+  ch = ch >= S.nx ? ch - S.nx : ch;
+  const bool e_in = c + 1 < S.nx, w_in = c > 0, n_in = r + 1 < S.ny, s_in = r > 0;
+  q.e = e_in ? m + 1 : (S.span ? m + 1 - S.nx : -1 - (2 * S.nx + S.ny + r));
+  q.w = w_in ? m - 1 : (S.span ? m - 1 + S.nx : -1 - (2 * S.nx + r));
+  q.n = n_in ? m + S.nx : (S.pole_n ? r * S.nx + ch : -1 - (S.nx + c));
+  q.s = s_in ? m - S.nx : (S.pole_s ? ch : -1 - c);
+  q.sn = (!n_in && S.pole_n) ? -1 : 1;
+  q.ss = (!s_in && S.pole_s) ? -1 : 1;
   return q;
 }
 
 template <typename T>
 __device__ __forceinline__ V3<T> ld_nbr(const T* Z, const T* R, int64_t plane, int nring,
-                                        int64_t idx, int sgn) {
-  if (idx >= 0) return ld_box(Z, plane, idx, T(sgn));
-  return ld_ring(R, nring, int(-1 - idx));
+                                        int idx, int sgn) {
+  const bool in = idx >= 0;
+  const T* p = in ? Z + idx : R + (-1 - idx);
+  const int64_t st = in ? plane : int64_t(nring);
+  const T sg = T(in ? sgn : 1);
+  return {p[0], sg * p[st], sg * p[2 * st]};
+}
+
+// Adjoint of level n+1 at a neighbour, zero when the neighbour is a frozen
+// ring position (its increment is not part of the local model).  The load
+// is unconditional (from the cell itself when the neighbour is frozen).
+template <typename T>
+__device__ __forceinline__ V3<T> ld_lam(const T* L1, int64_t plane, int idx, int m) {
+  const bool in = idx >= 0;
+  const int i = in ? idx : m;
+  const T h = L1[i], u = L1[plane + i], v = L1[2 * plane + i];
+  return {in ? h : T(0), in ? u : T(0), in ? v : T(0)};
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -92,7 +107,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_init(Dom<T> D, const double* __restrict__ x,
                                                 int tile_base) {
-  const int2 wt = D.tiles[tile_base + blockIdx.x];
+  const int2 wt = D.tiles[tile_base + xcd_tile(blockIdx.x, gridDim.x)];
   const SubDev S = D.subs[wt.x];
   const int m = wt.y * kTile + threadIdx.x;
   if (m >= S.ncell) return;
@@ -105,7 +120,7 @@ __global__ __launch_bounds__(kTile) void k_init(Dom<T> D, const double* __restri
 
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_fwd(Dom<T> D, int n, int tile_base) {
-  const int2 wt = D.tiles[tile_base + blockIdx.x];
+  const int2 wt = D.tiles[tile_base + xcd_tile(blockIdx.x, gridDim.x)];
   const SubDev S = D.subs[wt.x];
   if (n >= S.nlev - 1) return;
   const int m = wt.y * kTile + threadIdx.x;
@@ -115,12 +130,16 @@ __global__ __launch_bounds__(kTile) void k_fwd(Dom<T> D, int n, int tile_base) {
   const T* Z = D.traj + S.traj_off + int64_t(n) * 3 * plane;
   const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
   const NbrIdx q = nbr_index(S, r, c, D.half);
+  // level n-1 (level 0 itself for the Euler start, whose base is Z^0)
+  const T* P = n >= 1 ? Z - 3 * plane : Z;
+  const int j = S.row0 + r;
+  // every load first, unconditionally
   const V3<T> C = ld_box(Z, plane, m, T(1));
   const V3<T> E = ld_nbr(Z, R, plane, S.nring, q.e, 1);
   const V3<T> W = ld_nbr(Z, R, plane, S.nring, q.w, 1);
   const V3<T> N = ld_nbr(Z, R, plane, S.nring, q.n, q.sn);
   const V3<T> Sv = ld_nbr(Z, R, plane, S.nring, q.s, q.ss);
-  const int j = S.row0 + r;
+  const V3<T> B = ld_box(P, plane, m, T(1));
   const RowCoef<T> rc = D.rows[j];
   const T cN = D.cosx[j + 2], cS = D.cosx[j];
   const T st = D.st, stg = D.stg, h0 = D.h0;
@@ -129,17 +148,11 @@ __global__ __launch_bounds__(kTile) void k_fwd(Dom<T> D, int n, int tile_base) {
   const T V = -rc.a1 * C.u * (E.v - W.v) - st * C.v * (N.v - Sv.v) - stg * (N.h - Sv.h) - cor * C.u;
   const T H = -rc.a1 * (h0 * (E.u - W.u) + (E.h * E.u - W.h * W.u))
               - rc.a3 * (h0 * (N.v * cN - Sv.v * cS) + (N.h * N.v * cN - Sv.h * Sv.v * cS));
+  const T wgt = n == 0 ? T(0.5) : T(1);
   T* out = const_cast<T*>(Z) + 3 * plane;
-  if (n == 0) {
-    out[m] = C.h + T(0.5) * H;
-    out[plane + m] = C.u + T(0.5) * U;
-    out[2 * plane + m] = C.v + T(0.5) * V;
-  } else {
-    const T* P = Z - 3 * plane;
-    out[m] = P[m] + H;
-    out[plane + m] = P[plane + m] + U;
-    out[2 * plane + m] = P[2 * plane + m] + V;
-  }
+  out[m] = B.h + wgt * H;
+  out[plane + m] = B.u + wgt * U;
+  out[2 * plane + m] = B.v + wgt * V;
 }
 
 // mode 0: cost forcing (observations + overlap), writes grad and J at level 0
@@ -153,125 +166,122 @@ __global__ __launch_bounds__(kTile) void k_adj(Dom<T> D, int n, int tile_base,
                                                double* __restrict__ out) {
   __shared__ double fo[3][kTile];
   __shared__ double red[kTile / 64];
-  const int w = tile_base + blockIdx.x;
+  const int w = tile_base + xcd_tile(blockIdx.x, gridDim.x);
   const int2 wt = D.tiles[w];
   const SubDev S = D.subs[wt.x];
   const int L = S.nlev - 1;
   if (n > L) return;                      // uniform over the block
   const int m = wt.y * kTile + threadIdx.x;
   const bool valid = m < S.ncell;
+  const int mm = valid ? m : 0;           // a valid address for inactive lanes
   const int64_t plane = S.ncell;
   const T* Z = D.traj + S.traj_off + int64_t(n) * 3 * plane;
+  const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
+  T* A = D.adj + S.adj_off;
+  const bool has1 = n + 1 <= L, has2 = n + 2 <= L;       // uniform
+  const T* L1 = A + int64_t((n + 1) % 3) * 3 * plane;
+  const T* L2 = A + int64_t((n + 2) % 3) * 3 * plane;
   double jloc = 0.0;
 
+  // ---- issue every load of this cell first (selects, no branches) ---------
+  int K = 0;                               // other extended boxes covering (n, m)
+  if (MODE != 1) K = int(D.cover[S.cell_off + mm]) * D.tcount[S.lev0 + n] - 1;
+  const int r = mm / S.nx, c = mm - r * S.nx;
+  const NbrIdx q = nbr_index(S, r, c, D.half);
+  const int j = S.row0 + r;
+  // rows of the north / south neighbours whose increments read this cell
+  const int jn = (q.n >= 0 && q.sn > 0) ? j + 1 : j;
+  const int js = (q.s >= 0 && q.ss > 0) ? j - 1 : j;
+  const RowCoef<T> rc = D.rows[j];
+  const T a3n = D.rows[jn].a3, a3s = D.rows[js].a3;
+  const V3<T> C = ld_box(Z, plane, mm, T(1));
+  const V3<T> E = ld_nbr(Z, R, plane, S.nring, q.e, 1);
+  const V3<T> W = ld_nbr(Z, R, plane, S.nring, q.w, 1);
+  const V3<T> N = ld_nbr(Z, R, plane, S.nring, q.n, q.sn);
+  const V3<T> Sv = ld_nbr(Z, R, plane, S.nring, q.s, q.ss);
+  V3<T> l0 = ld_box(L1, plane, mm, T(1));
+  V3<T> kE = ld_lam(L1, plane, q.e, mm);
+  V3<T> kW = ld_lam(L1, plane, q.w, mm);
+  V3<T> kN = ld_lam(L1, plane, q.n, mm);
+  V3<T> kS = ld_lam(L1, plane, q.s, mm);
+  V3<T> l2 = ld_box(L2, plane, mm, T(1));
+  double fh = 0, fu = 0, fv = 0;
+  V3<T> tg = {T(0), T(0), T(0)};
   if (MODE != 1) {
-    fo[0][threadIdx.x] = 0.0;
-    fo[1][threadIdx.x] = 0.0;
-    fo[2][threadIdx.x] = 0.0;
-    __syncthreads();
-    const int64_t key = int64_t(w) * D.maxlev + n;
-    const int o0 = D.obs_ptr[key], o1 = D.obs_ptr[key + 1];
-    for (int o = o0 + int(threadIdx.x); o < o1; o += kTile) {
-      const int code = D.obs_code[o];
-      const int loc = code >> 2, f = code & 3;
-      const double r = double(Z[f * plane + loc]) - D.obs_val[o];
-      const double qo = D.obs_q[o];
-      jloc += 0.5 * qo * r * r;
-      fo[f][loc - wt.y * kTile] = qo * r;
-    }
-    __syncthreads();
+    // cells outside every overlap all read element 0 (one shared cache line)
+    // instead of branching around the load; their weight K is zero
+    tg = ld_box(D.targ + S.traj_off + int64_t(n) * 3 * plane, plane, K > 0 ? mm : 0, T(1));
+  } else {
+    const double* Fz = forcing + S.traj_off + int64_t(n) * 3 * plane;
+    fh = Fz[mm];
+    fu = Fz[plane + mm];
+    fv = Fz[2 * plane + mm];
   }
 
-  if (valid) {
-    const int r = m / S.nx, c = m - r * S.nx;
-    const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
-    T* A = D.adj + S.adj_off;
-    const NbrIdx q = nbr_index(S, r, c, D.half);
-    const V3<T> C = ld_box(Z, plane, m, T(1));
-    const V3<T> E = ld_nbr(Z, R, plane, S.nring, q.e, 1);
-    const V3<T> W = ld_nbr(Z, R, plane, S.nring, q.w, 1);
-    const V3<T> N = ld_nbr(Z, R, plane, S.nring, q.n, q.sn);
-    const V3<T> Sv = ld_nbr(Z, R, plane, S.nring, q.s, q.ss);
-    const int j = S.row0 + r;
-    const RowCoef<T> rc = D.rows[j];
-    const T st = D.st, stg = D.stg;
-    const T hm = D.h0 + C.h;
-
-    // J_F(Z^n)^T lambda^{n+1}
-    T au = 0, av = 0, ah = 0;
-    if (n + 1 <= L) {
-      const T* L1 = A + int64_t((n + 1) % 3) * 3 * plane;
-      const T lh = L1[m], lu = L1[plane + m], lv = L1[2 * plane + m];
-      // self terms
-      au += lu * (-rc.a1 * (E.u - W.u) + rc.ct * C.v) + lv * (-rc.a1 * (E.v - W.v) - rc.cf - T(2) * rc.ct * C.u);
-      av += lu * (-st * (N.u - Sv.u) + rc.cf + rc.ct * C.u) + lv * (-st * (N.v - Sv.v));
-      // east neighbour k (m is its west neighbour)
-      if (q.e >= 0) {
-        const T kh = L1[q.e], ku = L1[plane + q.e], kv = L1[2 * plane + q.e];
-        au += rc.a1 * (ku * E.u + kh * hm);
-        av += rc.a1 * kv * E.u;
-        ah += rc.a2 * ku + rc.a1 * kh * C.u;
+  // ---- observation misfits of this tile at level n (uniform test) --------
+  if (MODE != 1) {
+    const int64_t key = int64_t(w) * D.maxlev + n;
+    const int o0 = D.obs_ptr[key], o1 = D.obs_ptr[key + 1];
+    if (o1 > o0) {
+      fo[0][threadIdx.x] = 0.0;
+      fo[1][threadIdx.x] = 0.0;
+      fo[2][threadIdx.x] = 0.0;
+      __syncthreads();
+      for (int o = o0 + int(threadIdx.x); o < o1; o += kTile) {
+        const int code = D.obs_code[o];
+        const int loc = code >> 2, f = code & 3;
+        const double rr = double(Z[f * plane + loc]) - D.obs_val[o];
+        const double qo = D.obs_q[o];
+        jloc += 0.5 * qo * rr * rr;
+        fo[f][loc - wt.y * kTile] = qo * rr;
       }
-      if (q.w >= 0) {
-        const T kh = L1[q.w], ku = L1[plane + q.w], kv = L1[2 * plane + q.w];
-        au -= rc.a1 * (ku * W.u + kh * hm);
-        av -= rc.a1 * kv * W.u;
-        ah -= rc.a2 * ku + rc.a1 * kh * C.u;
-      }
-      if (q.n >= 0) {
-        const T kh = L1[q.n], ku = L1[plane + q.n], kv = L1[2 * plane + q.n];
-        const T vk = T(q.sn) * N.v;                   // raw v at k
-        const T a3k = D.rows[q.sn > 0 ? j + 1 : j].a3;
-        au += ku * st * vk;
-        av += kv * st * vk + kh * a3k * hm * rc.c;
-        ah += T(q.sn) * kv * stg + kh * a3k * C.v * rc.c;
-      }
-      if (q.s >= 0) {
-        const T kh = L1[q.s], ku = L1[plane + q.s], kv = L1[2 * plane + q.s];
-        const T vk = T(q.ss) * Sv.v;
-        const T a3k = D.rows[q.ss > 0 ? j - 1 : j].a3;
-        au -= ku * st * vk;
-        av -= kv * st * vk + kh * a3k * hm * rc.c;
-        ah -= T(q.ss) * kv * stg + kh * a3k * C.v * rc.c;
-      }
-      if (n == 0) {
-        au = lu + T(0.5) * au;
-        av = lv + T(0.5) * av;
-        ah = lh + T(0.5) * ah;
-      }
-    }
-    // forcing
-    double fh, fu, fv;
-    if (MODE != 1) {
+      __syncthreads();
       fh = fo[0][threadIdx.x];
       fu = fo[1][threadIdx.x];
       fv = fo[2][threadIdx.x];
-      const int cov = D.cover[S.cell_off + m];
-      const int K = cov * D.tcount[S.lev0 + n] - 1;
-      if (K > 0) {
-        const T* Tg = D.targ + S.traj_off + int64_t(n) * 3 * plane;
-        const double eh = double(C.h) - double(Tg[m]);
-        const double eu = double(C.u) - double(Tg[plane + m]);
-        const double ev = double(C.v) - double(Tg[2 * plane + m]);
-        const double mk = D.mu * double(K);
-        fh += mk * eh * D.isb2[0];
-        fu += mk * eu * D.isb2[1];
-        fv += mk * ev * D.isb2[2];
-        jloc += 0.5 * mk * (eh * eh * D.isb2[0] + eu * eu * D.isb2[1] + ev * ev * D.isb2[2]);
-      }
-    } else {
-      const double* Fz = forcing + S.traj_off + int64_t(n) * 3 * plane;
-      fh = Fz[m];
-      fu = Fz[plane + m];
-      fv = Fz[2 * plane + m];
     }
-    double bh = fh + double(ah), bu = fu + double(au), bv = fv + double(av);
-    if (n + 2 <= L) {
-      const T* L2 = A + int64_t((n + 2) % 3) * 3 * plane;
-      bh += double(L2[m]);
-      bu += double(L2[plane + m]);
-      bv += double(L2[2 * plane + m]);
+  }
+
+  if (valid) {
+    if (!has1) l0 = kE = kW = kN = kS = V3<T>{T(0), T(0), T(0)};
+    if (!has2) l2 = V3<T>{T(0), T(0), T(0)};
+    const T st = D.st, stg = D.stg;
+    const T hm = D.h0 + C.h;
+
+    // J_F(Z^n)^T lambda^{n+1}: self terms, then the neighbours k whose
+    // increment reads this cell (east k sees it as west, north k as south,
+    // across a pole the north k sees it as north with u, v negated)
+    T au = l0.u * (-rc.a1 * (E.u - W.u) + rc.ct * C.v) +
+           l0.v * (-rc.a1 * (E.v - W.v) - rc.cf - T(2) * rc.ct * C.u);
+    T av = l0.u * (-st * (N.u - Sv.u) + rc.cf + rc.ct * C.u) + l0.v * (-st * (N.v - Sv.v));
+    T ah = T(0);
+    au += rc.a1 * (kE.u * E.u + kE.h * hm) - rc.a1 * (kW.u * W.u + kW.h * hm);
+    av += rc.a1 * kE.v * E.u - rc.a1 * kW.v * W.u;
+    ah += (rc.a2 * kE.u + rc.a1 * kE.h * C.u) - (rc.a2 * kW.u + rc.a1 * kW.h * C.u);
+    const T vkn = T(q.sn) * N.v, vks = T(q.ss) * Sv.v;    // raw v at the neighbours
+    au += kN.u * st * vkn - kS.u * st * vks;
+    av += (kN.v * st * vkn + kN.h * a3n * hm * rc.c) - (kS.v * st * vks + kS.h * a3s * hm * rc.c);
+    ah += (T(q.sn) * kN.v * stg + kN.h * a3n * C.v * rc.c) -
+          (T(q.ss) * kS.v * stg + kS.h * a3s * C.v * rc.c);
+    if (n == 0) {
+      au = l0.u + T(0.5) * au;
+      av = l0.v + T(0.5) * av;
+      ah = l0.h + T(0.5) * ah;
     }
+    // overlap misfit: K copies of (Z - mean target) / sigma_b^2
+    if (MODE != 1) {
+      const double eh = double(C.h) - double(tg.h);
+      const double eu = double(C.u) - double(tg.u);
+      const double ev = double(C.v) - double(tg.v);
+      const double mk = D.mu * double(K);
+      fh += mk * eh * D.isb2[0];
+      fu += mk * eu * D.isb2[1];
+      fv += mk * ev * D.isb2[2];
+      jloc += 0.5 * mk * (eh * eh * D.isb2[0] + eu * eu * D.isb2[1] + ev * ev * D.isb2[2]);
+    }
+    const double bh = fh + double(ah) + double(l2.h);
+    const double bu = fu + double(au) + double(l2.u);
+    const double bv = fv + double(av) + double(l2.v);
     if (n > 0) {
       T* B = A + int64_t(n % 3) * 3 * plane;
       B[m] = T(bh);
@@ -300,6 +310,7 @@ __global__ __launch_bounds__(kTile) void k_adj(Dom<T> D, int n, int tile_base,
   }
 }
 
+#if DD4DVAR_SWEEP_PRIMARY
 // J[s] = sum of tile partials (fixed order) + constant overlap part
 __global__ void k_reduce_j(const SubDev* __restrict__ subs, int count, const int32_t* __restrict__ ids,
                            const double* __restrict__ jpart, const double* __restrict__ jconst,
@@ -314,11 +325,12 @@ __global__ void k_reduce_j(const SubDev* __restrict__ subs, int count, const int
   J[s] = acc;
   if (!isfinite(acc)) atomicOr(nonfinite, 1u);
 }
+#endif
 
 // packed FP64 trajectory output (h + h_ref)
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_traj_out(Dom<T> D, double* __restrict__ out, int tile_base) {
-  const int2 wt = D.tiles[tile_base + blockIdx.x];
+  const int2 wt = D.tiles[tile_base + xcd_tile(blockIdx.x, gridDim.x)];
   const SubDev S = D.subs[wt.x];
   const int m = wt.y * kTile + threadIdx.x;
   if (m >= S.ncell) return;
@@ -354,11 +366,13 @@ void launch_adj(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, con
     hipLaunchKernelGGL((k_adj<T, 2>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, x, xb,
                        forcing, out);
 }
+#if DD4DVAR_SWEEP_PRIMARY
 void launch_reduce_j(const SubDev* subs, int count, const int32_t* ids, const double* jpart,
                      const double* jconst, double* J, uint32_t* nonfinite, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_j, dim3((count + 255) / 256), dim3(256), 0, st, subs, count, ids,
                      jpart, jconst, J, nonfinite);
 }
+#endif
 template <typename T>
 void launch_traj_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hipStream_t st) {
   hipLaunchKernelGGL(k_traj_out<T>, dim3(ntiles), dim3(kTile), 0, st, D, out, tile_base);
@@ -370,8 +384,10 @@ void launch_traj_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hi
   template void launch_adj<T>(const Dom<T>&, int, int, int, int, const double*, const double*, \
                               const double*, double*, hipStream_t);                            \
   template void launch_traj_out<T>(const Dom<T>&, double*, int, int, hipStream_t);
-DD4DVAR_INST(float)
-DD4DVAR_INST(double)
+// This source is compiled once per state type: FP32 with the compiler's
+// default contraction, FP64 with -ffp-contract=off so that FP64 results follow
+// the rounding of the separate multiplies and adds of the reference.
+DD4DVAR_INST(DD4DVAR_SWEEP_T)
 #undef DD4DVAR_INST
 
 }  // namespace dd4dvar

@@ -20,12 +20,22 @@ from test_oracle_pins import MIXED_CFG, SPAN_CFG
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "fp32": 1e-4}
+TOL_GRAD = {"fp64": 2e-12, "fp32": 1e-4}
 TOL_TRAJ = {"fp64": 1e-12, "fp32": 2e-5}
+# FP64 results are compared with the oracle evaluated in extended precision.
+# J and trajectories are held to 1e-12.  Gradients are held to 2e-12: the
+# leapfrog adjoint amplifies per-step rounding (1e-15) by ~1e3 over these
+# windows, and the FP64 oracle itself lands up to 9e-13 from the
+# extended-precision gradient (see the rounding-floor pin), so 1e-12 is the
+# floor of any FP64 evaluation, not a margin.
+REF_DTYPE = {"fp64": np.longdouble, "fp32": np.float64}
 
 
 def _rel(a, b):
+    a = np.asarray(a, dtype=np.longdouble)
+    b = np.asarray(b, dtype=np.longdouble)
     nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
 def _prob(which):
@@ -104,9 +114,9 @@ def test_local_cost_grad(which, prec):
     for b in maps.boxes:
         s = b.sub
         Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], rings[s],
-                                 {k: trajs[k] for k in maps.neighbors[s]})
-        assert abs(J[s] - Jr) <= TOL[prec] * abs(Jr), (s, J[s], Jr)
-        assert _rel(grads[s], gr) <= TOL[prec], s
+                                 {k: trajs[k] for k in maps.neighbors[s]}, dtype=REF_DTYPE[prec])
+        ej, eg = float(abs(J[s] - Jr) / abs(Jr)), float(_rel(grads[s], gr))
+        assert ej <= TOL[prec] and eg <= TOL_GRAD[prec], (s, ej, eg)
 
 
 def test_cost_grad_at_background_and_subsets():
@@ -119,8 +129,8 @@ def test_cost_grad_at_background_and_subsets():
     J = J.cpu().numpy()
     for b in maps.boxes:
         Jr, gr = local.cost_grad(p, maps, b.sub, trajs[b.sub][0], trajs[b.sub][0], rings[b.sub],
-                                 {k: trajs[k] for k in maps.neighbors[b.sub]})
-        assert abs(J[b.sub] - Jr) <= 1e-12 * abs(Jr)
+                                 {k: trajs[k] for k in maps.neighbors[b.sub]}, dtype=np.longdouble)
+        assert float(abs(J[b.sub] - Jr) / abs(Jr)) <= 1e-12
     xs = ctx.pack_ctrl(_perturbed(p, maps, trajs, seed=2))
     J1, g1 = ctx.cost_grad(xs)
     ids = [5, 1, 6]
@@ -172,9 +182,9 @@ def test_exchange_then_cost_grad():
     for b in maps.boxes:
         s = b.sub
         Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], new_rings[s],
-                                 {k: new[k] for k in maps.neighbors[s]})
-        assert abs(J[s] - Jr) <= 1e-12 * abs(Jr)
-        assert _rel(grads[s], gr) <= 1e-12
+                                 {k: new[k] for k in maps.neighbors[s]}, dtype=np.longdouble)
+        ej, eg = float(abs(J[s] - Jr) / abs(Jr)), float(_rel(grads[s], gr))
+        assert ej <= TOL["fp64"] and eg <= TOL_GRAD["fp64"], (s, ej, eg)
 
 
 def test_gather_partition_of_unity():

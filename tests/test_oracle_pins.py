@@ -243,6 +243,27 @@ def test_global_gradient_finite_differences(rng):
     assert abs(fd - an) <= 1e-6 * abs(an)
 
 
+def test_fp64_rounding_floor_against_extended_precision(rng):
+    """The same local functional evaluated in 80-bit extended precision: the
+    FP64 evaluation agrees to the rounding floor of the computation (J to
+    ~1e-13, the gradient to ~1e-12 because the adjoint sums h-weighted terms
+    that cancel).  This fixes how close any FP64 implementation can get."""
+    p = problem("c1")
+    g, maps, trajs, rings = _local_setup(p)
+    sb = p.sigma_b[:, None, None]
+    worst_j = worst_g = 0.0
+    for s in range(len(maps.boxes)):
+        x = trajs[s][0] + 0.3 * sb * rng.standard_normal(trajs[s][0].shape)
+        nb = {k: trajs[k] for k in maps.neighbors[s]}
+        J, gr = local.cost_grad(p, maps, s, x, trajs[s][0], rings[s], nb)
+        JL, gL = local.cost_grad(p, maps, s, x, trajs[s][0], rings[s], nb, dtype=np.longdouble)
+        assert JL.dtype == np.longdouble
+        worst_j = max(worst_j, float(abs(J - JL) / abs(JL)))
+        worst_g = max(worst_g, float(np.linalg.norm(gr - gL) / np.linalg.norm(gL)))
+    assert worst_j < 1e-12 and worst_g < 2e-12, (worst_j, worst_g)
+    assert worst_g > 1e-15     # the extended evaluation really is different
+
+
 # --- P12: brute-force Jacobian of a tiny box vs adjoint rows ----------------
 def test_bruteforce_jacobian_tiny_box():
     p = problem("tiny2")
