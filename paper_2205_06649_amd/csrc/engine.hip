@@ -24,6 +24,7 @@
 #include "kernels.h"
 #include "launch.h"
 #include "plan.h"
+#include "solve.h"
 
 using namespace dd4dvar;
 
@@ -65,6 +66,7 @@ struct dd4dvar_ctx {
   int32_t *cptr = nullptr, *cpiece = nullptr;
   int32_t* d_ids = nullptr;
   uint32_t* nonfinite = nullptr;
+  const uint8_t* eval_mask = nullptr;   // subdomains evaluated by the sweeps (null = all)
   // the whole grid as one box (FP64), for background and global runs
   SubDev gsub{};
   int gtiles = 0;
@@ -140,6 +142,7 @@ Dom<T> local_dom(const dd4dvar_ctx* c) {
   D.hoff = c->hoff;
   D.hsign = c->hsign;
   D.hgcell = c->hgcell;
+  D.active = c->eval_mask;
   D.st = T(c->st);
   D.stg = T(c->stg);
   D.h0 = T(c->plan.model.h_ref);
@@ -727,9 +730,178 @@ dd4dvar_status dd4dvar_solve(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* opts,
 }  // extern "C"
 
 namespace dd4dvar {
-dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts*, const double*, double*,
-                          double*, dd4dvar_solve_report*) {
-  ctx->err = "solve is not available in this build";
-  return DD4DVAR_E_INVALID;
+
+namespace {
+// device buffers of one solve, released on every exit path
+struct SolveBuffers {
+  std::vector<void*> p;
+  ~SolveBuffers() {
+    for (void* q : p) (void)hipFree(q);
+  }
+  template <typename P>
+  P* get(size_t n) {
+    void* q = nullptr;
+    chk(hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(P)), "hipMalloc solve");
+    p.push_back(q);
+    return static_cast<P*>(q);
+  }
+};
+
+template <typename P>
+P read1(const P* d, hipStream_t st) {
+  P h{};
+  chk(hipMemcpyAsync(&h, d, sizeof(P), hipMemcpyDeviceToHost, st), "read");
+  chk(hipStreamSynchronize(st), "sync");
+  return h;
+}
+
+template <typename T>
+dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const double* x_init,
+                           double* x_out, double* xa_host, dd4dvar_solve_report* rep) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = nullptr;
+  chk(hipDeviceSynchronize(), "sync");
+  const int nsub = c->nsub;
+  const int64_t N = c->plan.ctrl_total;
+  SolveBuffers B;
+  LbState L{};
+  L.subs = c->d_subs;
+  L.nsub = nsub;
+  L.m = o->lbfgs_m;
+  L.max_iter = o->max_iter;
+  L.max_ls = o->max_ls;
+  L.N = N;
+  for (int f = 0; f < 3; ++f) L.sb[f] = c->plan.sigma_b[f];
+  L.c1 = o->armijo_c1;
+  L.grad_rtol = o->grad_rtol;
+  L.xb = c->xb;
+  L.xi = B.get<double>(N);
+  L.xi0 = B.get<double>(N);
+  L.g = B.get<double>(N);
+  L.d = B.get<double>(N);
+  L.xt = B.get<double>(N);
+  L.xphys = B.get<double>(N);
+  L.gradx = B.get<double>(N);
+  L.S = B.get<double>(size_t(L.m) * N);
+  L.Y = B.get<double>(size_t(L.m) * N);
+  L.J = B.get<double>(nsub);
+  L.Jt = B.get<double>(nsub);
+  L.gd = B.get<double>(nsub);
+  L.alpha = B.get<double>(nsub);
+  L.rho = B.get<double>(size_t(L.m) * nsub);
+  L.gamma = B.get<double>(nsub);
+  L.g0norm = B.get<double>(nsub);
+  L.gnorm = B.get<double>(nsub);
+  L.step = B.get<double>(nsub);
+  L.npairs = B.get<int32_t>(nsub);
+  L.head = B.get<int32_t>(nsub);
+  L.status = B.get<int32_t>(nsub);
+  L.iters = B.get<int32_t>(nsub);
+  L.trials = B.get<int32_t>(nsub);
+  L.ls = B.get<uint8_t>(nsub);
+  L.pending = B.get<int32_t>(1);
+  double* xa_dev = B.get<double>(size_t(3) * c->plan.model.nlat * c->plan.model.nlon);
+
+  struct MaskReset {
+    dd4dvar_ctx* c;
+    ~MaskReset() { c->eval_mask = nullptr; }
+  } reset{c};
+
+  if (x_init) lb_from_x(L, x_init, st);
+  else launch_fill(L.xi, N, 0.0, st);
+  int evals = 0, outer = 0, lbfgs_iters = 0;
+  bool met = false;
+  std::vector<int32_t> iters_h(nsub);
+  for (outer = 1; outer <= o->max_outer; ++outer) {
+    // local solves, all subdomains at once
+    c->eval_mask = nullptr;
+    lb_to_x(L, 0, 0, st);
+    cost_grad_impl<T>(c, nullptr, L.xphys, L.Jt, L.gradx, st);
+    ++evals;
+    lb_start(L, st);
+    for (;;) {
+      chk(hipMemsetAsync(L.pending, 0, sizeof(int32_t), st), "memset");
+      lb_count(L, st);
+      if (read1(L.pending, st) == 0) break;
+      lb_direction(L, st);
+      for (;;) {
+        lb_trial(L, st);
+        c->eval_mask = L.ls;
+        cost_grad_impl<T>(c, nullptr, L.xphys, L.Jt, L.gradx, st);
+        c->eval_mask = nullptr;
+        ++evals;
+        chk(hipMemsetAsync(L.pending, 0, sizeof(int32_t), st), "memset");
+        lb_armijo(L, st);
+        if (read1(L.pending, st) == 0) break;
+      }
+    }
+    chk(hipMemcpyAsync(iters_h.data(), L.iters, nsub * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+        "read iters");
+    lb_step(L, st);
+    std::vector<double> step(nsub);
+    chk(hipMemcpyAsync(step.data(), L.step, nsub * sizeof(double), hipMemcpyDeviceToHost, st),
+        "read step");
+    chk(hipStreamSynchronize(st), "sync");
+    lbfgs_iters += *std::max_element(iters_h.begin(), iters_h.end());
+    // exchange (Alg. 1): integrate the new controls, refresh rings and targets
+    lb_to_x(L, 0, 0, st);
+    exchange_impl<T>(c, L.xphys, st);
+    const double mx = *std::max_element(step.begin(), step.end());
+    if (!std::isfinite(mx)) {
+      c->err = "non-finite iterate in the local solves";
+      return DD4DVAR_E_NONFINITE;
+    }
+    if (mx < o->outer_tol) {
+      met = true;
+      break;
+    }
+  }
+  if (outer > o->max_outer) outer = o->max_outer;
+  // gather the analysis at level 0 (partition of unity, eq. rest)
+  const int64_t ncell = int64_t(c->plan.model.nlat) * c->plan.model.nlon;
+  launch_gather<T>(local_dom<T>(c), c->plan.nspace, c->plan.ntime, 0, ncell, c->cptr, c->cpiece,
+                   xa_dev, st);
+  chk(hipGetLastError(), "gather launch");
+  chk(hipMemcpyAsync(xa_host, xa_dev, size_t(3 * ncell) * sizeof(double), hipMemcpyDeviceToHost, st),
+      "copy analysis");
+  if (x_out)
+    chk(hipMemcpyAsync(x_out, L.xphys, size_t(N) * sizeof(double), hipMemcpyDeviceToDevice, st),
+        "copy controls");
+  std::vector<double> J(nsub), gn(nsub), g0(nsub);
+  chk(hipMemcpyAsync(J.data(), L.J, nsub * sizeof(double), hipMemcpyDeviceToHost, st), "read J");
+  chk(hipMemcpyAsync(gn.data(), L.gnorm, nsub * sizeof(double), hipMemcpyDeviceToHost, st), "read g");
+  chk(hipMemcpyAsync(g0.data(), L.g0norm, nsub * sizeof(double), hipMemcpyDeviceToHost, st), "read g0");
+  chk(hipStreamSynchronize(st), "sync");
+  if (rep) {
+    rep->outer_iters = outer;
+    rep->total_evals = evals;
+    rep->lbfgs_iters = lbfgs_iters;
+    double js = 0, ratio = 0;
+    for (int s = 0; s < nsub; ++s) {
+      js += J[s];
+      if (g0[s] > 0) ratio = std::max(ratio, gn[s] / g0[s]);
+    }
+    rep->J_final = js;
+    rep->gnorm_ratio_max = ratio;
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (!met) {
+    c->err = "outer iterations exhausted before the exchange step fell below outer_tol";
+    return DD4DVAR_E_NOTCONVERGED;
+  }
+  return DD4DVAR_OK;
+}
+}  // namespace
+
+dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* o, const double* x_init,
+                          double* x_out, double* xa_host, dd4dvar_solve_report* rep) {
+  if (o->lbfgs_m < 1 || o->lbfgs_m > kMaxPairs || o->max_iter < 0 || o->max_outer < 1 ||
+      o->max_ls < 1 || !(o->grad_rtol >= 0) || !(o->outer_tol >= 0) || !(o->armijo_c1 > 0) ||
+      !(o->armijo_c1 < 1)) {
+    ctx->err = "bad solve options";
+    return DD4DVAR_E_INVALID;
+  }
+  if (ctx->prec == DD4DVAR_FP64) return solve_typed<double>(ctx, o, x_init, x_out, xa_host, rep);
+  return solve_typed<float>(ctx, o, x_init, x_out, xa_host, rep);
 }
 }  // namespace dd4dvar

@@ -68,6 +68,7 @@ struct Dom {
   const int32_t* hoff;
   const int32_t* hsign;
   const int32_t* hgcell;
+  const uint8_t* active;     // per subdomain, 0 = skip (nullptr = all active)
   T st, stg, h0;
   double mu;
   double isb2[3];            // 1 / sigma_b^2

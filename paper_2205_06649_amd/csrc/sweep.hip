@@ -108,6 +108,7 @@ template <typename T>
 __global__ __launch_bounds__(kTile) void k_init(Dom<T> D, const double* __restrict__ x,
                                                 int tile_base) {
   const int2 wt = D.tiles[tile_base + xcd_tile(blockIdx.x, gridDim.x)];
+  if (D.active && !D.active[wt.x]) return;
   const SubDev S = D.subs[wt.x];
   const int m = wt.y * kTile + threadIdx.x;
   if (m >= S.ncell) return;
@@ -121,6 +122,7 @@ __global__ __launch_bounds__(kTile) void k_init(Dom<T> D, const double* __restri
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_fwd(Dom<T> D, int n, int tile_base) {
   const int2 wt = D.tiles[tile_base + xcd_tile(blockIdx.x, gridDim.x)];
+  if (D.active && !D.active[wt.x]) return;
   const SubDev S = D.subs[wt.x];
   if (n >= S.nlev - 1) return;
   const int m = wt.y * kTile + threadIdx.x;
@@ -168,6 +170,7 @@ __global__ __launch_bounds__(kTile) void k_adj(Dom<T> D, int n, int tile_base,
   __shared__ double red[kTile / 64];
   const int w = tile_base + xcd_tile(blockIdx.x, gridDim.x);
   const int2 wt = D.tiles[w];
+  if (D.active && !D.active[wt.x]) return;  // uniform over the block
   const SubDev S = D.subs[wt.x];
   const int L = S.nlev - 1;
   if (n > L) return;                      // uniform over the block
