@@ -27,6 +27,7 @@ HIP_UNITS = [
     ("sweep.hip", "sweep_f64.o", ["-DDD4DVAR_SWEEP_T=double", "-DDD4DVAR_SWEEP_PRIMARY=0",
                                   "-ffp-contract=off"]),
     ("exchange.hip", "exchange.o", []),
+    ("box.hip", "box.o", []),
     ("solve.hip", "solve.o", []),
     ("engine.hip", "engine.o", []),
 ]

@@ -1,0 +1,479 @@
+// Persistent per-box sweeps (FP32 state): one workgroup owns one box for its
+// whole time interval and keeps the current level in LDS, so that a forward
+// step touches HBM only to store the trajectory, to read the frozen halo ring
+// and to read back the level before (which stays in the last-level cache).
+// Same arithmetic as the step kernels of sweep.hip (restricted model,
+// eq. restricted; discrete U, V, H of Sec. 7; leapfrog with a forward-Euler
+// half step).
+//
+// LDS holds each field of the level on a padded (ny+2) x (nx+2) grid whose
+// one-cell frame carries the halo: frozen ring values (signs applied), or,
+// for a box spanning the circle, copies of the box's own cells across the
+// seam or the pole (u, v negated across a pole).  The stencil then needs no
+// branches.  Per-row coefficients sit in LDS as well.
+//
+// Thread t owns column t % nx of the rows k R + t / nx, k = 0, 1, ..., with
+// R = floor(1024 / nx) rows per pass, so all of its addresses are a base plus
+// multiples of uniform strides.
+#include "kernels.h"
+#include "launch.h"
+#include "stencil.h"
+
+namespace dd4dvar {
+
+using namespace stencil;
+
+namespace {
+constexpr int kBoxThreads = 1024;
+constexpr int kBoxK = 11;                 // passes: boxes up to 11 R rows
+
+// padded-frame index of ring position k of a box
+__device__ __forceinline__ int frame_index(int k, int nx, int ny) {
+  const int nxp = nx + 2;
+  if (k < nx) return k + 1;                             // south row
+  if (k < 2 * nx) return (ny + 1) * nxp + (k - nx) + 1;  // north row
+  if (k < 2 * nx + ny) return (k - 2 * nx + 1) * nxp;    // west column
+  return (k - 2 * nx - ny + 1) * nxp + nx + 1;           // east column
+}
+
+// copy the internal (wrapped) frame positions from the box interior; state
+// copies carry the across-pole sign of u, v, adjoint copies are raw (the
+// adjoint gather applies the sign itself)
+__device__ __forceinline__ void fill_wraps(float* Ph, float* Pu, float* Pv, const int32_t* hsrc,
+                                           const int32_t* hoff, const int32_t* hsgn, int nring,
+                                           int nx, int ny, bool signed_copy) {
+  const int nxp = nx + 2;
+  for (int k = threadIdx.x; k < nring; k += kBoxThreads) {
+    if (hsrc[k] >= 0) continue;
+    const int p = frame_index(k, nx, ny);
+    const int o = hoff[k], sr = o / nx, sc = o - sr * nx;
+    const int q = (sr + 1) * nxp + sc + 1;
+    const float sg = signed_copy ? float(hsgn[k]) : 1.0f;
+    Ph[p] = Ph[q];
+    Pu[p] = sg * Pu[q];
+    Pv[p] = sg * Pv[q];
+  }
+}
+
+__device__ __forceinline__ void fill_rowtab(float* rowtab, const Dom<float>& D, const SubDev& S) {
+  for (int r = threadIdx.x; r < S.ny; r += kBoxThreads) {
+    const int j = S.row0 + r;
+    const RowCoef<float> rc = D.rows[j];
+    float* q = rowtab + 8 * r;
+    q[0] = rc.a1; q[1] = rc.a2; q[2] = rc.a3; q[3] = rc.cf; q[4] = rc.ct; q[5] = rc.c;
+    q[6] = D.cosx[j + 2];
+    q[7] = D.cosx[j];
+  }
+}
+
+__device__ __forceinline__ double block_sum_box(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kBoxThreads / 64; ++i) r += sh[i];
+  return r;
+}
+}  // namespace
+
+__global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const double* __restrict__ x,
+                                                         const int32_t* __restrict__ order) {
+  extern __shared__ float lds[];
+  const int s = order[blockIdx.x];
+  if (D.active && !D.active[s]) return;
+  const SubDev S = D.subs[s];
+  const int nx = S.nx, ny = S.ny, nxp = nx + 2, npad = (ny + 2) * nxp;
+  const int ncell = S.ncell, nring = S.nring;
+  const int L = S.nlev - 1;
+  const int tid = threadIdx.x;
+  float* Ph = lds;
+  float* Pu = lds + npad;
+  float* Pv = lds + 2 * npad;
+  float* rowtab = lds + 3 * npad;          // [ny][8]: a1 a2 a3 cf ct c cN cS
+  const float h0 = D.h0, st = D.st, stg = D.stg;
+  const int64_t plane = ncell;
+  float* traj = D.traj + S.traj_off;
+  const float* ring = D.ring + S.ring_off;
+  const int32_t* hsrc = D.hsrc + S.hmap_off;
+  const int32_t* hoff = D.hoff + S.hmap_off;
+  const int32_t* hsgn = D.hsign + S.hmap_off;
+  const bool wraps = S.span != 0;
+  // this thread's column and first row
+  const int R = kBoxThreads / nx;
+  const int tr = tid / nx, tc = tid - tr * nx;
+  const bool lane_on = tr < R;
+  const int m0 = tr * nx + tc;                         // cell index, pass 0
+  const int p0 = (tr + 1) * nxp + tc + 1;              // padded index, pass 0
+  const int dm = R * nx, dp = R * nxp;                 // strides per pass
+
+  for (int r = tid; r < ny; r += kBoxThreads) {
+    const int j = S.row0 + r;
+    const RowCoef<float> rc = D.rows[j];
+    float* q = rowtab + 8 * r;
+    q[0] = rc.a1; q[1] = rc.a2; q[2] = rc.a3; q[3] = rc.cf; q[4] = rc.ct; q[5] = rc.c;
+    q[6] = D.cosx[j + 2];
+    q[7] = D.cosx[j];
+  }
+  // level 0 from the FP64 control
+  const double* xs = x + S.ctrl_off;
+#pragma unroll
+  for (int k = 0; k < kBoxK; ++k) {
+    const int r = tr + k * R;
+    if (lane_on && r < ny) {
+      const int m = m0 + k * dm, p = p0 + k * dp;
+      const float h = float(xs[m] - double(D.h0)), u = float(xs[plane + m]), v = float(xs[2 * plane + m]);
+      Ph[p] = h; Pu[p] = u; Pv[p] = v;
+      traj[m] = h; traj[plane + m] = u; traj[2 * plane + m] = v;
+    }
+  }
+  for (int k = tid; k < nring; k += kBoxThreads) {
+    if (hsrc[k] < 0) continue;
+    const int p = frame_index(k, nx, ny);
+    Ph[p] = ring[k]; Pu[p] = ring[nring + k]; Pv[p] = ring[2 * nring + k];
+  }
+  __syncthreads();
+  if (wraps) {
+    fill_wraps(Ph, Pu, Pv, hsrc, hoff, hsgn, nring, nx, ny, true);
+    __syncthreads();
+  }
+
+  for (int n = 0; n < L; ++n) {
+    // frozen ring of level n+1, fetched while this step computes
+    float rh = 0.f, ru = 0.f, rv = 0.f;
+    const bool ring_pos = tid < nring && hsrc[tid] >= 0;
+    if (ring_pos) {
+      const float* R1 = ring + int64_t(n + 1) * 3 * nring;
+      rh = R1[tid]; ru = R1[nring + tid]; rv = R1[2 * nring + tid];
+    }
+    float zn[3][kBoxK];
+    const float wgt = n == 0 ? 0.5f : 1.0f;
+    // opaque copies of the base offsets: the addresses derived from them are
+    // recomputed every step instead of being hoisted out of the time loop
+    // (11 passes x 15 neighbours of precomputed addresses spill)
+    int pb = p0, mb = m0;
+    asm volatile("" : "+v"(pb), "+v"(mb));
+    // base of the update: Z^{n-1}, stored by this thread two steps ago (it
+    // stays in the last-level cache), or Z^0 itself for the Euler start
+    const float* prev = traj + int64_t(n >= 1 ? n - 1 : 0) * 3 * plane;
+    // issue every read of the base first; the increments are added below
+#pragma unroll
+    for (int k = 0; k < kBoxK; ++k) {
+      const int r = tr + k * R;
+      if (lane_on && r < ny) {
+        const int m = mb + k * dm;
+        zn[0][k] = prev[m];
+        zn[1][k] = prev[plane + m];
+        zn[2][k] = prev[2 * plane + m];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kBoxK; ++k) {
+      const int r = tr + k * R;
+      if (lane_on && r < ny) {
+        const int p = pb + k * dp;
+        const float* q = rowtab + 8 * r;
+        const float a1 = q[0], a2 = q[1], a3 = q[2], cf = q[3], ct = q[4], cN = q[6], cS = q[7];
+        const float h = Ph[p], u = Pu[p], v = Pv[p];
+        const float hE = Ph[p + 1], uE = Pu[p + 1], vE = Pv[p + 1];
+        const float hW = Ph[p - 1], uW = Pu[p - 1], vW = Pv[p - 1];
+        const float hN = Ph[p + nxp], uN = Pu[p + nxp], vN = Pv[p + nxp];
+        const float hS = Ph[p - nxp], uS = Pu[p - nxp], vS = Pv[p - nxp];
+        const float cor = cf + ct * u;
+        const float U = -a1 * u * (uE - uW) - st * v * (uN - uS) - a2 * (hE - hW) + cor * v;
+        const float V = -a1 * u * (vE - vW) - st * v * (vN - vS) - stg * (hN - hS) - cor * u;
+        const float H = -a1 * (h0 * (uE - uW) + (hE * uE - hW * uW)) -
+                        a3 * (h0 * (vN * cN - vS * cS) + (hN * vN * cN - hS * vS * cS));
+        zn[0][k] += wgt * H;
+        zn[1][k] += wgt * U;
+        zn[2][k] += wgt * V;
+      }
+      // keep each pass's loads within its own iteration: hoisting them all
+      // ahead of the unrolled loop exhausts the register file
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();                                    // every read of level n done
+    float* out = traj + int64_t(n + 1) * 3 * plane;
+#pragma unroll
+    for (int k = 0; k < kBoxK; ++k) {
+      const int r = tr + k * R;
+      if (lane_on && r < ny) {
+        const int m = mb + k * dm, p = pb + k * dp;
+        Ph[p] = zn[0][k]; Pu[p] = zn[1][k]; Pv[p] = zn[2][k];
+        out[m] = zn[0][k]; out[plane + m] = zn[1][k]; out[2 * plane + m] = zn[2][k];
+      }
+    }
+    if (ring_pos) {
+      const int p = frame_index(tid, nx, ny);
+      Ph[p] = rh; Pu[p] = ru; Pv[p] = rv;
+    }
+    __syncthreads();
+    if (wraps) {
+      fill_wraps(Ph, Pu, Pv, hsrc, hoff, hsgn, nring, nx, ny, true);
+      __syncthreads();
+    }
+  }
+}
+
+// Persistent adjoint sweep: lambda^{n+1} of the box lives in LDS on the
+// padded grid (frozen ring entries of the frame stay zero: those increments
+// are not part of the local model; wrapped entries hold raw copies), Z^n and
+// the overlap targets are read from global memory, lambda^n goes to the
+// rolling slot n mod 3 (read back two levels later) and into LDS.  Gather
+// form and forcing exactly as in k_adj (sweep.hip).
+// MODE 0: cost forcing, gradient + J out; 1: caller forcing, adjoint out;
+// 2: cost forcing, adjoint out.
+template <int MODE>
+__global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const double* __restrict__ x,
+                                                         const double* __restrict__ xb,
+                                                         const double* __restrict__ forcing,
+                                                         double* __restrict__ out,
+                                                         const int32_t* __restrict__ order) {
+  extern __shared__ float lds[];
+  __shared__ double red[kBoxThreads / 64];
+  const int s = order[blockIdx.x];
+  if (D.active && !D.active[s]) return;
+  const SubDev S = D.subs[s];
+  const int nx = S.nx, ny = S.ny, nxp = nx + 2, npad = (ny + 2) * nxp;
+  const int ncell = S.ncell, nring = S.nring;
+  const int L = S.nlev - 1;
+  const int tid = threadIdx.x;
+  float* Lh = lds;
+  float* Lu = lds + npad;
+  float* Lv = lds + 2 * npad;
+  float* rowtab = lds + 3 * npad;
+  const int64_t plane = ncell;
+  const int32_t* hsrc = D.hsrc + S.hmap_off;
+  const int32_t* hoff = D.hoff + S.hmap_off;
+  const int32_t* hsgn = D.hsign + S.hmap_off;
+  const bool wraps = S.span != 0;
+  const float st = D.st, stg = D.stg;
+  float* A = D.adj + S.adj_off;
+  const int R = kBoxThreads / nx;
+  const int tr = tid / nx, tc = tid - tr * nx;
+  const bool lane_on = tr < R;
+  const int m0 = tr * nx + tc;
+  const int p0 = (tr + 1) * nxp + tc + 1;
+  const int dm = R * nx, dp = R * nxp;
+
+  fill_rowtab(rowtab, D, S);
+  for (int i = tid; i < 3 * npad; i += kBoxThreads) lds[i] = 0.0f;   // lambda^{L+1} = 0
+  __syncthreads();
+  double jloc = 0.0;
+
+  for (int n = L; n >= 0; --n) {
+    // opaque per-step copies: neighbour indices and addresses are recomputed
+    // each level rather than hoisted (and spilled) out of the level loop
+    int pb = p0, mb = m0, trb = tr, tcb = tc;
+    asm volatile("" : "+v"(pb), "+v"(mb), "+v"(trb), "+v"(tcb));
+    const float* Z = D.traj + S.traj_off + int64_t(n) * 3 * plane;
+    const float* Rg = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
+    const bool has2 = n + 2 <= L;
+    const float* L2 = A + int64_t((n + 2) % 3) * 3 * plane;
+    float* Bn = A + int64_t(n % 3) * 3 * plane;
+    const float* Tg = D.targ + S.traj_off + int64_t(n) * 3 * plane;
+    const int tcount = (MODE != 1) ? D.tcount[S.lev0 + n] : 0;
+    float ln[3][kBoxK];
+#pragma unroll
+    for (int k = 0; k < kBoxK; ++k) {
+      const int r = trb + k * R;
+      if (lane_on && r < ny) {
+        const int m = mb + k * dm, p = pb + k * dp;
+        const int c = tcb;
+        const NbrIdx q = nbr_index(S, r, c, D.half);
+        const float* rw = rowtab + 8 * r;
+        const float a1 = rw[0], a2 = rw[1], cf = rw[3], ct = rw[4], cc = rw[5];
+        const float a3n = rowtab[8 * (r + 1 < ny ? r + 1 : r) + 2];
+        const float a3s = rowtab[8 * (r > 0 ? r - 1 : r) + 2];
+        // loads: state of level n (global), targets, lambda^{n+2}, forcing
+        const V3<float> C = ld_box(Z, plane, m, 1.0f);
+        const V3<float> E = ld_nbr(Z, Rg, plane, nring, q.e, 1);
+        const V3<float> W = ld_nbr(Z, Rg, plane, nring, q.w, 1);
+        const V3<float> N = ld_nbr(Z, Rg, plane, nring, q.n, q.sn);
+        const V3<float> Sv = ld_nbr(Z, Rg, plane, nring, q.s, q.ss);
+        V3<float> l2 = ld_box(L2, plane, m, 1.0f);
+        if (!has2) l2 = V3<float>{0.f, 0.f, 0.f};
+        int K = 0;
+        V3<float> tg = {0.f, 0.f, 0.f};
+        double fh = 0, fu = 0, fv = 0;
+        if (MODE != 1) {
+          K = int(D.cover[S.cell_off + m]) * tcount - 1;
+          tg = ld_box(Tg, plane, K > 0 ? m : 0, 1.0f);
+        } else {
+          const double* Fz = forcing + S.traj_off + int64_t(n) * 3 * plane;
+          fh = Fz[m];
+          fu = Fz[plane + m];
+          fv = Fz[2 * plane + m];
+        }
+        // lambda^{n+1} from LDS (zero in frozen frame entries)
+        const V3<float> l0 = {Lh[p], Lu[p], Lv[p]};
+        const V3<float> kE = {Lh[p + 1], Lu[p + 1], Lv[p + 1]};
+        const V3<float> kW = {Lh[p - 1], Lu[p - 1], Lv[p - 1]};
+        const V3<float> kN = {Lh[p + nxp], Lu[p + nxp], Lv[p + nxp]};
+        const V3<float> kS = {Lh[p - nxp], Lu[p - nxp], Lv[p - nxp]};
+        const float hm = D.h0 + C.h;
+        float au = l0.u * (-a1 * (E.u - W.u) + ct * C.v) +
+                   l0.v * (-a1 * (E.v - W.v) - cf - 2.0f * ct * C.u);
+        float av = l0.u * (-st * (N.u - Sv.u) + cf + ct * C.u) + l0.v * (-st * (N.v - Sv.v));
+        float ah = 0.0f;
+        au += a1 * (kE.u * E.u + kE.h * hm) - a1 * (kW.u * W.u + kW.h * hm);
+        av += a1 * kE.v * E.u - a1 * kW.v * W.u;
+        ah += (a2 * kE.u + a1 * kE.h * C.u) - (a2 * kW.u + a1 * kW.h * C.u);
+        const float vkn = float(q.sn) * N.v, vks = float(q.ss) * Sv.v;
+        au += kN.u * st * vkn - kS.u * st * vks;
+        av += (kN.v * st * vkn + kN.h * a3n * hm * cc) - (kS.v * st * vks + kS.h * a3s * hm * cc);
+        ah += (float(q.sn) * kN.v * stg + kN.h * a3n * C.v * cc) -
+              (float(q.ss) * kS.v * stg + kS.h * a3s * C.v * cc);
+        if (n == 0) {
+          au = l0.u + 0.5f * au;
+          av = l0.v + 0.5f * av;
+          ah = l0.h + 0.5f * ah;
+        }
+        if (MODE != 1) {
+          const double eh = double(C.h) - double(tg.h);
+          const double eu = double(C.u) - double(tg.u);
+          const double ev = double(C.v) - double(tg.v);
+          const double mk = D.mu * double(K);
+          fh += mk * eh * D.isb2[0];
+          fu += mk * eu * D.isb2[1];
+          fv += mk * ev * D.isb2[2];
+          jloc += 0.5 * mk * (eh * eh * D.isb2[0] + eu * eu * D.isb2[1] + ev * ev * D.isb2[2]);
+        }
+        const double bh = fh + double(ah) + double(l2.h);
+        const double bu = fu + double(au) + double(l2.u);
+        const double bv = fv + double(av) + double(l2.v);
+        if (n > 0) {
+          ln[0][k] = float(bh);
+          ln[1][k] = float(bu);
+          ln[2][k] = float(bv);
+          Bn[m] = ln[0][k];
+          Bn[plane + m] = ln[1][k];
+          Bn[2 * plane + m] = ln[2][k];
+        } else {
+          const int64_t o = S.ctrl_off + m;
+          if (MODE == 0) {
+            const double wb = D.weight_mode ? 1.0 : 1.0 / double(D.cover[S.cell_off + m]);
+            const double dh = x[o] - xb[o];
+            const double du = x[o + plane] - xb[o + plane];
+            const double dv = x[o + 2 * plane] - xb[o + 2 * plane];
+            out[o] = wb * dh * D.isb2[0] + bh;
+            out[o + plane] = wb * du * D.isb2[1] + bu;
+            out[o + 2 * plane] = wb * dv * D.isb2[2] + bv;
+            jloc += 0.5 * wb * (dh * dh * D.isb2[0] + du * du * D.isb2[1] + dv * dv * D.isb2[2]);
+          } else {
+            out[o] = bh;
+            out[o + plane] = bu;
+            out[o + 2 * plane] = bv;
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // observations of this box at level n
+    int mine = 0;
+    if (MODE != 1)
+      for (int t = tid; t < S.ntile; t += kBoxThreads) {
+        const int64_t key = int64_t(S.tile0 + t) * D.maxlev + n;
+        mine += D.obs_ptr[key + 1] - D.obs_ptr[key];
+      }
+    const bool any_obs = __syncthreads_or(mine > 0);   // also: all reads of lambda^{n+1} done
+    if (n > 0) {
+#pragma unroll
+      for (int k = 0; k < kBoxK; ++k) {
+        const int r = trb + k * R;
+        if (lane_on && r < ny) {
+          const int p = pb + k * dp;
+          Lh[p] = ln[0][k];
+          Lu[p] = ln[1][k];
+          Lv[p] = ln[2][k];
+        }
+      }
+    }
+    if (MODE != 1 && any_obs) {
+      __syncthreads();                                   // lambda^n (or the gradient) complete
+      for (int t = 0; t < S.ntile; ++t) {
+        const int64_t key = int64_t(S.tile0 + t) * D.maxlev + n;
+        const int o0 = D.obs_ptr[key], o1 = D.obs_ptr[key + 1];
+        for (int o = o0 + tid; o < o1; o += kBoxThreads) {
+          const int code = D.obs_code[o];
+          const int loc = code >> 2, f = code & 3;
+          const double rr = double(Z[f * plane + loc]) - D.obs_val[o];
+          const double qo = D.obs_q[o];
+          jloc += 0.5 * qo * rr * rr;
+          if (n > 0) {
+            const int lr = loc / nx, lc = loc - lr * nx;
+            float* Lf = lds + f * npad;
+            const float nv = float(double(Lf[(lr + 1) * nxp + lc + 1]) + qo * rr);
+            Lf[(lr + 1) * nxp + lc + 1] = nv;
+            Bn[f * plane + loc] = nv;
+          } else {
+            out[S.ctrl_off + f * plane + loc] += qo * rr;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (wraps && n > 0) {
+      fill_wraps(Lh, Lu, Lv, hsrc, hoff, hsgn, nring, nx, ny, false);
+      __syncthreads();
+    }
+  }
+  if (MODE != 1) {
+    // the box total goes to its first tile slot, the others are cleared, so
+    // the per-subdomain reduction of the step path applies unchanged
+    const double tot = block_sum_box(jloc, red);
+    for (int t = tid + 1; t < S.ntile; t += kBoxThreads) D.jpart[S.tile0 + t] = 0.0;
+    if (tid == 0) D.jpart[S.tile0] = tot;
+  }
+}
+
+size_t box_lds_bytes(int ny, int nx) {
+  return size_t(3 * (ny + 2) * (nx + 2) + 8 * ny) * sizeof(float);
+}
+
+// whether a box fits one workgroup of the persistent kernels
+bool box_fits(int ny, int nx, int nring) {
+  if (nx > kBoxThreads || nring > kBoxThreads) return false;
+  const int R = kBoxThreads / nx;
+  return (ny + R - 1) / R <= kBoxK;
+}
+
+hipError_t launch_fwd_box(const Dom<float>& D, const double* x, const int32_t* order, int nboxes,
+                          size_t lds_bytes, hipStream_t st) {
+  static bool configured = false;
+  if (!configured) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_box),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    configured = true;
+  }
+  hipLaunchKernelGGL(k_fwd_box, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, order);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_adj_box_mode(const Dom<float>& D, const double* x, const double* xb,
+                                      const double* forcing, double* out, const int32_t* order,
+                                      int nboxes, size_t lds_bytes, hipStream_t st) {
+  static bool configured = false;
+  if (!configured) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adj_box<MODE>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    if (e != hipSuccess) return e;
+    configured = true;
+  }
+  hipLaunchKernelGGL(k_adj_box<MODE>, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, xb,
+                     forcing, out, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_box(const Dom<float>& D, int mode, const double* x, const double* xb,
+                          const double* forcing, double* out, const int32_t* order, int nboxes,
+                          size_t lds_bytes, hipStream_t st) {
+  if (mode == 0) return launch_adj_box_mode<0>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+  if (mode == 1) return launch_adj_box_mode<1>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+  return launch_adj_box_mode<2>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+}
+
+}  // namespace dd4dvar

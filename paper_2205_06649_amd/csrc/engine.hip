@@ -19,6 +19,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -67,6 +68,10 @@ struct dd4dvar_ctx {
   int32_t* d_ids = nullptr;
   uint32_t* nonfinite = nullptr;
   const uint8_t* eval_mask = nullptr;   // subdomains evaluated by the sweeps (null = all)
+  bool box_ok = false;                  // persistent per-box sweeps possible
+  size_t box_lds = 0;
+  std::vector<int32_t> h_order;         // boxes, longest first
+  int32_t* d_order = nullptr;
   // the whole grid as one box (FP64), for background and global runs
   SubDev gsub{};
   int gtiles = 0;
@@ -206,7 +211,14 @@ void global_forward(dd4dvar_ctx* c, const double* x, double* traj, hipStream_t s
 template <typename T>
 void local_forward(dd4dvar_ctx* c, const double* x, hipStream_t st) {
   Dom<T> D = local_dom<T>(c);
-  if (c->exec_mode == 0) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (c->exec_mode == 2) {
+      chk(launch_fwd_box(D, x, c->d_order, c->nsub, c->box_lds, st), "persistent forward launch");
+      c->have_forward = true;
+      return;
+    }
+  }
+  if (c->exec_mode != 1) {
     launch_init<T>(D, x, 0, c->ntiles, st);
     for (int n = 0; n + 1 < c->maxlev; ++n) launch_fwd<T>(D, n, 0, c->ntiles, st);
   } else {
@@ -223,7 +235,14 @@ template <typename T>
 void local_adjoint(dd4dvar_ctx* c, int mode, const double* x, const double* forcing, double* out,
                    const std::vector<int32_t>* ids, hipStream_t st) {
   Dom<T> D = local_dom<T>(c);
-  if (!ids && c->exec_mode == 0) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (!ids && c->exec_mode == 2) {
+      chk(launch_adj_box(D, mode, x, c->xb, forcing, out, c->d_order, c->nsub, c->box_lds, st),
+          "persistent adjoint launch");
+      return;
+    }
+  }
+  if (!ids && c->exec_mode != 1) {
     for (int n = c->maxlev - 1; n >= 0; --n)
       launch_adj<T>(D, n, 0, c->ntiles, mode, x, c->xb, forcing, out, st);
   } else {
@@ -282,7 +301,9 @@ void cost_grad_impl(dd4dvar_ctx* c, const std::vector<int32_t>* ids, const doubl
   mark(c, 3, st);
   if (c->timing) {
     int nf = 0, na = 0;
-    if (!ids && c->exec_mode == 0) {
+    if (!ids && c->exec_mode == 2 && std::is_same<T, float>::value) {
+      nf = na = 1;                      // one persistent launch per sweep
+    } else if (!ids && c->exec_mode == 0) {
       nf = c->maxlev;
       na = c->maxlev;
     } else {
@@ -379,6 +400,25 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
   }
   c->ntiles = tile;
   c->ring_blocks = (maxring + 255) / 256;
+  // persistent per-box sweeps: FP32, every box within one workgroup's cells
+  // and LDS; boxes run longest first
+  {
+    size_t lds = 0;
+    bool ok = c->prec == DD4DVAR_FP32_STATE;
+    for (const SubDev& S : c->subs) {
+      lds = std::max(lds, box_lds_bytes(S.ny, S.nx));
+      if (!box_fits(S.ny, S.nx, S.nring)) ok = false;
+    }
+    if (lds > size_t(160 * 1024)) ok = false;
+    c->box_ok = ok;
+    c->box_lds = lds;
+    std::vector<int32_t> order(P.nsub);
+    for (int s = 0; s < P.nsub; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return int64_t(c->subs[a].ncell) * c->subs[a].nlev > int64_t(c->subs[b].ncell) * c->subs[b].nlev;
+    });
+    c->h_order = order;
+  }
   c->tiles.resize(tile);
   for (int s = 0; s < P.nsub; ++s)
     for (int t = 0; t < c->subs[s].ntile; ++t) c->tiles[c->subs[s].tile0 + t] = make_int2(s, t);
@@ -474,6 +514,7 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
   // uploads
   c->d_subs = upload(c, c->subs, st);
   c->d_tiles = upload(c, c->tiles, st);
+  c->d_order = upload(c, c->h_order, st);
   c->d_gsub = upload(c, std::vector<SubDev>{G}, st);
   c->d_gtiles = upload(c, gt, st);
   c->rows64 = upload(c, r64, st);
@@ -579,7 +620,10 @@ const char* dd4dvar_last_error(const dd4dvar_ctx* ctx) {
 }
 
 dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode) {
-  if (!ctx || (mode != 0 && mode != 1)) return fail(ctx, DD4DVAR_E_INVALID, "bad exec mode");
+  if (!ctx || mode < 0 || mode > 2) return fail(ctx, DD4DVAR_E_INVALID, "bad exec mode");
+  if (mode == 2 && !ctx->box_ok)
+    return fail(ctx, DD4DVAR_E_INVALID,
+                "persistent per-box sweeps need FP32 state and boxes that fit one workgroup's LDS");
   ctx->exec_mode = mode;
   return DD4DVAR_OK;
 }

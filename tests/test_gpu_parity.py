@@ -207,3 +207,34 @@ def test_adjoint_before_forward_is_state_error():
     with pytest.raises(L.DD4DVarError) as e:
         ctx.adjoint(None)
     assert e.value.status == L.DD4DVAR_E_STATE
+
+
+@pytest.mark.parametrize("which", ["tiny1", "c1", "small", "span", "mixed"])
+def test_persistent_box_sweeps_fp32(which):
+    """One workgroup per box, level held in LDS (execution mode 2): same
+    trajectories and local cost/gradient as the oracle, FP32 bars."""
+    from paper_2205_06649_amd import _lib as L
+    p, maps, bg, trajs, rings = _oracle_state(which)
+    ctx = _ctx(which, "fp32")
+    ctx.set_exec_mode(2)
+    xs = _perturbed(p, maps, trajs, seed=8)
+    g = model.Grid.of(p)
+    traj = ctx.unpack_traj(ctx.forward(ctx.pack_ctrl(xs)))
+    for b in maps.boxes:
+        geo = local.LocalGeometry(g, maps, b.sub)
+        ref = local.forward(geo, xs[b.sub], rings[b.sub])
+        assert _rel(_anom(traj[b.sub], p.h_ref), _anom(ref, p.h_ref)) <= TOL_TRAJ["fp32"], b.sub
+    J, grad = ctx.cost_grad(ctx.pack_ctrl(xs))
+    J = J.cpu().numpy()
+    grads = ctx.unpack_ctrl(grad)
+    for b in maps.boxes:
+        s = b.sub
+        Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], rings[s],
+                                 {k: trajs[k] for k in maps.neighbors[s]})
+        ej, eg = float(abs(J[s] - Jr) / abs(Jr)), float(_rel(grads[s], gr))
+        assert ej <= TOL["fp32"] and eg <= TOL_GRAD["fp32"], (s, ej, eg)
+    # FP64 contexts keep the step kernels
+    ctx64 = _ctx(which, "fp64")
+    with pytest.raises(L.DD4DVarError) as e:
+        ctx64.set_exec_mode(2)
+    assert e.value.status == L.DD4DVAR_E_INVALID
