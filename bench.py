@@ -56,15 +56,22 @@ def gpu_truth_forward(spec, x0, steps):
     return out
 
 
-def algorithmic_bytes(ctx, prec_bytes):
+def algorithmic_bytes(ctx, prec_bytes, persistent=False):
     """Compulsory HBM bytes of one evaluation, per sweep (no re-reads).
 
-    Forward launch at level n, per active cell: read Z^n and Z^{n-1}, write
-    Z^{n+1} (3 fields each) + frozen ring values of level n.  Adjoint launch at
-    level n, per cell: read Z^n, lambda^{n+1}, lambda^{n+2}, write lambda^n
-    (when they exist), the overlap target where covered, the coverage byte,
-    ring values, 20 B per observation entry; level 0 reads x, x_b (FP64) and
-    writes the FP64 gradient instead of lambda^0.
+    Step kernels (one launch per level): the forward launch at level n reads
+    Z^n and Z^{n-1} and writes Z^{n+1} (3 fields each) plus the frozen ring
+    values of level n; the adjoint launch at level n reads Z^n, lambda^{n+1},
+    lambda^{n+2} and writes lambda^n (where they exist), reads the overlap
+    target where covered, the coverage byte, the ring values and 20 B per
+    observation entry; level 0 reads x, x_b (FP64) and writes the FP64
+    gradient instead of lambda^0.
+
+    Persistent sweeps (one workgroup per box for the whole window): the
+    current level and the one before stay on chip, so the forward only writes
+    each level once (and reads x and the ring) and the adjoint only reads
+    each level once (plus targets, coverage, ring, observations and the
+    level-0 control, background and gradient).
     """
     from paper_2205_06649_amd import _lib as L
     b = prec_bytes
@@ -82,16 +89,55 @@ def algorithmic_bytes(ctx, prec_bytes):
         # forward: init + L steps
         fwd += ncell * (24 + 3 * b)
         for n in range(L_):
-            fwd += ncell * 3 * b * (3 if n >= 1 else 2) + nfrozen * 3 * b
+            nvec = 1 if persistent else (3 if n >= 1 else 2)
+            fwd += ncell * 3 * b * nvec + nfrozen * 3 * b
         # adjoint: levels L..0
         for n in range(L_, -1, -1):
-            nvec = 1 + (n + 1 <= L_) + (n + 2 <= L_) + (n > 0)
+            if persistent:
+                nvec = 1
+            else:
+                nvec = 1 + (n + 1 <= L_) + (n + 2 <= L_) + (n > 0)
             covered = int(np.count_nonzero(cover * tcount[lev0 + n] - 1 > 0))
             adj += ncell * (nvec * 3 * b + 1) + covered * 3 * b + nfrozen * 3 * b
             if n == 0:
                 adj += ncell * 72
         adj += nobs * 20
     return fwd, adj, pts
+
+
+SOLVE_OPTS = dict(max_outer=2, max_iter=40, grad_rtol=1e-6, outer_tol=0.0)
+
+
+def solve_leg(prob, mode):
+    """DD solve (Alg. 1) with FP32 state sweeps against the same solve in
+    FP64: wall time, evaluations and the FP32 analysis error relative to the
+    FP64 analysis (per field, relative to its spread; maximum over fields)."""
+    import torch
+    from paper_2205_06649_amd.context import Context
+    out = {"options": dict(SOLVE_OPTS)}
+    xa = {}
+    for prec in ("fp64", "fp32"):
+        ctx = Context(prob, prec)
+        if prec == "fp32":
+            ctx.set_exec_mode(mode)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        a, rep, st, _ = ctx.solve(**SOLVE_OPTS)
+        sec = time.perf_counter() - t
+        xa[prec] = a
+        out[prec] = {"seconds": sec, "evaluations": int(rep.total_evals),
+                     "lbfgs_iters": int(rep.lbfgs_iters), "J_final": float(rep.J_final),
+                     "gnorm_ratio_max": float(rep.gnorm_ratio_max)}
+        log(f"{prec} solve: {sec:.2f} s, {rep.total_evals} evaluations")
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    ref = xa["fp64"]
+    out["fp32_analysis_rel_err"] = float(max(
+        np.linalg.norm(xa["fp32"][f] - ref[f]) / np.linalg.norm(ref[f] - ref[f].mean())
+        for f in range(3)))
+    out["speedup_fp32_vs_fp64"] = out["fp64"]["seconds"] / out["fp32"]["seconds"]
+    return out
 
 
 def time_evals(ctx, x, steps, warmup):
@@ -166,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the FP32-vs-FP64 DD solve (analysis error) leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -195,7 +243,7 @@ def main():
     x = xb + 0.3 * scale * torch.randn(ctx.ctrl_len, generator=gen, dtype=torch.float64, device="cuda")
 
     # step kernels over all boxes per launch (mode 0), then the persistent
-    # per-box forward (mode 2) when every box fits a workgroup: the faster
+    # per-box sweeps (mode 2) when every box fits a workgroup: the faster
     # one is the headline
     ms_step, J32, g32 = time_evals(ctx, x, args.steps, args.warmup)
     log(f"fp32 batched step kernels: {ms_step:.3f} ms/eval")
@@ -204,14 +252,15 @@ def main():
     try:
         ctx.set_exec_mode(2)
         ms_box, J32b, g32b = time_evals(ctx, x, args.steps, args.warmup)
-        log(f"fp32 persistent per-box forward: {ms_box:.3f} ms/eval")
+        log(f"fp32 persistent per-box sweeps: {ms_box:.3f} ms/eval")
         if ms_box < ms_step:
             mode, ms, J32, g32 = 2, ms_box, J32b, g32b
     except Exception as e:  # boxes too large for one workgroup
         log(f"persistent mode unavailable: {e}")
         ms_box = None
     ctx.set_exec_mode(mode)
-    fwd_b, adj_b, pts = algorithmic_bytes(ctx, 4)
+    fwd_b, adj_b, pts = algorithmic_bytes(ctx, 4, persistent=(mode == 2))
+    fwd_s, adj_s, _ = algorithmic_bytes(ctx, 4) if mode == 2 else (fwd_b, adj_b, pts)
     ctx.set_timing(True)
     for _ in range(3):
         ctx.cost_grad(x, J32, g32)
@@ -257,23 +306,31 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_adj (adjoint step, all subdomains per launch)",
+            "kernel": {0: "k_adj (adjoint step, all subdomains per launch)",
+                       2: "k_adj_box (persistent adjoint sweep, one workgroup per box)"}[mode],
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
             "algorithmic_bytes_per_launch": adj_b / tm["adj_launches"] * calls,
+            "bytes_model": {0: "step kernels: Z^n, lambda^{n+1}, lambda^{n+2} read, "
+                               "lambda^n written per level",
+                            2: "persistent: Z^n read once per level, adjoint "
+                               "vectors on chip"}[mode],
             "avg_launch_ms": adj_launch_ms,
         },
         "phases_ms": {"forward_sweep": fwd_ms, "adjoint_sweep": adj_ms,
                       "reduce": tm["reduce_ms"] / calls},
         "exec_mode": {0: "step kernels, all boxes per launch",
-                      2: "persistent per-box forward (level in LDS) + step-kernel adjoint"}[mode],
+                      2: "persistent per-box forward and adjoint sweeps (level in LDS)"}[mode],
         "step_kernels_ms": ms_step,
-        "persistent_forward_ms": ms_box,
+        "persistent_ms": ms_box,
         "forward_sweep_GBs": fwd_b / (fwd_ms * 1e-3) / 1e9,
         "whole_eval_algorithmic_GBs": (fwd_b + adj_b) / (ms * 1e-3) / 1e9,
+        # the same evaluation priced with the step-kernel byte model (every
+        # level's adjoint vectors through HBM), for comparison across modes
+        "whole_eval_step_model_GBs": (fwd_s + adj_s) / (ms * 1e-3) / 1e9,
         "global_point_steps_per_s": prob.nlat * prob.nlon * prob.nsteps / (ms * 1e-3),
     }
 
@@ -298,6 +355,9 @@ def main():
             "grad_norm": float(np.linalg.norm(g32h - g64h) / np.linalg.norm(g64h)),
         }
         log(f"fp64 batched {ms64:.2f} ms, plain {ms_plain:.1f} ms")
+
+    if not args.no_solve:
+        result["solve"] = solve_leg(prob, mode)
 
     if not args.no_cpu:
         log("timing the oracle on host cores")

@@ -216,8 +216,17 @@ dd4dvar_status dd4dvar_exchange(dd4dvar_ctx* ctx, const double* x_dev,
 dd4dvar_status dd4dvar_gather(dd4dvar_ctx* ctx, int32_t level, double* out_dev,
                               void* stream);
 
-/* Selects how local_cost_grad launches its kernels: 0 = all subdomains per
- * launch (default), 1 = one launch per subdomain per step (plain baseline). */
+/* Selects how local_cost_grad, forward_integrate (scope 1) and
+ * adjoint_integrate launch their kernels:
+ *   0 = one launch per time step over all subdomains (default);
+ *   1 = one launch per subdomain per step (the plain baseline);
+ *   2 = persistent sweeps, one workgroup per subdomain with the current level
+ *       held in LDS, one launch per sweep.  FP32 contexts only, and only when
+ *       every extended box fits a workgroup (at most 1024 columns x 11 passes
+ *       of rows and a padded level frame of at most 160 KB of LDS).
+ * Results of modes 0 and 1 are identical bit for bit; mode 2 differs from
+ * them by FP32 rounding order only.  E_INVALID for an unknown mode or for
+ * mode 2 where it does not apply. */
 dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode);
 
 /* Phase timing of local_cost_grad, for measurement: when on, every call
@@ -238,6 +247,12 @@ typedef struct {
   double grad_rtol;     /* stop a local solve at |g| <= grad_rtol |g0| */
   double outer_tol;     /* stop when max_s |xi_s - xi_s_prev|_inf < outer_tol */
   double armijo_c1;     /* 1e-4 */
+  double j_noise_rtol;  /* evaluation noise floor of J, relative (0 = off): a
+                           local solve stops when the decrease a step can
+                           still show, alpha |g^T d|, is at most
+                           j_noise_rtol |J| (FP32 state: J carries ~1e-7
+                           relative rounding noise, and backtracking below it
+                           only burns evaluations) */
 } dd4dvar_solve_opts;
 
 typedef struct {

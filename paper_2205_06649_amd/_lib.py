@@ -54,7 +54,7 @@ class dd4dvar_data_desc(C.Structure):
 class dd4dvar_solve_opts(C.Structure):
     _fields_ = [("lbfgs_m", C.c_int32), ("max_iter", C.c_int32), ("max_outer", C.c_int32),
                 ("max_ls", C.c_int32), ("grad_rtol", C.c_double), ("outer_tol", C.c_double),
-                ("armijo_c1", C.c_double)]
+                ("armijo_c1", C.c_double), ("j_noise_rtol", C.c_double)]
 
 
 class dd4dvar_solve_report(C.Structure):

@@ -35,6 +35,9 @@ class Context:
         self.plan = L.dd4dvar_ctx_plan(self.handle)
         self.nsub, self.ctrl_len, self.traj_len = L.dd4dvar_plan_sizes(self.plan)
         self.info = [L.dd4dvar_plan_subdomain_info(self.plan, s) for s in range(self.nsub)]
+        # bumped by every call that integrates the local models and so
+        # replaces the stored trajectories the adjoint linearizes around
+        self.traj_generation = 0
 
     # -- plumbing -----------------------------------------------------------
     def _stream(self):
@@ -81,11 +84,13 @@ class Context:
             grad = self.torch.zeros(self.ctrl_len, dtype=self.torch.float64, device=self.device)
         L.dd4dvar_local_cost_grad(self.handle, x.data_ptr(), J.data_ptr(), grad.data_ptr(),
                                   self._stream(), sub_ids=sub_ids)
+        self.traj_generation += 1
         return J, grad
 
     def forward(self, x, with_traj=True):
         traj = self.empty(self.traj_len) if with_traj else None
         L.dd4dvar_forward_integrate(self.handle, 1, x.data_ptr(), self.ptr(traj), self._stream())
+        self.traj_generation += 1
         return traj
 
     def forward_global(self, x0):
@@ -102,6 +107,7 @@ class Context:
 
     def exchange(self, x):
         L.dd4dvar_exchange(self.handle, x.data_ptr(), self._stream())
+        self.traj_generation += 1
 
     def gather(self, level):
         p = self.prob
@@ -109,15 +115,23 @@ class Context:
         L.dd4dvar_gather(self.handle, level, out.data_ptr(), self._stream())
         return out.view(3, p.nlat, p.nlon)
 
+    # noise floor of J used by default: FP32 state sweeps leave ~1e-7
+    # relative rounding noise in J; FP64 runs the plain Armijo search
+    J_NOISE_RTOL = {"fp64": 0.0, "fp32": 1e-6}
+
     def solve(self, lbfgs_m=8, max_iter=50, max_outer=5, max_ls=30, grad_rtol=0.0,
-              outer_tol=1e-6, armijo_c1=1e-4, x_init=None, want_controls=False):
+              outer_tol=1e-6, armijo_c1=1e-4, x_init=None, want_controls=False,
+              j_noise_rtol=None):
         p = self.prob
+        if j_noise_rtol is None:
+            j_noise_rtol = self.J_NOISE_RTOL[self.precision]
         opts = L.dd4dvar_solve_opts(lbfgs_m=lbfgs_m, max_iter=max_iter, max_outer=max_outer,
                                     max_ls=max_ls, grad_rtol=grad_rtol, outer_tol=outer_tol,
-                                    armijo_c1=armijo_c1)
+                                    armijo_c1=armijo_c1, j_noise_rtol=j_noise_rtol)
         xa = np.empty((3, p.nlat, p.nlon))
         xo = self.empty(self.ctrl_len) if want_controls else None
         st, rep = L.dd4dvar_solve(self.handle, opts, self.ptr(x_init), self.ptr(xo), xa)
+        self.traj_generation += 1
         return xa, rep, st, xo
 
     # -- layout helpers (host side) -----------------------------------------

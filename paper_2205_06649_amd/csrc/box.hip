@@ -1,7 +1,8 @@
 // Persistent per-box sweeps (FP32 state): one workgroup owns one box for its
-// whole time interval and keeps the current level in LDS, so that a forward
-// step touches HBM only to store the trajectory, to read the frozen halo ring
-// and to read back the level before (which stays in the last-level cache).
+// whole time interval and keeps the current level in LDS and the level
+// before it in registers, so that a forward step touches HBM only to store
+// the trajectory and to read the frozen halo ring, and an adjoint step only
+// to read the stored state, the overlap targets and the ring.
 // Same arithmetic as the step kernels of sweep.hip (restricted model,
 // eq. restricted; discrete U, V, H of Sec. 7; leapfrog with a forward-Euler
 // half step).
@@ -139,6 +140,13 @@ __global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const dou
     __syncthreads();
   }
 
+  // zr holds this thread's cells of Z^{n-1} on entry to step n >= 1 (the
+  // level before the one in LDS), so the base of the leapfrog update never
+  // comes back from memory; the new level replaces it in place and is then
+  // swapped with the LDS copy.
+  float zr[3][kBoxK];
+#pragma unroll
+  for (int k = 0; k < kBoxK; ++k) zr[0][k] = zr[1][k] = zr[2][k] = 0.0f;
   for (int n = 0; n < L; ++n) {
     // frozen ring of level n+1, fetched while this step computes
     float rh = 0.f, ru = 0.f, rv = 0.f;
@@ -147,32 +155,18 @@ __global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const dou
       const float* R1 = ring + int64_t(n + 1) * 3 * nring;
       rh = R1[tid]; ru = R1[nring + tid]; rv = R1[2 * nring + tid];
     }
-    float zn[3][kBoxK];
-    const float wgt = n == 0 ? 0.5f : 1.0f;
+    const bool euler = n == 0;
     // opaque copies of the base offsets: the addresses derived from them are
     // recomputed every step instead of being hoisted out of the time loop
     // (11 passes x 15 neighbours of precomputed addresses spill)
     int pb = p0, mb = m0;
     asm volatile("" : "+v"(pb), "+v"(mb));
-    // base of the update: Z^{n-1}, stored by this thread two steps ago (it
-    // stays in the last-level cache), or Z^0 itself for the Euler start
-    const float* prev = traj + int64_t(n >= 1 ? n - 1 : 0) * 3 * plane;
-    // issue every read of the base first; the increments are added below
+    float* out = traj + int64_t(n + 1) * 3 * plane;
 #pragma unroll
     for (int k = 0; k < kBoxK; ++k) {
       const int r = tr + k * R;
       if (lane_on && r < ny) {
-        const int m = mb + k * dm;
-        zn[0][k] = prev[m];
-        zn[1][k] = prev[plane + m];
-        zn[2][k] = prev[2 * plane + m];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kBoxK; ++k) {
-      const int r = tr + k * R;
-      if (lane_on && r < ny) {
-        const int p = pb + k * dp;
+        const int p = pb + k * dp, m = mb + k * dm;
         const float* q = rowtab + 8 * r;
         const float a1 = q[0], a2 = q[1], a3 = q[2], cf = q[3], ct = q[4], cN = q[6], cS = q[7];
         const float h = Ph[p], u = Pu[p], v = Pv[p];
@@ -185,23 +179,32 @@ __global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const dou
         const float V = -a1 * u * (vE - vW) - st * v * (vN - vS) - stg * (hN - hS) - cor * u;
         const float H = -a1 * (h0 * (uE - uW) + (hE * uE - hW * uW)) -
                         a3 * (h0 * (vN * cN - vS * cS) + (hN * vN * cN - hS * vS * cS));
-        zn[0][k] += wgt * H;
-        zn[1][k] += wgt * U;
-        zn[2][k] += wgt * V;
+        // Z^1 = Z^0 + F(Z^0)/2 (Euler start), else Z^{n+1} = Z^{n-1} + F(Z^n)
+        if (euler) {
+          zr[0][k] = h + 0.5f * H;
+          zr[1][k] = u + 0.5f * U;
+          zr[2][k] = v + 0.5f * V;
+        } else {
+          zr[0][k] += H;
+          zr[1][k] += U;
+          zr[2][k] += V;
+        }
+        out[m] = zr[0][k]; out[plane + m] = zr[1][k]; out[2 * plane + m] = zr[2][k];
       }
       // keep each pass's loads within its own iteration: hoisting them all
       // ahead of the unrolled loop exhausts the register file
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();                                    // every read of level n done
-    float* out = traj + int64_t(n + 1) * 3 * plane;
+    // level n+1 into LDS; level n into the registers (base of the next step)
 #pragma unroll
     for (int k = 0; k < kBoxK; ++k) {
       const int r = tr + k * R;
       if (lane_on && r < ny) {
-        const int m = mb + k * dm, p = pb + k * dp;
-        Ph[p] = zn[0][k]; Pu[p] = zn[1][k]; Pv[p] = zn[2][k];
-        out[m] = zn[0][k]; out[plane + m] = zn[1][k]; out[2 * plane + m] = zn[2][k];
+        const int p = pb + k * dp;
+        const float th = Ph[p], tu = Pu[p], tv = Pv[p];
+        Ph[p] = zr[0][k]; Pu[p] = zr[1][k]; Pv[p] = zr[2][k];
+        zr[0][k] = th; zr[1][k] = tu; zr[2][k] = tv;
       }
     }
     if (ring_pos) {
@@ -218,10 +221,11 @@ __global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const dou
 
 // Persistent adjoint sweep: lambda^{n+1} of the box lives in LDS on the
 // padded grid (frozen ring entries of the frame stay zero: those increments
-// are not part of the local model; wrapped entries hold raw copies), Z^n and
-// the overlap targets are read from global memory, lambda^n goes to the
-// rolling slot n mod 3 (read back two levels later) and into LDS.  Gather
-// form and forcing exactly as in k_adj (sweep.hip).
+// are not part of the local model; wrapped entries hold raw copies), and
+// each thread keeps its own cells of lambda^{n+2} in registers, where
+// lambda^n replaces it; after the level the register and LDS copies are
+// swapped.  Only Z^n, the overlap targets and the ring come from global
+// memory.  Gather form and forcing exactly as in k_adj (sweep.hip).
 // MODE 0: cost forcing, gradient + J out; 1: caller forcing, adjoint out;
 // 2: cost forcing, adjoint out.
 template <int MODE>
@@ -249,7 +253,8 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
   const int32_t* hsgn = D.hsign + S.hmap_off;
   const bool wraps = S.span != 0;
   const float st = D.st, stg = D.stg;
-  float* A = D.adj + S.adj_off;
+  const float mu_f = float(D.mu);
+  const float ib_h = float(D.isb2[0]), ib_u = float(D.isb2[1]), ib_v = float(D.isb2[2]);
   const int R = kBoxThreads / nx;
   const int tr = tid / nx, tc = tid - tr * nx;
   const bool lane_on = tr < R;
@@ -261,6 +266,10 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
   for (int i = tid; i < 3 * npad; i += kBoxThreads) lds[i] = 0.0f;   // lambda^{L+1} = 0
   __syncthreads();
   double jloc = 0.0;
+  // this thread's cells of lambda^{n+2} (zero above the window)
+  float ln[3][kBoxK];
+#pragma unroll
+  for (int k = 0; k < kBoxK; ++k) ln[0][k] = ln[1][k] = ln[2][k] = 0.0f;
 
   for (int n = L; n >= 0; --n) {
     // opaque per-step copies: neighbour indices and addresses are recomputed
@@ -269,12 +278,8 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
     asm volatile("" : "+v"(pb), "+v"(mb), "+v"(trb), "+v"(tcb));
     const float* Z = D.traj + S.traj_off + int64_t(n) * 3 * plane;
     const float* Rg = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
-    const bool has2 = n + 2 <= L;
-    const float* L2 = A + int64_t((n + 2) % 3) * 3 * plane;
-    float* Bn = A + int64_t(n % 3) * 3 * plane;
     const float* Tg = D.targ + S.traj_off + int64_t(n) * 3 * plane;
     const int tcount = (MODE != 1) ? D.tcount[S.lev0 + n] : 0;
-    float ln[3][kBoxK];
 #pragma unroll
     for (int k = 0; k < kBoxK; ++k) {
       const int r = trb + k * R;
@@ -286,25 +291,24 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
         const float a1 = rw[0], a2 = rw[1], cf = rw[3], ct = rw[4], cc = rw[5];
         const float a3n = rowtab[8 * (r + 1 < ny ? r + 1 : r) + 2];
         const float a3s = rowtab[8 * (r > 0 ? r - 1 : r) + 2];
-        // loads: state of level n (global), targets, lambda^{n+2}, forcing
+        // loads: state of level n (global), targets, forcing
         const V3<float> C = ld_box(Z, plane, m, 1.0f);
         const V3<float> E = ld_nbr(Z, Rg, plane, nring, q.e, 1);
         const V3<float> W = ld_nbr(Z, Rg, plane, nring, q.w, 1);
         const V3<float> N = ld_nbr(Z, Rg, plane, nring, q.n, q.sn);
         const V3<float> Sv = ld_nbr(Z, Rg, plane, nring, q.s, q.ss);
-        V3<float> l2 = ld_box(L2, plane, m, 1.0f);
-        if (!has2) l2 = V3<float>{0.f, 0.f, 0.f};
+        const V3<float> l2 = {ln[0][k], ln[1][k], ln[2][k]};
         int K = 0;
         V3<float> tg = {0.f, 0.f, 0.f};
-        double fh = 0, fu = 0, fv = 0;
+        float fh = 0.f, fu = 0.f, fv = 0.f;
         if (MODE != 1) {
           K = int(D.cover[S.cell_off + m]) * tcount - 1;
           tg = ld_box(Tg, plane, K > 0 ? m : 0, 1.0f);
         } else {
           const double* Fz = forcing + S.traj_off + int64_t(n) * 3 * plane;
-          fh = Fz[m];
-          fu = Fz[plane + m];
-          fv = Fz[2 * plane + m];
+          fh = float(Fz[m]);
+          fu = float(Fz[plane + m]);
+          fv = float(Fz[2 * plane + m]);
         }
         // lambda^{n+1} from LDS (zero in frozen frame entries)
         const V3<float> l0 = {Lh[p], Lu[p], Lv[p]};
@@ -331,25 +335,23 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
           ah = l0.h + 0.5f * ah;
         }
         if (MODE != 1) {
-          const double eh = double(C.h) - double(tg.h);
-          const double eu = double(C.u) - double(tg.u);
-          const double ev = double(C.v) - double(tg.v);
-          const double mk = D.mu * double(K);
-          fh += mk * eh * D.isb2[0];
-          fu += mk * eu * D.isb2[1];
-          fv += mk * ev * D.isb2[2];
-          jloc += 0.5 * mk * (eh * eh * D.isb2[0] + eu * eu * D.isb2[1] + ev * ev * D.isb2[2]);
+          // overlap residual (the FP32 difference is the correctly rounded
+          // exact one), its forcing in FP32 like the adjoint state, and the
+          // cell's term of J accumulated in FP64
+          const float eh = C.h - tg.h, eu = C.u - tg.u, ev = C.v - tg.v;
+          const float mk = mu_f * float(K);
+          fh = mk * ib_h * eh;
+          fu = mk * ib_u * eu;
+          fv = mk * ib_v * ev;
+          jloc += 0.5 * double(mk) * double(ib_h * eh * eh + ib_u * eu * eu + ib_v * ev * ev);
         }
-        const double bh = fh + double(ah) + double(l2.h);
-        const double bu = fu + double(au) + double(l2.u);
-        const double bv = fv + double(av) + double(l2.v);
+        const float bh = fh + ah + l2.h;
+        const float bu = fu + au + l2.u;
+        const float bv = fv + av + l2.v;
         if (n > 0) {
-          ln[0][k] = float(bh);
-          ln[1][k] = float(bu);
-          ln[2][k] = float(bv);
-          Bn[m] = ln[0][k];
-          Bn[plane + m] = ln[1][k];
-          Bn[2 * plane + m] = ln[2][k];
+          ln[0][k] = bh;
+          ln[1][k] = bu;
+          ln[2][k] = bv;
         } else {
           const int64_t o = S.ctrl_off + m;
           if (MODE == 0) {
@@ -357,14 +359,14 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
             const double dh = x[o] - xb[o];
             const double du = x[o + plane] - xb[o + plane];
             const double dv = x[o + 2 * plane] - xb[o + 2 * plane];
-            out[o] = wb * dh * D.isb2[0] + bh;
-            out[o + plane] = wb * du * D.isb2[1] + bu;
-            out[o + 2 * plane] = wb * dv * D.isb2[2] + bv;
+            out[o] = wb * dh * D.isb2[0] + double(bh);
+            out[o + plane] = wb * du * D.isb2[1] + double(bu);
+            out[o + 2 * plane] = wb * dv * D.isb2[2] + double(bv);
             jloc += 0.5 * wb * (dh * dh * D.isb2[0] + du * du * D.isb2[1] + dv * dv * D.isb2[2]);
           } else {
-            out[o] = bh;
-            out[o + plane] = bu;
-            out[o + 2 * plane] = bv;
+            out[o] = double(bh);
+            out[o + plane] = double(bu);
+            out[o + 2 * plane] = double(bv);
           }
         }
       }
@@ -379,14 +381,20 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
       }
     const bool any_obs = __syncthreads_or(mine > 0);   // also: all reads of lambda^{n+1} done
     if (n > 0) {
+      // lambda^n into LDS; lambda^{n+1} into the registers (the lambda^{n+2}
+      // of the next level)
 #pragma unroll
       for (int k = 0; k < kBoxK; ++k) {
         const int r = trb + k * R;
         if (lane_on && r < ny) {
           const int p = pb + k * dp;
+          const float th = Lh[p], tu = Lu[p], tv = Lv[p];
           Lh[p] = ln[0][k];
           Lu[p] = ln[1][k];
           Lv[p] = ln[2][k];
+          ln[0][k] = th;
+          ln[1][k] = tu;
+          ln[2][k] = tv;
         }
       }
     }
@@ -404,9 +412,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
           if (n > 0) {
             const int lr = loc / nx, lc = loc - lr * nx;
             float* Lf = lds + f * npad;
-            const float nv = float(double(Lf[(lr + 1) * nxp + lc + 1]) + qo * rr);
-            Lf[(lr + 1) * nxp + lc + 1] = nv;
-            Bn[f * plane + loc] = nv;
+            Lf[(lr + 1) * nxp + lc + 1] = float(double(Lf[(lr + 1) * nxp + lc + 1]) + qo * rr);
           } else {
             out[S.ctrl_off + f * plane + loc] += qo * rr;
           }

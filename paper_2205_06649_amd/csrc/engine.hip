@@ -817,6 +817,7 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
   L.N = N;
   for (int f = 0; f < 3; ++f) L.sb[f] = c->plan.sigma_b[f];
   L.c1 = o->armijo_c1;
+  L.jnoise = o->j_noise_rtol;
   L.grad_rtol = o->grad_rtol;
   L.xb = c->xb;
   L.xi = B.get<double>(N);
@@ -941,7 +942,7 @@ dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* o, const d
                           double* x_out, double* xa_host, dd4dvar_solve_report* rep) {
   if (o->lbfgs_m < 1 || o->lbfgs_m > kMaxPairs || o->max_iter < 0 || o->max_outer < 1 ||
       o->max_ls < 1 || !(o->grad_rtol >= 0) || !(o->outer_tol >= 0) || !(o->armijo_c1 > 0) ||
-      !(o->armijo_c1 < 1)) {
+      !(o->armijo_c1 < 1) || !(o->j_noise_rtol >= 0) || !std::isfinite(o->j_noise_rtol)) {
     ctx->err = "bad solve options";
     return DD4DVAR_E_INVALID;
   }

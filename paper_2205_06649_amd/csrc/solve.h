@@ -15,7 +15,7 @@ struct LbState {
   int nsub, m, max_iter, max_ls;
   int64_t N;                // packed control length
   double sb[3];             // sigma_b per field
-  double c1, grad_rtol;
+  double c1, grad_rtol, jnoise;
   const double* xb;         // packed background controls
   // vectors (packed layout, FP64); S and Y hold m vectors each
   double *xi, *xi0, *g, *d, *xt, *xphys, *gradx, *S, *Y;

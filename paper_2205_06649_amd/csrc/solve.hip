@@ -8,7 +8,10 @@
 // Per subdomain: two-loop recursion with the m newest pairs and initial
 // scaling gamma = s^T y / y^T y of the newest pair (1 without pairs);
 // descent safeguard (steepest descent when g^T d >= 0); Armijo backtracking
-// from step 1, halving; a pair is kept when s^T y > 1e-12 |s| |y|.
+// from step 1, halving; a pair is kept when s^T y > 1e-12 |s| |y|.  With a
+// noise floor eps > 0, a local solve also stops when alpha |g^T d| <= eps |J|:
+// decreases that small are below the rounding noise of J and cannot be
+// resolved by the Armijo test.
 #include "kernels.h"
 #include "solve.h"
 
@@ -161,7 +164,10 @@ __global__ __launch_bounds__(kB) void k_lb_direction(LbState L) {
     L.gd[s] = gd;
     L.alpha[s] = 1.0;
     L.trials[s] = 0;
-    L.ls[s] = 1;
+    // a full step could not show a decrease above the noise floor of J
+    const bool flat = -gd <= L.jnoise * fabs(L.J[s]);
+    L.ls[s] = flat ? 0 : 1;
+    if (flat) L.status[s] = 1;
   }
 }
 
@@ -202,8 +208,9 @@ __global__ __launch_bounds__(kB) void k_lb_armijo(LbState L) {
     if (threadIdx.x == 0) {
       const int t = L.trials[s] + 1;
       L.trials[s] = t;
-      L.alpha[s] *= 0.5;
-      if (t >= L.max_ls) {
+      const double a = 0.5 * L.alpha[s];
+      L.alpha[s] = a;
+      if (t >= L.max_ls || a * fabs(L.gd[s]) <= L.jnoise * fabs(L.J[s])) {
         L.ls[s] = 0;
         L.status[s] = 2;              // line search failed: keep the iterate
       } else {

@@ -75,4 +75,7 @@ def test_solve_reports_and_options():
     with pytest.raises(L.DD4DVarError) as e:
         ctx.solve(lbfgs_m=0)
     assert e.value.status == L.DD4DVAR_E_INVALID
+    with pytest.raises(L.DD4DVarError) as e:
+        ctx.solve(j_noise_rtol=-1.0)
+    assert e.value.status == L.DD4DVAR_E_INVALID
     ctx.close()
