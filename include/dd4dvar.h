@@ -220,13 +220,20 @@ dd4dvar_status dd4dvar_gather(dd4dvar_ctx* ctx, int32_t level, double* out_dev,
  * adjoint_integrate launch their kernels:
  *   0 = one launch per time step over all subdomains (default);
  *   1 = one launch per subdomain per step (the plain baseline);
- *   2 = persistent sweeps, one workgroup per subdomain with the current level
- *       held in LDS, one launch per sweep.  FP32 contexts only, and only when
- *       every extended box fits a workgroup (at most 1024 columns x 11 passes
- *       of rows and a padded level frame of at most 160 KB of LDS).
- * Results of modes 0 and 1 are identical bit for bit; mode 2 differs from
- * them by FP32 rounding order only.  E_INVALID for an unknown mode or for
- * mode 2 where it does not apply. */
+ *   2 = persistent sweeps: one workgroup per subdomain holds the current
+ *       level in LDS and the level before it in registers, one launch per
+ *       sweep over all subdomains;
+ *   3 = as 2, but local_cost_grad over all subdomains is ONE launch in which
+ *       each workgroup runs its box's forward and then its adjoint sweep
+ *       (forward_integrate and adjoint_integrate as in 2).
+ * Modes 2 and 3 need an FP32 context whose extended boxes all fit one
+ * workgroup (at most 1024 columns, 11 passes of rows, and the padded level
+ * frame with per-row tables and ring staging within 159 KB of LDS).
+ * Results of modes 0 and 1 are identical bit for bit; modes 2 and 3 are
+ * identical to each other and differ from 0 and 1 by FP32 rounding only (the
+ * overlap forcing is formed in FP32 there).  E_INVALID for an unknown mode or
+ * for modes 2, 3 where they do not apply.  The sub_ids form of
+ * local_cost_grad always uses the step kernels. */
 dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode);
 
 /* Phase timing of local_cost_grad, for measurement: when on, every call

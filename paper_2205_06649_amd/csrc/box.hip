@@ -27,6 +27,8 @@ using namespace stencil;
 namespace {
 constexpr int kBoxThreads = 1024;
 constexpr int kBoxK = 11;                 // passes: boxes up to 11 R rows
+// dynamic LDS limit (160 KB per workgroup less the static reduction buffer)
+constexpr size_t kBoxLdsMax = 160 * 1024 - 1024;
 
 // padded-frame index of ring position k of a box
 __device__ __forceinline__ int frame_index(int k, int nx, int ny) {
@@ -67,6 +69,49 @@ __device__ __forceinline__ void fill_rowtab(float* rowtab, const Dom<float>& D, 
   }
 }
 
+// Raw buffer loads: a 32-bit byte offset per lane plus a wave-uniform one,
+// against a range-checked resource, so neighbour and field addresses cost no
+// 64-bit arithmetic.  Word 3 of the resource is the gfx9-family raw format.
+constexpr int kRsrcWord3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kRsrcWord3);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ V3<float> bload3(__amdgpu_buffer_rsrc_t r, int voff, int soff, int fstride) {
+  return {bload(r, voff, soff), bload(r, voff, soff + fstride), bload(r, voff, soff + 2 * fstride)};
+}
+
+// per-lane choice a (lanes set in mask) or b, as one v_cndmask: written out
+// so that the compiler cannot turn the choice into a branch around the load
+// of b, which would make it wait for the load of a first
+__device__ __forceinline__ float pick(float a, float b, uint64_t mask) {
+  float r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+  return r;
+}
+__device__ __forceinline__ V3<float> pick3(const V3<float>& a, const V3<float>& b, uint64_t mask) {
+  return {pick(a.h, b.h, mask), pick(a.u, b.u, mask), pick(a.v, b.v, mask)};
+}
+
+// value of ring position k of a box at one level: the frozen ring value, or
+// for a position that wraps inside the box the box's own cell (u, v with the
+// across-pole sign)
+__device__ __forceinline__ V3<float> ring_value(const Dom<float>& D, const SubDev& S, int k,
+                                                int level) {
+  const int nring = S.nring;
+  const int64_t plane = S.ncell;
+  if (D.hsrc[S.hmap_off + k] >= 0) {
+    const float* R = D.ring + S.ring_off + int64_t(level) * 3 * nring;
+    return {R[k], R[nring + k], R[2 * nring + k]};
+  }
+  const float* Z = D.traj + S.traj_off + int64_t(level) * 3 * plane;
+  const int o = D.hoff[S.hmap_off + k];
+  const float sg = float(D.hsign[S.hmap_off + k]);
+  return {Z[o], sg * Z[plane + o], sg * Z[2 * plane + o]};
+}
+
 __device__ __forceinline__ double block_sum_box(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -79,11 +124,9 @@ __device__ __forceinline__ double block_sum_box(double v, double* sh) {
 }
 }  // namespace
 
-__global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const double* __restrict__ x,
-                                                         const int32_t* __restrict__ order) {
-  extern __shared__ float lds[];
-  const int s = order[blockIdx.x];
-  if (D.active && !D.active[s]) return;
+// forward sweep of box s by the whole workgroup
+__device__ __forceinline__ void fwd_box_body(const Dom<float>& D, const double* __restrict__ x,
+                                             int s, float* lds) {
   const SubDev S = D.subs[s];
   const int nx = S.nx, ny = S.ny, nxp = nx + 2, npad = (ny + 2) * nxp;
   const int ncell = S.ncell, nring = S.nring;
@@ -225,19 +268,18 @@ __global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const dou
 // each thread keeps its own cells of lambda^{n+2} in registers, where
 // lambda^n replaces it; after the level the register and LDS copies are
 // swapped.  Only Z^n, the overlap targets and the ring come from global
-// memory.  Gather form and forcing exactly as in k_adj (sweep.hip).
+// memory: Z^n and the targets through buffer loads with clamped offsets, and
+// neighbours outside the box from a copy of the level's ring (frozen values
+// or wrapped cells, signs applied) staged in LDS one level ahead.  Gather
+// form and forcing as in k_adj (sweep.hip).
 // MODE 0: cost forcing, gradient + J out; 1: caller forcing, adjoint out;
 // 2: cost forcing, adjoint out.
 template <int MODE>
-__global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const double* __restrict__ x,
-                                                         const double* __restrict__ xb,
-                                                         const double* __restrict__ forcing,
-                                                         double* __restrict__ out,
-                                                         const int32_t* __restrict__ order) {
-  extern __shared__ float lds[];
-  __shared__ double red[kBoxThreads / 64];
-  const int s = order[blockIdx.x];
-  if (D.active && !D.active[s]) return;
+__device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* __restrict__ x,
+                                             const double* __restrict__ xb,
+                                             const double* __restrict__ forcing,
+                                             double* __restrict__ out, int s, float* lds,
+                                             double* red) {
   const SubDev S = D.subs[s];
   const int nx = S.nx, ny = S.ny, nxp = nx + 2, npad = (ny + 2) * nxp;
   const int ncell = S.ncell, nring = S.nring;
@@ -247,12 +289,17 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
   float* Lu = lds + npad;
   float* Lv = lds + 2 * npad;
   float* rowtab = lds + 3 * npad;
+  float* zring = rowtab + 8 * ny;          // [2 levels][3][nring]: state on the ring
+  uint8_t* covl = reinterpret_cast<uint8_t*>(zring + 6 * nring);   // [ny*nx] coverage
   const int64_t plane = ncell;
   const int32_t* hsrc = D.hsrc + S.hmap_off;
   const int32_t* hoff = D.hoff + S.hmap_off;
   const int32_t* hsgn = D.hsign + S.hmap_off;
   const bool wraps = S.span != 0;
   const float st = D.st, stg = D.stg;
+  const int fp = ncell * 4, nx4 = nx * 4, lvb = 3 * ncell * 4;   // byte strides
+  const __amdgpu_buffer_rsrc_t zrs = make_rsrc(D.traj + S.traj_off, S.nlev * lvb);
+  const __amdgpu_buffer_rsrc_t trs = make_rsrc(D.targ + S.traj_off, S.nlev * lvb);
   const float mu_f = float(D.mu);
   const float ib_h = float(D.isb2[0]), ib_u = float(D.isb2[1]), ib_v = float(D.isb2[2]);
   const int R = kBoxThreads / nx;
@@ -264,6 +311,14 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
 
   fill_rowtab(rowtab, D, S);
   for (int i = tid; i < 3 * npad; i += kBoxThreads) lds[i] = 0.0f;   // lambda^{L+1} = 0
+  for (int k = tid; k < nring; k += kBoxThreads) {
+    const V3<float> g = ring_value(D, S, k, L);
+    float* Zr = zring + (L & 1) * 3 * nring;
+    Zr[k] = g.h; Zr[nring + k] = g.u; Zr[2 * nring + k] = g.v;
+  }
+  // coverage counts (the same at every level), kept in LDS so that the
+  // target loads wait on an LDS read only
+  for (int i = tid; i < ncell; i += kBoxThreads) covl[i] = D.cover[S.cell_off + i];
   __syncthreads();
   double jloc = 0.0;
   // this thread's cells of lambda^{n+2} (zero above the window)
@@ -277,39 +332,63 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
     int pb = p0, mb = m0, trb = tr, tcb = tc;
     asm volatile("" : "+v"(pb), "+v"(mb), "+v"(trb), "+v"(tcb));
     const float* Z = D.traj + S.traj_off + int64_t(n) * 3 * plane;
-    const float* Rg = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
-    const float* Tg = D.targ + S.traj_off + int64_t(n) * 3 * plane;
+    const int so = n * lvb;                              // level n, field h
+    const float* Zr = zring + (n & 1) * 3 * nring;
     const int tcount = (MODE != 1) ? D.tcount[S.lev0 + n] : 0;
+    // ring of level n-1, fetched now and staged after this level's reads
+    V3<float> gnext = {0.f, 0.f, 0.f};
+    const bool ring_thread = tid < nring && n > 0;
+    if (ring_thread) gnext = ring_value(D, S, tid, n - 1);
 #pragma unroll
     for (int k = 0; k < kBoxK; ++k) {
       const int r = trb + k * R;
       if (lane_on && r < ny) {
         const int m = mb + k * dm, p = pb + k * dp;
         const int c = tcb;
-        const NbrIdx q = nbr_index(S, r, c, D.half);
+        const bool e_in = c + 1 < nx, w_in = c > 0, n_in = r + 1 < ny, s_in = r > 0;
         const float* rw = rowtab + 8 * r;
         const float a1 = rw[0], a2 = rw[1], cf = rw[3], ct = rw[4], cc = rw[5];
         const float a3n = rowtab[8 * (r + 1 < ny ? r + 1 : r) + 2];
         const float a3s = rowtab[8 * (r > 0 ? r - 1 : r) + 2];
-        // loads: state of level n (global), targets, forcing
-        const V3<float> C = ld_box(Z, plane, m, 1.0f);
-        const V3<float> E = ld_nbr(Z, Rg, plane, nring, q.e, 1);
-        const V3<float> W = ld_nbr(Z, Rg, plane, nring, q.w, 1);
-        const V3<float> N = ld_nbr(Z, Rg, plane, nring, q.n, q.sn);
-        const V3<float> Sv = ld_nbr(Z, Rg, plane, nring, q.s, q.ss);
-        const V3<float> l2 = {ln[0][k], ln[1][k], ln[2][k]};
+        const int v0 = m * 4;
+        // overlap targets (needed where covered) or the caller's forcing
         int K = 0;
         V3<float> tg = {0.f, 0.f, 0.f};
         float fh = 0.f, fu = 0.f, fv = 0.f;
         if (MODE != 1) {
-          K = int(D.cover[S.cell_off + m]) * tcount - 1;
-          tg = ld_box(Tg, plane, K > 0 ? m : 0, 1.0f);
+          K = int(covl[m]) * tcount - 1;
+          tg = bload3(trs, K > 0 ? v0 : 0, so, fp);
         } else {
           const double* Fz = forcing + S.traj_off + int64_t(n) * 3 * plane;
           fh = float(Fz[m]);
           fu = float(Fz[plane + m]);
           fv = float(Fz[2 * plane + m]);
         }
+        // state of level n: the cell and its neighbours inside the box
+        // (offsets clamped to the cell itself at the box edge) ...
+        const V3<float> C = bload3(zrs, v0, so, fp);
+        V3<float> E = bload3(zrs, e_in ? v0 + 4 : v0, so, fp);
+        V3<float> W = bload3(zrs, w_in ? v0 - 4 : v0, so, fp);
+        V3<float> N = bload3(zrs, n_in ? v0 + nx4 : v0, so, fp);
+        V3<float> Sv = bload3(zrs, s_in ? v0 - nx4 : v0, so, fp);
+        // ... and outside it, from the staged ring (every lane reads a valid
+        // position and keeps it only at the edge)
+        const int iE = e_in ? 0 : 2 * nx + ny + r, iW = w_in ? 0 : 2 * nx + r;
+        const int iN = n_in ? 0 : nx + c, iS = s_in ? 0 : c;
+        const V3<float> rE = {Zr[iE], Zr[nring + iE], Zr[2 * nring + iE]};
+        const V3<float> rW = {Zr[iW], Zr[nring + iW], Zr[2 * nring + iW]};
+        const V3<float> rN = {Zr[iN], Zr[nring + iN], Zr[2 * nring + iN]};
+        const V3<float> rS = {Zr[iS], Zr[nring + iS], Zr[2 * nring + iS]};
+        // every load of the cell is in flight before the first use
+        __builtin_amdgcn_sched_barrier(0);
+        E = pick3(E, rE, __builtin_amdgcn_ballot_w64(e_in));
+        W = pick3(W, rW, __builtin_amdgcn_ballot_w64(w_in));
+        N = pick3(N, rN, __builtin_amdgcn_ballot_w64(n_in));
+        Sv = pick3(Sv, rS, __builtin_amdgcn_ballot_w64(s_in));
+        // across a pole (boxes spanning the circle) the adjoint of a wrapped
+        // neighbour carries the sign of u, v
+        const int sn = (!n_in && S.pole_n) ? -1 : 1, ss = (!s_in && S.pole_s) ? -1 : 1;
+        const V3<float> l2 = {ln[0][k], ln[1][k], ln[2][k]};
         // lambda^{n+1} from LDS (zero in frozen frame entries)
         const V3<float> l0 = {Lh[p], Lu[p], Lv[p]};
         const V3<float> kE = {Lh[p + 1], Lu[p + 1], Lv[p + 1]};
@@ -324,11 +403,11 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
         au += a1 * (kE.u * E.u + kE.h * hm) - a1 * (kW.u * W.u + kW.h * hm);
         av += a1 * kE.v * E.u - a1 * kW.v * W.u;
         ah += (a2 * kE.u + a1 * kE.h * C.u) - (a2 * kW.u + a1 * kW.h * C.u);
-        const float vkn = float(q.sn) * N.v, vks = float(q.ss) * Sv.v;
+        const float vkn = float(sn) * N.v, vks = float(ss) * Sv.v;
         au += kN.u * st * vkn - kS.u * st * vks;
         av += (kN.v * st * vkn + kN.h * a3n * hm * cc) - (kS.v * st * vks + kS.h * a3s * hm * cc);
-        ah += (float(q.sn) * kN.v * stg + kN.h * a3n * C.v * cc) -
-              (float(q.ss) * kS.v * stg + kS.h * a3s * C.v * cc);
+        ah += (float(sn) * kN.v * stg + kN.h * a3n * C.v * cc) -
+              (float(ss) * kS.v * stg + kS.h * a3s * C.v * cc);
         if (n == 0) {
           au = l0.u + 0.5f * au;
           av = l0.v + 0.5f * av;
@@ -380,6 +459,10 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
         mine += D.obs_ptr[key + 1] - D.obs_ptr[key];
       }
     const bool any_obs = __syncthreads_or(mine > 0);   // also: all reads of lambda^{n+1} done
+    if (ring_thread) {
+      float* Zq = zring + ((n - 1) & 1) * 3 * nring;
+      Zq[tid] = gnext.h; Zq[nring + tid] = gnext.u; Zq[2 * nring + tid] = gnext.v;
+    }
     if (n > 0) {
       // lambda^n into LDS; lambda^{n+1} into the registers (the lambda^{n+2}
       // of the next level)
@@ -434,13 +517,59 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
   }
 }
 
-size_t box_lds_bytes(int ny, int nx) {
-  return size_t(3 * (ny + 2) * (nx + 2) + 8 * ny) * sizeof(float);
+__global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const double* __restrict__ x,
+                                                         const int32_t* __restrict__ order) {
+  extern __shared__ float lds[];
+  const int s = order[blockIdx.x];
+  if (D.active && !D.active[s]) return;
+  fwd_box_body(D, x, s, lds);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const double* __restrict__ x,
+                                                         const double* __restrict__ xb,
+                                                         const double* __restrict__ forcing,
+                                                         double* __restrict__ out,
+                                                         const int32_t* __restrict__ order) {
+  extern __shared__ float lds[];
+  __shared__ double red[kBoxThreads / 64];
+  const int s = order[blockIdx.x];
+  if (D.active && !D.active[s]) return;
+  adj_box_body<MODE>(D, x, xb, forcing, out, s, lds, red);
+}
+
+// one whole local cost/gradient evaluation of box s in one workgroup: the
+// forward sweep, then the adjoint sweep with the cost forcing (the levels the
+// adjoint reads first are the ones the forward wrote last, still in the
+// last-level cache)
+__global__ __launch_bounds__(kBoxThreads) void k_eval_box(Dom<float> D, const double* __restrict__ x,
+                                                          const double* __restrict__ xb,
+                                                          double* __restrict__ grad,
+                                                          const int32_t* __restrict__ order) {
+  extern __shared__ float lds[];
+  __shared__ double red[kBoxThreads / 64];
+  const int s = order[blockIdx.x];
+  if (D.active && !D.active[s]) return;
+  fwd_box_body(D, x, s, lds);
+  __syncthreads();
+  // an opaque copy of the box index: the adjoint recomputes its own indices
+  // instead of keeping the forward's alive (which would spill)
+  int sa = s;
+  asm volatile("" : "+s"(sa));
+  adj_box_body<0>(D, x, xb, nullptr, grad, sa, lds, red);
+}
+
+// dynamic LDS of the persistent kernels: padded level frame, per-row
+// coefficients, and (adjoint) the state on the ring for two levels and the
+// coverage byte of every cell
+size_t box_lds_bytes(int ny, int nx, int nring) {
+  return size_t(3 * (ny + 2) * (nx + 2) + 8 * ny + 6 * nring) * sizeof(float) + size_t(ny) * nx;
 }
 
 // whether a box fits one workgroup of the persistent kernels
 bool box_fits(int ny, int nx, int nring) {
   if (nx > kBoxThreads || nring > kBoxThreads) return false;
+  if (box_lds_bytes(ny, nx, nring) > kBoxLdsMax) return false;
   const int R = kBoxThreads / nx;
   return (ny + R - 1) / R <= kBoxK;
 }
@@ -450,7 +579,7 @@ hipError_t launch_fwd_box(const Dom<float>& D, const double* x, const int32_t* o
   static bool configured = false;
   if (!configured) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_box),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(kBoxLdsMax));
     if (e != hipSuccess) return e;
     configured = true;
   }
@@ -465,12 +594,26 @@ static hipError_t launch_adj_box_mode(const Dom<float>& D, const double* x, cons
   static bool configured = false;
   if (!configured) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adj_box<MODE>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(kBoxLdsMax));
     if (e != hipSuccess) return e;
     configured = true;
   }
   hipLaunchKernelGGL(k_adj_box<MODE>, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, xb,
                      forcing, out, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_box(const Dom<float>& D, const double* x, const double* xb, double* grad,
+                           const int32_t* order, int nboxes, size_t lds_bytes, hipStream_t st) {
+  static bool configured = false;
+  if (!configured) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval_box),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(kBoxLdsMax));
+    if (e != hipSuccess) return e;
+    configured = true;
+  }
+  hipLaunchKernelGGL(k_eval_box, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, xb, grad,
+                     order);
   return hipGetLastError();
 }
 

@@ -209,14 +209,16 @@ def test_adjoint_before_forward_is_state_error():
     assert e.value.status == L.DD4DVAR_E_STATE
 
 
+@pytest.mark.parametrize("mode", [2, 3])
 @pytest.mark.parametrize("which", ["tiny1", "c1", "small", "span", "mixed"])
-def test_persistent_box_sweeps_fp32(which):
-    """One workgroup per box, level held in LDS (execution mode 2): same
-    trajectories and local cost/gradient as the oracle, FP32 bars."""
+def test_persistent_box_sweeps_fp32(which, mode):
+    """One workgroup per box, level held in LDS (execution modes 2: one launch
+    per sweep, 3: forward and adjoint fused in one launch): same trajectories
+    and local cost/gradient as the oracle, FP32 bars."""
     from paper_2205_06649_amd import _lib as L
     p, maps, bg, trajs, rings = _oracle_state(which)
     ctx = _ctx(which, "fp32")
-    ctx.set_exec_mode(2)
+    ctx.set_exec_mode(mode)
     xs = _perturbed(p, maps, trajs, seed=8)
     g = model.Grid.of(p)
     traj = ctx.unpack_traj(ctx.forward(ctx.pack_ctrl(xs)))
@@ -233,8 +235,12 @@ def test_persistent_box_sweeps_fp32(which):
                                  {k: trajs[k] for k in maps.neighbors[s]})
         ej, eg = float(abs(J[s] - Jr) / abs(Jr)), float(_rel(grads[s], gr))
         assert ej <= TOL["fp32"] and eg <= TOL_GRAD["fp32"], (s, ej, eg)
+    # the fused and the separate launches run the same arithmetic
+    ctx.set_exec_mode(5 - mode)
+    J2, grad2 = ctx.cost_grad(ctx.pack_ctrl(xs))
+    assert np.array_equal(J2.cpu().numpy(), J) and np.array_equal(grad2.cpu().numpy(), grad.cpu().numpy())
     # FP64 contexts keep the step kernels
     ctx64 = _ctx(which, "fp64")
     with pytest.raises(L.DD4DVarError) as e:
-        ctx64.set_exec_mode(2)
+        ctx64.set_exec_mode(mode)
     assert e.value.status == L.DD4DVAR_E_INVALID
