@@ -70,6 +70,7 @@ struct dd4dvar_ctx {
   const uint8_t* eval_mask = nullptr;   // subdomains evaluated by the sweeps (null = all)
   bool box_ok = false;                  // persistent per-box sweeps possible
   size_t box_lds = 0;
+  int box_k = 0;                        // passes of 1024 cells of the largest box
   std::vector<int32_t> h_order;         // boxes, longest first
   int32_t* d_order = nullptr;
   // the whole grid as one box (FP64), for background and global runs
@@ -213,7 +214,8 @@ void local_forward(dd4dvar_ctx* c, const double* x, hipStream_t st) {
   Dom<T> D = local_dom<T>(c);
   if constexpr (std::is_same<T, float>::value) {
     if (c->exec_mode >= 2) {
-      chk(launch_fwd_box(D, x, c->d_order, c->nsub, c->box_lds, st), "persistent forward launch");
+      chk(launch_fwd_box(D, x, c->d_order, c->nsub, c->box_lds, c->box_k, st),
+          "persistent forward launch");
       c->have_forward = true;
       return;
     }
@@ -237,7 +239,8 @@ void local_adjoint(dd4dvar_ctx* c, int mode, const double* x, const double* forc
   Dom<T> D = local_dom<T>(c);
   if constexpr (std::is_same<T, float>::value) {
     if (!ids && c->exec_mode >= 2) {
-      chk(launch_adj_box(D, mode, x, c->xb, forcing, out, c->d_order, c->nsub, c->box_lds, st),
+      chk(launch_adj_box(D, mode, x, c->xb, forcing, out, c->d_order, c->nsub, c->box_lds, c->box_k,
+                         st),
           "persistent adjoint launch");
       return;
     }
@@ -277,7 +280,7 @@ void cost_grad_impl(dd4dvar_ctx* c, const std::vector<int32_t>* ids, const doubl
     if (!ids && c->exec_mode == 3) {
       // one fused persistent launch: each workgroup runs its box's forward
       // sweep and then its adjoint sweep
-      chk(launch_eval_box(D, x, c->xb, grad, c->d_order, c->nsub, c->box_lds, st),
+      chk(launch_eval_box(D, x, c->xb, grad, c->d_order, c->nsub, c->box_lds, c->box_k, st),
           "persistent evaluation launch");
       c->have_forward = true;
       mark(c, 1, st);
@@ -423,13 +426,17 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
   // and LDS; boxes run longest first
   {
     size_t lds = 0;
+    int kmax = 0;
     bool ok = c->prec == DD4DVAR_FP32_STATE;
     for (const SubDev& S : c->subs) {
-      lds = std::max(lds, box_lds_bytes(S.ny, S.nx, S.nring));
-      if (!box_fits(S.ny, S.nx, S.nring)) ok = false;
+      lds = std::max(lds, box_lds_bytes(S.ny, S.nx, S.nring, S.nlev));
+      const int k = box_passes(S.ny, S.nx, S.nring, S.nlev);
+      if (k == 0) ok = false;
+      kmax = std::max(kmax, k);
     }
     c->box_ok = ok;
     c->box_lds = lds;
+    c->box_k = kmax;
     std::vector<int32_t> order(P.nsub);
     for (int s = 0; s < P.nsub; ++s) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {

@@ -40,14 +40,15 @@ void launch_add_href(double* traj, int64_t nlev, int64_t plane, double h0, hipSt
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 
 // box.hip: persistent per-box sweeps (FP32 state)
-size_t box_lds_bytes(int ny, int nx, int nring);
-bool box_fits(int ny, int nx, int nring);
+size_t box_lds_bytes(int ny, int nx, int nring, int nlev);
+int box_passes(int ny, int nx, int nring, int nlev);
 hipError_t launch_fwd_box(const Dom<float>& D, const double* x, const int32_t* order, int nboxes,
-                          size_t lds_bytes, hipStream_t st);
-hipError_t launch_eval_box(const Dom<float>& D, const double* x, const double* xb, double* grad,
-                           const int32_t* order, int nboxes, size_t lds_bytes, hipStream_t st);
+                          size_t lds_bytes, int passes, hipStream_t st);
 hipError_t launch_adj_box(const Dom<float>& D, int mode, const double* x, const double* xb,
                           const double* forcing, double* out, const int32_t* order, int nboxes,
-                          size_t lds_bytes, hipStream_t st);
+                          size_t lds_bytes, int passes, hipStream_t st);
+hipError_t launch_eval_box(const Dom<float>& D, const double* x, const double* xb, double* grad,
+                           const int32_t* order, int nboxes, size_t lds_bytes, int passes,
+                           hipStream_t st);
 
 }  // namespace dd4dvar
