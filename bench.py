@@ -11,9 +11,14 @@ steps, 999,999 observations every 10 steps; FP32 state sweeps with FP64
 costs and gradients.  Inputs are seeded and synthetic (twin experiment); the
 truth run that produces the observation values runs on the GPU library.
 
-Prints one JSON line.  Extra fields: the plain per-subdomain FP64 path
-(one launch per subdomain per step) and the batched FP64 path, the FP32
-error against FP64, phase timings, and the oracle timed on host cores.
+The library's autotuner picks the execution plan (step kernels, or
+persistent per-box sweeps with one launch per sweep or fused), timing HIP
+graph replays; the timed steps are graph replays of that plan.
+
+Prints one JSON line.  Extra fields: the autotuner's candidates, the same
+plan launched eagerly, the plain per-subdomain FP64 path (one launch per
+subdomain per step) and the batched FP64 path, the FP32 error against FP64,
+phase timings, an FP32-vs-FP64 DD solve, and the oracle timed on host cores.
 """
 from __future__ import annotations
 
@@ -277,20 +282,20 @@ def main():
     # step kernels over all boxes per launch (mode 0), then the persistent
     # per-box sweeps (mode 2) when every box fits a workgroup: the faster
     # one is the headline
-    # every execution mode that applies; the fastest is the headline
-    times, outs = {}, {}
-    for md in (0, 2, 3):
-        try:
-            ctx.set_exec_mode(md)
-        except Exception as e:  # boxes too large for one workgroup
-            log(f"mode {md} unavailable: {e}")
-            continue
-        times[md], Jm, gm = time_evals(ctx, x, args.steps, args.warmup)
-        outs[md] = (Jm, gm)
-        log(f"fp32 mode {md} ({EXEC_MODES[md]}): {times[md]:.3f} ms/eval")
-    mode = min(times, key=times.get)
-    ms = times[mode]
-    J32, g32 = outs[mode]
+    # the library's autotuner times every execution plan that applies (HIP
+    # graph replays) and keeps the fastest; the headline times K replays of
+    # that plan, and the same plan launched eagerly is reported beside it
+    ctx.set_graph(True)
+    tune = ctx.autotune(x, reps=3)
+    for i, c in enumerate(tune["candidates"]):
+        log(f"autotune: mode {c['mode']} ({EXEC_MODES[c['mode']]}), passes {c['passes']}: "
+            f"{c['ms']:.3f} ms/eval{'  <- chosen' if i == tune['chosen'] else ''}")
+    mode = tune["candidates"][tune["chosen"]]["mode"]
+    ms, J32, g32 = time_evals(ctx, x, args.steps, args.warmup)
+    log(f"fp32 graph replays, mode {mode}: {ms:.3f} ms/eval")
+    ctx.set_graph(False)
+    ms_eager, _, _ = time_evals(ctx, x, args.steps, args.warmup)
+    log(f"fp32 eager launches, mode {mode}: {ms_eager:.3f} ms/eval")
     fwd_b, adj_b, pts = algorithmic_bytes(ctx, 4, persistent=(mode >= 2))
     fwd_s, adj_s, _ = algorithmic_bytes(ctx, 4)
 
@@ -372,7 +377,9 @@ def main():
         "phases_ms": {"forward_sweep": fwd_ms, "adjoint_sweep": adj_ms,
                       "reduce": tm["reduce_ms"] / calls},
         "exec_mode": EXEC_MODES[mode],
-        "ms_per_mode": {str(k): v for k, v in times.items()},
+        "autotune": tune,
+        "timed": "HIP graph replays of the chosen plan",
+        "eager_ms_per_step": ms_eager,
         "forward_sweep_GBs": fwd_b / (fwd_ms * 1e-3) / 1e9,
         "whole_eval_algorithmic_GBs": (fwd_b + adj_b) / (ms * 1e-3) / 1e9,
         # the same evaluation priced with the step-kernel byte model (every

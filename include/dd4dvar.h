@@ -236,6 +236,35 @@ dd4dvar_status dd4dvar_gather(dd4dvar_ctx* ctx, int32_t level, double* out_dev,
  * local_cost_grad always uses the step kernels. */
 dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode);
 
+/* Graph mode (on != 0): local_cost_grad over all subdomains (sub_ids NULL)
+ * records its launches into a HIP graph the first time it meets a given
+ * (x_dev, J_dev, grad_dev, execution plan) and replays that graph afterwards
+ * (up to 8 graphs are kept; the oldest is dropped).  The graph reads the
+ * buffers' contents at replay time, so new controls in the same buffer, an
+ * exchange or a solve in between are all seen.  Calls with sub_ids, with
+ * phase timing on, or inside dd4dvar_solve run eagerly.  Off by default. */
+dd4dvar_status dd4dvar_set_graph(dd4dvar_ctx* ctx, int32_t on);
+
+/* Autotuner of the execution plan of local_cost_grad: candidates are the
+ * step kernels (mode 0) and, where the persistent sweeps apply, mode 2 with
+ * the smallest pass count (1024 cells per pass) that holds the largest box,
+ * mode 2 with the maximum pass count, and mode 3.  Each candidate evaluates
+ * every subdomain at x_dev once untimed and then reps times (1..1000) between
+ * HIP events on the stream, writing J_dev / grad_dev (caller's scratch, the
+ * local_cost_grad layouts; in graph mode the replays are timed).  The fastest
+ * becomes the context's plan; the report lists every candidate.  Blocks until
+ * the timing is read.  Nothing is allocated on the device. */
+typedef struct {
+  int32_t ncand;        /* candidates timed (<= 8) */
+  int32_t mode[8];      /* execution mode of each */
+  int32_t passes[8];    /* pass count of the persistent kernels (0 for mode 0) */
+  double ms[8];         /* milliseconds per evaluation */
+  int32_t chosen;       /* index of the plan now in use */
+} dd4dvar_tune_report;
+dd4dvar_status dd4dvar_autotune(dd4dvar_ctx* ctx, const double* x_dev, double* J_dev,
+                                double* grad_dev, int32_t reps, void* stream,
+                                dd4dvar_tune_report* report);
+
 /* Phase timing of local_cost_grad, for measurement: when on, every call
  * records HIP events on its stream around the forward sweep, the adjoint
  * sweep and the final reduction.  dd4dvar_get_timing waits for them and

@@ -63,6 +63,11 @@ class dd4dvar_solve_report(C.Structure):
                 ("gnorm_ratio_max", C.c_double), ("seconds", C.c_double)]
 
 
+class dd4dvar_tune_report(C.Structure):
+    _fields_ = [("ncand", C.c_int32), ("mode", C.c_int32 * 8), ("passes", C.c_int32 * 8),
+                ("ms", C.c_double * 8), ("chosen", C.c_int32)]
+
+
 _VP = C.c_void_p
 _SIGS = {
     "dd4dvar_plan_create": (C.c_int, [C.POINTER(dd4dvar_model_desc), C.POINTER(dd4dvar_partition_desc),
@@ -86,6 +91,8 @@ _SIGS = {
     "dd4dvar_gather": (C.c_int, [_VP, C.c_int32, _VP, _VP]),
     "dd4dvar_set_exec_mode": (C.c_int, [_VP, C.c_int32]),
     "dd4dvar_set_timing": (C.c_int, [_VP, C.c_int32]),
+    "dd4dvar_set_graph": (C.c_int, [_VP, C.c_int32]),
+    "dd4dvar_autotune": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, _VP, C.POINTER(dd4dvar_tune_report)]),
     "dd4dvar_get_timing": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "dd4dvar_solve": (C.c_int, [_VP, C.POINTER(dd4dvar_solve_opts), _VP, _VP, _VP,
                                 C.POINTER(dd4dvar_solve_report)]),
@@ -222,6 +229,19 @@ def dd4dvar_set_exec_mode(ctx, mode):
 
 def dd4dvar_set_timing(ctx, on):
     check(lib().dd4dvar_set_timing(ctx, int(bool(on))), ctx)
+
+
+def dd4dvar_set_graph(ctx, on):
+    check(lib().dd4dvar_set_graph(ctx, int(bool(on))), ctx)
+
+
+def dd4dvar_autotune(ctx, x_dev, J_dev, grad_dev, reps, stream=None):
+    rep = dd4dvar_tune_report()
+    check(lib().dd4dvar_autotune(ctx, x_dev, J_dev, grad_dev, reps, stream, C.byref(rep)), ctx)
+    n = rep.ncand
+    return {"candidates": [{"mode": rep.mode[i], "passes": rep.passes[i], "ms": rep.ms[i]}
+                           for i in range(n)],
+            "chosen": rep.chosen}
 
 
 def dd4dvar_get_timing(ctx):

@@ -64,6 +64,21 @@ class Context:
     def set_exec_mode(self, mode):
         L.dd4dvar_set_exec_mode(self.handle, mode)
 
+    def set_graph(self, on):
+        L.dd4dvar_set_graph(self.handle, on)
+
+    def autotune(self, x, reps=5, J=None, grad=None):
+        """Time the execution plans of local_cost_grad at x and keep the
+        fastest; returns the report (every candidate and the choice)."""
+        if J is None:
+            J = self.torch.empty(self.nsub, dtype=self.torch.float64, device=self.device)
+        if grad is None:
+            grad = self.empty(self.ctrl_len)
+        rep = L.dd4dvar_autotune(self.handle, x.data_ptr(), J.data_ptr(), grad.data_ptr(), reps,
+                                 self._stream())
+        self.traj_generation += 1
+        return rep
+
     def set_timing(self, on):
         L.dd4dvar_set_timing(self.handle, on)
 

@@ -629,20 +629,24 @@ int box_passes(int ny, int nx, int nring, int nlev) {
 
 namespace {
 template <typename F>
-hipError_t configure_once(F* kernel, bool& done) {
-  if (done) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(kBoxLdsMax));
-  if (e == hipSuccess) done = true;
+hipError_t allow_lds(F* kernel) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(kBoxLdsMax));
+}
+
+template <int K>
+hipError_t prepare_k() {
+  hipError_t e = allow_lds(&k_fwd_box<K>);
+  if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 0>);
+  if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 1>);
+  if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 2>);
+  if (e == hipSuccess) e = allow_lds(&k_eval_box<K>);
   return e;
 }
 
 template <int K>
 hipError_t fwd_box_k(const Dom<float>& D, const double* x, const int32_t* order, int nboxes,
                      size_t lds_bytes, hipStream_t st) {
-  static bool done = false;
-  hipError_t e = configure_once(&k_fwd_box<K>, done);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fwd_box<K>, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, order);
   return hipGetLastError();
 }
@@ -651,10 +655,7 @@ template <int K, int MODE>
 hipError_t adj_box_k(const Dom<float>& D, const double* x, const double* xb, const double* forcing,
                      double* out, const int32_t* order, int nboxes, size_t lds_bytes,
                      hipStream_t st) {
-  static bool done = false;
   auto* kern = &k_adj_box<K, MODE>;
-  hipError_t e = configure_once(kern, done);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, xb, forcing, out,
                      order);
   return hipGetLastError();
@@ -663,9 +664,6 @@ hipError_t adj_box_k(const Dom<float>& D, const double* x, const double* xb, con
 template <int K>
 hipError_t eval_box_k(const Dom<float>& D, const double* x, const double* xb, double* grad,
                       const int32_t* order, int nboxes, size_t lds_bytes, hipStream_t st) {
-  static bool done = false;
-  hipError_t e = configure_once(&k_eval_box<K>, done);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_eval_box<K>, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, xb, grad,
                      order);
   return hipGetLastError();
@@ -680,6 +678,14 @@ hipError_t adj_box_mode(const Dom<float>& D, int mode, const double* x, const do
   return adj_box_k<K, 2>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
 }
 }  // namespace
+
+int box_passes_max() { return kBoxKMax; }
+
+// raises the dynamic LDS limit of the kernels that run the given pass count
+// (once per process and device, before any launch or stream capture)
+hipError_t box_prepare(int passes) {
+  return passes <= 10 ? prepare_k<10>() : prepare_k<kBoxKMax>();
+}
 
 // kernels are instantiated for 10 passes (boxes of up to 10240 cells, e.g.
 // 72 x 136) and for the maximum of 11

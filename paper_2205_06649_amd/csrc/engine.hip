@@ -87,10 +87,27 @@ struct dd4dvar_ctx {
     int nfwd, nadj;
   };
   std::vector<Mark> marks;
+  // graph mode: local_cost_grad over all subdomains recorded once per
+  // (x, J, grad, execution plan) into a HIP graph and replayed
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;     // recording stream (the caller's may be the null stream)
+  struct GraphEntry {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    const double* x;
+    double *J, *grad;
+    int mode, passes;
+  };
+  std::vector<GraphEntry> graphs;
   DeviceArrays mem;
   ~dd4dvar_ctx() {
     for (Mark& m : marks)
       for (hipEvent_t e : m.ev) (void)hipEventDestroy(e);
+    for (GraphEntry& g : graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipGraphDestroy(g.graph);
+    }
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
 
@@ -437,6 +454,12 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
     c->box_ok = ok;
     c->box_lds = lds;
     c->box_k = kmax;
+    // LDS limits of the persistent kernels are set here, outside any stream
+    // capture, for the pass counts the context can run
+    if (ok) {
+      chk(box_prepare(kmax), "persistent kernel set-up");
+      chk(box_prepare(box_passes_max()), "persistent kernel set-up");
+    }
     std::vector<int32_t> order(P.nsub);
     for (int s = 0; s < P.nsub; ++s) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -593,6 +616,55 @@ dd4dvar_status fail(dd4dvar_ctx* c, dd4dvar_status s, const std::string& msg) {
   return s;
 }
 
+// local_cost_grad of every subdomain, eagerly or (graph mode) by replaying
+// the graph recorded for these pointers and this execution plan; recorded on
+// a stream of the context's own (the caller's may be the null stream, which
+// cannot be captured) and launched on the caller's
+void eval_all(dd4dvar_ctx* c, const double* x, double* J, double* grad, hipStream_t st) {
+  auto eager = [&](hipStream_t s) {
+    if (c->prec == DD4DVAR_FP64)
+      cost_grad_impl<double>(c, nullptr, x, J, grad, s);
+    else
+      cost_grad_impl<float>(c, nullptr, x, J, grad, s);
+  };
+  if (!c->use_graph || c->timing || c->eval_mask) {
+    eager(st);
+    return;
+  }
+  dd4dvar_ctx::GraphEntry* hit = nullptr;
+  for (dd4dvar_ctx::GraphEntry& g : c->graphs)
+    if (g.x == x && g.J == J && g.grad == grad && g.mode == c->exec_mode && g.passes == c->box_k)
+      hit = &g;
+  if (!hit) {
+    if (!c->cap_stream) chk(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "stream");
+    hipGraph_t g = nullptr;
+    chk(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+      eager(c->cap_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(c->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    chk(hipStreamEndCapture(c->cap_stream, &g), "end capture");
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      chk(e, "graph instantiate");
+    }
+    if (c->graphs.size() >= 8) {              // a small cache: drop the oldest
+      (void)hipGraphExecDestroy(c->graphs.front().exec);
+      (void)hipGraphDestroy(c->graphs.front().graph);
+      c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back({g, ex, x, J, grad, c->exec_mode, c->box_k});
+    hit = &c->graphs.back();
+  }
+  chk(hipGraphLaunch(hit->exec, st), "graph launch");
+  c->have_forward = true;
+}
+
 #define API_GUARD(ctx, ...)                                    \
   try {                                                        \
     __VA_ARGS__                                                \
@@ -710,10 +782,81 @@ dd4dvar_status dd4dvar_local_cost_grad(dd4dvar_ctx* ctx, int32_t nsub, const int
   }
   API_GUARD(ctx, {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (ctx->prec == DD4DVAR_FP64)
-      cost_grad_impl<double>(ctx, sub_ids ? &ids : nullptr, x_dev, J_dev, grad_dev, st);
-    else
-      cost_grad_impl<float>(ctx, sub_ids ? &ids : nullptr, x_dev, J_dev, grad_dev, st);
+    if (!sub_ids) {
+      eval_all(ctx, x_dev, J_dev, grad_dev, st);
+    } else if (ctx->prec == DD4DVAR_FP64) {
+      cost_grad_impl<double>(ctx, &ids, x_dev, J_dev, grad_dev, st);
+    } else {
+      cost_grad_impl<float>(ctx, &ids, x_dev, J_dev, grad_dev, st);
+    }
+    return DD4DVAR_OK;
+  })
+}
+
+dd4dvar_status dd4dvar_set_graph(dd4dvar_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(ctx, DD4DVAR_E_INVALID, "null context");
+  ctx->use_graph = on != 0;
+  return DD4DVAR_OK;
+}
+
+dd4dvar_status dd4dvar_autotune(dd4dvar_ctx* ctx, const double* x_dev, double* J_dev,
+                                double* grad_dev, int32_t reps, void* stream,
+                                dd4dvar_tune_report* report) {
+  if (!ctx || !x_dev || !J_dev || !grad_dev || !report) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  if (reps < 1 || reps > 1000) return fail(ctx, DD4DVAR_E_INVALID, "reps must be in 1..1000");
+  API_GUARD(ctx, {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // candidate execution plans: step kernels, then the persistent sweeps
+    // (one launch per sweep, or fused) with the smallest pass count that
+    // holds the largest box and with the maximum one
+    std::vector<std::pair<int, int>> cand = {{0, ctx->box_k}};
+    if (ctx->box_ok) {
+      const int kmin = ctx->box_k, kmax = box_passes_max();
+      cand.push_back({2, kmin});
+      if (kmax != kmin) cand.push_back({2, kmax});
+      cand.push_back({3, kmin});
+    }
+    const int mode0 = ctx->exec_mode, k0 = ctx->box_k;
+    const bool timing0 = ctx->timing;
+    ctx->timing = false;
+    hipEvent_t a = nullptr, b = nullptr;
+    try {
+      chk(hipEventCreate(&a), "event");
+      chk(hipEventCreate(&b), "event");
+      std::memset(report, 0, sizeof(*report));
+      report->ncand = int32_t(cand.size());
+      double best = 0;
+      for (size_t i = 0; i < cand.size(); ++i) {
+        ctx->exec_mode = cand[i].first;
+        ctx->box_k = cand[i].second;
+        eval_all(ctx, x_dev, J_dev, grad_dev, st);           // warm-up (records a graph in graph mode)
+        chk(hipEventRecord(a, st), "event");
+        for (int r = 0; r < reps; ++r) eval_all(ctx, x_dev, J_dev, grad_dev, st);
+        chk(hipEventRecord(b, st), "event");
+        chk(hipEventSynchronize(b), "event sync");
+        float ms = 0;
+        chk(hipEventElapsedTime(&ms, a, b), "elapsed");
+        report->mode[i] = cand[i].first;
+        report->passes[i] = cand[i].first >= 2 ? cand[i].second : 0;
+        report->ms[i] = double(ms) / reps;
+        if (i == 0 || report->ms[i] < best) {
+          best = report->ms[i];
+          report->chosen = int32_t(i);
+        }
+      }
+    } catch (...) {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+      ctx->exec_mode = mode0;
+      ctx->box_k = k0;
+      ctx->timing = timing0;
+      throw;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    ctx->exec_mode = report->mode[report->chosen];
+    ctx->box_k = cand[report->chosen].second;
+    ctx->timing = timing0;
     return DD4DVAR_OK;
   })
 }

@@ -42,6 +42,8 @@ void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 // box.hip: persistent per-box sweeps (FP32 state)
 size_t box_lds_bytes(int ny, int nx, int nring, int nlev);
 int box_passes(int ny, int nx, int nring, int nlev);
+int box_passes_max();
+hipError_t box_prepare(int passes);
 hipError_t launch_fwd_box(const Dom<float>& D, const double* x, const int32_t* order, int nboxes,
                           size_t lds_bytes, int passes, hipStream_t st);
 hipError_t launch_adj_box(const Dom<float>& D, int mode, const double* x, const double* xb,
