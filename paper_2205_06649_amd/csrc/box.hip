@@ -150,8 +150,9 @@ __device__ __forceinline__ double block_sum_box(double v, double* sh) {
 }
 }  // namespace
 
-// forward sweep of box s by the whole workgroup (K passes of 1024 cells)
-template <int K>
+// forward sweep of box s by the whole workgroup (K passes of 1024 cells);
+// SPAN: some box of the launch spans the circle (wrapped frame positions)
+template <int K, bool SPAN>
 __device__ __forceinline__ void fwd_box_body(const Dom<float>& D, const double* __restrict__ x,
                                              int s, float* lds) {
   const SubDev S = D.subs[s];
@@ -166,7 +167,7 @@ __device__ __forceinline__ void fwd_box_body(const Dom<float>& D, const double* 
   const int32_t* hsrc = D.hsrc + S.hmap_off;
   const int32_t* hoff = D.hoff + S.hmap_off;
   const int32_t* hsgn = D.hsign + S.hmap_off;
-  const bool wraps = S.span != 0;
+  const bool wraps = SPAN && S.span != 0;
   const int fp = ncell * 4, lvb = 3 * ncell * 4;   // byte strides: field, level
   const __amdgpu_buffer_rsrc_t zrs = make_rsrc(D.traj + S.traj_off, S.nlev * lvb);
   const int dr = kBoxThreads / nx, dc = kBoxThreads - dr * nx;
@@ -297,7 +298,7 @@ __device__ __forceinline__ void fwd_box_body(const Dom<float>& D, const double* 
 // or north.  Gather form and forcing as in k_adj (sweep.hip).
 // MODE 0: cost forcing, gradient + J out; 1: caller forcing, adjoint out;
 // 2: cost forcing, adjoint out.
-template <int K, int MODE>
+template <int K, int MODE, bool SPAN>
 __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* __restrict__ x,
                                              const double* __restrict__ xb,
                                              const double* __restrict__ forcing,
@@ -319,7 +320,7 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
   const int32_t* hsrc = D.hsrc + S.hmap_off;
   const int32_t* hoff = D.hoff + S.hmap_off;
   const int32_t* hsgn = D.hsign + S.hmap_off;
-  const bool wraps = S.span != 0;
+  const bool wraps = SPAN && S.span != 0;
   const float st = D.st, stg = D.stg;
   const int fp = ncell * 4, nx4 = nx * 4, lvb = 3 * ncell * 4;   // byte strides
   const __amdgpu_buffer_rsrc_t zrs = make_rsrc(D.traj + S.traj_off, S.nlev * lvb);
@@ -386,44 +387,70 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
       const int64_t fs = rfrozen ? int64_t(nring) : plane;
       gnext = {src[0], rsg * src[fs], rsg * src[2 * fs]};
     }
+    // Global loads of one pass (the state of level n at the cell and at its
+    // neighbours inside the box, offsets clamped to the cell itself at the
+    // box edge, and the overlap target), issued one pass ahead of their use
+    // so that their latency overlaps the arithmetic of the pass before.
+    // Loads for cells past the box end stay inside the range-checked buffer
+    // (or read as zero) and are never used.
+    struct PassLoads {
+      V3<float> C, E, W, N, Sv, tg;
+      int Kc;
+    };
+    auto issue = [&](const Cell& cq, bool edge) {
+      PassLoads L;
+      const int v0 = cq.m * 4;
+      const bool e_in = cq.c + 1 < nx, w_in = cq.c > 0;
+      const bool n_in = !edge || cq.r + 1 < ny, s_in = !edge || cq.r > 0;
+      L.Kc = 0;
+      L.tg = {0.f, 0.f, 0.f};
+      if (MODE != 1) {
+        L.Kc = int(covl[cq.m < ncell ? cq.m : ncell - 1]) * tcount - 1;
+        L.tg = bload3(trs, L.Kc > 0 ? v0 : 0, so, fp);
+      }
+      L.C = bload3(zrs, v0, so, fp);
+      L.E = bload3(zrs, e_in ? v0 + 4 : v0, so, fp);
+      L.W = bload3(zrs, w_in ? v0 - 4 : v0, so, fp);
+      L.N = bload3(zrs, n_in ? v0 + nx4 : v0, so, fp);
+      L.Sv = bload3(zrs, s_in ? v0 - nx4 : v0, so, fp);
+      return L;
+    };
     // opaque per-step copy of the start cell (see the forward)
     Cell q = q0;
     asm volatile("" : "+v"(q.m), "+v"(q.r), "+v"(q.c));
+    PassLoads cur = issue(q, true);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       // passes holding the box's first or last row (wave-uniform)
       const bool edge_rows = k == 0 || (k + 1) * kBoxThreads > ncell - nx;
-      if (k * kBoxThreads < ncell && q.m < ncell) {
-        const int m = q.m, r = q.r, c = q.c;
+      const Cell qc = q;
+      next_cell(q, nx, dr, dc);
+      PassLoads nxt = cur;
+      if (k + 1 < K && (k + 1) * kBoxThreads < ncell)
+        nxt = issue(q, (k + 2) * kBoxThreads > ncell - nx);
+      // the next pass's loads are in flight before this pass computes
+      __builtin_amdgcn_sched_barrier(0);
+      if (k * kBoxThreads < ncell && qc.m < ncell) {
+        const int m = qc.m, r = qc.r, c = qc.c;
         const bool e_in = c + 1 < nx, w_in = c > 0;
         const bool n_in = !edge_rows || r + 1 < ny, s_in = !edge_rows || r > 0;
         const float* rw = rowtab + 8 * r;
         const float a1 = rw[0], a2 = rw[1], cf = rw[3], ct = rw[4], cc = rw[5];
         const float a3n = rowtab[8 * (n_in ? r + 1 : r) + 2];
         const float a3s = rowtab[8 * (s_in ? r - 1 : r) + 2];
-        const int v0 = m * 4;
-        // overlap targets (needed where covered) or the caller's forcing
-        int Kc = 0;
-        V3<float> tg = {0.f, 0.f, 0.f};
+        const int Kc = cur.Kc;
+        const V3<float> tg = cur.tg, C = cur.C;
+        V3<float> E = cur.E, W = cur.W, N = cur.N, Sv = cur.Sv;
+        // the caller's forcing (adjoint_integrate)
         float fh = 0.f, fu = 0.f, fv = 0.f;
-        if (MODE != 1) {
-          Kc = int(covl[m]) * tcount - 1;
-          tg = bload3(trs, Kc > 0 ? v0 : 0, so, fp);
-        } else {
+        if (MODE == 1) {
           const double* Fz = forcing + S.traj_off + int64_t(n) * 3 * plane;
           fh = float(Fz[m]);
           fu = float(Fz[plane + m]);
           fv = float(Fz[2 * plane + m]);
         }
-        // state of level n: the cell and its neighbours inside the box
-        // (offsets clamped to the cell itself at the box edge) ...
-        const V3<float> C = bload3(zrs, v0, so, fp);
-        V3<float> E = bload3(zrs, e_in ? v0 + 4 : v0, so, fp);
-        V3<float> W = bload3(zrs, w_in ? v0 - 4 : v0, so, fp);
-        V3<float> N = bload3(zrs, n_in ? v0 + nx4 : v0, so, fp);
-        V3<float> Sv = bload3(zrs, s_in ? v0 - nx4 : v0, so, fp);
-        // ... and outside it, from the staged ring (every lane reads a valid
-        // position and keeps it only at the edge)
+        // neighbours outside the box, from the staged ring (every lane reads
+        // a valid position and keeps it only at the edge)
         const int iE = e_in ? 0 : 3 * (2 * nx + ny + r), iW = w_in ? 0 : 3 * (2 * nx + r);
         const V3<float> rE = lds3(Zr, iE), rW = lds3(Zr, iW);
         V3<float> rN = {0.f, 0.f, 0.f}, rS = {0.f, 0.f, 0.f};
@@ -431,8 +458,6 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
           rN = lds3(Zr, n_in ? 0 : 3 * (nx + c));
           rS = lds3(Zr, s_in ? 0 : 3 * c);
         }
-        // every load of the cell is in flight before the first use
-        __builtin_amdgcn_sched_barrier(0);
         E = pick3(E, rE, __builtin_amdgcn_ballot_w64(e_in));
         W = pick3(W, rW, __builtin_amdgcn_ballot_w64(w_in));
         if (edge_rows) {
@@ -441,24 +466,25 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
         }
         // across a pole (boxes spanning the circle) the adjoint of a wrapped
         // neighbour carries the sign of u, v
-        const float sn = (!n_in && S.pole_n) ? -1.0f : 1.0f, ss = (!s_in && S.pole_s) ? -1.0f : 1.0f;
+        const float sn = (SPAN && !n_in && S.pole_n) ? -1.0f : 1.0f;
+        const float ss = (SPAN && !s_in && S.pole_s) ? -1.0f : 1.0f;
         const V3<float> l2 = {ln[0][k], ln[1][k], ln[2][k]};
         // lambda^{n+1} from LDS (zero in frozen frame entries)
         const float* Lc = Lm + 3 * ((r + 1) * nxp + c + 1);
         const V3<float> l0 = lds3(Lc, 0), kE = lds3(Lc, 3), kW = lds3(Lc, -3);
         const V3<float> kN = lds3(Lc, n3), kS = lds3(Lc, -n3);
+        // transposed Jacobian of the increments of the cell and of its four
+        // neighbours applied to lambda^{n+1}, grouped by shared factors
         const float hm = D.h0 + C.h;
-        float au = l0.u * (-a1 * (E.u - W.u) + ct * C.v) +
-                   l0.v * (-a1 * (E.v - W.v) - cf - 2.0f * ct * C.u);
-        float av = l0.u * (-st * (N.u - Sv.u) + cf + ct * C.u) + l0.v * (-st * (N.v - Sv.v));
-        float ah = 0.0f;
-        au += a1 * (kE.u * E.u + kE.h * hm) - a1 * (kW.u * W.u + kW.h * hm);
-        av += a1 * kE.v * E.u - a1 * kW.v * W.u;
-        ah += (a2 * kE.u + a1 * kE.h * C.u) - (a2 * kW.u + a1 * kW.h * C.u);
+        const float ctu = ct * C.u;
+        const float dh = kE.h - kW.h;                       // east - west height adjoints
+        const float q = kN.h * a3n - kS.h * a3s;            // north - south, with cos factors
         const float vkn = sn * N.v, vks = ss * Sv.v;
-        au += kN.u * st * vkn - kS.u * st * vks;
-        av += (kN.v * st * vkn + kN.h * a3n * hm * cc) - (kS.v * st * vks + kS.h * a3s * hm * cc);
-        ah += (sn * kN.v * stg + kN.h * a3n * C.v * cc) - (ss * kS.v * stg + kS.h * a3s * C.v * cc);
+        float au = l0.u * (ct * C.v - a1 * (E.u - W.u)) + l0.v * (-a1 * (E.v - W.v) - cf - 2.0f * ctu);
+        au += a1 * ((kE.u * E.u - kW.u * W.u) + dh * hm) + st * (kN.u * vkn - kS.u * vks);
+        float av = l0.u * (cf + ctu - st * (N.u - Sv.u)) - l0.v * (st * (N.v - Sv.v));
+        av += a1 * (kE.v * E.u - kW.v * W.u) + st * (kN.v * vkn - kS.v * vks) + (hm * cc) * q;
+        float ah = a2 * (kE.u - kW.u) + (a1 * C.u) * dh + stg * (sn * kN.v - ss * kS.v) + (C.v * cc) * q;
         if (n == 0) {
           au = l0.u + 0.5f * au;
           av = l0.v + 0.5f * av;
@@ -501,7 +527,7 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
         }
       }
       __builtin_amdgcn_sched_barrier(0);
-      next_cell(q, nx, dr, dc);
+      cur = nxt;
     }
     // observations of this box at level n
     const bool any_obs = MODE != 1 && lvl_obs[n] > 0;
@@ -566,16 +592,16 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
   }
 }
 
-template <int K>
+template <int K, bool SPAN>
 __global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const double* __restrict__ x,
                                                          const int32_t* __restrict__ order) {
   extern __shared__ float lds[];
   const int s = order[blockIdx.x];
   if (D.active && !D.active[s]) return;
-  fwd_box_body<K>(D, x, s, lds);
+  fwd_box_body<K, SPAN>(D, x, s, lds);
 }
 
-template <int K, int MODE>
+template <int K, int MODE, bool SPAN>
 __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const double* __restrict__ x,
                                                          const double* __restrict__ xb,
                                                          const double* __restrict__ forcing,
@@ -585,14 +611,14 @@ __global__ __launch_bounds__(kBoxThreads) void k_adj_box(Dom<float> D, const dou
   __shared__ double red[kBoxThreads / 64];
   const int s = order[blockIdx.x];
   if (D.active && !D.active[s]) return;
-  adj_box_body<K, MODE>(D, x, xb, forcing, out, s, lds, red);
+  adj_box_body<K, MODE, SPAN>(D, x, xb, forcing, out, s, lds, red);
 }
 
 // one whole local cost/gradient evaluation of box s in one workgroup: the
 // forward sweep, then the adjoint sweep with the cost forcing (the levels the
 // adjoint reads first are the ones the forward wrote last, still in the
 // last-level cache)
-template <int K>
+template <int K, bool SPAN>
 __global__ __launch_bounds__(kBoxThreads) void k_eval_box(Dom<float> D, const double* __restrict__ x,
                                                           const double* __restrict__ xb,
                                                           double* __restrict__ grad,
@@ -601,13 +627,13 @@ __global__ __launch_bounds__(kBoxThreads) void k_eval_box(Dom<float> D, const do
   __shared__ double red[kBoxThreads / 64];
   const int s = order[blockIdx.x];
   if (D.active && !D.active[s]) return;
-  fwd_box_body<K>(D, x, s, lds);
+  fwd_box_body<K, SPAN>(D, x, s, lds);
   __syncthreads();
   // an opaque copy of the box index: the adjoint recomputes its own indices
   // instead of keeping the forward's alive (which would spill)
   int sa = s;
   asm volatile("" : "+s"(sa));
-  adj_box_body<K, 0>(D, x, xb, nullptr, grad, sa, lds, red);
+  adj_box_body<K, 0, SPAN>(D, x, xb, nullptr, grad, sa, lds, red);
 }
 
 // dynamic LDS of the persistent kernels: padded level frame, per-row
@@ -634,48 +660,49 @@ hipError_t allow_lds(F* kernel) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(kBoxLdsMax));
 }
 
-template <int K>
-hipError_t prepare_k() {
-  hipError_t e = allow_lds(&k_fwd_box<K>);
-  if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 0>);
-  if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 1>);
-  if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 2>);
-  if (e == hipSuccess) e = allow_lds(&k_eval_box<K>);
+template <int K, bool SPAN>
+hipError_t prepare_ks() {
+  hipError_t e = allow_lds(&k_fwd_box<K, SPAN>);
+  if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 0, SPAN>);
+  if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 1, SPAN>);
+  if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 2, SPAN>);
+  if (e == hipSuccess) e = allow_lds(&k_eval_box<K, SPAN>);
   return e;
 }
 
-template <int K>
+template <int K, bool SPAN>
 hipError_t fwd_box_k(const Dom<float>& D, const double* x, const int32_t* order, int nboxes,
                      size_t lds_bytes, hipStream_t st) {
-  hipLaunchKernelGGL(k_fwd_box<K>, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, order);
+  auto* kern = &k_fwd_box<K, SPAN>;
+  hipLaunchKernelGGL(kern, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, order);
   return hipGetLastError();
 }
 
-template <int K, int MODE>
+template <int K, int MODE, bool SPAN>
 hipError_t adj_box_k(const Dom<float>& D, const double* x, const double* xb, const double* forcing,
                      double* out, const int32_t* order, int nboxes, size_t lds_bytes,
                      hipStream_t st) {
-  auto* kern = &k_adj_box<K, MODE>;
+  auto* kern = &k_adj_box<K, MODE, SPAN>;
   hipLaunchKernelGGL(kern, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, xb, forcing, out,
                      order);
   return hipGetLastError();
 }
 
-template <int K>
+template <int K, bool SPAN>
 hipError_t eval_box_k(const Dom<float>& D, const double* x, const double* xb, double* grad,
                       const int32_t* order, int nboxes, size_t lds_bytes, hipStream_t st) {
-  hipLaunchKernelGGL(k_eval_box<K>, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, xb, grad,
-                     order);
+  auto* kern = &k_eval_box<K, SPAN>;
+  hipLaunchKernelGGL(kern, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, xb, grad, order);
   return hipGetLastError();
 }
 
-template <int K>
+template <int K, bool SPAN>
 hipError_t adj_box_mode(const Dom<float>& D, int mode, const double* x, const double* xb,
                         const double* forcing, double* out, const int32_t* order, int nboxes,
                         size_t lds_bytes, hipStream_t st) {
-  if (mode == 0) return adj_box_k<K, 0>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
-  if (mode == 1) return adj_box_k<K, 1>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
-  return adj_box_k<K, 2>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+  if (mode == 0) return adj_box_k<K, 0, SPAN>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+  if (mode == 1) return adj_box_k<K, 1, SPAN>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+  return adj_box_k<K, 2, SPAN>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
 }
 }  // namespace
 
@@ -684,30 +711,41 @@ int box_passes_max() { return kBoxKMax; }
 // raises the dynamic LDS limit of the kernels that run the given pass count
 // (once per process and device, before any launch or stream capture)
 hipError_t box_prepare(int passes) {
-  return passes <= 10 ? prepare_k<10>() : prepare_k<kBoxKMax>();
+  hipError_t e = passes <= 10 ? prepare_ks<10, false>() : prepare_ks<kBoxKMax, false>();
+  if (e == hipSuccess) e = passes <= 10 ? prepare_ks<10, true>() : prepare_ks<kBoxKMax, true>();
+  return e;
 }
 
 // kernels are instantiated for 10 passes (boxes of up to 10240 cells, e.g.
-// 72 x 136) and for the maximum of 11
+// 72 x 136) and for the maximum of 11, without and with wrapped frame
+// positions (span: some box of the launch spans the circle)
 hipError_t launch_fwd_box(const Dom<float>& D, const double* x, const int32_t* order, int nboxes,
-                          size_t lds_bytes, int passes, hipStream_t st) {
-  if (passes <= 10) return fwd_box_k<10>(D, x, order, nboxes, lds_bytes, st);
-  return fwd_box_k<kBoxKMax>(D, x, order, nboxes, lds_bytes, st);
+                          size_t lds_bytes, int passes, bool span, hipStream_t st) {
+  if (passes <= 10)
+    return span ? fwd_box_k<10, true>(D, x, order, nboxes, lds_bytes, st)
+                : fwd_box_k<10, false>(D, x, order, nboxes, lds_bytes, st);
+  return span ? fwd_box_k<kBoxKMax, true>(D, x, order, nboxes, lds_bytes, st)
+              : fwd_box_k<kBoxKMax, false>(D, x, order, nboxes, lds_bytes, st);
 }
 
 hipError_t launch_adj_box(const Dom<float>& D, int mode, const double* x, const double* xb,
                           const double* forcing, double* out, const int32_t* order, int nboxes,
-                          size_t lds_bytes, int passes, hipStream_t st) {
+                          size_t lds_bytes, int passes, bool span, hipStream_t st) {
   if (passes <= 10)
-    return adj_box_mode<10>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st);
-  return adj_box_mode<kBoxKMax>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+    return span ? adj_box_mode<10, true>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st)
+                : adj_box_mode<10, false>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+  return span ? adj_box_mode<kBoxKMax, true>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st)
+              : adj_box_mode<kBoxKMax, false>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st);
 }
 
 hipError_t launch_eval_box(const Dom<float>& D, const double* x, const double* xb, double* grad,
                            const int32_t* order, int nboxes, size_t lds_bytes, int passes,
-                           hipStream_t st) {
-  if (passes <= 10) return eval_box_k<10>(D, x, xb, grad, order, nboxes, lds_bytes, st);
-  return eval_box_k<kBoxKMax>(D, x, xb, grad, order, nboxes, lds_bytes, st);
+                           bool span, hipStream_t st) {
+  if (passes <= 10)
+    return span ? eval_box_k<10, true>(D, x, xb, grad, order, nboxes, lds_bytes, st)
+                : eval_box_k<10, false>(D, x, xb, grad, order, nboxes, lds_bytes, st);
+  return span ? eval_box_k<kBoxKMax, true>(D, x, xb, grad, order, nboxes, lds_bytes, st)
+              : eval_box_k<kBoxKMax, false>(D, x, xb, grad, order, nboxes, lds_bytes, st);
 }
 
 }  // namespace dd4dvar

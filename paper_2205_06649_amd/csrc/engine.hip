@@ -71,6 +71,7 @@ struct dd4dvar_ctx {
   bool box_ok = false;                  // persistent per-box sweeps possible
   size_t box_lds = 0;
   int box_k = 0;                        // passes of 1024 cells of the largest box
+  bool box_span = false;                // some box spans the circle
   std::vector<int32_t> h_order;         // boxes, longest first
   int32_t* d_order = nullptr;
   // the whole grid as one box (FP64), for background and global runs
@@ -231,7 +232,7 @@ void local_forward(dd4dvar_ctx* c, const double* x, hipStream_t st) {
   Dom<T> D = local_dom<T>(c);
   if constexpr (std::is_same<T, float>::value) {
     if (c->exec_mode >= 2) {
-      chk(launch_fwd_box(D, x, c->d_order, c->nsub, c->box_lds, c->box_k, st),
+      chk(launch_fwd_box(D, x, c->d_order, c->nsub, c->box_lds, c->box_k, c->box_span, st),
           "persistent forward launch");
       c->have_forward = true;
       return;
@@ -257,7 +258,7 @@ void local_adjoint(dd4dvar_ctx* c, int mode, const double* x, const double* forc
   if constexpr (std::is_same<T, float>::value) {
     if (!ids && c->exec_mode >= 2) {
       chk(launch_adj_box(D, mode, x, c->xb, forcing, out, c->d_order, c->nsub, c->box_lds, c->box_k,
-                         st),
+                         c->box_span, st),
           "persistent adjoint launch");
       return;
     }
@@ -297,7 +298,8 @@ void cost_grad_impl(dd4dvar_ctx* c, const std::vector<int32_t>* ids, const doubl
     if (!ids && c->exec_mode == 3) {
       // one fused persistent launch: each workgroup runs its box's forward
       // sweep and then its adjoint sweep
-      chk(launch_eval_box(D, x, c->xb, grad, c->d_order, c->nsub, c->box_lds, c->box_k, st),
+      chk(launch_eval_box(D, x, c->xb, grad, c->d_order, c->nsub, c->box_lds, c->box_k, c->box_span,
+                          st),
           "persistent evaluation launch");
       c->have_forward = true;
       mark(c, 1, st);
@@ -450,6 +452,7 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
       const int k = box_passes(S.ny, S.nx, S.nring, S.nlev);
       if (k == 0) ok = false;
       kmax = std::max(kmax, k);
+      if (S.span) c->box_span = true;
     }
     c->box_ok = ok;
     c->box_lds = lds;

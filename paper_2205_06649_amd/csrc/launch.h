@@ -45,12 +45,12 @@ int box_passes(int ny, int nx, int nring, int nlev);
 int box_passes_max();
 hipError_t box_prepare(int passes);
 hipError_t launch_fwd_box(const Dom<float>& D, const double* x, const int32_t* order, int nboxes,
-                          size_t lds_bytes, int passes, hipStream_t st);
+                          size_t lds_bytes, int passes, bool span, hipStream_t st);
 hipError_t launch_adj_box(const Dom<float>& D, int mode, const double* x, const double* xb,
                           const double* forcing, double* out, const int32_t* order, int nboxes,
-                          size_t lds_bytes, int passes, hipStream_t st);
+                          size_t lds_bytes, int passes, bool span, hipStream_t st);
 hipError_t launch_eval_box(const Dom<float>& D, const double* x, const double* xb, double* grad,
                            const int32_t* order, int nboxes, size_t lds_bytes, int passes,
-                           hipStream_t st);
+                           bool span, hipStream_t st);
 
 }  // namespace dd4dvar
