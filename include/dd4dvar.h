@@ -236,6 +236,24 @@ dd4dvar_status dd4dvar_gather(dd4dvar_ctx* ctx, int32_t level, double* out_dev,
  * local_cost_grad always uses the step kernels. */
 dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode);
 
+/* Storage of the local trajectories for the adjoint (Sec. 2 adjoint model;
+ * square-root checkpointing of the forward states).  stride = 0 (default):
+ * every level of every box is kept.  stride >= 3: only the level pairs
+ * n = k stride, k stride + 1 are kept, plus one segment of stride - 2 levels
+ * per box; the adjoint recomputes each segment from its pair, last segment
+ * first, so a local cost/gradient costs one more forward sweep and the state
+ * arena shrinks from L + 1 to about 2 (L / stride + 1) + stride - 2 levels per
+ * box (smallest near stride = sqrt(2 L)).  Results are identical bit for bit
+ * to stride 0.  The exchange then integrates the boxes in step by global
+ * level and stages the new rings until the end.  gather is limited to levels
+ * that every box covering them keeps (level 0 always), and forward_integrate
+ * writes trajectory output level by level as it computes.  Not with the
+ * persistent execution modes 2 and 3 (E_INVALID).  Reallocates the state
+ * arena (synchronizes the device, drops recorded graphs) and clears the
+ * stored forward (an adjoint needs a new forward: E_STATE).  *state_bytes
+ * (nullable) receives the arena size. */
+dd4dvar_status dd4dvar_set_checkpointing(dd4dvar_ctx* ctx, int32_t stride, int64_t* state_bytes);
+
 /* Graph mode (on != 0): local_cost_grad over all subdomains (sub_ids NULL)
  * records its launches into a HIP graph the first time it meets a given
  * (x_dev, J_dev, grad_dev, execution plan) and replays that graph afterwards

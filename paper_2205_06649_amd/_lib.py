@@ -92,6 +92,7 @@ _SIGS = {
     "dd4dvar_set_exec_mode": (C.c_int, [_VP, C.c_int32]),
     "dd4dvar_set_timing": (C.c_int, [_VP, C.c_int32]),
     "dd4dvar_set_graph": (C.c_int, [_VP, C.c_int32]),
+    "dd4dvar_set_checkpointing": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int64)]),
     "dd4dvar_autotune": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, _VP, C.POINTER(dd4dvar_tune_report)]),
     "dd4dvar_get_timing": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "dd4dvar_solve": (C.c_int, [_VP, C.POINTER(dd4dvar_solve_opts), _VP, _VP, _VP,
@@ -229,6 +230,12 @@ def dd4dvar_set_exec_mode(ctx, mode):
 
 def dd4dvar_set_timing(ctx, on):
     check(lib().dd4dvar_set_timing(ctx, int(bool(on))), ctx)
+
+
+def dd4dvar_set_checkpointing(ctx, stride):
+    nbytes = C.c_int64(0)
+    check(lib().dd4dvar_set_checkpointing(ctx, stride, C.byref(nbytes)), ctx)
+    return nbytes.value
 
 
 def dd4dvar_set_graph(ctx, on):

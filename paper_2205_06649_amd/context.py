@@ -64,6 +64,14 @@ class Context:
     def set_exec_mode(self, mode):
         L.dd4dvar_set_exec_mode(self.handle, mode)
 
+    def set_checkpointing(self, stride):
+        """0: keep every level; stride >= 3: keep checkpoint pairs every
+        stride levels and recompute segments in the adjoint.  Returns the
+        bytes of the state arena."""
+        nbytes = L.dd4dvar_set_checkpointing(self.handle, int(stride))
+        self.traj_generation += 1
+        return nbytes
+
     def set_graph(self, on):
         L.dd4dvar_set_graph(self.handle, on)
 

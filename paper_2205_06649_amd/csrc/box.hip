@@ -17,6 +17,8 @@
 //
 // Thread t handles cells t + 1024 k, k = 0 .. K-1 (K passes, row-major), and
 // tracks the row and column of its cell incrementally from pass to pass.
+// These kernels need every level stored (no checkpoints): level n of a box
+// sits at slot n of its state arena.
 #include "kernels.h"
 #include "launch.h"
 #include "stencil.h"
@@ -114,7 +116,7 @@ __device__ __forceinline__ V3<float> ring_value(const Dom<float>& D, const SubDe
     const float* R = D.ring + S.ring_off + int64_t(level) * 3 * nring;
     return {R[k], R[nring + k], R[2 * nring + k]};
   }
-  const float* Z = D.traj + S.traj_off + int64_t(level) * 3 * plane;
+  const float* Z = D.traj + S.zoff + int64_t(level) * 3 * plane;
   const int o = D.hoff[S.hmap_off + k];
   const float sg = float(D.hsign[S.hmap_off + k]);
   return {Z[o], sg * Z[plane + o], sg * Z[2 * plane + o]};
@@ -169,7 +171,7 @@ __device__ __forceinline__ void fwd_box_body(const Dom<float>& D, const double* 
   const int32_t* hsgn = D.hsign + S.hmap_off;
   const bool wraps = SPAN && S.span != 0;
   const int fp = ncell * 4, lvb = 3 * ncell * 4;   // byte strides: field, level
-  const __amdgpu_buffer_rsrc_t zrs = make_rsrc(D.traj + S.traj_off, S.nlev * lvb);
+  const __amdgpu_buffer_rsrc_t zrs = make_rsrc(D.traj + S.zoff, S.nlev * lvb);
   const int dr = kBoxThreads / nx, dc = kBoxThreads - dr * nx;
   const int n3 = 3 * nxp;                  // one padded row, in floats
 
@@ -323,7 +325,7 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
   const bool wraps = SPAN && S.span != 0;
   const float st = D.st, stg = D.stg;
   const int fp = ncell * 4, nx4 = nx * 4, lvb = 3 * ncell * 4;   // byte strides
-  const __amdgpu_buffer_rsrc_t zrs = make_rsrc(D.traj + S.traj_off, S.nlev * lvb);
+  const __amdgpu_buffer_rsrc_t zrs = make_rsrc(D.traj + S.zoff, S.nlev * lvb);
   const __amdgpu_buffer_rsrc_t trs = make_rsrc(D.targ + S.traj_off, S.nlev * lvb);
   const float mu_f = float(D.mu);
   const float ib_h = float(D.isb2[0]), ib_u = float(D.isb2[1]), ib_v = float(D.isb2[2]);
@@ -372,7 +374,7 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
   const Cell q0 = first_cell(nx);
 
   for (int n = L; n >= 0; --n) {
-    const float* Z = D.traj + S.traj_off + int64_t(n) * 3 * plane;
+    const float* Z = D.traj + S.zoff + int64_t(n) * 3 * plane;
     // level n, field h (wave-uniform: kept in a scalar register, as the
     // buffer loads need it there)
     const int so = __builtin_amdgcn_readfirstlane(n * lvb);
@@ -383,7 +385,7 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
     const bool ring_thread = ring_thread0 && n > 0;
     if (ring_thread) {
       const float* src = rfrozen ? D.ring + S.ring_off + int64_t(n - 1) * 3 * nring + roff
-                                 : D.traj + S.traj_off + int64_t(n - 1) * 3 * plane + roff;
+                                 : D.traj + S.zoff + int64_t(n - 1) * 3 * plane + roff;
       const int64_t fs = rfrozen ? int64_t(nring) : plane;
       gnext = {src[0], rsg * src[fs], rsg * src[2 * fs]};
     }

@@ -72,6 +72,14 @@ struct dd4dvar_ctx {
   size_t box_lds = 0;
   int box_k = 0;                        // passes of 1024 cells of the largest box
   bool box_span = false;                // some box spans the circle
+  // state storage: every level (ckpt = 0), or checkpoint pairs every ckpt
+  // levels plus one segment that the adjoint recomputes
+  int ckpt = 0;
+  int nslot = 0;                        // slots per box with checkpoints
+  int32_t* d_zslot = nullptr;           // slot of each local level
+  int32_t* d_zslot_id = nullptr;        // identity (every level stored; global runs)
+  void* ring_next = nullptr;            // exchange staging for the rings (with checkpoints)
+  size_t traj_bytes = 0, ring_bytes = 0;
   std::vector<int32_t> h_order;         // boxes, longest first
   int32_t* d_order = nullptr;
   // the whole grid as one box (FP64), for background and global runs
@@ -167,6 +175,7 @@ Dom<T> local_dom(const dd4dvar_ctx* c) {
   D.hsign = c->hsign;
   D.hgcell = c->hgcell;
   D.active = c->eval_mask;
+  D.zslot = c->d_zslot;
   D.st = T(c->st);
   D.stg = T(c->stg);
   D.h0 = T(c->plan.model.h_ref);
@@ -184,6 +193,7 @@ Dom<double> global_dom(const dd4dvar_ctx* c, double* traj) {
   D.subs = c->d_gsub;
   D.tiles = c->d_gtiles;
   D.traj = traj;
+  D.zslot = c->d_zslot_id;
   D.rows = c->rows64;
   D.cosx = c->cosx64;
   D.st = c->st;
@@ -227,26 +237,35 @@ void global_forward(dd4dvar_ctx* c, const double* x, double* traj, hipStream_t s
   chk(hipGetLastError(), "global forward launch");
 }
 
+// local forward sweeps of every box; traj_out (nullable) receives the packed
+// FP64 trajectory, level by level as it is computed when levels share slots
 template <typename T>
-void local_forward(dd4dvar_ctx* c, const double* x, hipStream_t st) {
+void local_forward(dd4dvar_ctx* c, const double* x, hipStream_t st, double* traj_out = nullptr) {
   Dom<T> D = local_dom<T>(c);
   if constexpr (std::is_same<T, float>::value) {
     if (c->exec_mode >= 2) {
       chk(launch_fwd_box(D, x, c->d_order, c->nsub, c->box_lds, c->box_k, c->box_span, st),
           "persistent forward launch");
+      if (traj_out) launch_traj_out<T>(D, traj_out, 0, c->ntiles, -1, st);
       c->have_forward = true;
       return;
     }
   }
-  if (c->exec_mode != 1) {
-    launch_init<T>(D, x, 0, c->ntiles, st);
-    for (int n = 0; n + 1 < c->maxlev; ++n) launch_fwd<T>(D, n, 0, c->ntiles, st);
-  } else {
-    for (const SubDev& S : c->subs) {
-      launch_init<T>(D, x, S.tile0, S.ntile, st);
-      for (int n = 0; n + 1 < S.nlev; ++n) launch_fwd<T>(D, n, S.tile0, S.ntile, st);
+  const bool per_level = traj_out && c->ckpt;
+  auto sweep = [&](int tile_base, int ntiles, int nlev) {
+    launch_init<T>(D, x, tile_base, ntiles, st);
+    if (per_level) launch_traj_out<T>(D, traj_out, tile_base, ntiles, 0, st);
+    for (int n = 0; n + 1 < nlev; ++n) {
+      launch_fwd<T>(D, n, tile_base, ntiles, st);
+      if (per_level) launch_traj_out<T>(D, traj_out, tile_base, ntiles, n + 1, st);
     }
+  };
+  if (c->exec_mode != 1) {
+    sweep(0, c->ntiles, c->maxlev);
+  } else {
+    for (const SubDev& S : c->subs) sweep(S.tile0, S.ntile, S.nlev);
   }
+  if (traj_out && !per_level) launch_traj_out<T>(D, traj_out, 0, c->ntiles, -1, st);
   chk(hipGetLastError(), "forward launch");
   c->have_forward = true;
 }
@@ -263,14 +282,27 @@ void local_adjoint(dd4dvar_ctx* c, int mode, const double* x, const double* forc
       return;
     }
   }
+  // adjoint levels lmax .. 0 of a tile range; with checkpoints, segment by
+  // segment from the last, each first recomputed from its checkpoint pair
+  // (levels lo, lo+1) into the shared segment slots
+  auto levels = [&](int tile_base, int ntiles, int lmax) {
+    const int cs = c->ckpt;
+    if (cs == 0) {
+      for (int n = lmax; n >= 0; --n)
+        launch_adj<T>(D, n, tile_base, ntiles, mode, x, c->xb, forcing, out, st);
+      return;
+    }
+    for (int lo = (lmax / cs) * cs; lo >= 0; lo -= cs) {
+      const int hi = std::min(lo + cs - 1, lmax);
+      for (int n = lo + 1; n < hi; ++n) launch_fwd<T>(D, n, tile_base, ntiles, st);
+      for (int n = hi; n >= lo; --n)
+        launch_adj<T>(D, n, tile_base, ntiles, mode, x, c->xb, forcing, out, st);
+    }
+  };
   if (!ids && c->exec_mode != 1) {
-    for (int n = c->maxlev - 1; n >= 0; --n)
-      launch_adj<T>(D, n, 0, c->ntiles, mode, x, c->xb, forcing, out, st);
+    levels(0, c->ntiles, c->maxlev - 1);
   } else {
-    auto run = [&](const SubDev& S) {
-      for (int n = S.nlev - 1; n >= 0; --n)
-        launch_adj<T>(D, n, S.tile0, S.ntile, mode, x, c->xb, forcing, out, st);
-    };
+    auto run = [&](const SubDev& S) { levels(S.tile0, S.ntile, S.nlev - 1); };
     if (ids)
       for (int32_t s : *ids) run(c->subs[s]);
     else
@@ -359,12 +391,58 @@ void cost_grad_impl(dd4dvar_ctx* c, const std::vector<int32_t>* ids, const doubl
   }
 }
 
+// Exchange when levels share slots: the boxes advance in step by global
+// level, interval by interval, and every level's rings and targets are taken
+// as soon as all intervals hold it.  The forward keeps using the rings of the
+// previous exchange (as the local solves did): the new ones are written to a
+// staging arena that replaces the rings at the end.
+template <typename T>
+void exchange_lockstep(dd4dvar_ctx* c, const double* x, hipStream_t st) {
+  const dd4dvar_plan& P = c->plan;
+  Dom<T> D = local_dom<T>(c);
+  Dom<T> Dn = D;
+  Dn.ring = static_cast<T*>(c->ring_next);
+  const int nsp = P.nspace, ntm = P.ntime;
+  std::vector<int> tb(ntm), nt(ntm), lev0(ntm), nlev(ntm);
+  for (int j = 0; j < ntm; ++j) {
+    const SubDev& A = c->subs[j * nsp];
+    const SubDev& B = c->subs[(j + 1) * nsp - 1];
+    tb[j] = A.tile0;
+    nt[j] = B.tile0 + B.ntile - A.tile0;
+    lev0[j] = A.lev0;
+    nlev[j] = A.nlev;
+  }
+  launch_init<T>(D, x, 0, c->ntiles, st);
+  for (int g = 0; g <= P.model.nsteps; ++g) {
+    for (int j = 0; j < ntm; ++j) {
+      const int n = g - lev0[j];
+      if (n >= 1 && n < nlev[j]) launch_fwd<T>(D, n - 1, tb[j], nt[j], st);
+    }
+    for (int j = 0; j < ntm; ++j) {
+      const int n = g - lev0[j];
+      if (n < 0 || n >= nlev[j]) continue;
+      launch_ring_from_local<T>(Dn, j * nsp, nsp, c->ring_blocks, n, st);
+      launch_targets_from_local<T>(D, n, tb[j], nt[j], c->jc, st);
+    }
+  }
+  launch_reduce_jconst(c->d_subs, c->nsub, c->jc, 0.5 * P.model.mu_overlap, c->jconst, st);
+  chk(hipGetLastError(), "exchange launch");
+  // every frozen ring entry of every level has been staged; copied (not
+  // swapped) so that recorded graphs keep pointing at the live rings
+  chk(hipMemcpyAsync(c->ring, c->ring_next, c->ring_bytes, hipMemcpyDeviceToDevice, st), "ring copy");
+  c->have_forward = true;
+}
+
 template <typename T>
 void exchange_impl(dd4dvar_ctx* c, const double* x, hipStream_t st) {
+  if (c->ckpt) {
+    exchange_lockstep<T>(c, x, st);
+    return;
+  }
   local_forward<T>(c, x, st);
   Dom<T> D = local_dom<T>(c);
-  launch_ring_from_local<T>(D, c->nsub, c->ring_blocks, st);
-  for (int n = 0; n < c->maxlev; ++n) launch_targets_from_local<T>(D, n, c->ntiles, c->jc, st);
+  launch_ring_from_local<T>(D, 0, c->nsub, c->ring_blocks, -1, st);
+  for (int n = 0; n < c->maxlev; ++n) launch_targets_from_local<T>(D, n, 0, c->ntiles, c->jc, st);
   launch_reduce_jconst(c->d_subs, c->nsub, c->jc, 0.5 * c->plan.model.mu_overlap, c->jconst, st);
   chk(hipGetLastError(), "exchange launch");
 }
@@ -428,6 +506,7 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
     S.nbr1 = int32_t(P.nbr_ptr[s + 1]);
     S.pad_ = 0;
     S.traj_off = b.traj_off;
+    S.zoff = b.traj_off;
     S.ring_off = ring_off;
     S.adj_off = adj_off;
     S.ctrl_off = b.ctrl_off;
@@ -567,6 +646,12 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
   c->d_tiles = upload(c, c->tiles, st);
   c->d_order = upload(c, c->h_order, st);
   c->d_gsub = upload(c, std::vector<SubDev>{G}, st);
+  {
+    std::vector<int32_t> id(std::max<int>(c->maxlev, m.nsteps + 1));
+    for (size_t i = 0; i < id.size(); ++i) id[i] = int32_t(i);
+    c->d_zslot_id = upload(c, id, st);
+    c->d_zslot = c->d_zslot_id;
+  }
   c->d_gtiles = upload(c, gt, st);
   c->rows64 = upload(c, r64, st);
   c->cosx64 = upload(c, c64, st);
@@ -601,9 +686,11 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
   c->nonfinite = dalloc<uint32_t>(c, 1);
   chk(hipMemsetAsync(c->nonfinite, 0, sizeof(uint32_t), st), "memset");
   // large arenas
-  c->traj = dalloc<char>(c, size_t(P.traj_total) * tsz);
+  c->traj_bytes = size_t(P.traj_total) * tsz;
+  c->traj = dalloc<char>(c, c->traj_bytes);
   c->targ = dalloc<char>(c, size_t(P.traj_total) * tsz);
-  c->ring = dalloc<char>(c, size_t(std::max<int64_t>(ring_off, 1)) * tsz);
+  c->ring_bytes = size_t(std::max<int64_t>(ring_off, 1)) * tsz;
+  c->ring = dalloc<char>(c, c->ring_bytes);
   c->adj = dalloc<char>(c, size_t(std::max<int64_t>(adj_off, 1)) * tsz);
   chk(hipMemsetAsync(c->ring, 0, size_t(std::max<int64_t>(ring_off, 1)) * tsz, st), "memset ring");
   chk(hipMemsetAsync(c->targ, 0, size_t(P.traj_total) * tsz, st), "memset targets");
@@ -724,6 +811,8 @@ dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode) {
   if (mode >= 2 && !ctx->box_ok)
     return fail(ctx, DD4DVAR_E_INVALID,
                 "persistent per-box sweeps need FP32 state and boxes that fit one workgroup's LDS");
+  if (mode >= 2 && ctx->ckpt)
+    return fail(ctx, DD4DVAR_E_INVALID, "persistent per-box sweeps store every level (checkpoints on)");
   ctx->exec_mode = mode;
   return DD4DVAR_OK;
 }
@@ -796,6 +885,71 @@ dd4dvar_status dd4dvar_local_cost_grad(dd4dvar_ctx* ctx, int32_t nsub, const int
   })
 }
 
+dd4dvar_status dd4dvar_set_checkpointing(dd4dvar_ctx* ctx, int32_t stride, int64_t* state_bytes) {
+  if (!ctx) return fail(ctx, DD4DVAR_E_INVALID, "null context");
+  if (stride != 0 && stride < 3) return fail(ctx, DD4DVAR_E_INVALID, "stride must be 0 or >= 3");
+  if (stride != 0 && ctx->exec_mode >= 2)
+    return fail(ctx, DD4DVAR_E_INVALID, "persistent per-box sweeps store every level");
+  API_GUARD(ctx, {
+    const size_t tsz = ctx->prec == DD4DVAR_FP64 ? sizeof(double) : sizeof(float);
+    const int maxl = ctx->maxlev - 1;
+    std::vector<int32_t> slot(ctx->maxlev);
+    int nslot = 0;
+    if (stride) {
+      const int K = maxl / stride + 1;                 // checkpoint pairs
+      for (int n = 0; n <= maxl; ++n) {
+        const int r = n % stride;
+        slot[n] = r < 2 ? 2 * (n / stride) + r : 2 * K + r - 2;
+      }
+      nslot = 2 * K + stride - 2;
+    }
+    // each box gets as many slots as its own levels reach
+    std::vector<SubDev> subs = ctx->subs;
+    int64_t off = 0;
+    for (SubDev& S : subs) {
+      int need = S.nlev;
+      if (stride) {
+        need = 0;
+        for (int n = 0; n < S.nlev; ++n) need = std::max(need, slot[n] + 1);
+      }
+      S.zoff = off;
+      off += int64_t(need) * 3 * S.ncell;
+    }
+    const size_t bytes = size_t(std::max<int64_t>(off, 1)) * tsz;
+    chk(hipDeviceSynchronize(), "sync");
+    // graphs recorded with the old arena would read freed memory
+    for (dd4dvar_ctx::GraphEntry& g : ctx->graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipGraphDestroy(g.graph);
+    }
+    ctx->graphs.clear();
+    void* fresh = nullptr;
+    chk(hipMalloc(&fresh, bytes), "hipMalloc state arena");
+    auto& owned = ctx->mem.owned;
+    owned.erase(std::remove(owned.begin(), owned.end(), ctx->traj), owned.end());
+    (void)hipFree(ctx->traj);
+    ctx->traj = fresh;
+    owned.push_back(fresh);
+    ctx->traj_bytes = bytes;
+    if (stride && !ctx->ring_next) ctx->ring_next = dalloc<char>(ctx, ctx->ring_bytes);
+    if (stride) {
+      if (ctx->d_zslot == ctx->d_zslot_id) ctx->d_zslot = dalloc<int32_t>(ctx, ctx->maxlev);
+      chk(hipMemcpy(ctx->d_zslot, slot.data(), slot.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+          "upload slots");
+    } else {
+      ctx->d_zslot = ctx->d_zslot_id;
+    }
+    chk(hipMemcpy(ctx->d_subs, subs.data(), subs.size() * sizeof(SubDev), hipMemcpyHostToDevice),
+        "upload subdomains");
+    ctx->subs = subs;
+    ctx->ckpt = stride;
+    ctx->nslot = nslot;
+    ctx->have_forward = false;
+    if (state_bytes) *state_bytes = int64_t(bytes);
+    return DD4DVAR_OK;
+  })
+}
+
 dd4dvar_status dd4dvar_set_graph(dd4dvar_ctx* ctx, int32_t on) {
   if (!ctx) return fail(ctx, DD4DVAR_E_INVALID, "null context");
   ctx->use_graph = on != 0;
@@ -813,7 +967,7 @@ dd4dvar_status dd4dvar_autotune(dd4dvar_ctx* ctx, const double* x_dev, double* J
     // (one launch per sweep, or fused) with the smallest pass count that
     // holds the largest box and with the maximum one
     std::vector<std::pair<int, int>> cand = {{0, ctx->box_k}};
-    if (ctx->box_ok) {
+    if (ctx->box_ok && !ctx->ckpt) {
       const int kmin = ctx->box_k, kmax = box_passes_max();
       cand.push_back({2, kmin});
       if (kmax != kmin) cand.push_back({2, kmax});
@@ -879,13 +1033,10 @@ dd4dvar_status dd4dvar_forward_integrate(dd4dvar_ctx* ctx, int32_t scope, const 
       chk(hipGetLastError(), "global forward");
       return DD4DVAR_OK;
     }
-    if (ctx->prec == DD4DVAR_FP64) {
-      local_forward<double>(ctx, x_dev, st);
-      if (traj_dev) launch_traj_out<double>(local_dom<double>(ctx), traj_dev, 0, ctx->ntiles, st);
-    } else {
-      local_forward<float>(ctx, x_dev, st);
-      if (traj_dev) launch_traj_out<float>(local_dom<float>(ctx), traj_dev, 0, ctx->ntiles, st);
-    }
+    if (ctx->prec == DD4DVAR_FP64)
+      local_forward<double>(ctx, x_dev, st, traj_dev);
+    else
+      local_forward<float>(ctx, x_dev, st, traj_dev);
     chk(hipGetLastError(), "trajectory output");
     return DD4DVAR_OK;
   })
@@ -921,6 +1072,14 @@ dd4dvar_status dd4dvar_gather(dd4dvar_ctx* ctx, int32_t level, double* out_dev, 
   if (!ctx || !out_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
   if (level < 0 || level > ctx->plan.model.nsteps) return fail(ctx, DD4DVAR_E_INVALID, "bad level");
   if (!ctx->have_forward) return fail(ctx, DD4DVAR_E_STATE, "gather before any forward");
+  if (ctx->ckpt) {
+    // only checkpoint levels stay stored
+    for (const SubDev& S : ctx->subs) {
+      const int n = level - S.lev0;
+      if (n >= 0 && n < S.nlev && n % ctx->ckpt >= 2)
+        return fail(ctx, DD4DVAR_E_STATE, "level not stored: checkpoints keep levels kc, kc+1 only");
+    }
+  }
   API_GUARD(ctx, {
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t ncell = int64_t(ctx->plan.model.nlat) * ctx->plan.model.nlon;

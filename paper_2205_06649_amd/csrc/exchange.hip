@@ -74,9 +74,10 @@ __global__ void k_ring_from_global(Dom<T> D, const double* __restrict__ bg, int6
   }
 }
 
+// every level (level < 0) or one local level of the boxes box_base, ...
 template <typename T>
-__global__ void k_ring_from_local(Dom<T> D) {
-  const SubDev S = D.subs[blockIdx.x];
+__global__ void k_ring_from_local(Dom<T> D, int box_base, int level) {
+  const SubDev S = D.subs[box_base + blockIdx.x];
   const int k = blockIdx.y * blockDim.x + threadIdx.x;
   if (k >= S.nring) return;
   const int src = D.hsrc[S.hmap_off + k];
@@ -84,8 +85,9 @@ __global__ void k_ring_from_local(Dom<T> D) {
   const SubDev P = D.subs[src];
   const int64_t off = D.hoff[S.hmap_off + k];
   const T sg = T(D.hsign[S.hmap_off + k]);
-  for (int n = 0; n < S.nlev; ++n) {   // same interval: same levels
-    const T* Z = D.traj + P.traj_off + int64_t(n) * 3 * P.ncell;
+  const int n0 = level < 0 ? 0 : level, n1 = level < 0 ? S.nlev : (level < S.nlev ? level + 1 : level);
+  for (int n = n0; n < n1; ++n) {   // same interval: same levels
+    const T* Z = zlevel(D, P, n);
     T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
     R[k] = Z[off];
     R[S.nring + k] = sg * Z[P.ncell + off];
@@ -94,10 +96,10 @@ __global__ void k_ring_from_local(Dom<T> D) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int n,
+__global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int n, int tile_base,
                                                               double* __restrict__ jc) {
   __shared__ double red[kTile / 64];
-  const int w = xcd_tile(blockIdx.x, gridDim.x);
+  const int w = tile_base + xcd_tile(blockIdx.x, gridDim.x);
   const int2 wt = D.tiles[w];
   const SubDev S = D.subs[wt.x];
   if (n >= S.nlev) return;                 // uniform over the block
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int n,
         int cc = gcol - P.col0;
         if (cc < 0) cc += D.nlon;
         if (cc >= P.nx) continue;
-        const T* Z = D.traj + P.traj_off + int64_t(gl - P.lev0) * 3 * P.ncell + int64_t(rr) * P.nx + cc;
+        const T* Z = zlevel(D, P, gl - P.lev0) + int64_t(rr) * P.nx + cc;
         sh += double(Z[0]);
         su += double(Z[P.ncell]);
         sv += double(Z[2 * P.ncell]);
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int n,
         int cc = gcol - P.col0;
         if (cc < 0) cc += D.nlon;
         if (cc >= P.nx) continue;
-        const T* Z = D.traj + P.traj_off + int64_t(gl - P.lev0) * 3 * P.ncell + int64_t(rr) * P.nx + cc;
+        const T* Z = zlevel(D, P, gl - P.lev0) + int64_t(rr) * P.nx + cc;
         const double a = double(Z[0]) - mh, b = double(Z[P.ncell]) - mu, e = double(Z[2 * P.ncell]) - mv;
         dh += a * a;
         du += b * b;
@@ -182,8 +184,7 @@ __global__ void k_gather(Dom<T> D, int nspace, int ntime, int level, int64_t nce
       if (level < S.lev0 || level >= S.lev0 + S.nlev) continue;
       int cc = col - S.col0;
       if (cc < 0) cc += D.nlon;
-      const T* Z = D.traj + S.traj_off + int64_t(level - S.lev0) * 3 * S.ncell +
-                   int64_t(row - S.row0) * S.nx + cc;
+      const T* Z = zlevel(D, S, level - S.lev0) + int64_t(row - S.row0) * S.nx + cc;
       ah += double(Z[0]);
       au += double(Z[S.ncell]);
       av += double(Z[2 * S.ncell]);
@@ -222,12 +223,16 @@ void launch_ring_from_global(const Dom<T>& D, int nsub, int ring_blocks, const d
                      gplane);
 }
 template <typename T>
-void launch_ring_from_local(const Dom<T>& D, int nsub, int ring_blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_ring_from_local<T>, dim3(nsub, ring_blocks), dim3(256), 0, st, D);
+void launch_ring_from_local(const Dom<T>& D, int box_base, int nbox, int ring_blocks, int level,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_ring_from_local<T>, dim3(nbox, ring_blocks), dim3(256), 0, st, D, box_base,
+                     level);
 }
 template <typename T>
-void launch_targets_from_local(const Dom<T>& D, int level, int ntiles, double* jc, hipStream_t st) {
-  hipLaunchKernelGGL(k_targets_from_local<T>, dim3(ntiles), dim3(kTile), 0, st, D, level, jc);
+void launch_targets_from_local(const Dom<T>& D, int level, int tile_base, int ntiles, double* jc,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_targets_from_local<T>, dim3(ntiles), dim3(kTile), 0, st, D, level, tile_base,
+                     jc);
 }
 void launch_reduce_jconst(const SubDev* subs, int nsub, const double* jc, double half_mu,
                           double* jconst, hipStream_t st) {
@@ -255,8 +260,8 @@ void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
                                       hipStream_t);                                              \
   template void launch_ring_from_global<T>(const Dom<T>&, int, int, const double*, int64_t,      \
                                            hipStream_t);                                         \
-  template void launch_ring_from_local<T>(const Dom<T>&, int, int, hipStream_t);                 \
-  template void launch_targets_from_local<T>(const Dom<T>&, int, int, double*, hipStream_t);     \
+  template void launch_ring_from_local<T>(const Dom<T>&, int, int, int, int, hipStream_t);       \
+  template void launch_targets_from_local<T>(const Dom<T>&, int, int, int, double*, hipStream_t); \
   template void launch_gather<T>(const Dom<T>&, int, int, int, int64_t, const int32_t*,          \
                                  const int32_t*, double*, hipStream_t);
 DD4DVAR_INST(float)

@@ -27,12 +27,13 @@ struct SubDev {
   int32_t ncell, nring, tile0, ntile;
   int32_t nbr0, nbr1;        // neighbour list range
   int32_t pad_;
-  int64_t traj_off;          // state arena (and packed FP64 trajectory) offset
+  int64_t traj_off;          // packed FP64 trajectory and overlap-target offset
   int64_t ring_off;          // ring arena offset, level stride 3*nring
   int64_t adj_off;           // adjoint arena offset: 3 slots x 3 x ncell
   int64_t ctrl_off;          // packed control offset
   int64_t cell_off;          // per-cell coverage offset
   int64_t hmap_off;          // halo map offset
+  int64_t zoff;              // state arena offset (level slots, see Dom::zslot)
 };
 
 // Per-row coefficients of the discrete increment.
@@ -50,7 +51,7 @@ template <typename T>
 struct Dom {
   const SubDev* subs;
   const int2* tiles;         // (subdomain, tile within subdomain)
-  T* traj;                   // [nlev][3][ncell] per subdomain, h stored as h - h_ref
+  T* traj;                   // [slots][3][ncell] per subdomain, h stored as h - h_ref
   T* ring;                   // [nlev][3][nring] per subdomain, signs applied
   T* targ;                   // mean overlap target, traj layout
   T* adj;                    // rolling adjoint levels
@@ -69,10 +70,20 @@ struct Dom {
   const int32_t* hsign;
   const int32_t* hgcell;
   const uint8_t* active;     // per subdomain, 0 = skip (nullptr = all active)
+  // slot of the state arena holding each local level: the level itself when
+  // every level is stored; with checkpoints, level pairs n = kc, kc+1 keep
+  // their own slots and the others share a segment that the adjoint refills
+  const int32_t* zslot;
   T st, stg, h0;
   double mu;
   double isb2[3];            // 1 / sigma_b^2
   int32_t nlon, half, maxlev, weight_mode;
 };
+
+// state of local level n of subdomain S
+template <typename T>
+__device__ __forceinline__ T* zlevel(const Dom<T>& D, const SubDev& S, int n) {
+  return D.traj + S.zoff + int64_t(D.zslot[n]) * 3 * S.ncell;
+}
 
 }  // namespace dd4dvar

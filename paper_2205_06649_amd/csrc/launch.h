@@ -17,7 +17,8 @@ void launch_adj(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, con
 void launch_reduce_j(const SubDev* subs, int count, const int32_t* ids, const double* jpart,
                      const double* jconst, double* J, uint32_t* nonfinite, hipStream_t st);
 template <typename T>
-void launch_traj_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hipStream_t st);
+void launch_traj_out(const Dom<T>& D, double* out, int tile_base, int ntiles, int level,
+                     hipStream_t st);
 
 // exchange.hip
 template <typename T>
@@ -27,9 +28,10 @@ template <typename T>
 void launch_ring_from_global(const Dom<T>& D, int nsub, int ring_blocks, const double* bg,
                              int64_t gplane, hipStream_t st);
 template <typename T>
-void launch_ring_from_local(const Dom<T>& D, int nsub, int ring_blocks, hipStream_t st);
+void launch_ring_from_local(const Dom<T>& D, int box_base, int nbox, int ring_blocks, int level,
+                            hipStream_t st);
 template <typename T>
-void launch_targets_from_local(const Dom<T>& D, int level, int ntiles, double* jc,
+void launch_targets_from_local(const Dom<T>& D, int level, int tile_base, int ntiles, double* jc,
                                hipStream_t st);
 void launch_reduce_jconst(const SubDev* subs, int nsub, const double* jc, double half_mu,
                           double* jconst, hipStream_t st);

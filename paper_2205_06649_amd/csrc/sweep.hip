@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kTile) void k_init(Dom<T> D, const double* __restri
   const int m = wt.y * kTile + threadIdx.x;
   if (m >= S.ncell) return;
   const double* xs = x + S.ctrl_off;
-  T* Z = D.traj + S.traj_off;
+  T* Z = zlevel(D, S, 0);
   Z[m] = T(xs[m] - double(D.h0));
   Z[S.ncell + m] = T(xs[S.ncell + m]);
   Z[2 * S.ncell + m] = T(xs[2 * S.ncell + m]);
@@ -57,11 +57,11 @@ __global__ __launch_bounds__(kTile) void k_fwd(Dom<T> D, int n, int tile_base) {
   if (m >= S.ncell) return;
   const int r = m / S.nx, c = m - r * S.nx;
   const int64_t plane = S.ncell;
-  const T* Z = D.traj + S.traj_off + int64_t(n) * 3 * plane;
+  const T* Z = zlevel(D, S, n);
   const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
   const NbrIdx q = nbr_index(S, r, c, D.half);
   // level n-1 (level 0 itself for the Euler start, whose base is Z^0)
-  const T* P = n >= 1 ? Z - 3 * plane : Z;
+  const T* P = n >= 1 ? zlevel(D, S, n - 1) : Z;
   const int j = S.row0 + r;
   // every load first, unconditionally
   const V3<T> C = ld_box(Z, plane, m, T(1));
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kTile) void k_fwd(Dom<T> D, int n, int tile_base) {
   const T H = -rc.a1 * (h0 * (E.u - W.u) + (E.h * E.u - W.h * W.u))
               - rc.a3 * (h0 * (N.v * cN - Sv.v * cS) + (N.h * N.v * cN - Sv.h * Sv.v * cS));
   const T wgt = n == 0 ? T(0.5) : T(1);
-  T* out = const_cast<T*>(Z) + 3 * plane;
+  T* out = zlevel(D, S, n + 1);
   out[m] = B.h + wgt * H;
   out[plane + m] = B.u + wgt * U;
   out[2 * plane + m] = B.v + wgt * V;
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kTile) void k_adj(Dom<T> D, int n, int tile_base,
   const bool valid = m < S.ncell;
   const int mm = valid ? m : 0;           // a valid address for inactive lanes
   const int64_t plane = S.ncell;
-  const T* Z = D.traj + S.traj_off + int64_t(n) * 3 * plane;
+  const T* Z = zlevel(D, S, n);
   const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
   T* A = D.adj + S.adj_off;
   const bool has1 = n + 1 <= L, has2 = n + 2 <= L;       // uniform
@@ -258,16 +258,18 @@ __global__ void k_reduce_j(const SubDev* __restrict__ subs, int count, const int
 }
 #endif
 
-// packed FP64 trajectory output (h + h_ref)
+// packed FP64 trajectory output (h + h_ref): every level (level < 0) or one
 template <typename T>
-__global__ __launch_bounds__(kTile) void k_traj_out(Dom<T> D, double* __restrict__ out, int tile_base) {
+__global__ __launch_bounds__(kTile) void k_traj_out(Dom<T> D, double* __restrict__ out, int tile_base,
+                                                    int level) {
   const int2 wt = D.tiles[tile_base + xcd_tile(blockIdx.x, gridDim.x)];
   const SubDev S = D.subs[wt.x];
   const int m = wt.y * kTile + threadIdx.x;
   if (m >= S.ncell) return;
   const int64_t plane = S.ncell;
-  for (int n = 0; n < S.nlev; ++n) {
-    const T* Z = D.traj + S.traj_off + int64_t(n) * 3 * plane;
+  const int n0 = level < 0 ? 0 : level, n1 = level < 0 ? S.nlev : (level < S.nlev ? level + 1 : level);
+  for (int n = n0; n < n1; ++n) {
+    const T* Z = zlevel(D, S, n);
     double* o = out + S.traj_off + int64_t(n) * 3 * plane;
     o[m] = double(Z[m]) + double(D.h0);
     o[plane + m] = double(Z[plane + m]);
@@ -305,8 +307,9 @@ void launch_reduce_j(const SubDev* subs, int count, const int32_t* ids, const do
 }
 #endif
 template <typename T>
-void launch_traj_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hipStream_t st) {
-  hipLaunchKernelGGL(k_traj_out<T>, dim3(ntiles), dim3(kTile), 0, st, D, out, tile_base);
+void launch_traj_out(const Dom<T>& D, double* out, int tile_base, int ntiles, int level,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_traj_out<T>, dim3(ntiles), dim3(kTile), 0, st, D, out, tile_base, level);
 }
 
 #define DD4DVAR_INST(T)                                                                        \
@@ -314,7 +317,7 @@ void launch_traj_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hi
   template void launch_fwd<T>(const Dom<T>&, int, int, int, hipStream_t);                      \
   template void launch_adj<T>(const Dom<T>&, int, int, int, int, const double*, const double*, \
                               const double*, double*, hipStream_t);                            \
-  template void launch_traj_out<T>(const Dom<T>&, double*, int, int, hipStream_t);
+  template void launch_traj_out<T>(const Dom<T>&, double*, int, int, int, hipStream_t);
 // This source is compiled once per state type: FP32 with the compiler's
 // default contraction, FP64 with -ffp-contract=off so that FP64 results follow
 // the rounding of the separate multiplies and adds of the reference.
