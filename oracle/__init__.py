@@ -24,10 +24,13 @@ regularized inverse ill-posed problems in 4D variational data assimilation"):
                  (eq. eq:cost:parallel1) and its gradient.
 * ``lbfgs``   -- limited-memory BFGS with Armijo backtracking (the L-BFGS
                  variant named in the remark after Alg. 5).
+* ``gn``      -- the Gauss-Newton local solver (Alg. 5 / Alg. 6): normal
+                 matrix products (eq. line5and7) from the TLM and the adjoint,
+                 conjugate gradients in the B^{1/2}-preconditioned variables.
 * ``dd``      -- Alg. 1 (DD-4DVar): background run, local solves, exchange,
                  gather.
 * ``brute``   -- per-cell pure-Python loops for tiny grids (a pin).
 
 Readings of points the paper leaves open are stated where they are used.
 """
-from . import model, ddmaps, local, lbfgs, dd, brute  # noqa: F401
+from . import model, ddmaps, local, lbfgs, gn, dd, brute  # noqa: F401

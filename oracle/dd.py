@@ -23,6 +23,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import ddmaps as ddm
+from . import gn
 from . import lbfgs
 from . import local
 from . import model
@@ -66,7 +67,11 @@ def gather(prob, maps, trajs, level=0):
 
 
 def solve(prob, maps=None, max_outer=5, outer_tol=1e-6, lbfgs_m=8, max_iter=50,
-          grad_rtol=0.0, max_ls=30, c1=1e-4, verbose=False):
+          grad_rtol=0.0, max_ls=30, c1=1e-4, verbose=False, local_solver="lbfgs",
+          cg_max_iter=50, cg_rtol=1e-6):
+    """Alg. 1.  ``local_solver`` "lbfgs" (the default) or "gn": Gauss-Newton
+    (Alg. 5 / Alg. 6, see ``gn``) with ``max_iter`` updates per local solve and
+    conjugate gradients of at most ``cg_max_iter`` iterations."""
     if maps is None:
         maps = ddm.build(prob)
     bg, trajs = background(prob, maps)
@@ -89,8 +94,15 @@ def solve(prob, maps=None, max_outer=5, outer_tol=1e-6, lbfgs_m=8, max_iter=50,
                 return J, (sb * gr).ravel()
 
             xi0 = ((xs[s] - xb[s]) / sb).ravel()
-            res = lbfgs.minimize(fun, xi0, m=lbfgs_m, max_iter=max_iter,
-                                 grad_rtol=grad_rtol, c1=c1, max_ls=max_ls)
+            if local_solver == "gn":
+                res = gn.minimize(prob, maps, s, xs[s], xb[s], rings[s],
+                                  {k: targets[k] for k in maps.neighbors[s]}, max_iter=max_iter,
+                                  grad_rtol=grad_rtol, cg_max_iter=cg_max_iter, cg_rtol=cg_rtol)
+                res["x"] = res["xi"].ravel()
+                report["cg_iters"] = report.get("cg_iters", 0) + res["cg_iters"]
+            else:
+                res = lbfgs.minimize(fun, xi0, m=lbfgs_m, max_iter=max_iter,
+                                     grad_rtol=grad_rtol, c1=c1, max_ls=max_ls)
             report["evals"] += res["nfev"]
             new_xs[s] = xb[s] + sb * res["x"].reshape(shape)
             step = max(step, float(np.max(np.abs(res["x"] - xi0))))

@@ -13,7 +13,7 @@ import pytest
 
 import synth
 from conftest import custom_problem, problem
-from oracle import brute, dd, ddmaps, lbfgs, local, model
+from oracle import brute, dd, ddmaps, gn, lbfgs, local, model
 
 
 def _grid(p):
@@ -410,6 +410,34 @@ def test_normal_equations_global():
     assert np.linalg.norm(dx_l - dx_star) <= 1e-8 * np.linalg.norm(dx_star)
 
 
+def _dense_normal_matrix(p, maps, s, g, rings, x):
+    """Dense B^-1 + M^T W M of subdomain s about control x, from TLM columns
+    and weights W enumerated residual by residual."""
+    b = maps.boxes[s]
+    geo = local.LocalGeometry(g, maps, s)
+    lt = local.forward(geo, x, rings[s])
+    n = x.size
+    M = _dense_tlm(lambda e: local.tlm(geo, lt, rings[s], e.reshape(x.shape)), n)
+    W = np.zeros(lt.size)
+    flat_idx = np.arange(lt.size).reshape(b.nlev, 3, -1)
+    _, csp = local.weights(p, maps, s)
+    for o in maps.obs_bin[s]:
+        cell = int(p.obs_cell[o])
+        loc = int(maps.box_index(b, cell // p.nlon, cell % p.nlon))
+        k = int(p.obs_step[o])
+        w = 1.0 / (csp[loc] * maps.time_count[k])
+        W[flat_idx[k - b.lev0, int(p.obs_field[o]), loc]] += p.lambda_obs * w / p.obs_sigma[o] ** 2
+    gr_, gc_ = maps.box_cells_global(b)
+    for sp in maps.neighbors[s]:
+        bp = maps.boxes[int(sp)]
+        mine = np.nonzero(maps.box_index(bp, gr_, gc_) >= 0)[0]
+        for lev in range(max(b.lev0, bp.lev0), min(b.lev0 + b.nlev, bp.lev0 + bp.nlev)):
+            for f in range(3):
+                W[flat_idx[lev - b.lev0, f, mine]] += p.mu_overlap / p.sigma_b[f] ** 2
+    Binv = (local.weights(p, maps, s)[0][None, :] / (p.sigma_b ** 2)[:, None]).ravel()
+    return np.diag(Binv) + M.T @ (W[:, None] * M), lt, W
+
+
 def test_normal_equations_local():
     """Same closed form for one subdomain of a 2x2x2 decomposition: obs and
     overlap penalties act as weighted observations of the local trajectory,
@@ -461,6 +489,105 @@ def test_normal_equations_local():
     _, g1 = local.cost_grad(p, maps, s, xb + dprobe.reshape(xb.shape), xb, rings[s], nb)
     pred = A @ dprobe
     assert np.linalg.norm((g1 - g0).ravel() - pred) <= 1e-2 * np.linalg.norm(pred)
+
+
+# --- P7 (Gauss-Newton): the local solver of Alg. 5 / Alg. 6 ------------------
+def _perturbed_local(p, maps, trajs, s, seed, scale=0.3):
+    r = np.random.default_rng(seed)
+    return trajs[s][0] + scale * p.sigma_b[:, None, None] * r.standard_normal(trajs[s][0].shape)
+
+
+@pytest.mark.parametrize("s", [0, 6])
+def test_gn_normal_matrix_product(s):
+    """gn.hessvec is the dense normal matrix of eq. line5and7 (TLM columns,
+    weights enumerated residual by residual) applied to a vector, about a
+    perturbed control; gn.residual_weights equals that enumeration."""
+    p = problem("tiny2")
+    g, maps, trajs, rings = _local_setup(p)
+    x = _perturbed_local(p, maps, trajs, s, seed=11)
+    A, lt, W = _dense_normal_matrix(p, maps, s, g, rings, x)
+    np.testing.assert_allclose(gn.residual_weights(p, maps, s).ravel(), W, rtol=1e-15, atol=0)
+    v = np.random.default_rng(12).standard_normal(x.shape)
+    Av = gn.hessvec(p, maps, s, lt, rings[s], v)
+    ref = A @ v.ravel()
+    assert np.linalg.norm(Av.ravel() - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_gn_step_solves_normal_equations():
+    """One Gauss-Newton update with conjugate gradients run to convergence is
+    the closed-form solution of the normal equations, delta x* = -A^-1 grad J."""
+    p = problem("tiny2")
+    g, maps, trajs, rings = _local_setup(p)
+    s = 6
+    x0 = _perturbed_local(p, maps, trajs, s, seed=13)
+    xb = trajs[s][0]
+    nb = {k: trajs[k] for k in maps.neighbors[s]}
+    A, _, _ = _dense_normal_matrix(p, maps, s, g, rings, x0)
+    _, g0 = local.cost_grad(p, maps, s, x0, xb, rings[s], nb)
+    dx_star = np.linalg.solve(A, -g0.ravel())
+    res = gn.minimize(p, maps, s, x0, xb, rings[s], nb, max_iter=1, cg_max_iter=10 * x0.size,
+                      cg_rtol=1e-14)
+    assert res["iters"] == 1 and res["cg_iters"] <= 10 * x0.size
+    assert np.linalg.norm((res["x"] - x0).ravel() - dx_star) <= 1e-8 * np.linalg.norm(dx_star)
+
+
+def test_gn_quadratic_functional_one_step():
+    """Without observations and overlap penalty J_s is the background term
+    alone, a quadratic: one Gauss-Newton update lands on x^b from any start."""
+    p = problem("c1")
+    p = p.replace(obs_step=p.obs_step[:0], obs_cell=p.obs_cell[:0], obs_field=p.obs_field[:0],
+                  obs_value=p.obs_value[:0], obs_sigma=p.obs_sigma[:0], obs_noise=p.obs_noise[:0],
+                  mu_overlap=0.0)
+    g, maps, trajs, rings = _local_setup(p)
+    for s in (0, len(maps.boxes) - 1):
+        xb = trajs[s][0]
+        x0 = _perturbed_local(p, maps, trajs, s, seed=14)
+        nb = {k: trajs[k] for k in maps.neighbors[s]}
+        res = gn.minimize(p, maps, s, x0, xb, rings[s], nb, max_iter=1, cg_max_iter=200,
+                          cg_rtol=1e-15)
+        err = np.abs(res["x"] - xb) / p.sigma_b[:, None, None]
+        assert np.max(err) <= 1e-10 and res["J"] <= 1e-18 * max(1.0, res["history"][0])
+
+
+@pytest.mark.parametrize("which,s", [("tiny2", 6), ("c1", 3)])
+def test_gn_converges_to_local_minimizer(which, s):
+    """Gauss-Newton drives the gradient of J_s to zero (fast local
+    convergence on these small-residual problems) at the minimizer that
+    L-BFGS (pinned on quadratics) reaches."""
+    p = problem(which)
+    g, maps, trajs, rings = _local_setup(p)
+    xb = trajs[s][0]
+    x0 = _perturbed_local(p, maps, trajs, s, seed=15, scale=0.2)
+    nb = {k: trajs[k] for k in maps.neighbors[s]}
+    res = gn.minimize(p, maps, s, x0, xb, rings[s], nb, max_iter=6, cg_max_iter=400, cg_rtol=1e-12)
+    assert res["gnorm"] <= 1e-8 * res["g0norm"]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(res["history"], res["history"][1:]))
+    sb = p.sigma_b[:, None, None]
+
+    def fun(xi):
+        xx = xb + sb * xi.reshape(xb.shape)
+        J, gr = local.cost_grad(p, maps, s, xx, xb, rings[s], nb)
+        return J, (sb * gr).ravel()
+
+    lb = lbfgs.minimize(fun, ((x0 - xb) / sb).ravel(), max_iter=2000, grad_rtol=1e-10)
+    x_lb = xb + sb * lb["x"].reshape(xb.shape)
+    assert np.linalg.norm((res["x"] - x_lb) / sb) <= 1e-6 * np.linalg.norm((res["x"] - xb) / sb)
+
+
+def test_dd_solve_gauss_newton():
+    """Alg. 1 with the Gauss-Newton local solver: the analysis improves on
+    the background, and with converged local solves it is the fixed point
+    that the L-BFGS local solver reaches."""
+    p = problem("tiny2")
+    xa, rep = dd.solve(p, max_outer=3, max_iter=5, local_solver="gn", cg_max_iter=300,
+                       cg_rtol=1e-12, outer_tol=0.0)
+    assert rep["outer"] == 3 and rep["cg_iters"] > 0
+    e_b = np.linalg.norm((p.xb0 - p.truth0) / p.sigma_b[:, None, None])
+    e_a = np.linalg.norm((xa - p.truth0) / p.sigma_b[:, None, None])
+    assert e_a < e_b
+    xl, _ = dd.solve(p, max_outer=3, max_iter=400, grad_rtol=1e-11, outer_tol=0.0)
+    sb = p.sigma_b[:, None, None]
+    assert np.linalg.norm((xa - xl) / sb) <= 1e-6 * np.linalg.norm((xl - p.xb0) / sb)
 
 
 # --- P10: map invariants -----------------------------------------------------
