@@ -204,6 +204,28 @@ dd4dvar_status dd4dvar_adjoint_integrate(dd4dvar_ctx* ctx, int32_t scope,
                                          const double* forcing_dev,
                                          double* adj0_dev, void* stream);
 
+/* Tangent linear model of the local sweeps (the TLM step of Alg. 6; the
+ * linearized restricted model, eq. restricted) about the trajectories of the
+ * last scope-1 forward (forward_integrate, local_cost_grad or exchange):
+ * dZ = M' dx for every subdomain from the packed FP64 control perturbation
+ * dx_dev; the frozen halo ring is not perturbed.  dtraj_dev (nullable)
+ * receives the packed FP64 perturbation trajectories (every level, h as is).
+ * Step kernels in every execution mode.  E_INVALID with checkpoints on,
+ * E_STATE if no forward ran.  Asynchronous. */
+dd4dvar_status dd4dvar_tangent_linear(dd4dvar_ctx* ctx, const double* dx_dev,
+                                      double* dtraj_dev, void* stream);
+
+/* Gauss-Newton normal matrix of each local functional (eqs. line5and7,
+ * Eq_matrixAV:1) applied to dx_dev, about the trajectories of the last
+ * scope-1 forward: out_dev = (B_w^{-1} + M'^T W M') dx_dev, with B_w^{-1}
+ * the background weight w^b / sigma_b^2 per control entry and W the weights
+ * of the observation and overlap residuals of J_s per trajectory entry.  The
+ * tangent-linear sweep then the adjoint sweep forced by W dZ (packed FP64 in
+ * and out, distinct buffers).  E_INVALID with checkpoints on or when
+ * dx_dev == out_dev, E_STATE if no forward ran.  Asynchronous. */
+dd4dvar_status dd4dvar_gn_hessvec(dd4dvar_ctx* ctx, const double* dx_dev,
+                                  double* out_dev, void* stream);
+
 /* Exchange (Alg. 1): integrates every subdomain from the packed controls
  * x_dev, then refreshes the frozen halo rings from the owners' trajectories
  * and the overlap targets from the neighbours' trajectories.  Asynchronous. */
@@ -307,17 +329,30 @@ typedef struct {
                            j_noise_rtol |J| (FP32 state: J carries ~1e-7
                            relative rounding noise, and backtracking below it
                            only burns evaluations) */
+  int32_t local_solver; /* 0 = L-BFGS (default); 1 = Gauss-Newton (Alg. 5 /
+                           Alg. 6): max_iter full updates per local solve,
+                           each solving the normal equations of eq. line5and7
+                           in xi by conjugate gradients from zero; stops at
+                           |g| <= grad_rtol |g0| like L-BFGS; needs every
+                           level stored (no checkpoints), else E_INVALID */
+  int32_t cg_max_iter;  /* CG iterations per Gauss-Newton update (>= 0) */
+  double cg_rtol;       /* CG stop at |r| <= cg_rtol |r0| (also stops when the
+                           curvature p^T A p is not positive) */
 } dd4dvar_solve_opts;
 
 typedef struct {
-  int32_t outer_iters, total_evals, lbfgs_iters;
+  int32_t outer_iters, total_evals;
+  int32_t lbfgs_iters;       /* local iterations (L-BFGS or Gauss-Newton), the
+                                maximum over subdomains summed over sweeps */
+  int32_t gn_products;       /* batched normal-matrix products (CG iterations) */
   double J_final;            /* sum over subdomains of the final local J */
   double gnorm_ratio_max;    /* max_s |g_s| / |g_s,0| at the end */
   double seconds;
 } dd4dvar_solve_report;
 
 /* Runs Alg. 1 from x_init_dev (packed controls, NULL = background): batched
- * L-BFGS over all subdomains in xi = (x - x^b_s) / sigma_b, then forward,
+ * local solves (L-BFGS, or Gauss-Newton with conjugate gradients, see
+ * local_solver) over all subdomains in xi = (x - x^b_s) / sigma_b, then forward,
  * exchange and the outer stop test; finally the partition-of-unity gather of
  * level 0 into xa_host [3][nlat][nlon].  x_out_dev (nullable) receives the
  * final packed controls.  Synchronous.  E_NOTCONVERGED when max_outer was

@@ -54,12 +54,13 @@ class dd4dvar_data_desc(C.Structure):
 class dd4dvar_solve_opts(C.Structure):
     _fields_ = [("lbfgs_m", C.c_int32), ("max_iter", C.c_int32), ("max_outer", C.c_int32),
                 ("max_ls", C.c_int32), ("grad_rtol", C.c_double), ("outer_tol", C.c_double),
-                ("armijo_c1", C.c_double), ("j_noise_rtol", C.c_double)]
+                ("armijo_c1", C.c_double), ("j_noise_rtol", C.c_double),
+                ("local_solver", C.c_int32), ("cg_max_iter", C.c_int32), ("cg_rtol", C.c_double)]
 
 
 class dd4dvar_solve_report(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("total_evals", C.c_int32),
-                ("lbfgs_iters", C.c_int32), ("J_final", C.c_double),
+                ("lbfgs_iters", C.c_int32), ("gn_products", C.c_int32), ("J_final", C.c_double),
                 ("gnorm_ratio_max", C.c_double), ("seconds", C.c_double)]
 
 
@@ -87,6 +88,8 @@ _SIGS = {
     "dd4dvar_local_cost_grad": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32), _VP, _VP, _VP, _VP]),
     "dd4dvar_forward_integrate": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP]),
     "dd4dvar_adjoint_integrate": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP]),
+    "dd4dvar_tangent_linear": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "dd4dvar_gn_hessvec": (C.c_int, [_VP, _VP, _VP, _VP]),
     "dd4dvar_exchange": (C.c_int, [_VP, _VP, _VP]),
     "dd4dvar_gather": (C.c_int, [_VP, C.c_int32, _VP, _VP]),
     "dd4dvar_set_exec_mode": (C.c_int, [_VP, C.c_int32]),
@@ -214,6 +217,14 @@ def dd4dvar_forward_integrate(ctx, scope, x_dev, traj_dev, stream=None):
 
 def dd4dvar_adjoint_integrate(ctx, scope, forcing_dev, adj0_dev, stream=None):
     check(lib().dd4dvar_adjoint_integrate(ctx, scope, forcing_dev, adj0_dev, stream), ctx)
+
+
+def dd4dvar_tangent_linear(ctx, dx_dev, dtraj_dev, stream=None):
+    check(lib().dd4dvar_tangent_linear(ctx, dx_dev, dtraj_dev, stream), ctx)
+
+
+def dd4dvar_gn_hessvec(ctx, dx_dev, out_dev, stream=None):
+    check(lib().dd4dvar_gn_hessvec(ctx, dx_dev, out_dev, stream), ctx)
 
 
 def dd4dvar_exchange(ctx, x_dev, stream=None):

@@ -26,6 +26,9 @@ HIP_UNITS = [
     ("sweep.hip", "sweep_f32.o", ["-DDD4DVAR_SWEEP_T=float", "-DDD4DVAR_SWEEP_PRIMARY=1"]),
     ("sweep.hip", "sweep_f64.o", ["-DDD4DVAR_SWEEP_T=double", "-DDD4DVAR_SWEEP_PRIMARY=0",
                                   "-ffp-contract=off"]),
+    ("tlm.hip", "tlm_f32.o", ["-DDD4DVAR_TLM_T=float"]),
+    ("tlm.hip", "tlm_f64.o", ["-DDD4DVAR_TLM_T=double", "-ffp-contract=off"]),
+    ("gn.hip", "gn.o", []),
     ("exchange.hip", "exchange.o", []),
     ("box.hip", "box.o", []),
     ("solve.hip", "solve.o", []),

@@ -128,6 +128,19 @@ class Context:
                                     self._stream())
         return out
 
+    def tangent_linear(self, dx, with_traj=True):
+        """dZ = M' dx about the trajectories of the last forward (packed
+        FP64 perturbation trajectories, or None)."""
+        out = self.empty(self.traj_len) if with_traj else None
+        L.dd4dvar_tangent_linear(self.handle, dx.data_ptr(), self.ptr(out), self._stream())
+        return out
+
+    def gn_hessvec(self, dx):
+        """(B_w^{-1} + M'^T W M') dx about the trajectories of the last forward."""
+        out = self.empty(self.ctrl_len)
+        L.dd4dvar_gn_hessvec(self.handle, dx.data_ptr(), out.data_ptr(), self._stream())
+        return out
+
     def exchange(self, x):
         L.dd4dvar_exchange(self.handle, x.data_ptr(), self._stream())
         self.traj_generation += 1
@@ -142,15 +155,19 @@ class Context:
     # relative rounding noise in J; FP64 runs the plain Armijo search
     J_NOISE_RTOL = {"fp64": 0.0, "fp32": 1e-6}
 
+    LOCAL_SOLVERS = {"lbfgs": 0, "gn": 1}
+
     def solve(self, lbfgs_m=8, max_iter=50, max_outer=5, max_ls=30, grad_rtol=0.0,
               outer_tol=1e-6, armijo_c1=1e-4, x_init=None, want_controls=False,
-              j_noise_rtol=None):
+              j_noise_rtol=None, local_solver="lbfgs", cg_max_iter=50, cg_rtol=1e-6):
         p = self.prob
         if j_noise_rtol is None:
             j_noise_rtol = self.J_NOISE_RTOL[self.precision]
         opts = L.dd4dvar_solve_opts(lbfgs_m=lbfgs_m, max_iter=max_iter, max_outer=max_outer,
                                     max_ls=max_ls, grad_rtol=grad_rtol, outer_tol=outer_tol,
-                                    armijo_c1=armijo_c1, j_noise_rtol=j_noise_rtol)
+                                    armijo_c1=armijo_c1, j_noise_rtol=j_noise_rtol,
+                                    local_solver=self.LOCAL_SOLVERS[local_solver],
+                                    cg_max_iter=cg_max_iter, cg_rtol=cg_rtol)
         xa = np.empty((3, p.nlat, p.nlon))
         xo = self.empty(self.ctrl_len) if want_controls else None
         st, rep = L.dd4dvar_solve(self.handle, opts, self.ptr(x_init), self.ptr(xo), xa)

@@ -24,6 +24,7 @@
 
 #include "kernels.h"
 #include "launch.h"
+#include "gn.h"
 #include "plan.h"
 #include "solve.h"
 
@@ -79,6 +80,7 @@ struct dd4dvar_ctx {
   int32_t* d_zslot = nullptr;           // slot of each local level
   int32_t* d_zslot_id = nullptr;        // identity (every level stored; global runs)
   void* ring_next = nullptr;            // exchange staging for the rings (with checkpoints)
+  void* dz = nullptr;                   // tangent-linear trajectory, every level (first use)
   size_t traj_bytes = 0, ring_bytes = 0;
   std::vector<int32_t> h_order;         // boxes, longest first
   int32_t* d_order = nullptr;
@@ -160,6 +162,7 @@ Dom<T> local_dom(const dd4dvar_ctx* c) {
   D.ring = static_cast<T*>(c->ring);
   D.targ = static_cast<T*>(c->targ);
   D.adj = static_cast<T*>(c->adj);
+  D.dz = static_cast<T*>(c->dz);
   D.rows = static_cast<const RowCoef<T>*>(c->rows);
   D.cosx = static_cast<const T*>(c->cosx);
   D.cover = c->cover;
@@ -275,7 +278,7 @@ void local_adjoint(dd4dvar_ctx* c, int mode, const double* x, const double* forc
                    const std::vector<int32_t>* ids, hipStream_t st) {
   Dom<T> D = local_dom<T>(c);
   if constexpr (std::is_same<T, float>::value) {
-    if (!ids && c->exec_mode >= 2) {
+    if (!ids && c->exec_mode >= 2 && mode != 3) {
       chk(launch_adj_box(D, mode, x, c->xb, forcing, out, c->d_order, c->nsub, c->box_lds, c->box_k,
                          c->box_span, st),
           "persistent adjoint launch");
@@ -309,6 +312,42 @@ void local_adjoint(dd4dvar_ctx* c, int mode, const double* x, const double* forc
       for (const SubDev& S : c->subs) run(S);
   }
   chk(hipGetLastError(), "adjoint launch");
+}
+
+// tangent-linear trajectory arena (every level, the layout of the state
+// arena without checkpoints), allocated on first use
+void ensure_dz(dd4dvar_ctx* c) {
+  if (c->dz) return;
+  const size_t tsz = c->prec == DD4DVAR_FP64 ? sizeof(double) : sizeof(float);
+  c->dz = dalloc<char>(c, size_t(c->plan.traj_total) * tsz);
+}
+
+// tangent-linear sweeps of every box (or of the boxes in c->eval_mask) about
+// the stored trajectory: dZ = M' dx, every level into the dz arena.  The
+// step kernels serve every execution mode (the persistent sweeps store the
+// same trajectory layout).
+template <typename T>
+void local_tlm(dd4dvar_ctx* c, const double* dx, hipStream_t st) {
+  ensure_dz(c);
+  Dom<T> D = local_dom<T>(c);
+  auto sweep = [&](int tile_base, int ntiles, int nlev) {
+    launch_tlm_init<T>(D, dx, tile_base, ntiles, st);
+    for (int n = 0; n + 1 < nlev; ++n) launch_tlm<T>(D, n, tile_base, ntiles, st);
+  };
+  if (c->exec_mode != 1) {
+    sweep(0, c->ntiles, c->maxlev);
+  } else {
+    for (const SubDev& S : c->subs) sweep(S.tile0, S.ntile, S.nlev);
+  }
+  chk(hipGetLastError(), "tangent-linear launch");
+}
+
+// M'^T W M' dx (no background block): the tangent-linear sweep, then the
+// adjoint sweep forced by the observation and overlap weights applied to dZ
+template <typename T>
+void gn_product(dd4dvar_ctx* c, const double* dx, double* out, hipStream_t st) {
+  local_tlm<T>(c, dx, st);
+  local_adjoint<T>(c, 3, nullptr, nullptr, out, nullptr, st);
 }
 
 void mark(dd4dvar_ctx* c, int which, hipStream_t st) {
@@ -1058,6 +1097,42 @@ dd4dvar_status dd4dvar_adjoint_integrate(dd4dvar_ctx* ctx, int32_t scope, const 
   })
 }
 
+dd4dvar_status dd4dvar_tangent_linear(dd4dvar_ctx* ctx, const double* dx_dev, double* dtraj_dev,
+                                      void* stream) {
+  if (!ctx || !dx_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  if (ctx->ckpt) return fail(ctx, DD4DVAR_E_INVALID, "the tangent-linear model needs every level stored");
+  if (!ctx->have_forward) return fail(ctx, DD4DVAR_E_STATE, "tangent-linear model before any forward");
+  API_GUARD(ctx, {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (ctx->prec == DD4DVAR_FP64) {
+      local_tlm<double>(ctx, dx_dev, st);
+      if (dtraj_dev) launch_dz_out<double>(local_dom<double>(ctx), dtraj_dev, 0, ctx->ntiles, st);
+    } else {
+      local_tlm<float>(ctx, dx_dev, st);
+      if (dtraj_dev) launch_dz_out<float>(local_dom<float>(ctx), dtraj_dev, 0, ctx->ntiles, st);
+    }
+    chk(hipGetLastError(), "tangent-linear output launch");
+    return DD4DVAR_OK;
+  })
+}
+
+dd4dvar_status dd4dvar_gn_hessvec(dd4dvar_ctx* ctx, const double* dx_dev, double* out_dev,
+                                  void* stream) {
+  if (!ctx || !dx_dev || !out_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  if (dx_dev == out_dev) return fail(ctx, DD4DVAR_E_INVALID, "dx_dev and out_dev must differ");
+  if (ctx->ckpt) return fail(ctx, DD4DVAR_E_INVALID, "Gauss-Newton products need every level stored");
+  if (!ctx->have_forward) return fail(ctx, DD4DVAR_E_STATE, "Gauss-Newton product before any forward");
+  API_GUARD(ctx, {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (ctx->prec == DD4DVAR_FP64) gn_product<double>(ctx, dx_dev, out_dev, st);
+    else gn_product<float>(ctx, dx_dev, out_dev, st);
+    launch_add_bdiag(ctx->d_subs, ctx->nsub, ctx->cover, ctx->plan.model.weight_mode,
+                     ctx->plan.sigma_b.data(), dx_dev, out_dev, st);
+    chk(hipGetLastError(), "background block launch");
+    return DD4DVAR_OK;
+  })
+}
+
 dd4dvar_status dd4dvar_exchange(dd4dvar_ctx* ctx, const double* x_dev, void* stream) {
   if (!ctx || !x_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
   API_GUARD(ctx, {
@@ -1157,8 +1232,10 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
   L.xt = B.get<double>(N);
   L.xphys = B.get<double>(N);
   L.gradx = B.get<double>(N);
-  L.S = B.get<double>(size_t(L.m) * N);
-  L.Y = B.get<double>(size_t(L.m) * N);
+  const bool use_gn = o->local_solver == 1;
+  // the pair memory only for L-BFGS
+  L.S = B.get<double>(use_gn ? 1 : size_t(L.m) * N);
+  L.Y = B.get<double>(use_gn ? 1 : size_t(L.m) * N);
   L.J = B.get<double>(nsub);
   L.Jt = B.get<double>(nsub);
   L.gd = B.get<double>(nsub);
@@ -1175,6 +1252,45 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
   L.trials = B.get<int32_t>(nsub);
   L.ls = B.get<uint8_t>(nsub);
   L.pending = B.get<int32_t>(1);
+  // Gauss-Newton state: iterate, evaluation, norms and stop flags shared
+  // with the L-BFGS state above, CG vectors of its own
+  GnState G{};
+  if (use_gn) {
+    G.subs = c->d_subs;
+    G.nsub = nsub;
+    G.max_iter = o->max_iter;
+    G.cg_max_iter = o->cg_max_iter;
+    G.weight_mode = c->plan.model.weight_mode;
+    G.N = N;
+    for (int f = 0; f < 3; ++f) G.sb[f] = c->plan.sigma_b[f];
+    G.grad_rtol = o->grad_rtol;
+    G.cg_rtol = o->cg_rtol;
+    G.xb = c->xb;
+    G.cover = c->cover;
+    G.xi = L.xi;
+    G.xi0 = L.xi0;
+    G.xphys = L.xphys;
+    G.gradx = L.gradx;
+    G.dxi = B.get<double>(N);
+    G.r = B.get<double>(N);
+    G.p = B.get<double>(N);
+    G.dx = B.get<double>(N);
+    G.hv = B.get<double>(N);
+    G.J = L.J;
+    G.Jt = L.Jt;
+    G.g0norm = L.g0norm;
+    G.gnorm = L.gnorm;
+    G.step = L.step;
+    G.rr = B.get<double>(nsub);
+    G.rr0 = B.get<double>(nsub);
+    G.status = L.status;
+    G.iters = L.iters;
+    G.cg_k = B.get<int32_t>(nsub);
+    G.cg_total = B.get<int32_t>(nsub);
+    G.gn_on = B.get<uint8_t>(nsub);
+    G.cg_on = B.get<uint8_t>(nsub);
+    G.pending = L.pending;
+  }
   double* xa_dev = B.get<double>(size_t(3) * c->plan.model.nlat * c->plan.model.nlon);
 
   struct MaskReset {
@@ -1184,7 +1300,7 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
 
   if (x_init) lb_from_x(L, x_init, st);
   else launch_fill(L.xi, N, 0.0, st);
-  int evals = 0, outer = 0, lbfgs_iters = 0;
+  int evals = 0, outer = 0, lbfgs_iters = 0, products = 0;
   bool met = false;
   std::vector<int32_t> iters_h(nsub);
   for (outer = 1; outer <= o->max_outer; ++outer) {
@@ -1193,6 +1309,36 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
     lb_to_x(L, 0, 0, st);
     cost_grad_impl<T>(c, nullptr, L.xphys, L.Jt, L.gradx, st);
     ++evals;
+    if (use_gn) {
+      // Gauss-Newton: CG on the normal equations about the stored
+      // trajectory, the full update, a new evaluation (masked to the
+      // subdomains still iterating)
+      gn_start(G, st);
+      for (;;) {
+        chk(hipMemsetAsync(L.pending, 0, sizeof(int32_t), st), "memset");
+        gn_count(G, st);
+        if (read1(L.pending, st) == 0) break;
+        gn_cg_start(G, st);
+        for (;;) {
+          chk(hipMemsetAsync(L.pending, 0, sizeof(int32_t), st), "memset");
+          gn_cg_count(G, st);
+          if (read1(L.pending, st) == 0) break;
+          gn_cg_dir(G, st);
+          c->eval_mask = G.cg_on;
+          gn_product<T>(c, G.dx, G.hv, st);
+          c->eval_mask = nullptr;
+          ++products;
+          gn_cg_update(G, st);
+        }
+        gn_update(G, st);
+        lb_to_x(L, 0, 0, st);
+        c->eval_mask = G.gn_on;
+        cost_grad_impl<T>(c, nullptr, L.xphys, L.Jt, L.gradx, st);
+        c->eval_mask = nullptr;
+        ++evals;
+        gn_after(G, st);
+      }
+    } else {
     lb_start(L, st);
     for (;;) {
       chk(hipMemsetAsync(L.pending, 0, sizeof(int32_t), st), "memset");
@@ -1209,6 +1355,7 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
         lb_armijo(L, st);
         if (read1(L.pending, st) == 0) break;
       }
+    }
     }
     chk(hipMemcpyAsync(iters_h.data(), L.iters, nsub * sizeof(int32_t), hipMemcpyDeviceToHost, st),
         "read iters");
@@ -1251,6 +1398,7 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
     rep->outer_iters = outer;
     rep->total_evals = evals;
     rep->lbfgs_iters = lbfgs_iters;
+    rep->gn_products = products;
     double js = 0, ratio = 0;
     for (int s = 0; s < nsub; ++s) {
       js += J[s];
@@ -1272,8 +1420,14 @@ dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* o, const d
                           double* x_out, double* xa_host, dd4dvar_solve_report* rep) {
   if (o->lbfgs_m < 1 || o->lbfgs_m > kMaxPairs || o->max_iter < 0 || o->max_outer < 1 ||
       o->max_ls < 1 || !(o->grad_rtol >= 0) || !(o->outer_tol >= 0) || !(o->armijo_c1 > 0) ||
-      !(o->armijo_c1 < 1) || !(o->j_noise_rtol >= 0) || !std::isfinite(o->j_noise_rtol)) {
+      !(o->armijo_c1 < 1) || !(o->j_noise_rtol >= 0) || !std::isfinite(o->j_noise_rtol) ||
+      o->local_solver < 0 || o->local_solver > 1 || o->cg_max_iter < 0 || !(o->cg_rtol >= 0) ||
+      !std::isfinite(o->cg_rtol)) {
     ctx->err = "bad solve options";
+    return DD4DVAR_E_INVALID;
+  }
+  if (o->local_solver == 1 && ctx->ckpt) {
+    ctx->err = "the Gauss-Newton local solver needs every level stored (checkpoints on)";
     return DD4DVAR_E_INVALID;
   }
   if (ctx->prec == DD4DVAR_FP64) return solve_typed<double>(ctx, o, x_init, x_out, xa_host, rep);

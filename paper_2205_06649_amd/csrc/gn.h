@@ -1,0 +1,44 @@
+// Batched Gauss-Newton local solver state (device pointers, passed by value).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace dd4dvar {
+
+struct GnState {
+  const SubDev* subs;
+  int nsub, max_iter, cg_max_iter;
+  int weight_mode;
+  int64_t N;                // packed control length
+  double sb[3];             // sigma_b per field
+  double grad_rtol, cg_rtol;
+  const double* xb;         // packed background controls
+  const uint8_t* cover;     // spatial coverage per box cell (background weights)
+  // vectors (packed layout, FP64)
+  double *xi, *xi0, *dxi, *r, *p, *dx, *hv, *xphys, *gradx;
+  // per subdomain
+  double *J, *Jt, *g0norm, *gnorm, *rr, *rr0, *step;
+  int32_t *status, *iters, *cg_k, *cg_total;
+  uint8_t *gn_on, *cg_on;   // evaluation masks: in the GN loop, in CG
+  int32_t* pending;         // device counter
+};
+
+void gn_to_x(const GnState& G, hipStream_t st);
+void gn_from_x(const GnState& G, const double* x, hipStream_t st);
+void gn_start(const GnState& G, hipStream_t st);
+void gn_count(const GnState& G, hipStream_t st);
+void gn_cg_start(const GnState& G, hipStream_t st);
+void gn_cg_count(const GnState& G, hipStream_t st);
+void gn_cg_dir(const GnState& G, hipStream_t st);
+void gn_cg_update(const GnState& G, hipStream_t st);
+void gn_update(const GnState& G, hipStream_t st);
+void gn_after(const GnState& G, hipStream_t st);
+void gn_step(const GnState& G, hipStream_t st);
+// out += B_w^{-1} dx over every subdomain (w^b / sigma_b^2 per control entry)
+void launch_add_bdiag(const SubDev* subs, int nsub, const uint8_t* cover, int weight_mode,
+                      const double sb[3], const double* dx, double* out, hipStream_t st);
+
+}  // namespace dd4dvar

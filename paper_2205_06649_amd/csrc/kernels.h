@@ -55,6 +55,7 @@ struct Dom {
   T* ring;                   // [nlev][3][nring] per subdomain, signs applied
   T* targ;                   // mean overlap target, traj layout
   T* adj;                    // rolling adjoint levels
+  T* dz;                     // tangent-linear trajectory, every level (zoff layout)
   const RowCoef<T>* rows;    // [nlat]
   const T* cosx;             // [nlat+2]: cos of rows -1..nlat (pole-mapped)
   const uint8_t* cover;      // spatial coverage count per box cell

@@ -41,6 +41,14 @@ void launch_gather(const Dom<T>& D, int nspace, int ntime, int level, int64_t nc
 void launch_add_href(double* traj, int64_t nlev, int64_t plane, double h0, hipStream_t st);
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 
+// tlm.hip: tangent linear model of the local sweeps
+template <typename T>
+void launch_tlm_init(const Dom<T>& D, const double* dx, int tile_base, int ntiles, hipStream_t st);
+template <typename T>
+void launch_tlm(const Dom<T>& D, int n, int tile_base, int ntiles, hipStream_t st);
+template <typename T>
+void launch_dz_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hipStream_t st);
+
 // box.hip: persistent per-box sweeps (FP32 state)
 size_t box_lds_bytes(int ny, int nx, int nring, int nlev);
 int box_passes(int ny, int nx, int nring, int nlev);

@@ -88,6 +88,9 @@ __global__ __launch_bounds__(kTile) void k_fwd(Dom<T> D, int n, int tile_base) {
 // mode 0: cost forcing (observations + overlap), writes grad and J at level 0
 // mode 1: caller forcing (packed FP64, trajectory layout), writes adj0
 // mode 2: cost forcing, writes adj0 (no background term)
+// mode 3: Gauss-Newton forcing W dZ^n from the tangent-linear trajectory
+//         (the observation and overlap weights of the cost applied to the
+//         perturbation; eq. line5and7), writes adj0, no cost
 template <typename T, int MODE>
 __global__ __launch_bounds__(kTile) void k_adj(Dom<T> D, int n, int tile_base,
                                                const double* __restrict__ x,
@@ -138,7 +141,10 @@ __global__ __launch_bounds__(kTile) void k_adj(Dom<T> D, int n, int tile_base,
   V3<T> l2 = ld_box(L2, plane, mm, T(1));
   double fh = 0, fu = 0, fv = 0;
   V3<T> tg = {T(0), T(0), T(0)};
-  if (MODE != 1) {
+  if (MODE == 3) {
+    // the perturbation at the cell takes the place of the overlap residual
+    tg = ld_box(D.dz + S.zoff + int64_t(n) * 3 * plane, plane, mm, T(1));
+  } else if (MODE != 1) {
     // cells outside every overlap all read element 0 (one shared cache line)
     // instead of branching around the load; their weight K is zero
     tg = ld_box(D.targ + S.traj_off + int64_t(n) * 3 * plane, plane, K > 0 ? mm : 0, T(1));
@@ -161,9 +167,10 @@ __global__ __launch_bounds__(kTile) void k_adj(Dom<T> D, int n, int tile_base,
       for (int o = o0 + int(threadIdx.x); o < o1; o += kTile) {
         const int code = D.obs_code[o];
         const int loc = code >> 2, f = code & 3;
-        const double rr = double(Z[f * plane + loc]) - D.obs_val[o];
+        const double rr = MODE == 3 ? double(D.dz[S.zoff + int64_t(n) * 3 * plane + f * plane + loc])
+                                    : double(Z[f * plane + loc]) - D.obs_val[o];
         const double qo = D.obs_q[o];
-        jloc += 0.5 * qo * rr * rr;
+        if (MODE != 3) jloc += 0.5 * qo * rr * rr;
         fo[f][loc - wt.y * kTile] = qo * rr;
       }
       __syncthreads();
@@ -201,14 +208,15 @@ __global__ __launch_bounds__(kTile) void k_adj(Dom<T> D, int n, int tile_base,
     }
     // overlap misfit: K copies of (Z - mean target) / sigma_b^2
     if (MODE != 1) {
-      const double eh = double(C.h) - double(tg.h);
-      const double eu = double(C.u) - double(tg.u);
-      const double ev = double(C.v) - double(tg.v);
+      const double eh = MODE == 3 ? double(tg.h) : double(C.h) - double(tg.h);
+      const double eu = MODE == 3 ? double(tg.u) : double(C.u) - double(tg.u);
+      const double ev = MODE == 3 ? double(tg.v) : double(C.v) - double(tg.v);
       const double mk = D.mu * double(K);
       fh += mk * eh * D.isb2[0];
       fu += mk * eu * D.isb2[1];
       fv += mk * ev * D.isb2[2];
-      jloc += 0.5 * mk * (eh * eh * D.isb2[0] + eu * eu * D.isb2[1] + ev * ev * D.isb2[2]);
+      if (MODE != 3)
+        jloc += 0.5 * mk * (eh * eh * D.isb2[0] + eu * eu * D.isb2[1] + ev * ev * D.isb2[2]);
     }
     const double bh = fh + double(ah) + double(l2.h);
     const double bu = fu + double(au) + double(l2.u);
@@ -235,7 +243,7 @@ __global__ __launch_bounds__(kTile) void k_adj(Dom<T> D, int n, int tile_base,
       out[o + 2 * plane] = bv;
     }
   }
-  if (MODE != 1) {
+  if (MODE == 0 || MODE == 2) {
     const double tot = block_sum(jloc, red);
     if (threadIdx.x == 0) D.jpart[w] = (n == L) ? tot : D.jpart[w] + tot;
   }
@@ -295,8 +303,11 @@ void launch_adj(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, con
   else if (mode == 1)
     hipLaunchKernelGGL((k_adj<T, 1>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, x, xb,
                        forcing, out);
-  else
+  else if (mode == 2)
     hipLaunchKernelGGL((k_adj<T, 2>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, x, xb,
+                       forcing, out);
+  else
+    hipLaunchKernelGGL((k_adj<T, 3>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, x, xb,
                        forcing, out);
 }
 #if DD4DVAR_SWEEP_PRIMARY
