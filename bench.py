@@ -110,6 +110,48 @@ def algorithmic_bytes(ctx, prec_bytes, persistent=False):
     return fwd, adj, pts
 
 
+def gn_product_bytes(ctx, prec_bytes, persistent=False):
+    """Compulsory HBM bytes of one Gauss-Newton normal-matrix product: the
+    tangent-linear sweep and the adjoint sweep with the Gauss-Newton forcing.
+
+    Step kernels: the tangent-linear launch at level n reads Z^n, dZ^n,
+    dZ^{n-1} and writes dZ^{n+1} (plus the ring of Z^n); the adjoint launch
+    reads Z^n, lambda^{n+1}, lambda^{n+2}, dZ^n and writes lambda^n.
+    Persistent sweeps: dZ^n and dZ^{n-1} (lambda^{n+1}, lambda^{n+2}) stay on
+    chip, so the tangent-linear sweep reads Z^n and writes dZ^{n+1} once per
+    level and the adjoint reads Z^n, and dZ^n only where another box covers
+    the cell.  Both read dx (FP64) at level 0 and write the FP64 product
+    there, and 20 B per observation entry.
+    """
+    from paper_2205_06649_amd import _lib as L
+    b = prec_bytes
+    tcount = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_TIME_COUNT, 0)
+    tlm = adj = 0.0
+    for s, inf in enumerate(ctx.info):
+        ny, nx, lev0, nlev = int(inf[1]), int(inf[3]), int(inf[4]), int(inf[5])
+        ncell = ny * nx
+        L_ = nlev - 1
+        nfrozen = int(np.count_nonzero(L.dd4dvar_plan_get_map(ctx.plan, L.MAP_HALO_SRC, s) >= 0))
+        cover = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_COVER, s).astype(np.int64)
+        nobs = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_OBS_BIN, s).size
+        tlm += ncell * (24 + 3 * b)
+        for n in range(L_):
+            nvec = 2 if persistent else (4 if n >= 1 else 3)
+            tlm += ncell * 3 * b * nvec + nfrozen * 3 * b
+        for n in range(L_, -1, -1):
+            if persistent:
+                nvec = 1
+                dz = int(np.count_nonzero(cover * tcount[lev0 + n] - 1 > 0))
+            else:
+                nvec = 1 + (n + 1 <= L_) + (n + 2 <= L_) + (n > 0)
+                dz = ncell
+            adj += ncell * (nvec * 3 * b + 1) + dz * 3 * b + nfrozen * 3 * b
+            if n == 0:
+                adj += ncell * 24
+        adj += nobs * 20
+    return tlm, adj
+
+
 # HBM bytes per launch of the dominant kernels on the default workload, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch, scaled by 2.0 and
 # 1.0: what the two counters read for a plain 1 GiB device copy), keyed by a
@@ -167,6 +209,83 @@ def solve_leg(prob, mode):
                      "lbfgs_iters": int(rep.lbfgs_iters), "J_final": float(rep.J_final),
                      "gnorm_ratio_max": float(rep.gnorm_ratio_max)}
         log(f"{prec} solve: {sec:.2f} s, {rep.total_evals} evaluations")
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    ref = xa["fp64"]
+    out["fp32_analysis_rel_err"] = float(max(
+        np.linalg.norm(xa["fp32"][f] - ref[f]) / np.linalg.norm(ref[f] - ref[f].mean())
+        for f in range(3)))
+    out["speedup_fp32_vs_fp64"] = out["fp64"]["seconds"] / out["fp32"]["seconds"]
+    return out
+
+
+GN_OPTS = dict(max_outer=2, max_iter=3, cg_max_iter=20, cg_rtol=1e-4, grad_rtol=1e-6,
+               outer_tol=0.0)
+
+
+def gn_leg(prob, x, mode, reps=10):
+    """Gauss-Newton local solver (Alg. 5 / Alg. 6).  The normal-matrix
+    product (tangent-linear sweep, then the adjoint sweep forced by the
+    residual weights applied to the perturbation) timed at x in FP32, and DD
+    solves with Gauss-Newton local solves in FP32 and FP64: wall time,
+    evaluations, products, and the FP32 analysis error relative to the FP64
+    Gauss-Newton analysis (per field, relative to its spread)."""
+    import torch
+    from paper_2205_06649_amd.context import Context
+    out = {"options": dict(GN_OPTS)}
+    ctx = Context(prob, "fp32")
+    ctx.set_exec_mode(mode)
+    ctx.forward(x, with_traj=False)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    sb = torch.tensor(prob.sigma_b, dtype=torch.float64, device="cuda")
+    scale = torch.cat([sb[f].expand(int(i[1]) * int(i[3])) for i in ctx.info for f in range(3)])
+    dx = scale * torch.randn(ctx.ctrl_len, generator=gen, dtype=torch.float64, device="cuda")
+    hv = torch.empty_like(dx)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms_prod = timed(lambda: ctx.gn_hessvec(dx, hv))
+    ms_tlm = timed(lambda: ctx.tangent_linear(dx, with_traj=False))
+    tlm_b, adj_b = gn_product_bytes(ctx, 4, persistent=(mode >= 2))
+    out["exec_mode"] = EXEC_MODES[mode]
+    out["product_ms"] = ms_prod
+    out["tlm_ms"] = ms_tlm
+    out["adjoint_ms"] = ms_prod - ms_tlm
+    out["tlm_algorithmic_bytes"] = tlm_b
+    out["adjoint_algorithmic_bytes"] = adj_b
+    out["product_algorithmic_GBs"] = (tlm_b + adj_b) / (ms_prod * 1e-3) / 1e9
+    out["tlm_algorithmic_GBs"] = tlm_b / (ms_tlm * 1e-3) / 1e9
+    out["adjoint_algorithmic_GBs"] = adj_b / ((ms_prod - ms_tlm) * 1e-3) / 1e9
+    log(f"gauss-newton product {ms_prod:.2f} ms (tangent-linear {ms_tlm:.2f} ms)")
+    ctx.close()
+    del ctx, dx, hv
+    torch.cuda.empty_cache()
+    xa = {}
+    for prec in ("fp64", "fp32"):
+        ctx = Context(prob, prec)
+        if prec == "fp32":
+            ctx.set_exec_mode(mode)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        a, rep, st, _ = ctx.solve(local_solver="gn", **GN_OPTS)
+        sec = time.perf_counter() - t
+        xa[prec] = a
+        out[prec] = {"seconds": sec, "evaluations": int(rep.total_evals),
+                     "gn_iters": int(rep.lbfgs_iters), "products": int(rep.gn_products),
+                     "J_final": float(rep.J_final), "gnorm_ratio_max": float(rep.gnorm_ratio_max)}
+        log(f"{prec} gauss-newton solve: {sec:.2f} s, {rep.total_evals} evaluations, "
+            f"{rep.gn_products} products")
         ctx.close()
         del ctx
         torch.cuda.empty_cache()
@@ -252,6 +371,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the FP32-vs-FP64 DD solve (analysis error) leg")
+    ap.add_argument("--no-gn", action="store_true",
+                    help="skip the Gauss-Newton leg (normal-matrix product, GN solves)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -420,6 +541,8 @@ def main():
 
     if not args.no_solve:
         result["solve"] = solve_leg(prob, mode)
+    if not args.no_gn:
+        result["gauss_newton"] = gn_leg(prob, x, mode)
 
     if not args.no_cpu:
         log("timing the oracle on host cores")

@@ -135,9 +135,10 @@ class Context:
         L.dd4dvar_tangent_linear(self.handle, dx.data_ptr(), self.ptr(out), self._stream())
         return out
 
-    def gn_hessvec(self, dx):
+    def gn_hessvec(self, dx, out=None):
         """(B_w^{-1} + M'^T W M') dx about the trajectories of the last forward."""
-        out = self.empty(self.ctrl_len)
+        if out is None:
+            out = self.empty(self.ctrl_len)
         L.dd4dvar_gn_hessvec(self.handle, dx.data_ptr(), out.data_ptr(), self._stream())
         return out
 

@@ -287,6 +287,197 @@ __device__ __forceinline__ void fwd_box_body(const Dom<float>& D, const double* 
   }
 }
 
+// Tangent-linear sweep of box s (the TLM step of Alg. 6, linearized about
+// the stored trajectory; frozen ring unperturbed): the perturbation level
+// dZ^n lives in the LDS frame (frozen ring entries zero, wrapped entries
+// copies of the box's own cells with the across-pole sign) and dZ^{n-1} in
+// registers, as the forward keeps Z^n and Z^{n-1}; the state Z^n comes from
+// the stored trajectory through buffer loads issued a pass ahead, its
+// out-of-box neighbours from the level's ring staged in LDS one level ahead
+// (as in the adjoint); each new level dZ^{n+1} is written once.  Derivative
+// of the increments of fwd_box_body, with the flux terms linearized as
+// (h_ref + h) du + dh u.
+template <int K, bool SPAN>
+__device__ __forceinline__ void tlm_box_body(const Dom<float>& D, const double* __restrict__ dx,
+                                             int s, float* lds) {
+  const SubDev S = D.subs[s];
+  const int nx = S.nx, ny = S.ny, nxp = nx + 2, npad = (ny + 2) * nxp;
+  const int ncell = S.ncell, nring = S.nring;
+  const int L = S.nlev - 1;
+  const int tid = threadIdx.x;
+  float* P = lds;                          // [npad][3]: dZ^n
+  float* rowtab = lds + 3 * npad;          // [ny][8]
+  float* zring = rowtab + 8 * ny;          // [2 levels][nring][3]: Z on the ring
+  const int64_t plane = ncell;
+  const int32_t* hsrc = D.hsrc + S.hmap_off;
+  const int32_t* hoff = D.hoff + S.hmap_off;
+  const int32_t* hsgn = D.hsign + S.hmap_off;
+  const bool wraps = SPAN && S.span != 0;
+  const float h0 = D.h0, st = D.st, stg = D.stg;
+  const int fp = ncell * 4, nx4 = nx * 4, lvb = 3 * ncell * 4;   // byte strides
+  const __amdgpu_buffer_rsrc_t zrs = make_rsrc(D.traj + S.zoff, S.nlev * lvb);
+  const __amdgpu_buffer_rsrc_t drs = make_rsrc(D.dz + S.zoff, S.nlev * lvb);
+  const int dr = kBoxThreads / nx, dc = kBoxThreads - dr * nx;
+  const int n3 = 3 * nxp;
+
+  fill_rowtab(rowtab, D, S);
+  for (int i = tid; i < 3 * npad; i += kBoxThreads) P[i] = 0.0f;
+  for (int k = tid; k < nring; k += kBoxThreads) {
+    const V3<float> g = ring_value(D, S, k, 0);
+    float* Zr = zring + 3 * k;
+    Zr[0] = g.h; Zr[1] = g.u; Zr[2] = g.v;
+  }
+  __syncthreads();                         // frame cleared before the level-0 cells
+  // level 0 = dx
+  const double* dxs = dx + S.ctrl_off;
+  {
+    Cell q = first_cell(nx);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (q.m < ncell) {
+        const int p = 3 * ((q.r + 1) * nxp + q.c + 1);
+        const float h = float(dxs[q.m]), u = float(dxs[ncell + q.m]), v = float(dxs[2 * ncell + q.m]);
+        P[p] = h; P[p + 1] = u; P[p + 2] = v;
+        bstore(drs, h, q.m * 4, 0);
+        bstore(drs, u, q.m * 4, fp);
+        bstore(drs, v, q.m * 4, 2 * fp);
+      }
+      next_cell(q, nx, dr, dc);
+    }
+  }
+  // this thread's ring position and its source for every level
+  const bool ring_thread0 = tid < nring;
+  bool rfrozen = true;
+  int roff = 0;
+  float rsg = 1.0f;
+  if (ring_thread0) {
+    rfrozen = hsrc[tid] >= 0;
+    roff = rfrozen ? tid : hoff[tid];
+    rsg = rfrozen ? 1.0f : float(hsgn[tid]);
+  }
+  __syncthreads();
+  if (wraps) {
+    fill_wraps(P, hsrc, hoff, hsgn, nring, nx, ny, true);
+    __syncthreads();
+  }
+
+  float zr[3][K];                          // dZ^{n-1} of this thread's cells
+#pragma unroll
+  for (int k = 0; k < K; ++k) zr[0][k] = zr[1][k] = zr[2][k] = 0.0f;
+  const Cell q0 = first_cell(nx);
+  for (int n = 0; n < L; ++n) {
+    const int so = __builtin_amdgcn_readfirstlane(n * lvb);        // Z^n
+    const int sw = __builtin_amdgcn_readfirstlane((n + 1) * lvb);  // dZ^{n+1}
+    const float* Zr = zring + (n & 1) * 3 * nring;
+    // ring of level n+1, fetched now and staged after this level's reads
+    V3<float> gnext = {0.f, 0.f, 0.f};
+    if (ring_thread0) {
+      const float* src = rfrozen ? D.ring + S.ring_off + int64_t(n + 1) * 3 * nring + roff
+                                 : D.traj + S.zoff + int64_t(n + 1) * 3 * plane + roff;
+      const int64_t fs = rfrozen ? int64_t(nring) : plane;
+      gnext = {src[0], rsg * src[fs], rsg * src[2 * fs]};
+    }
+    const bool euler = n == 0;
+    struct PassLoads {
+      V3<float> C, E, W, N, Sv;
+    };
+    auto issue = [&](const Cell& cq, bool edge) {
+      PassLoads Q;
+      const int v0 = cq.m * 4;
+      const bool e_in = cq.c + 1 < nx, w_in = cq.c > 0;
+      const bool n_in = !edge || cq.r + 1 < ny, s_in = !edge || cq.r > 0;
+      Q.C = bload3(zrs, v0, so, fp);
+      Q.E = bload3(zrs, e_in ? v0 + 4 : v0, so, fp);
+      Q.W = bload3(zrs, w_in ? v0 - 4 : v0, so, fp);
+      Q.N = bload3(zrs, n_in ? v0 + nx4 : v0, so, fp);
+      Q.Sv = bload3(zrs, s_in ? v0 - nx4 : v0, so, fp);
+      return Q;
+    };
+    Cell q = q0;
+    asm volatile("" : "+v"(q.m), "+v"(q.r), "+v"(q.c));
+    PassLoads cur = issue(q, true);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const bool edge_rows = k == 0 || (k + 1) * kBoxThreads > ncell - nx;
+      const Cell qc = q;
+      next_cell(q, nx, dr, dc);
+      // issued whether or not the next pass holds cells of this box (an
+      // in-range read past the end is never used): a conditional issue would
+      // first copy this pass's loads, waiting for them
+      PassLoads nxt = cur;
+      if (k + 1 < K) nxt = issue(q, (k + 2) * kBoxThreads > ncell - nx);
+      __builtin_amdgcn_sched_barrier(0);
+      if (k * kBoxThreads < ncell && qc.m < ncell) {
+        const int m = qc.m, r = qc.r, c = qc.c;
+        const bool e_in = c + 1 < nx, w_in = c > 0;
+        const bool n_in = !edge_rows || r + 1 < ny, s_in = !edge_rows || r > 0;
+        const float* rw = rowtab + 8 * r;
+        const float a1 = rw[0], a2 = rw[1], a3 = rw[2], cf = rw[3], ct = rw[4], cN = rw[6], cS = rw[7];
+        const V3<float> C = cur.C;
+        const V3<float> rE = lds3(Zr, e_in ? 0 : 3 * (2 * nx + ny + r));
+        const V3<float> rW = lds3(Zr, w_in ? 0 : 3 * (2 * nx + r));
+        const V3<float> E = pick3(cur.E, rE, __builtin_amdgcn_ballot_w64(e_in));
+        const V3<float> W = pick3(cur.W, rW, __builtin_amdgcn_ballot_w64(w_in));
+        V3<float> N = cur.N, Sv = cur.Sv;
+        if (edge_rows) {
+          N = pick3(N, lds3(Zr, n_in ? 0 : 3 * (nx + c)), __builtin_amdgcn_ballot_w64(n_in));
+          Sv = pick3(Sv, lds3(Zr, s_in ? 0 : 3 * c), __builtin_amdgcn_ballot_w64(s_in));
+        }
+        const float* Pc = P + 3 * ((r + 1) * nxp + c + 1);
+        const V3<float> dC = lds3(Pc, 0), dE = lds3(Pc, 3), dW = lds3(Pc, -3);
+        const V3<float> dN = lds3(Pc, n3), dS = lds3(Pc, -n3);
+        const float cor = cf + ct * C.u;
+        const float dU = -a1 * (dC.u * (E.u - W.u) + C.u * (dE.u - dW.u)) -
+                         st * (dC.v * (N.u - Sv.u) + C.v * (dN.u - dS.u)) - a2 * (dE.h - dW.h) +
+                         (cor * dC.v + ct * dC.u * C.v);
+        const float dV = -a1 * (dC.u * (E.v - W.v) + C.u * (dE.v - dW.v)) -
+                         st * (dC.v * (N.v - Sv.v) + C.v * (dN.v - dS.v)) - stg * (dN.h - dS.h) -
+                         (cor * dC.u + ct * dC.u * C.u);
+        const float dH = -a1 * (((h0 + E.h) * dE.u + dE.h * E.u) - ((h0 + W.h) * dW.u + dW.h * W.u)) -
+                         a3 * (((h0 + N.h) * dN.v + dN.h * N.v) * cN -
+                               ((h0 + Sv.h) * dS.v + dS.h * Sv.v) * cS);
+        if (euler) {
+          zr[0][k] = dC.h + 0.5f * dH;
+          zr[1][k] = dC.u + 0.5f * dU;
+          zr[2][k] = dC.v + 0.5f * dV;
+        } else {
+          zr[0][k] += dH;
+          zr[1][k] += dU;
+          zr[2][k] += dV;
+        }
+        bstore(drs, zr[0][k], m * 4, sw);
+        bstore(drs, zr[1][k], m * 4, sw + fp);
+        bstore(drs, zr[2][k], m * 4, sw + 2 * fp);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      cur = nxt;
+    }
+    __syncthreads();                                    // every read of dZ^n and the ring done
+    // dZ^{n+1} into LDS; dZ^n into the registers (base of the next step)
+    q = q0;
+    asm volatile("" : "+v"(q.m), "+v"(q.r), "+v"(q.c));
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (q.m < ncell) {
+        float* Pc = P + 3 * ((q.r + 1) * nxp + q.c + 1);
+        const float th = Pc[0], tu = Pc[1], tv = Pc[2];
+        Pc[0] = zr[0][k]; Pc[1] = zr[1][k]; Pc[2] = zr[2][k];
+        zr[0][k] = th; zr[1][k] = tu; zr[2][k] = tv;
+      }
+      next_cell(q, nx, dr, dc);
+    }
+    if (ring_thread0) {
+      float* Zq = zring + ((n + 1) & 1) * 3 * nring + 3 * tid;
+      Zq[0] = gnext.h; Zq[1] = gnext.u; Zq[2] = gnext.v;
+    }
+    __syncthreads();
+    if (wraps) {
+      fill_wraps(P, hsrc, hoff, hsgn, nring, nx, ny, true);
+      __syncthreads();
+    }
+  }
+}
+
 // Persistent adjoint sweep: lambda^{n+1} of the box lives in LDS on the
 // padded grid (frozen ring entries of the frame stay zero: those increments
 // are not part of the local model; wrapped entries hold raw copies), and
@@ -299,7 +490,8 @@ __device__ __forceinline__ void fwd_box_body(const Dom<float>& D, const double* 
 // passes that hold the box's first or last row look beyond it to the south
 // or north.  Gather form and forcing as in k_adj (sweep.hip).
 // MODE 0: cost forcing, gradient + J out; 1: caller forcing, adjoint out;
-// 2: cost forcing, adjoint out.
+// 2: cost forcing, adjoint out; 3: Gauss-Newton forcing (the observation and
+// overlap weights applied to the tangent-linear trajectory), adjoint out.
 template <int K, int MODE, bool SPAN>
 __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* __restrict__ x,
                                              const double* __restrict__ xb,
@@ -326,7 +518,10 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
   const float st = D.st, stg = D.stg;
   const int fp = ncell * 4, nx4 = nx * 4, lvb = 3 * ncell * 4;   // byte strides
   const __amdgpu_buffer_rsrc_t zrs = make_rsrc(D.traj + S.zoff, S.nlev * lvb);
-  const __amdgpu_buffer_rsrc_t trs = make_rsrc(D.targ + S.traj_off, S.nlev * lvb);
+  // overlap targets, or (MODE 3) the tangent-linear trajectory: both read
+  // only where the cell is covered by another box
+  const __amdgpu_buffer_rsrc_t trs =
+      make_rsrc(MODE == 3 ? D.dz + S.zoff : D.targ + S.traj_off, S.nlev * lvb);
   const float mu_f = float(D.mu);
   const float ib_h = float(D.isb2[0]), ib_u = float(D.isb2[1]), ib_v = float(D.isb2[2]);
   const int dr = kBoxThreads / nx, dc = kBoxThreads - dr * nx;
@@ -496,12 +691,15 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
           // overlap residual (the FP32 difference is the correctly rounded
           // exact one), its forcing in FP32 like the adjoint state, and the
           // cell's term of J accumulated in FP64
-          const float eh = C.h - tg.h, eu = C.u - tg.u, ev = C.v - tg.v;
+          const float eh = MODE == 3 ? tg.h : C.h - tg.h;
+          const float eu = MODE == 3 ? tg.u : C.u - tg.u;
+          const float ev = MODE == 3 ? tg.v : C.v - tg.v;
           const float mk = mu_f * float(Kc);
           fh = mk * ib_h * eh;
           fu = mk * ib_u * eu;
           fv = mk * ib_v * ev;
-          jloc += 0.5 * double(mk) * double(ib_h * eh * eh + ib_u * eu * eu + ib_v * ev * ev);
+          if (MODE != 3)
+            jloc += 0.5 * double(mk) * double(ib_h * eh * eh + ib_u * eu * eu + ib_v * ev * ev);
         }
         const float bh = fh + ah + l2.h;
         const float bu = fu + au + l2.u;
@@ -566,9 +764,10 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
         for (int o = o0 + tid; o < o1; o += kBoxThreads) {
           const int code = D.obs_code[o];
           const int loc = code >> 2, f = code & 3;
-          const double rr = double(Z[f * plane + loc]) - D.obs_val[o];
+          const double rr = MODE == 3 ? double(D.dz[S.zoff + int64_t(n) * 3 * plane + f * plane + loc])
+                                      : double(Z[f * plane + loc]) - D.obs_val[o];
           const double qo = D.obs_q[o];
-          jloc += 0.5 * qo * rr * rr;
+          if (MODE != 3) jloc += 0.5 * qo * rr * rr;
           if (n > 0) {
             const int lr = loc / nx, lc = loc - lr * nx;
             float* Lf = Lm + 3 * ((lr + 1) * nxp + lc + 1) + f;
@@ -585,7 +784,7 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
       __syncthreads();
     }
   }
-  if (MODE != 1) {
+  if (MODE == 0 || MODE == 2) {
     // the box total goes to its first tile slot, the others are cleared, so
     // the per-subdomain reduction of the step path applies unchanged
     const double tot = block_sum_box(jloc, red);
@@ -601,6 +800,15 @@ __global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const dou
   const int s = order[blockIdx.x];
   if (D.active && !D.active[s]) return;
   fwd_box_body<K, SPAN>(D, x, s, lds);
+}
+
+template <int K, bool SPAN>
+__global__ __launch_bounds__(kBoxThreads) void k_tlm_box(Dom<float> D, const double* __restrict__ dx,
+                                                         const int32_t* __restrict__ order) {
+  extern __shared__ float lds[];
+  const int s = order[blockIdx.x];
+  if (D.active && !D.active[s]) return;
+  tlm_box_body<K, SPAN>(D, dx, s, lds);
 }
 
 template <int K, int MODE, bool SPAN>
@@ -668,6 +876,8 @@ hipError_t prepare_ks() {
   if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 0, SPAN>);
   if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 1, SPAN>);
   if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 2, SPAN>);
+  if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 3, SPAN>);
+  if (e == hipSuccess) e = allow_lds(&k_tlm_box<K, SPAN>);
   if (e == hipSuccess) e = allow_lds(&k_eval_box<K, SPAN>);
   return e;
 }
@@ -677,6 +887,14 @@ hipError_t fwd_box_k(const Dom<float>& D, const double* x, const int32_t* order,
                      size_t lds_bytes, hipStream_t st) {
   auto* kern = &k_fwd_box<K, SPAN>;
   hipLaunchKernelGGL(kern, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, order);
+  return hipGetLastError();
+}
+
+template <int K, bool SPAN>
+hipError_t tlm_box_k(const Dom<float>& D, const double* dx, const int32_t* order, int nboxes,
+                     size_t lds_bytes, hipStream_t st) {
+  auto* kern = &k_tlm_box<K, SPAN>;
+  hipLaunchKernelGGL(kern, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, dx, order);
   return hipGetLastError();
 }
 
@@ -704,6 +922,7 @@ hipError_t adj_box_mode(const Dom<float>& D, int mode, const double* x, const do
                         size_t lds_bytes, hipStream_t st) {
   if (mode == 0) return adj_box_k<K, 0, SPAN>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
   if (mode == 1) return adj_box_k<K, 1, SPAN>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+  if (mode == 3) return adj_box_k<K, 3, SPAN>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
   return adj_box_k<K, 2, SPAN>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
 }
 }  // namespace
@@ -728,6 +947,15 @@ hipError_t launch_fwd_box(const Dom<float>& D, const double* x, const int32_t* o
                 : fwd_box_k<10, false>(D, x, order, nboxes, lds_bytes, st);
   return span ? fwd_box_k<kBoxKMax, true>(D, x, order, nboxes, lds_bytes, st)
               : fwd_box_k<kBoxKMax, false>(D, x, order, nboxes, lds_bytes, st);
+}
+
+hipError_t launch_tlm_box(const Dom<float>& D, const double* dx, const int32_t* order, int nboxes,
+                          size_t lds_bytes, int passes, bool span, hipStream_t st) {
+  if (passes <= 10)
+    return span ? tlm_box_k<10, true>(D, dx, order, nboxes, lds_bytes, st)
+                : tlm_box_k<10, false>(D, dx, order, nboxes, lds_bytes, st);
+  return span ? tlm_box_k<kBoxKMax, true>(D, dx, order, nboxes, lds_bytes, st)
+              : tlm_box_k<kBoxKMax, false>(D, dx, order, nboxes, lds_bytes, st);
 }
 
 hipError_t launch_adj_box(const Dom<float>& D, int mode, const double* x, const double* xb,

@@ -278,7 +278,7 @@ void local_adjoint(dd4dvar_ctx* c, int mode, const double* x, const double* forc
                    const std::vector<int32_t>* ids, hipStream_t st) {
   Dom<T> D = local_dom<T>(c);
   if constexpr (std::is_same<T, float>::value) {
-    if (!ids && c->exec_mode >= 2 && mode != 3) {
+    if (!ids && c->exec_mode >= 2) {
       chk(launch_adj_box(D, mode, x, c->xb, forcing, out, c->d_order, c->nsub, c->box_lds, c->box_k,
                          c->box_span, st),
           "persistent adjoint launch");
@@ -323,13 +323,19 @@ void ensure_dz(dd4dvar_ctx* c) {
 }
 
 // tangent-linear sweeps of every box (or of the boxes in c->eval_mask) about
-// the stored trajectory: dZ = M' dx, every level into the dz arena.  The
-// step kernels serve every execution mode (the persistent sweeps store the
-// same trajectory layout).
+// the stored trajectory: dZ = M' dx, every level into the dz arena (the
+// persistent per-box kernel in modes 2 and 3, else the step kernels)
 template <typename T>
 void local_tlm(dd4dvar_ctx* c, const double* dx, hipStream_t st) {
   ensure_dz(c);
   Dom<T> D = local_dom<T>(c);
+  if constexpr (std::is_same<T, float>::value) {
+    if (c->exec_mode >= 2) {
+      chk(launch_tlm_box(D, dx, c->d_order, c->nsub, c->box_lds, c->box_k, c->box_span, st),
+          "persistent tangent-linear launch");
+      return;
+    }
+  }
   auto sweep = [&](int tile_base, int ntiles, int nlev) {
     launch_tlm_init<T>(D, dx, tile_base, ntiles, st);
     for (int n = 0; n + 1 < nlev; ++n) launch_tlm<T>(D, n, tile_base, ntiles, st);

@@ -56,6 +56,8 @@ int box_passes_max();
 hipError_t box_prepare(int passes);
 hipError_t launch_fwd_box(const Dom<float>& D, const double* x, const int32_t* order, int nboxes,
                           size_t lds_bytes, int passes, bool span, hipStream_t st);
+hipError_t launch_tlm_box(const Dom<float>& D, const double* dx, const int32_t* order, int nboxes,
+                          size_t lds_bytes, int passes, bool span, hipStream_t st);
 hipError_t launch_adj_box(const Dom<float>& D, int mode, const double* x, const double* xb,
                           const double* forcing, double* out, const int32_t* order, int nboxes,
                           size_t lds_bytes, int passes, bool span, hipStream_t st);

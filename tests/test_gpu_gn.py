@@ -20,8 +20,10 @@ from test_oracle_pins import MIXED_CFG, SPAN_CFG
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-4}
+TOL = {"fp64": 1e-12, "fp32": 1e-4, "fp32-box": 1e-4}
 CASES = ["tiny1", "c1", "small", "span", "mixed"]
+# "fp32-box": FP32 state with the persistent per-box kernels (execution mode 2)
+PRECS = ["fp64", "fp32", "fp32-box"]
 
 
 def _rel(a, b):
@@ -50,7 +52,10 @@ def _oracle_state(which):
 
 def _ctx(which, prec):
     from paper_2205_06649_amd.context import Context
-    return Context(_prob(which), precision=prec)
+    ctx = Context(_prob(which), precision=prec.split("-")[0])
+    if prec.endswith("-box"):
+        ctx.set_exec_mode(2)
+    return ctx
 
 
 def _controls(p, maps, trajs, seed, scale=0.3):
@@ -62,7 +67,7 @@ def _controls(p, maps, trajs, seed, scale=0.3):
     return xs, dxs
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("which", CASES)
 def test_tangent_linear(which, prec):
     """dZ = M' dx about the stored trajectory, every level of every box,
@@ -81,7 +86,7 @@ def test_tangent_linear(which, prec):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("fp32-box", 1e-5)])
 @pytest.mark.parametrize("which", ["c1", "span", "mixed"])
 def test_tangent_linear_adjoint_dot_product(which, prec, tol):
     """<M' dx, y> = <dx, M'^T y> with the device TLM and the device adjoint
@@ -103,7 +108,7 @@ def test_tangent_linear_adjoint_dot_product(which, prec, tol):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("which", CASES)
 def test_gn_hessvec(which, prec):
     """(B_w^-1 + M'^T W M') dx against the oracle's normal-matrix product."""
@@ -167,39 +172,23 @@ def test_gn_solve_matches_oracle(which, opts):
     ctx.close()
 
 
-def test_gn_solve_fp32_against_fp64():
-    """FP32 state sweeps with the FP64 CG: analysis within the FP32 bar of the
-    FP64 device solve (per field, relative to the spread of the analysis)."""
+@pytest.mark.parametrize("prec", ["fp32", "fp32-box"])
+def test_gn_solve_fp32_against_fp64(prec):
+    """FP32 state sweeps (step kernels, or the persistent per-box kernels)
+    with the FP64 CG: analysis within the FP32 bar of the FP64 device solve
+    (per field, relative to the spread of the analysis)."""
     opts = dict(max_outer=2, max_iter=3, cg_max_iter=30, cg_rtol=1e-8, outer_tol=0.0,
                 local_solver="gn")
     res = {}
-    for prec in ("fp64", "fp32"):
-        ctx = _ctx("c2", prec)
+    for pr in ("fp64", prec):
+        ctx = _ctx("c2", pr)
         xa, rep, st, _ = ctx.solve(**opts)
-        res[prec] = xa
+        res[pr] = xa
         ctx.close()
     ref = res["fp64"]
-    err = max(np.linalg.norm(res["fp32"][f] - ref[f]) / np.linalg.norm(ref[f] - ref[f].mean())
+    err = max(np.linalg.norm(res[prec][f] - ref[f]) / np.linalg.norm(ref[f] - ref[f].mean())
               for f in range(3))
     assert err <= 1e-4, err
-
-
-def test_gn_persistent_trajectory():
-    """After a forward by the persistent per-box sweeps (FP32, mode 2) the
-    normal-matrix product runs about the same stored trajectory."""
-    p, maps, bg, trajs, rings = _oracle_state("c1")
-    ctx = _ctx("c1", "fp32")
-    ctx.set_exec_mode(2)
-    xs, dxs = _controls(p, maps, trajs, seed=27)
-    ctx.forward(ctx.pack_ctrl(xs), with_traj=False)
-    hv = ctx.unpack_ctrl(ctx.gn_hessvec(ctx.pack_ctrl(dxs)))
-    g = model.Grid.of(p)
-    for b in maps.boxes:
-        geo = local.LocalGeometry(g, maps, b.sub)
-        lt = local.forward(geo, xs[b.sub], rings[b.sub])
-        ref = gn.hessvec(p, maps, b.sub, lt, rings[b.sub], dxs[b.sub])
-        assert _rel(hv[b.sub], ref) <= TOL["fp32"], b.sub
-    ctx.close()
 
 
 def test_gn_rules():
