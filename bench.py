@@ -158,10 +158,13 @@ def gn_product_bytes(ctx, prec_bytes, persistent=False):
 # digest of the kernel sources they were measured on: a changed kernel (or
 # another workload) reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    "k_adj": ("sweep", "417f36ec3965e28f", 1169811474),
-    "k_adj_box/10": ("box", "b7b295954134d02d", 16114477768),
-    "k_adj_box/11": ("box", "b7b295954134d02d", 16506388339),
-    "k_eval_box/10": ("box", "b7b295954134d02d", 29551498368),
+    "k_adj": ("sweep", "bbfd2274bc1461e2", 1169846272),
+    "k_adj_box/10": ("box", "cae7c26932a8a8c2", 16113092608),
+    "k_adj_box/11": ("box", "cae7c26932a8a8c2", 16506113024),
+    "k_eval_box/10": ("box", "cae7c26932a8a8c2", 29929473024),
+    # Gauss-Newton normal-matrix product (persistent, 10 passes)
+    "k_tlm_box/10": ("box", "cae7c26932a8a8c2", 16793479168),
+    "k_adj_box_gn/10": ("box", "cae7c26932a8a8c2", 15120503808),
 }
 KERNEL_SOURCES = {"sweep": ("sweep.hip", "kernels.h", "stencil.h"),
                   "box": ("box.hip", "kernels.h", "stencil.h")}
@@ -224,7 +227,7 @@ GN_OPTS = dict(max_outer=2, max_iter=3, cg_max_iter=20, cg_rtol=1e-4, grad_rtol=
                outer_tol=0.0)
 
 
-def gn_leg(prob, x, mode, reps=10):
+def gn_leg(prob, x, mode, config, reps=10, solves=True):
     """Gauss-Newton local solver (Alg. 5 / Alg. 6).  The normal-matrix
     product (tangent-linear sweep, then the adjoint sweep forced by the
     residual weights applied to the perturbation) timed at x in FP32, and DD
@@ -267,10 +270,17 @@ def gn_leg(prob, x, mode, reps=10):
     out["product_algorithmic_GBs"] = (tlm_b + adj_b) / (ms_prod * 1e-3) / 1e9
     out["tlm_algorithmic_GBs"] = tlm_b / (ms_tlm * 1e-3) / 1e9
     out["adjoint_algorithmic_GBs"] = adj_b / ((ms_prod - ms_tlm) * 1e-3) / 1e9
+    if mode >= 2:
+        # HBM bytes the counters measured per launch (the context's first plan:
+        # 10 passes of 1024 cells), while the kernel sources are unchanged
+        out["tlm_traffic"] = measured_traffic("k_tlm_box/10", config)
+        out["adjoint_traffic"] = measured_traffic("k_adj_box_gn/10", config)
     log(f"gauss-newton product {ms_prod:.2f} ms (tangent-linear {ms_tlm:.2f} ms)")
     ctx.close()
     del ctx, dx, hv
     torch.cuda.empty_cache()
+    if not solves:
+        return out
     xa = {}
     for prec in ("fp64", "fp32"):
         ctx = Context(prob, prec)
@@ -373,6 +383,8 @@ def main():
                     help="skip the FP32-vs-FP64 DD solve (analysis error) leg")
     ap.add_argument("--no-gn", action="store_true",
                     help="skip the Gauss-Newton leg (normal-matrix product, GN solves)")
+    ap.add_argument("--no-gn-solve", action="store_true",
+                    help="time the Gauss-Newton normal-matrix product only")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -542,7 +554,7 @@ def main():
     if not args.no_solve:
         result["solve"] = solve_leg(prob, mode)
     if not args.no_gn:
-        result["gauss_newton"] = gn_leg(prob, x, mode)
+        result["gauss_newton"] = gn_leg(prob, x, mode, args.config, solves=not args.no_gn_solve)
 
     if not args.no_cpu:
         log("timing the oracle on host cores")
