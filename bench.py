@@ -184,9 +184,10 @@ def measured_traffic(kernel, config):
 
 EXEC_MODES = {0: "step kernels, all boxes per launch",
               2: "persistent per-box forward and adjoint sweeps, one launch each",
-              3: "persistent per-box sweeps, forward and adjoint fused in one launch"}
+              3: "persistent per-box sweeps, forward and adjoint fused in one launch",
+              4: "persistent per-box sweeps, the adjoint in column strips"}
 
-KERNEL_NAMES = {0: "k_adj", 2: "k_adj_box", 3: "k_eval_box"}
+KERNEL_NAMES = {0: "k_adj", 2: "k_adj_box", 3: "k_eval_box", 4: "k_adj_strip"}
 
 SOLVE_OPTS = dict(max_outer=2, max_iter=40, grad_rtol=1e-6, outer_tol=0.0)
 
@@ -501,7 +502,8 @@ def main():
             "kernel": KERNEL_NAMES[mode] + {
                 0: " (adjoint step, all subdomains per launch)",
                 2: " (persistent adjoint sweep, one workgroup per box)",
-                3: " (fused persistent forward + adjoint, one workgroup per box)"}[mode],
+                3: " (fused persistent forward + adjoint, one workgroup per box)",
+                4: " (persistent adjoint sweep in column strips, one workgroup per box)"}[mode],
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -247,14 +247,19 @@ dd4dvar_status dd4dvar_gather(dd4dvar_ctx* ctx, int32_t level, double* out_dev,
  *       sweep over all subdomains;
  *   3 = as 2, but local_cost_grad over all subdomains is ONE launch in which
  *       each workgroup runs its box's forward and then its adjoint sweep
- *       (forward_integrate and adjoint_integrate as in 2).
- * Modes 2 and 3 need an FP32 context whose extended boxes all fit one
+ *       (forward_integrate and adjoint_integrate as in 2);
+ *   4 = as 2, with the adjoint in column strips: each thread walks one
+ *       column of up to 11 consecutive rows of its box (needs
+ *       ceil(ny / floor(1024 / nx)) <= 11 for every extended box).
+ * Modes 2 to 4 need an FP32 context whose extended boxes all fit one
  * workgroup (at most 1024 columns, 11 passes of rows, and the padded level
  * frame with per-row tables and ring staging within 159 KB of LDS).
  * Results of modes 0 and 1 are identical bit for bit; modes 2 and 3 are
- * identical to each other and differ from 0 and 1 by FP32 rounding only (the
- * overlap forcing is formed in FP32 there).  E_INVALID for an unknown mode or
- * for modes 2, 3 where they do not apply.  The sub_ids form of
+ * identical to each other, mode 4 runs their arithmetic (up to the
+ * compiler's choice of fused multiply-adds) and sums J's FP64 terms in
+ * another order; modes 2 to 4 differ from 0 and 1 by FP32 rounding only (the
+ * overlap forcing is formed in FP32 there).  E_INVALID
+ * for an unknown mode or for modes 2 to 4 where they do not apply.  The sub_ids form of
  * local_cost_grad always uses the step kernels. */
 dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode);
 
@@ -288,7 +293,8 @@ dd4dvar_status dd4dvar_set_graph(dd4dvar_ctx* ctx, int32_t on);
 /* Autotuner of the execution plan of local_cost_grad: candidates are the
  * step kernels (mode 0) and, where the persistent sweeps apply, mode 2 with
  * the smallest pass count (1024 cells per pass) that holds the largest box,
- * mode 2 with the maximum pass count, and mode 3.  Each candidate evaluates
+ * mode 2 with the maximum pass count, mode 3, and mode 4 where it applies.
+ * Each candidate evaluates
  * every subdomain at x_dev once untimed and then reps times (1..1000) between
  * HIP events on the stream, writing J_dev / grad_dev (caller's scratch, the
  * local_cost_grad layouts; in graph mode the replays are timed).  The fastest

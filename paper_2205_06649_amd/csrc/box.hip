@@ -140,6 +140,36 @@ __device__ __forceinline__ void next_cell(Cell& q, int nx, int dr, int dc) {
   q.r = wrap ? q.r + 1 : q.r;
 }
 
+// per-row coefficients a cell's adjoint gather needs
+struct RowK {
+  float a1, a2, cf, ct, cc, a3n, a3s;
+};
+
+// transposed Jacobian of the increments of a cell and of its four neighbours
+// applied to lambda^{n+1} (l0 at the cell, kE .. kS at the neighbours), grouped
+// by shared factors; C .. Sv is the state of level n at the cell and its
+// neighbours, sn / ss the across-pole signs.  Returns (h, u, v).
+__device__ __forceinline__ V3<float> gather_cell(const RowK& k, float st, float stg, float h0,
+                                                 const V3<float>& C, const V3<float>& E,
+                                                 const V3<float>& W, const V3<float>& N,
+                                                 const V3<float>& Sv, const V3<float>& l0,
+                                                 const V3<float>& kE, const V3<float>& kW,
+                                                 const V3<float>& kN, const V3<float>& kS, float sn,
+                                                 float ss) {
+  const float a1 = k.a1, a2 = k.a2, cf = k.cf, ct = k.ct, cc = k.cc, a3n = k.a3n, a3s = k.a3s;
+  const float hm = h0 + C.h;
+  const float ctu = ct * C.u;
+  const float dh = kE.h - kW.h;                       // east - west height adjoints
+  const float q = kN.h * a3n - kS.h * a3s;            // north - south, with cos factors
+  const float vkn = sn * N.v, vks = ss * Sv.v;
+  float au = l0.u * (ct * C.v - a1 * (E.u - W.u)) + l0.v * (-a1 * (E.v - W.v) - cf - 2.0f * ctu);
+  au += a1 * ((kE.u * E.u - kW.u * W.u) + dh * hm) + st * (kN.u * vkn - kS.u * vks);
+  float av = l0.u * (cf + ctu - st * (N.u - Sv.u)) - l0.v * (st * (N.v - Sv.v));
+  av += a1 * (kE.v * E.u - kW.v * W.u) + st * (kN.v * vkn - kS.v * vks) + (hm * cc) * q;
+  const float ah = a2 * (kE.u - kW.u) + (a1 * C.u) * dh + stg * (sn * kN.v - ss * kS.v) + (C.v * cc) * q;
+  return {ah, au, av};
+}
+
 __device__ __forceinline__ double block_sum_box(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -670,18 +700,9 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
         const float* Lc = Lm + 3 * ((r + 1) * nxp + c + 1);
         const V3<float> l0 = lds3(Lc, 0), kE = lds3(Lc, 3), kW = lds3(Lc, -3);
         const V3<float> kN = lds3(Lc, n3), kS = lds3(Lc, -n3);
-        // transposed Jacobian of the increments of the cell and of its four
-        // neighbours applied to lambda^{n+1}, grouped by shared factors
-        const float hm = D.h0 + C.h;
-        const float ctu = ct * C.u;
-        const float dh = kE.h - kW.h;                       // east - west height adjoints
-        const float q = kN.h * a3n - kS.h * a3s;            // north - south, with cos factors
-        const float vkn = sn * N.v, vks = ss * Sv.v;
-        float au = l0.u * (ct * C.v - a1 * (E.u - W.u)) + l0.v * (-a1 * (E.v - W.v) - cf - 2.0f * ctu);
-        au += a1 * ((kE.u * E.u - kW.u * W.u) + dh * hm) + st * (kN.u * vkn - kS.u * vks);
-        float av = l0.u * (cf + ctu - st * (N.u - Sv.u)) - l0.v * (st * (N.v - Sv.v));
-        av += a1 * (kE.v * E.u - kW.v * W.u) + st * (kN.v * vkn - kS.v * vks) + (hm * cc) * q;
-        float ah = a2 * (kE.u - kW.u) + (a1 * C.u) * dh + stg * (sn * kN.v - ss * kS.v) + (C.v * cc) * q;
+        const V3<float> gth = gather_cell({a1, a2, cf, ct, cc, a3n, a3s}, st, stg, D.h0, C, E, W, N,
+                                          Sv, l0, kE, kW, kN, kS, sn, ss);
+        float ah = gth.h, au = gth.u, av = gth.v;
         if (n == 0) {
           au = l0.u + 0.5f * au;
           av = l0.v + 0.5f * av;
@@ -802,6 +823,306 @@ __global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const dou
   fwd_box_body<K, SPAN>(D, x, s, lds);
 }
 
+// Persistent adjoint sweep with column strips: thread t owns column
+// c = t mod nx of the rows g R .. g R + R - 1 of its strip g = t div nx
+// (G = 1024 div nx strips side by side, R = ceil(ny / G) <= K rows each) and
+// walks them one row per pass.  The state of row r+1, loaded for the north
+// neighbour of row r, is the centre of the next pass and the south
+// neighbour of the one after, and the same holds for lambda^{n+1} in LDS, so
+// a cell costs 10 buffer loads (its north state, east and west u, v, the
+// overlap target) instead of 14 and 9 LDS reads of lambda instead of 15; a
+// thread's column and its east/west edge masks are fixed for the whole
+// sweep.  Arithmetic, forcing, ring staging, observations and outputs as in
+// adj_box_body.
+template <int K, int MODE, bool SPAN>
+__device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double* __restrict__ x,
+                                               const double* __restrict__ xb,
+                                               const double* __restrict__ forcing,
+                                               double* __restrict__ out, int s, float* lds,
+                                               double* red) {
+  const SubDev S = D.subs[s];
+  const int nx = S.nx, ny = S.ny, nxp = nx + 2, npad = (ny + 2) * nxp;
+  const int ncell = S.ncell, nring = S.nring;
+  const int L = S.nlev - 1;
+  const int tid = threadIdx.x;
+  float* Lm = lds;                         // [npad][3]: lambda^{n+1}
+  float* rowtab = lds + 3 * npad;          // [ny][8]
+  float* zring = rowtab + 8 * ny;          // [2 levels][nring][3]: state on the ring
+  uint8_t* covl = reinterpret_cast<uint8_t*>(zring + 6 * nring);   // [ny*nx] coverage
+  int* lvl_tc = reinterpret_cast<int*>(covl + ((ncell + 3) & ~3));
+  int* lvl_obs = lvl_tc + S.nlev;
+  const int64_t plane = ncell;
+  const int32_t* hsrc = D.hsrc + S.hmap_off;
+  const int32_t* hoff = D.hoff + S.hmap_off;
+  const int32_t* hsgn = D.hsign + S.hmap_off;
+  const bool wraps = SPAN && S.span != 0;
+  const float st = D.st, stg = D.stg;
+  const int fp = ncell * 4, nx4 = nx * 4, lvb = 3 * ncell * 4;   // byte strides
+  const __amdgpu_buffer_rsrc_t zrs = make_rsrc(D.traj + S.zoff, S.nlev * lvb);
+  const __amdgpu_buffer_rsrc_t trs =
+      make_rsrc(MODE == 3 ? D.dz + S.zoff : D.targ + S.traj_off, S.nlev * lvb);
+  const float mu_f = float(D.mu);
+  const float ib_h = float(D.isb2[0]), ib_u = float(D.isb2[1]), ib_v = float(D.isb2[2]);
+  const int n3 = 3 * nxp;
+  // this thread's strip
+  const int G = kBoxThreads / nx;
+  const int R = (ny + G - 1) / G;
+  const int c = tid % nx, g = tid / nx;
+  const int r0 = g * R;
+  // rows this thread owns (none beyond the last strip or past the box end)
+  const int nrows = g < G ? max(0, min(R, ny - r0)) : 0;
+  // LDS addressing stays on the thread's own rows (a row of the box for the
+  // threads without rows), so every frame read is inside the frame
+  const int ra = nrows > 0 ? r0 : ny - 1;
+  const int kl = nrows > 0 ? nrows - 1 : 0;
+  const bool w_in = c > 0, e_in = c + 1 < nx;
+  const uint64_t mw = __builtin_amdgcn_ballot_w64(w_in), me = __builtin_amdgcn_ballot_w64(e_in);
+
+  fill_rowtab(rowtab, D, S);
+  for (int i = tid; i < 3 * npad; i += kBoxThreads) Lm[i] = 0.0f;   // lambda^{L+1} = 0
+  for (int k = tid; k < nring; k += kBoxThreads) {
+    const V3<float> gv = ring_value(D, S, k, L);
+    float* Zr = zring + (L & 1) * 3 * nring + 3 * k;
+    Zr[0] = gv.h; Zr[1] = gv.u; Zr[2] = gv.v;
+  }
+  for (int i = tid; i < ncell; i += kBoxThreads) covl[i] = D.cover[S.cell_off + i];
+  for (int n = tid; n < S.nlev; n += kBoxThreads) {
+    lvl_tc[n] = (MODE != 1) ? D.tcount[S.lev0 + n] : 0;
+    int cnt = 0;
+    if (MODE != 1)
+      for (int t = 0; t < S.ntile; ++t) {
+        const int64_t key = int64_t(S.tile0 + t) * D.maxlev + n;
+        cnt += D.obs_ptr[key + 1] - D.obs_ptr[key];
+      }
+    lvl_obs[n] = cnt;
+  }
+  const bool ring_thread0 = tid < nring;
+  bool rfrozen = true;
+  int roff = 0;
+  float rsg = 1.0f;
+  if (ring_thread0) {
+    rfrozen = hsrc[tid] >= 0;
+    roff = rfrozen ? tid : hoff[tid];
+    rsg = rfrozen ? 1.0f : float(hsgn[tid]);
+  }
+  __syncthreads();
+  double jloc = 0.0;
+  float ln[3][K];                          // lambda^{n+2} of rows r0 .. r0+K-1
+#pragma unroll
+  for (int k = 0; k < K; ++k) ln[0][k] = ln[1][k] = ln[2][k] = 0.0f;
+  // byte offset of (r0, c) and LDS frame index of (ra, c)
+  const int v00 = (r0 * nx + c) * 4, f00 = 3 * ((ra + 1) * nxp + c + 1);
+
+  for (int n = L; n >= 0; --n) {
+    const float* Z = D.traj + S.zoff + int64_t(n) * 3 * plane;
+    const int so = __builtin_amdgcn_readfirstlane(n * lvb);
+    const float* Zr = zring + (n & 1) * 3 * nring;
+    const int tcount = lvl_tc[n];
+    V3<float> gnext = {0.f, 0.f, 0.f};
+    const bool ring_thread = ring_thread0 && n > 0;
+    if (ring_thread) {
+      const float* src = rfrozen ? D.ring + S.ring_off + int64_t(n - 1) * 3 * nring + roff
+                                 : D.traj + S.zoff + int64_t(n - 1) * 3 * plane + roff;
+      const int64_t fs = rfrozen ? int64_t(nring) : plane;
+      gnext = {src[0], rsg * src[fs], rsg * src[2 * fs]};
+    }
+    // loads of the pass for row r: the state of row r+1 (clamped to row r on
+    // the last row), east and west u, v (clamped at the box edge) and the
+    // overlap target where covered; past the box end in-range and unused
+    struct RowLoads {
+      V3<float> Cn, tg;
+      float Eu, Ev, Wu, Wv;
+      int Kc;
+    };
+    auto issue = [&](int r, int v) {
+      RowLoads Q;
+      const int vn = r + 1 < ny ? v + nx4 : v;
+      Q.Cn = bload3(zrs, vn, so, fp);
+      const int ve = e_in ? v + 4 : v, vw = w_in ? v - 4 : v;
+      Q.Eu = bload(zrs, ve, so + fp);
+      Q.Ev = bload(zrs, ve, so + 2 * fp);
+      Q.Wu = bload(zrs, vw, so + fp);
+      Q.Wv = bload(zrs, vw, so + 2 * fp);
+      Q.Kc = 0;
+      Q.tg = {0.f, 0.f, 0.f};
+      if (MODE != 1) {
+        const int mc = v >> 2;
+        Q.Kc = int(covl[mc < ncell ? mc : ncell - 1]) * tcount - 1;
+        Q.tg = bload3(trs, Q.Kc > 0 ? v : 0, so, fp);
+      }
+      return Q;
+    };
+    // opaque per-level copies of the thread's start offsets and row range:
+    // every per-pass offset is rebuilt from them at each level instead of
+    // being hoisted out of the level loop (which would spill)
+    int v0 = v00, fb = f00, rb = r0, nr = nrows, kk = kl;
+    asm volatile("" : "+v"(v0), "+v"(fb), "+v"(rb), "+v"(nr), "+v"(kk));
+    // rows r0-1 and r0 (row -1: the cell itself, replaced from the ring)
+    V3<float> Cs = bload3(zrs, rb > 0 ? v0 - nx4 : v0, so, fp);
+    V3<float> Cc = bload3(zrs, v0, so, fp);
+    const float* L0 = Lm + fb;
+    V3<float> lp = lds3(L0, -n3), lc = lds3(L0, 0);   // lambda^{n+1} of rows r0-1, r0
+    RowLoads cur = issue(rb, v0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int r = rb + k;
+      const int v = v0 + k * nx4;
+      RowLoads nxt = cur;
+      if (k + 1 < K) nxt = issue(r + 1, v + nx4);
+      __builtin_amdgcn_sched_barrier(0);
+      const float* Lc = L0 + (k < kk ? k : kk) * n3;
+      const V3<float> ln1 = lds3(Lc, n3);            // lambda^{n+1} of row r+1
+      if (k < nr) {
+        const int m = v >> 2;
+        const bool n_in = r + 1 < ny, s_in = r > 0;
+        const float* rw = rowtab + 8 * r;
+        const RowK rk = {rw[0], rw[1], rw[3], rw[4], rw[5], rowtab[8 * (n_in ? r + 1 : r) + 2],
+                         rowtab[8 * (s_in ? r - 1 : r) + 2]};
+        const V3<float> C = Cc;
+        const V3<float> rE = lds3(Zr, e_in ? 0 : 3 * (2 * nx + ny + r));
+        const V3<float> rW = lds3(Zr, w_in ? 0 : 3 * (2 * nx + r));
+        const V3<float> E = pick3({0.f, cur.Eu, cur.Ev}, rE, me);
+        const V3<float> W = pick3({0.f, cur.Wu, cur.Wv}, rW, mw);
+        V3<float> N = cur.Cn, Sv = Cs;
+        // rows at the box's south or north edge (wave-uniform test)
+        if (__builtin_amdgcn_ballot_w64(!n_in || !s_in) != 0) {
+          N = pick3(N, lds3(Zr, n_in ? 0 : 3 * (nx + c)), __builtin_amdgcn_ballot_w64(n_in));
+          Sv = pick3(Sv, lds3(Zr, s_in ? 0 : 3 * c), __builtin_amdgcn_ballot_w64(s_in));
+        }
+        const float sn = (SPAN && !n_in && S.pole_n) ? -1.0f : 1.0f;
+        const float ss = (SPAN && !s_in && S.pole_s) ? -1.0f : 1.0f;
+        const V3<float> l0 = lc, kE = lds3(Lc, 3), kW = lds3(Lc, -3);
+        const V3<float> gth = gather_cell(rk, st, stg, D.h0, C, E, W, N, Sv, l0, kE, kW, ln1, lp,
+                                          sn, ss);
+        float ah = gth.h, au = gth.u, av = gth.v;
+        if (n == 0) {
+          au = l0.u + 0.5f * au;
+          av = l0.v + 0.5f * av;
+          ah = l0.h + 0.5f * ah;
+        }
+        float fh = 0.f, fu = 0.f, fv = 0.f;
+        if (MODE == 1) {
+          const double* Fz = forcing + S.traj_off + int64_t(n) * 3 * plane;
+          fh = float(Fz[m]);
+          fu = float(Fz[plane + m]);
+          fv = float(Fz[2 * plane + m]);
+        } else {
+          const V3<float> tg = cur.tg;
+          const float eh = MODE == 3 ? tg.h : C.h - tg.h;
+          const float eu = MODE == 3 ? tg.u : C.u - tg.u;
+          const float ev = MODE == 3 ? tg.v : C.v - tg.v;
+          const float mk = mu_f * float(cur.Kc);
+          fh = mk * ib_h * eh;
+          fu = mk * ib_u * eu;
+          fv = mk * ib_v * ev;
+          if (MODE != 3)
+            jloc += 0.5 * double(mk) * double(ib_h * eh * eh + ib_u * eu * eu + ib_v * ev * ev);
+        }
+        const float bh = fh + ah + ln[0][k];
+        const float bu = fu + au + ln[1][k];
+        const float bv = fv + av + ln[2][k];
+        if (n > 0) {
+          ln[0][k] = bh;
+          ln[1][k] = bu;
+          ln[2][k] = bv;
+        } else {
+          const int64_t o = S.ctrl_off + m;
+          if (MODE == 0) {
+            const double wb = D.weight_mode ? 1.0 : 1.0 / double(covl[m]);
+            const double dh = x[o] - xb[o];
+            const double du = x[o + plane] - xb[o + plane];
+            const double dv = x[o + 2 * plane] - xb[o + 2 * plane];
+            out[o] = wb * dh * D.isb2[0] + double(bh);
+            out[o + plane] = wb * du * D.isb2[1] + double(bu);
+            out[o + 2 * plane] = wb * dv * D.isb2[2] + double(bv);
+            jloc += 0.5 * wb * (dh * dh * D.isb2[0] + du * du * D.isb2[1] + dv * dv * D.isb2[2]);
+          } else {
+            out[o] = double(bh);
+            out[o + plane] = double(bu);
+            out[o + 2 * plane] = double(bv);
+          }
+        }
+      }
+      // roll rows: r becomes the south row, r+1 the centre
+      Cs = Cc;
+      Cc = cur.Cn;
+      lp = lc;
+      lc = ln1;
+      __builtin_amdgcn_sched_barrier(0);
+      cur = nxt;
+    }
+    const bool any_obs = MODE != 1 && lvl_obs[n] > 0;
+    __syncthreads();                                   // all reads of lambda^{n+1} done
+    if (ring_thread) {
+      float* Zq = zring + ((n - 1) & 1) * 3 * nring + 3 * tid;
+      Zq[0] = gnext.h; Zq[1] = gnext.u; Zq[2] = gnext.v;
+    }
+    if (n > 0) {
+      // lambda^n into LDS; lambda^{n+1} into the registers
+      int fs = f00, ns = nrows;
+      asm volatile("" : "+v"(fs), "+v"(ns));
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (k < ns) {
+          float* Lc = Lm + fs + k * n3;
+          const float th = Lc[0], tu = Lc[1], tv = Lc[2];
+          Lc[0] = ln[0][k];
+          Lc[1] = ln[1][k];
+          Lc[2] = ln[2][k];
+          ln[0][k] = th;
+          ln[1][k] = tu;
+          ln[2][k] = tv;
+        }
+      }
+    }
+    if (MODE != 1 && any_obs) {
+      __syncthreads();
+      for (int t = 0; t < S.ntile; ++t) {
+        const int64_t key = int64_t(S.tile0 + t) * D.maxlev + n;
+        const int o0 = D.obs_ptr[key], o1 = D.obs_ptr[key + 1];
+        for (int o = o0 + tid; o < o1; o += kBoxThreads) {
+          const int code = D.obs_code[o];
+          const int loc = code >> 2, f = code & 3;
+          const double rr = MODE == 3 ? double(D.dz[S.zoff + int64_t(n) * 3 * plane + f * plane + loc])
+                                      : double(Z[f * plane + loc]) - D.obs_val[o];
+          const double qo = D.obs_q[o];
+          if (MODE != 3) jloc += 0.5 * qo * rr * rr;
+          if (n > 0) {
+            const int lr = loc / nx, lcc = loc - lr * nx;
+            float* Lf = Lm + 3 * ((lr + 1) * nxp + lcc + 1) + f;
+            *Lf = float(double(*Lf) + qo * rr);
+          } else {
+            out[S.ctrl_off + f * plane + loc] += qo * rr;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (wraps && n > 0) {
+      fill_wraps(Lm, hsrc, hoff, hsgn, nring, nx, ny, false);
+      __syncthreads();
+    }
+  }
+  if (MODE == 0 || MODE == 2) {
+    const double tot = block_sum_box(jloc, red);
+    for (int t = tid + 1; t < S.ntile; t += kBoxThreads) D.jpart[S.tile0 + t] = 0.0;
+    if (tid == 0) D.jpart[S.tile0] = tot;
+  }
+}
+
+template <int K, int MODE, bool SPAN>
+__global__ __launch_bounds__(kBoxThreads) void k_adj_strip(Dom<float> D, const double* __restrict__ x,
+                                                           const double* __restrict__ xb,
+                                                           const double* __restrict__ forcing,
+                                                           double* __restrict__ out,
+                                                           const int32_t* __restrict__ order) {
+  extern __shared__ float lds[];
+  __shared__ double red[kBoxThreads / 64];
+  const int s = order[blockIdx.x];
+  if (D.active && !D.active[s]) return;
+  adj_strip_body<K, MODE, SPAN>(D, x, xb, forcing, out, s, lds, red);
+}
+
 template <int K, bool SPAN>
 __global__ __launch_bounds__(kBoxThreads) void k_tlm_box(Dom<float> D, const double* __restrict__ dx,
                                                          const int32_t* __restrict__ order) {
@@ -878,6 +1199,10 @@ hipError_t prepare_ks() {
   if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 2, SPAN>);
   if (e == hipSuccess) e = allow_lds(&k_adj_box<K, 3, SPAN>);
   if (e == hipSuccess) e = allow_lds(&k_tlm_box<K, SPAN>);
+  if (e == hipSuccess) e = allow_lds(&k_adj_strip<K, 0, SPAN>);
+  if (e == hipSuccess) e = allow_lds(&k_adj_strip<K, 1, SPAN>);
+  if (e == hipSuccess) e = allow_lds(&k_adj_strip<K, 2, SPAN>);
+  if (e == hipSuccess) e = allow_lds(&k_adj_strip<K, 3, SPAN>);
   if (e == hipSuccess) e = allow_lds(&k_eval_box<K, SPAN>);
   return e;
 }
@@ -916,6 +1241,26 @@ hipError_t eval_box_k(const Dom<float>& D, const double* x, const double* xb, do
   return hipGetLastError();
 }
 
+template <int K, int MODE, bool SPAN>
+hipError_t adj_strip_k(const Dom<float>& D, const double* x, const double* xb, const double* forcing,
+                       double* out, const int32_t* order, int nboxes, size_t lds_bytes,
+                       hipStream_t st) {
+  auto* kern = &k_adj_strip<K, MODE, SPAN>;
+  hipLaunchKernelGGL(kern, dim3(nboxes), dim3(kBoxThreads), lds_bytes, st, D, x, xb, forcing, out,
+                     order);
+  return hipGetLastError();
+}
+
+template <int K, bool SPAN>
+hipError_t adj_strip_mode(const Dom<float>& D, int mode, const double* x, const double* xb,
+                          const double* forcing, double* out, const int32_t* order, int nboxes,
+                          size_t lds_bytes, hipStream_t st) {
+  if (mode == 0) return adj_strip_k<K, 0, SPAN>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+  if (mode == 1) return adj_strip_k<K, 1, SPAN>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+  if (mode == 3) return adj_strip_k<K, 3, SPAN>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+  return adj_strip_k<K, 2, SPAN>(D, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+}
+
 template <int K, bool SPAN>
 hipError_t adj_box_mode(const Dom<float>& D, int mode, const double* x, const double* xb,
                         const double* forcing, double* out, const int32_t* order, int nboxes,
@@ -928,6 +1273,14 @@ hipError_t adj_box_mode(const Dom<float>& D, int mode, const double* x, const do
 }  // namespace
 
 int box_passes_max() { return kBoxKMax; }
+
+// rows per column strip of the strip adjoint (0 when it does not apply)
+int box_strip_rows(int ny, int nx, int nring, int nlev) {
+  if (box_passes(ny, nx, nring, nlev) == 0) return 0;
+  const int G = kBoxThreads / nx;
+  const int R = (ny + G - 1) / G;
+  return R <= kBoxKMax ? R : 0;
+}
 
 // raises the dynamic LDS limit of the kernels that run the given pass count
 // (once per process and device, before any launch or stream capture)
@@ -960,7 +1313,14 @@ hipError_t launch_tlm_box(const Dom<float>& D, const double* dx, const int32_t* 
 
 hipError_t launch_adj_box(const Dom<float>& D, int mode, const double* x, const double* xb,
                           const double* forcing, double* out, const int32_t* order, int nboxes,
-                          size_t lds_bytes, int passes, bool span, hipStream_t st) {
+                          size_t lds_bytes, int passes, bool span, bool strip, hipStream_t st) {
+  // column strips: passes = rows per strip
+  if (strip && passes <= 10)
+    return span ? adj_strip_mode<10, true>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st)
+                : adj_strip_mode<10, false>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st);
+  if (strip)
+    return span ? adj_strip_mode<kBoxKMax, true>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st)
+                : adj_strip_mode<kBoxKMax, false>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st);
   if (passes <= 10)
     return span ? adj_box_mode<10, true>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st)
                 : adj_box_mode<10, false>(D, mode, x, xb, forcing, out, order, nboxes, lds_bytes, st);

@@ -71,8 +71,10 @@ struct dd4dvar_ctx {
   const uint8_t* eval_mask = nullptr;   // subdomains evaluated by the sweeps (null = all)
   bool box_ok = false;                  // persistent per-box sweeps possible
   size_t box_lds = 0;
-  int box_k = 0;                        // passes of 1024 cells of the largest box
+  int box_k = 0;                        // passes of 1024 cells of the launches
+  int box_kmin = 0;                     // passes that hold the largest box
   bool box_span = false;                // some box spans the circle
+  int strip_k = 0;                      // rows per column strip of the strip adjoint (0: n/a)
   // state storage: every level (ckpt = 0), or checkpoint pairs every ckpt
   // levels plus one segment that the adjoint recomputes
   int ckpt = 0;
@@ -279,8 +281,9 @@ void local_adjoint(dd4dvar_ctx* c, int mode, const double* x, const double* forc
   Dom<T> D = local_dom<T>(c);
   if constexpr (std::is_same<T, float>::value) {
     if (!ids && c->exec_mode >= 2) {
-      chk(launch_adj_box(D, mode, x, c->xb, forcing, out, c->d_order, c->nsub, c->box_lds, c->box_k,
-                         c->box_span, st),
+      const bool strip = c->exec_mode == 4;
+      chk(launch_adj_box(D, mode, x, c->xb, forcing, out, c->d_order, c->nsub, c->box_lds,
+                         strip ? c->strip_k : c->box_k, c->box_span, strip, st),
           "persistent adjoint launch");
       return;
     }
@@ -419,7 +422,7 @@ void cost_grad_impl(dd4dvar_ctx* c, const std::vector<int32_t>* ids, const doubl
   mark(c, 3, st);
   if (c->timing) {
     int nf = 0, na = 0;
-    if (!ids && c->exec_mode == 2 && std::is_same<T, float>::value) {
+    if (!ids && (c->exec_mode == 2 || c->exec_mode == 4) && std::is_same<T, float>::value) {
       nf = na = 1;                      // one persistent launch per sweep
     } else if (!ids && c->exec_mode == 0) {
       nf = c->maxlev;
@@ -571,7 +574,10 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
     size_t lds = 0;
     int kmax = 0;
     bool ok = c->prec == DD4DVAR_FP32_STATE;
+    int strip = 0;
     for (const SubDev& S : c->subs) {
+      const int rs = box_strip_rows(S.ny, S.nx, S.nring, S.nlev);
+      strip = (rs == 0 || strip < 0) ? -1 : std::max(strip, rs);
       lds = std::max(lds, box_lds_bytes(S.ny, S.nx, S.nring, S.nlev));
       const int k = box_passes(S.ny, S.nx, S.nring, S.nlev);
       if (k == 0) ok = false;
@@ -579,8 +585,10 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
       if (S.span) c->box_span = true;
     }
     c->box_ok = ok;
+    c->strip_k = (ok && strip > 0) ? strip : 0;
     c->box_lds = lds;
     c->box_k = kmax;
+    c->box_kmin = kmax;
     // LDS limits of the persistent kernels are set here, outside any stream
     // capture, for the pass counts the context can run
     if (ok) {
@@ -852,7 +860,9 @@ const char* dd4dvar_last_error(const dd4dvar_ctx* ctx) {
 }
 
 dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode) {
-  if (!ctx || mode < 0 || mode > 3) return fail(ctx, DD4DVAR_E_INVALID, "bad exec mode");
+  if (!ctx || mode < 0 || mode > 4) return fail(ctx, DD4DVAR_E_INVALID, "bad exec mode");
+  if (mode == 4 && ctx->box_ok && ctx->strip_k == 0)
+    return fail(ctx, DD4DVAR_E_INVALID, "the column-strip adjoint needs at most 11 rows per strip");
   if (mode >= 2 && !ctx->box_ok)
     return fail(ctx, DD4DVAR_E_INVALID,
                 "persistent per-box sweeps need FP32 state and boxes that fit one workgroup's LDS");
@@ -1008,15 +1018,17 @@ dd4dvar_status dd4dvar_autotune(dd4dvar_ctx* ctx, const double* x_dev, double* J
   if (reps < 1 || reps > 1000) return fail(ctx, DD4DVAR_E_INVALID, "reps must be in 1..1000");
   API_GUARD(ctx, {
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // candidate execution plans: step kernels, then the persistent sweeps
-    // (one launch per sweep, or fused) with the smallest pass count that
-    // holds the largest box and with the maximum one
-    std::vector<std::pair<int, int>> cand = {{0, ctx->box_k}};
+    // candidate execution plans (mode, passes of the forward): step kernels,
+    // then the persistent sweeps (one launch per sweep, or fused) with the
+    // smallest pass count that holds the largest box and with the maximum
+    // one, and the column-strip adjoint where it applies
+    const int kmin = ctx->box_kmin, kmax = box_passes_max();
+    std::vector<std::pair<int, int>> cand = {{0, kmin}};
     if (ctx->box_ok && !ctx->ckpt) {
-      const int kmin = ctx->box_k, kmax = box_passes_max();
       cand.push_back({2, kmin});
       if (kmax != kmin) cand.push_back({2, kmax});
       cand.push_back({3, kmin});
+      if (ctx->strip_k > 0) cand.push_back({4, kmin});
     }
     const int mode0 = ctx->exec_mode, k0 = ctx->box_k;
     const bool timing0 = ctx->timing;
@@ -1039,7 +1051,7 @@ dd4dvar_status dd4dvar_autotune(dd4dvar_ctx* ctx, const double* x_dev, double* J
         float ms = 0;
         chk(hipEventElapsedTime(&ms, a, b), "elapsed");
         report->mode[i] = cand[i].first;
-        report->passes[i] = cand[i].first >= 2 ? cand[i].second : 0;
+        report->passes[i] = cand[i].first == 4 ? ctx->strip_k : (cand[i].first >= 2 ? cand[i].second : 0);
         report->ms[i] = double(ms) / reps;
         if (i == 0 || report->ms[i] < best) {
           best = report->ms[i];

@@ -53,6 +53,7 @@ void launch_dz_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hipS
 size_t box_lds_bytes(int ny, int nx, int nring, int nlev);
 int box_passes(int ny, int nx, int nring, int nlev);
 int box_passes_max();
+int box_strip_rows(int ny, int nx, int nring, int nlev);
 hipError_t box_prepare(int passes);
 hipError_t launch_fwd_box(const Dom<float>& D, const double* x, const int32_t* order, int nboxes,
                           size_t lds_bytes, int passes, bool span, hipStream_t st);
@@ -60,7 +61,7 @@ hipError_t launch_tlm_box(const Dom<float>& D, const double* dx, const int32_t* 
                           size_t lds_bytes, int passes, bool span, hipStream_t st);
 hipError_t launch_adj_box(const Dom<float>& D, int mode, const double* x, const double* xb,
                           const double* forcing, double* out, const int32_t* order, int nboxes,
-                          size_t lds_bytes, int passes, bool span, hipStream_t st);
+                          size_t lds_bytes, int passes, bool span, bool strip, hipStream_t st);
 hipError_t launch_eval_box(const Dom<float>& D, const double* x, const double* xb, double* grad,
                            const int32_t* order, int nboxes, size_t lds_bytes, int passes,
                            bool span, hipStream_t st);

@@ -38,11 +38,18 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
+# boxes spanning the circle, 128 columns wide (several rows per column strip)
+WIDE_CFG = dict(index=112, nlat=48, nlon=128, nsteps=8, bands=3, pieces=1, ntime=2,
+                overlap_cells=2, overlap_steps=1, obs_frac=0.05, obs_every=2)
+
+
 def _prob(which):
     if which == "span":
         return custom_problem(SPAN_CFG)
     if which == "mixed":
         return custom_problem(MIXED_CFG)
+    if which == "wide":
+        return custom_problem(WIDE_CFG)
     return problem(which)
 
 
@@ -145,6 +152,42 @@ def test_cost_grad_at_background_and_subsets():
     ctx.set_exec_mode(1)
     J3, g3 = ctx.cost_grad(xs)
     assert np.array_equal(J3.cpu().numpy(), J1) and np.array_equal(g3.cpu().numpy(), g1.cpu().numpy())
+
+
+@pytest.mark.parametrize("which", ["tiny1", "c1", "span", "mixed", "wide", "c2"])
+def test_persistent_strip_adjoint_fp32(which):
+    """Execution mode 4 (the persistent adjoint walking column strips of up to
+    11 rows per thread): the oracle's local cost and gradient to the FP32
+    bars, and the FP32 arithmetic of mode 2 up to the compiler's choice of
+    fused multiply-adds -- gradients, adjoints of a caller forcing and
+    Gauss-Newton products within 1e-5 of mode 2's, J within 1e-9."""
+    p, maps, bg, trajs, rings = _oracle_state(which)
+    ctx = _ctx(which, "fp32")
+    xs = _perturbed(p, maps, trajs, seed=8)
+    xp = ctx.pack_ctrl(xs)
+    res = {}
+    rng = np.random.default_rng(4)
+    forcing = ctx.pack_traj([rng.standard_normal((b.nlev, 3, b.ny, b.nx)) for b in maps.boxes])
+    dx = ctx.pack_ctrl([p.sigma_b[:, None, None] * rng.standard_normal((3, b.ny, b.nx))
+                        for b in maps.boxes])
+    for mode in (2, 4):
+        ctx.set_exec_mode(mode)
+        J, grad = ctx.cost_grad(xp)
+        adj = ctx.adjoint(forcing)
+        hv = ctx.gn_hessvec(dx)
+        res[mode] = (J.cpu().numpy(), grad.cpu().numpy(), adj.cpu().numpy(), hv.cpu().numpy())
+    J, g4, a4, h4 = res[4]
+    grads = ctx.unpack_ctrl(g4)
+    for b in maps.boxes:
+        s = b.sub
+        Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], rings[s],
+                                 {k: trajs[k] for k in maps.neighbors[s]})
+        ej, eg = float(abs(J[s] - Jr) / abs(Jr)), float(_rel(grads[s], gr))
+        assert ej <= TOL["fp32"] and eg <= TOL_GRAD["fp32"], (s, ej, eg)
+    J2, g2, a2, h2 = res[2]
+    for a, b in ((g4, g2), (a4, a2), (h4, h2)):
+        assert _rel(a, b) <= 1e-5, _rel(a, b)
+    assert np.allclose(J, J2, rtol=1e-9, atol=0)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
