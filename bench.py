@@ -158,13 +158,15 @@ def gn_product_bytes(ctx, prec_bytes, persistent=False):
 # digest of the kernel sources they were measured on: a changed kernel (or
 # another workload) reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    "k_adj": ("sweep", "bbfd2274bc1461e2", 1169846272),
-    "k_adj_box/10": ("box", "cae7c26932a8a8c2", 16113092608),
-    "k_adj_box/11": ("box", "cae7c26932a8a8c2", 16506113024),
-    "k_eval_box/10": ("box", "cae7c26932a8a8c2", 29929473024),
-    # Gauss-Newton normal-matrix product (persistent, 10 passes)
-    "k_tlm_box/10": ("box", "cae7c26932a8a8c2", 16793479168),
-    "k_adj_box_gn/10": ("box", "cae7c26932a8a8c2", 15120503808),
+    "k_adj": ("sweep", "bbfd2274bc1461e2", 1169846538),
+    "k_adj_box/10": ("box", "63bf9193f4688190", 16113218920),
+    "k_adj_box/11": ("box", "63bf9193f4688190", 16124804760),
+    "k_adj_strip/11": ("box", "63bf9193f4688190", 17810969082),
+    "k_eval_box/10": ("box", "63bf9193f4688190", 29933486080),
+    # Gauss-Newton normal-matrix product: tangent-linear sweep (10 passes)
+    # and the adjoint with the Gauss-Newton forcing (column strips, 11 rows)
+    "k_tlm_box/10": ("box", "63bf9193f4688190", 16795821514),
+    "k_adj_strip_gn/11": ("box", "63bf9193f4688190", 16550625608),
 }
 KERNEL_SOURCES = {"sweep": ("sweep.hip", "kernels.h", "stencil.h"),
                   "box": ("box.hip", "kernels.h", "stencil.h")}
@@ -228,7 +230,7 @@ GN_OPTS = dict(max_outer=2, max_iter=3, cg_max_iter=20, cg_rtol=1e-4, grad_rtol=
                outer_tol=0.0)
 
 
-def gn_leg(prob, x, mode, config, reps=10, solves=True):
+def gn_leg(prob, x, mode, passes, config, reps=10, solves=True):
     """Gauss-Newton local solver (Alg. 5 / Alg. 6).  The normal-matrix
     product (tangent-linear sweep, then the adjoint sweep forced by the
     residual weights applied to the perturbation) timed at x in FP32, and DD
@@ -273,9 +275,11 @@ def gn_leg(prob, x, mode, config, reps=10, solves=True):
     out["adjoint_algorithmic_GBs"] = adj_b / ((ms_prod - ms_tlm) * 1e-3) / 1e9
     if mode >= 2:
         # HBM bytes the counters measured per launch (the context's first plan:
-        # 10 passes of 1024 cells), while the kernel sources are unchanged
+        # 10 passes of 1024 cells; the strip adjoint with the autotuned rows),
+        # while the kernel sources are unchanged
         out["tlm_traffic"] = measured_traffic("k_tlm_box/10", config)
-        out["adjoint_traffic"] = measured_traffic("k_adj_box_gn/10", config)
+        out["adjoint_traffic"] = measured_traffic(
+            f"k_adj_strip_gn/{passes}" if mode == 4 else "k_adj_box_gn/10", config)
     log(f"gauss-newton product {ms_prod:.2f} ms (tangent-linear {ms_tlm:.2f} ms)")
     ctx.close()
     del ctx, dx, hv
@@ -556,7 +560,8 @@ def main():
     if not args.no_solve:
         result["solve"] = solve_leg(prob, mode)
     if not args.no_gn:
-        result["gauss_newton"] = gn_leg(prob, x, mode, args.config, solves=not args.no_gn_solve)
+        result["gauss_newton"] = gn_leg(prob, x, mode, passes, args.config,
+                                        solves=not args.no_gn_solve)
 
     if not args.no_cpu:
         log("timing the oracle on host cores")
