@@ -151,6 +151,81 @@ def test_fullsize_solve_fp32_against_fp64():
         assert np.linalg.norm((xa - p.truth0) / sb) < np.linalg.norm((p.xb0 - p.truth0) / sb)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp64", 2e-12)])
+def test_fullsize_gn_product_sampled_subdomains(prec, tol):
+    """The Gauss-Newton normal-matrix product (eq. line5and7) of all 2048
+    local functionals in one batched call, against the oracle's product on
+    sampled first-interval boxes (FP32: the persistent kernels of mode 2)."""
+    from oracle import gn
+    from paper_2205_06649_amd.context import Context
+    p, maps, sample, bg = _fullsize()
+    print(f"full-size Gauss-Newton product {prec}, sample {sample}", flush=True)
+    ctx = Context(p, prec)
+    if prec == "fp32":
+        ctx.set_exec_mode(2)
+    rng = np.random.default_rng(12)
+    xs = [x + 0.3 * p.sigma_b[:, None, None] * rng.standard_normal(x.shape)
+          for x in ctx.unpack_ctrl(ctx.background_controls())]
+    dxs = [p.sigma_b[:, None, None] * rng.standard_normal(x.shape) for x in xs]
+    ctx.forward(ctx.pack_ctrl(xs), with_traj=False)
+    hv = ctx.gn_hessvec(ctx.pack_ctrl(dxs)).cpu().numpy()
+    assert np.all(np.isfinite(hv))
+    hvs = ctx.unpack_ctrl(hv)
+    g = model.Grid.of(p)
+    trajs = {}
+    for s in sample:
+        need = set(maps.neighbors[s].tolist()) | {int(k) for k in maps.halo_src[s] if k >= 0} | {s}
+        for k in need:
+            if k not in trajs:
+                trajs[k] = local.restrict_global(maps, k, bg)
+        ring = local.ring_from_trajs(maps, s, trajs)
+        geo = local.LocalGeometry(g, maps, s)
+        lt = local.forward(geo, xs[s], ring)
+        ref = gn.hessvec(p, maps, s, lt, ring, dxs[s])
+        e = _rel(hvs[s], ref)
+        print(f"  subdomain {s}: product rel {e:.2e}", flush=True)
+        assert e <= tol, (s, e)
+    ctx.close()
+
+
+def test_fullsize_gn_solve_fp32_against_fp64():
+    """Full-size DD solve with Gauss-Newton local solves (two outer
+    iterations of three updates, CG to 1e-4 or 20 iterations): the FP32
+    analysis (persistent kernels) within 1e-4 of the FP64 one, both closer to
+    the truth than the background."""
+    import time
+    import torch
+    from paper_2205_06649_amd.context import Context
+    p, maps, sample, bg = _fullsize()
+    opts = dict(max_outer=2, max_iter=3, cg_max_iter=20, cg_rtol=1e-4, grad_rtol=1e-6,
+                outer_tol=0.0, local_solver="gn")
+    res = {}
+    for prec in ("fp64", "fp32"):
+        print(f"full-size Gauss-Newton solve {prec}", flush=True)
+        ctx = Context(p, prec)
+        if prec == "fp32":
+            ctx.set_exec_mode(2)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        xa, rep, st, _ = ctx.solve(**opts)
+        dt = time.perf_counter() - t
+        print(f"  {prec}: {dt:.2f} s, {rep.total_evals} evaluations, {rep.gn_products} products, "
+              f"gradient ratio {rep.gnorm_ratio_max:.2e}", flush=True)
+        assert np.all(np.isfinite(xa))
+        res[prec] = xa
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    ref = res["fp64"]
+    err = max(np.linalg.norm(res["fp32"][f] - ref[f]) / np.linalg.norm(ref[f] - ref[f].mean())
+              for f in range(3))
+    print(f"  fp32 analysis error vs fp64: {err:.2e}", flush=True)
+    assert err <= 1e-4
+    sb = p.sigma_b[:, None, None]
+    for xa in res.values():
+        assert np.linalg.norm((xa - p.truth0) / sb) < np.linalg.norm((p.xb0 - p.truth0) / sb)
+
+
 @functools.lru_cache(maxsize=None)
 def _long_window():
     """512 x 1024, 1000 steps, 8 x 8 x 10 boxes: local windows of 103-106
