@@ -6,9 +6,11 @@ its own time interval (eq. restricted) with the frozen halo ring of the last
 exchange, run by dd4dvar_forward_integrate.  Its backward is the library's
 hand-written adjoint sweep (dd4dvar_adjoint_integrate): the transpose of the
 discrete tangent-linear model applied in reverse time, with the incoming
-trajectory gradient as forcing at every level.  Autograd never traces the
+trajectory gradient as forcing at every level.  Its forward-mode derivative
+(``torch.autograd.forward_ad``) is the library's tangent-linear sweep
+(dd4dvar_tangent_linear, the TLM of Alg. 6).  Autograd never traces the
 time loop; any torch function of the trajectories (a misfit, a projection)
-can be differentiated back to x.
+can be differentiated back to x, in reverse or forward mode.
 
 ``LocalCost`` is the regularized local functional of every subdomain
 (eq. eq:cost:parallel1: background, observation and overlap terms) as a
@@ -47,7 +49,17 @@ class LocalSweep(torch.autograd.Function):
         fctx.dd = dd
         fctx.gen = dd.traj_generation
         fctx.save_for_backward(x)
+        fctx.save_for_forward(x)
         return traj
+
+    @staticmethod
+    def jvp(fctx, x_t, dd_t):
+        dd = fctx.dd
+        (x,) = fctx.saved_tensors
+        if dd.traj_generation != fctx.gen:
+            dd.forward(x, with_traj=False)
+            fctx.gen = dd.traj_generation
+        return dd.tangent_linear(x_t.to(torch.float64).contiguous())
 
     @staticmethod
     def backward(fctx, g):

@@ -57,6 +57,37 @@ def test_local_sweep_backward_is_the_adjoint(which, prec):
         assert _rel(grads[b.sub], ref) <= TOL[prec], b.sub
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("which", ["c1", "small"])
+def test_local_sweep_forward_mode_is_the_tlm(which, prec):
+    """Forward-mode AD of LocalSweep (a dual tensor through the sweep) is the
+    tangent-linear model: against the oracle's TLM per box, and consistent
+    with the reverse mode (<M' dx, y> = <dx, M'^T y>)."""
+    import torch.autograd.forward_ad as fwAD
+    from paper_2205_06649_amd.autograd import local_sweep
+    p, maps, rings, ctx, xs, x, torch = _setup(which, prec, seed=4)
+    rng = np.random.default_rng(5)
+    dxs = [p.sigma_b[:, None, None] * rng.standard_normal(xx.shape) for xx in xs]
+    dx = ctx.pack_ctrl(dxs)
+    with fwAD.dual_level():
+        out = local_sweep(ctx, fwAD.make_dual(x, dx))
+        tangent = fwAD.unpack_dual(out).tangent
+    dt = ctx.unpack_traj(tangent)
+    g = model.Grid.of(p)
+    for b in maps.boxes:
+        geo = local.LocalGeometry(g, maps, b.sub)
+        lt = local.forward(geo, xs[b.sub], rings[b.sub])
+        ref = local.tlm(geo, lt, rings[b.sub], dxs[b.sub])
+        assert _rel(dt[b.sub], ref) <= TOL[prec], b.sub
+    w = [rng.standard_normal((b.nlev, 3, b.ny, b.nx)) for b in maps.boxes]
+    W = ctx.pack_traj(w)
+    xr = x.clone().requires_grad_(True)
+    (local_sweep(ctx, xr) * W).sum().backward()
+    lhs = float((tangent * W).sum())
+    rhs = float((xr.grad * dx).sum())
+    assert abs(lhs - rhs) <= (1e-12 if prec == "fp64" else 1e-5) * abs(lhs)
+
+
 def test_local_sweep_nonlinear_loss_finite_differences():
     """A nonlinear torch loss of the trajectories: <grad, d> from autograd
     against centred differences of the loss."""
