@@ -326,9 +326,46 @@ def time_evals(ctx, x, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps, J, g
 
 
+def step_distribution(ctx, x, steps):
+    """Per-evaluation durations from HIP events on the launch stream (one
+    pair per evaluation, after the timed run): median, p10, p90 in ms."""
+    import torch
+    J = torch.empty(ctx.nsub, dtype=torch.float64, device="cuda")
+    g = torch.empty(ctx.ctrl_len, dtype=torch.float64, device="cuda")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        ctx.cost_grad(x, J, g)
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"median": float(np.median(t)), "p10": float(np.percentile(t, 10)),
+            "p90": float(np.percentile(t, 90)), "n": int(steps)}
+
+
+_POOL = {}
+
+
+def _pool_eval(s):
+    """One local cost+gradient evaluation in a forked worker (inputs inherited
+    from the parent); returns (local point-steps, seconds)."""
+    from oracle import local
+    d = _POOL
+    b = d["maps"].boxes[s]
+    t0 = time.perf_counter()
+    local.cost_grad(d["prob"], d["maps"], s, d["x"][s], d["trajs"][s][0], d["rings"][s],
+                    {k: d["trajs"][k] for k in d["maps"].neighbors[s]})
+    return b.ny * b.nx * (b.nlev - 1), time.perf_counter() - t0
+
+
 def cpu_baseline(spec, budget_s=20.0):
     """The FP64 oracle timed on host cores over a bounded sample: whole local
-    cost+gradient evaluations of first-interval subdomains of the workload."""
+    cost+gradient evaluations of first-interval subdomains of the workload,
+    first in one process, then in a pool of forked processes (one per host
+    core, at most 16) over further subdomains of the same sample.  Runs before
+    the GPU is touched, so the workers inherit no device state."""
+    import multiprocessing as mp
     from oracle import ddmaps, local, model
     g = model.Grid.of(spec)
     maps = ddmaps.build(spec.replace(obs_value=np.zeros(spec.nobs)))
@@ -345,33 +382,58 @@ def cpu_baseline(spec, budget_s=20.0):
                  + spec.obs_sigma[sel] * spec.obs_noise[sel])
     prob = spec.replace(obs_value=vals)   # later steps are never read by the sample
     bg = model.forward(g, spec.xb0, lmax)
-    trajs = {}
+    log(f"cpu baseline: oracle inputs ready ({len(sample)} candidate subdomains)")
+    trajs, rings, xs = {}, {}, {}
     rng = np.random.default_rng(1)
-    done = 0
-    pts = 0
-    t_total = 0.0
     for s in sample:
-        b = maps.boxes[s]
         need = set(maps.neighbors[s].tolist()) | set(int(k) for k in maps.halo_src[s] if k >= 0)
-        for k in need:
+        for k in need | {s}:
             if k not in trajs:
                 trajs[k] = local.restrict_global(maps, k, bg)
-        trajs.setdefault(s, local.restrict_global(maps, s, bg))
-        ring = local.ring_from_trajs(maps, s, trajs)
-        xb = trajs[s][0]
-        x = xb + 0.3 * spec.sigma_b[:, None, None] * rng.standard_normal(xb.shape)
-        t0 = time.perf_counter()
-        local.cost_grad(prob, maps, s, x, xb, ring, {k: trajs[k] for k in maps.neighbors[s]})
-        t_total += time.perf_counter() - t0
-        pts += b.ny * b.nx * (b.nlev - 1)
+        rings[s] = local.ring_from_trajs(maps, s, trajs)
+        xs[s] = trajs[s][0] + 0.3 * spec.sigma_b[:, None, None] * rng.standard_normal(trajs[s][0].shape)
+    _POOL.update(prob=prob, maps=maps, trajs=trajs, rings=rings, x=xs)
+    # one process
+    done = pts = 0
+    t_total = 0.0
+    for s in sample * 4:
+        n, dt = _pool_eval(s)
+        pts += n
+        t_total += dt
         done += 1
-        if t_total >= budget_s:
+        if t_total >= budget_s / 2:
             break
-    return dict(value=pts / t_total, unit="local grid-point-steps/s", cores=1, kind="oracle",
-                sample=f"{done} full local cost+gradient evaluations of first-interval "
-                       f"{maps.boxes[sample[0]].ny}x{maps.boxes[sample[0]].nx}x"
-                       f"{maps.boxes[sample[0]].nlev - 1}-step subdomains of the same workload "
-                       f"(NumPy FP64, one process, {t_total:.1f} s)",
+    single = pts / t_total
+    log(f"cpu baseline: one process {single:.3e} local point-steps/s ({done} evaluations)")
+    # a pool of forked processes over the subdomains of the sample, taken in
+    # turn (again from the first when the sample is exhausted)
+    ncores = max(1, min(16, os.cpu_count() or 1))
+    per_eval = t_total / done
+    nwork = int(max(ncores, ncores * round(budget_s / 2 / per_eval))) if ncores > 1 else 0
+    work = [sample[(done + i) % len(sample)] for i in range(nwork)]
+    pool_rate, pool_wall = None, None
+    if work:
+        ctx = mp.get_context("fork")
+        t0 = time.perf_counter()
+        with ctx.Pool(ncores) as pool:
+            res = pool.map(_pool_eval, work, chunksize=1)
+        pool_wall = time.perf_counter() - t0
+        pool_rate = sum(r[0] for r in res) / pool_wall
+        log(f"cpu baseline: {ncores} processes {pool_rate:.3e} local point-steps/s "
+            f"({len(work)} evaluations, {pool_wall:.1f} s)")
+    box = maps.boxes[sample[0]]
+    shape = f"{box.ny}x{box.nx}x{box.nlev - 1}-step"
+    if pool_rate is not None:
+        return dict(value=pool_rate, unit="local grid-point-steps/s", cores=ncores, kind="oracle",
+                    sample=f"{len(work)} full local cost+gradient evaluations of first-interval "
+                           f"{shape} subdomains of the same workload in {ncores} forked processes "
+                           f"(NumPy FP64, {pool_wall:.1f} s wall)",
+                    seconds=pool_wall,
+                    single_process={"value": single, "cores": 1, "evaluations": done,
+                                    "seconds": t_total})
+    return dict(value=single, unit="local grid-point-steps/s", cores=1, kind="oracle",
+                sample=f"{done} full local cost+gradient evaluations of first-interval {shape} "
+                       f"subdomains of the same workload (NumPy FP64, one process, {t_total:.1f} s)",
                 seconds=t_total)
 
 
@@ -398,12 +460,20 @@ def main():
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         return 2
 
-    import torch
     import synth
-    from paper_2205_06649_amd.context import Context
 
     t0 = time.perf_counter()
     spec = synth.make_spec(args.config)
+    cpu = None
+    if not args.no_cpu:
+        # before any device work: the worker processes are forked from here
+        log("timing the oracle on host cores")
+        cpu = cpu_baseline(spec, args.cpu_budget)
+        cpu["host_cpu"] = _cpu_model()
+
+    import torch
+    from paper_2205_06649_amd.context import Context
+
     log(f"spec {args.config}: {spec.nlat}x{spec.nlon}x{spec.nsteps}, nobs={spec.nobs} "
         f"({time.perf_counter() - t0:.1f}s)")
     prob = synth.finish_spec(spec, gpu_truth_forward)
@@ -433,6 +503,8 @@ def main():
     passes = tune["candidates"][tune["chosen"]]["passes"]
     ms, J32, g32 = time_evals(ctx, x, args.steps, args.warmup)
     log(f"fp32 graph replays, mode {mode}: {ms:.3f} ms/eval")
+    dist = step_distribution(ctx, x, args.steps)
+    log(f"per replay: median {dist['median']:.3f} ms, p10 {dist['p10']:.3f}, p90 {dist['p90']:.3f}")
     ctx.set_graph(False)
     ms_eager, _, _ = time_evals(ctx, x, args.steps, args.warmup)
     log(f"fp32 eager launches, mode {mode}: {ms_eager:.3f} ms/eval")
@@ -468,6 +540,18 @@ def main():
         kernel_bytes = adj_b / tm["adj_launches"] * calls
     achieved = kernel_bytes / (kernel_ms * 1e-3) / 1e9
     J32h, g32h = J32.cpu().numpy(), g32.cpu().numpy()
+    # the exchange of Alg. 1 (once per outer iteration): every box integrated
+    # from x, then rings and overlap targets from the new trajectories
+    for _ in range(2):
+        ctx.exchange(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        ctx.exchange(x)
+    e1.record()
+    e1.synchronize()
+    exchange_ms = e0.elapsed_time(e1) / 5
+    log(f"exchange: {exchange_ms:.3f} ms")
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         a.fill_(1.0)
@@ -522,7 +606,8 @@ def main():
             "avg_launch_ms": kernel_ms,
         },
         "phases_ms": {"forward_sweep": fwd_ms, "adjoint_sweep": adj_ms,
-                      "reduce": tm["reduce_ms"] / calls},
+                      "reduce": tm["reduce_ms"] / calls, "exchange": exchange_ms},
+        "per_replay_ms": dist,
         "exec_mode": EXEC_MODES[mode],
         "autotune": tune,
         "timed": "HIP graph replays of the chosen plan",
@@ -563,10 +648,8 @@ def main():
         result["gauss_newton"] = gn_leg(prob, x, mode, passes, args.config,
                                         solves=not args.no_gn_solve)
 
-    if not args.no_cpu:
-        log("timing the oracle on host cores")
-        result["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
-        result["cpu_baseline"]["host_cpu"] = _cpu_model()
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
     return 0
 
