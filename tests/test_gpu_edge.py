@@ -1,0 +1,125 @@
+"""Edge cases of the hot path on the GPU, against the oracle.
+
+* one box (P = Q = 1): the local functional is global 4D-Var (eq. min3sec),
+  compared with the oracle's global functional directly;
+* no observations at all (background and overlap terms only);
+* the largest box the persistent kernels take (80 x 136 cells, 159.7 KB of
+  LDS, 11 passes), where the column-strip adjoint does not apply (12 rows
+  per strip) and is refused;
+* one-step intervals (local windows of 3 or 4 levels).
+
+Bars as in the parity tests: FP64 J 1e-12, gradients 2e-12; FP32 1e-4.
+Execution modes: 0 (step kernels) for both precisions, 2 and 4 (persistent)
+for FP32 where they apply.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import custom_problem
+from oracle import dd, ddmaps, local, model
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-4}
+TOL_GRAD = {"fp64": 2e-12, "fp32": 1e-4}
+
+C1 = synth.CONFIGS["c1"]
+CASES = {
+    "one_box": dict(C1, bands=1, pieces=1, ntime=1, overlap_cells=0, overlap_steps=0,
+                    index=113),
+    "no_obs": dict(C1, index=114),
+    "largest_box": dict(index=115, nlat=152, nlon=256, nsteps=8, bands=2, pieces=2, ntime=1,
+                        overlap_cells=4, overlap_steps=0, obs_frac=0.02, obs_every=4),
+    "one_step": dict(C1, nsteps=4, ntime=4, overlap_steps=1, obs_every=1, index=116),
+}
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.longdouble)
+    b = np.asarray(b, dtype=np.longdouble)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+@functools.lru_cache(maxsize=None)
+def _state(which):
+    p = custom_problem(CASES[which])
+    if which == "no_obs":
+        p = p.replace(obs_step=p.obs_step[:0], obs_cell=p.obs_cell[:0], obs_field=p.obs_field[:0],
+                      obs_value=p.obs_value[:0], obs_sigma=p.obs_sigma[:0],
+                      obs_noise=p.obs_noise[:0])
+    maps = ddmaps.build(p)
+    bg, trajs = dd.background(p, maps)
+    rings, _ = dd.exchange(maps, trajs)
+    return p, maps, trajs, rings
+
+
+def _controls(p, maps, trajs, seed):
+    rng = np.random.default_rng(seed)
+    sb = p.sigma_b[:, None, None]
+    return [trajs[b.sub][0] + 0.3 * sb * rng.standard_normal(trajs[b.sub][0].shape)
+            for b in maps.boxes]
+
+
+def _run(which, prec, mode, xs):
+    from paper_2205_06649_amd.context import Context
+    p, maps, trajs, rings = _state(which)
+    ctx = Context(p, prec)
+    ctx.set_exec_mode(mode)
+    J, grad = ctx.cost_grad(ctx.pack_ctrl(xs))
+    out = J.cpu().numpy(), ctx.unpack_ctrl(grad)
+    ctx.close()
+    return out
+
+
+PLANS = [("fp64", 0), ("fp32", 0), ("fp32", 2), ("fp32", 4)]
+
+
+@pytest.mark.parametrize("prec,mode", PLANS)
+def test_one_box_is_global_4dvar(prec, mode):
+    p, maps, trajs, rings = _state("one_box")
+    assert len(maps.boxes) == 1 and (maps.halo_src[0] < 0).all()
+    xs = _controls(p, maps, trajs, seed=1)
+    J, grads = _run("one_box", prec, mode, xs)
+    Jg, gg = model.cost_grad(p, xs[0])
+    assert abs(J[0] - Jg) / abs(Jg) <= TOL[prec]
+    assert _rel(grads[0], gg) <= TOL_GRAD[prec]
+
+
+@pytest.mark.parametrize("which", ["no_obs", "one_step", "largest_box"])
+@pytest.mark.parametrize("prec,mode", PLANS)
+def test_edge_configurations(which, prec, mode):
+    from paper_2205_06649_amd import _lib as L
+    p, maps, trajs, rings = _state(which)
+    xs = _controls(p, maps, trajs, seed=2)
+    if which == "largest_box" and mode == 4:
+        # 80 rows in strips of 136 columns: 12 rows per strip, beyond 11
+        from paper_2205_06649_amd.context import Context
+        ctx = Context(p, prec)
+        ctx.set_exec_mode(2)
+        with pytest.raises(L.DD4DVarError) as e:
+            ctx.set_exec_mode(4)
+        assert e.value.status == L.DD4DVAR_E_INVALID
+        ctx.close()
+        return
+    J, grads = _run(which, prec, mode, xs)
+    for b in maps.boxes:
+        s = b.sub
+        Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], rings[s],
+                                 {k: trajs[k] for k in maps.neighbors[s]},
+                                 dtype=np.longdouble if prec == "fp64" else np.float64)
+        ej, eg = float(abs(J[s] - Jr) / abs(Jr)), _rel(grads[s], gr)
+        assert ej <= TOL[prec] and eg <= TOL_GRAD[prec], (s, ej, eg)
+
+
+def test_case_shapes():
+    """The cases have the shapes they are meant to exercise."""
+    p, maps, _, _ = _state("largest_box")
+    assert {(b.ny, b.nx) for b in maps.boxes} == {(80, 136)}
+    p, maps, _, _ = _state("one_step")
+    assert min(b.nlev for b in maps.boxes) == 3 and max(b.nlev for b in maps.boxes) == 4
+    p, maps, _, _ = _state("no_obs")
+    assert p.nobs == 0 and all(maps.obs_bin[b.sub].size == 0 for b in maps.boxes)
