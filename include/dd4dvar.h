@@ -367,6 +367,23 @@ dd4dvar_status dd4dvar_solve(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* opts,
                              const double* x_init_dev, double* x_out_dev,
                              double* xa_host, dd4dvar_solve_report* report);
 
+/* Mixed-precision Gauss-Newton solve (Alg. 1 with the local solver of
+ * Alg. 5 / Alg. 6): ctx (FP64) evaluates every J_s and gradient, the stop
+ * tests, the exchange and the gather; ctx_lo, an FP32-state context created
+ * from the same descriptors on the same device, integrates each iterate
+ * again in FP32 and supplies the normal-matrix products of the conjugate
+ * gradients from its own sweeps (persistent ones in its execution modes 2 to
+ * 4).  An inexact Newton method: the iterates converge to the stationary
+ * point of the FP64 functionals while most of the sweeps run in FP32.  opts
+ * as for dd4dvar_solve with local_solver = 1; both contexts are exchanged at
+ * every outer iteration.  E_INVALID for another local solver, wrong
+ * precisions, differing plans or devices, or checkpoints on either context.
+ * Synchronous; outputs as for dd4dvar_solve. */
+dd4dvar_status dd4dvar_solve_mixed(dd4dvar_ctx* ctx, dd4dvar_ctx* ctx_lo,
+                                   const dd4dvar_solve_opts* opts,
+                                   const double* x_init_dev, double* x_out_dev,
+                                   double* xa_host, dd4dvar_solve_report* report);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,6 +100,8 @@ _SIGS = {
     "dd4dvar_get_timing": (C.c_int, [_VP, C.POINTER(C.c_double)]),
     "dd4dvar_solve": (C.c_int, [_VP, C.POINTER(dd4dvar_solve_opts), _VP, _VP, _VP,
                                 C.POINTER(dd4dvar_solve_report)]),
+    "dd4dvar_solve_mixed": (C.c_int, [_VP, _VP, C.POINTER(dd4dvar_solve_opts), _VP, _VP, _VP,
+                                      C.POINTER(dd4dvar_solve_report)]),
 }
 
 _lib = None
@@ -273,6 +275,15 @@ def dd4dvar_solve(ctx, opts, x_init_dev, x_out_dev, xa_host):
     rep = dd4dvar_solve_report()
     st = lib().dd4dvar_solve(ctx, C.byref(opts), x_init_dev, x_out_dev,
                              _ptr(xa_host, C.c_double), C.byref(rep))
+    if st not in (DD4DVAR_OK, DD4DVAR_E_NOTCONVERGED):
+        check(st, ctx)
+    return st, rep
+
+
+def dd4dvar_solve_mixed(ctx, ctx_lo, opts, x_init_dev, x_out_dev, xa_host):
+    rep = dd4dvar_solve_report()
+    st = lib().dd4dvar_solve_mixed(ctx, ctx_lo, C.byref(opts), x_init_dev, x_out_dev,
+                                   _ptr(xa_host, C.c_double), C.byref(rep))
     if st not in (DD4DVAR_OK, DD4DVAR_E_NOTCONVERGED):
         check(st, ctx)
     return st, rep

@@ -160,7 +160,11 @@ class Context:
 
     def solve(self, lbfgs_m=8, max_iter=50, max_outer=5, max_ls=30, grad_rtol=0.0,
               outer_tol=1e-6, armijo_c1=1e-4, x_init=None, want_controls=False,
-              j_noise_rtol=None, local_solver="lbfgs", cg_max_iter=50, cg_rtol=1e-6):
+              j_noise_rtol=None, local_solver="lbfgs", cg_max_iter=50, cg_rtol=1e-6,
+              products=None):
+        """Alg. 1.  products: an FP32-state Context of the same problem whose
+        sweeps supply the Gauss-Newton normal-matrix products while this
+        (FP64) context evaluates J and the gradients (dd4dvar_solve_mixed)."""
         p = self.prob
         if j_noise_rtol is None:
             j_noise_rtol = self.J_NOISE_RTOL[self.precision]
@@ -171,7 +175,12 @@ class Context:
                                     cg_max_iter=cg_max_iter, cg_rtol=cg_rtol)
         xa = np.empty((3, p.nlat, p.nlon))
         xo = self.empty(self.ctrl_len) if want_controls else None
-        st, rep = L.dd4dvar_solve(self.handle, opts, self.ptr(x_init), self.ptr(xo), xa)
+        if products is None:
+            st, rep = L.dd4dvar_solve(self.handle, opts, self.ptr(x_init), self.ptr(xo), xa)
+        else:
+            st, rep = L.dd4dvar_solve_mixed(self.handle, products.handle, opts, self.ptr(x_init),
+                                            self.ptr(xo), xa)
+            products.traj_generation += 1
         self.traj_generation += 1
         return xa, rep, st, xo
 

@@ -32,7 +32,8 @@ using namespace dd4dvar;
 
 namespace dd4dvar {
 dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* opts, const double* x_init,
-                          double* x_out, double* xa_host, dd4dvar_solve_report* rep);
+                          double* x_out, double* xa_host, dd4dvar_solve_report* rep,
+                          dd4dvar_ctx* lo);
 }
 
 struct DeviceArrays {
@@ -1191,7 +1192,16 @@ dd4dvar_status dd4dvar_solve(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* opts,
                              const double* x_init_dev, double* x_out_dev, double* xa_host,
                              dd4dvar_solve_report* report) {
   if (!ctx || !opts || !xa_host) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
-  API_GUARD(ctx, { return solve_impl(ctx, opts, x_init_dev, x_out_dev, xa_host, report); })
+  API_GUARD(ctx, { return solve_impl(ctx, opts, x_init_dev, x_out_dev, xa_host, report, nullptr); })
+}
+
+dd4dvar_status dd4dvar_solve_mixed(dd4dvar_ctx* ctx, dd4dvar_ctx* ctx_lo,
+                                   const dd4dvar_solve_opts* opts, const double* x_init_dev,
+                                   double* x_out_dev, double* xa_host,
+                                   dd4dvar_solve_report* report) {
+  if (!ctx || !ctx_lo || !opts || !xa_host) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  if (ctx == ctx_lo) return fail(ctx, DD4DVAR_E_INVALID, "the two contexts must differ");
+  API_GUARD(ctx, { return solve_impl(ctx, opts, x_init_dev, x_out_dev, xa_host, report, ctx_lo); })
 }
 
 }  // extern "C"
@@ -1222,9 +1232,13 @@ P read1(const P* d, hipStream_t st) {
   return h;
 }
 
+// lo (nullable, Gauss-Newton only): an FP32-state context of the same plan
+// whose sweeps supply the normal-matrix products, linearized about its own
+// trajectory of the current iterate; c evaluates J and the gradient
 template <typename T>
 dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const double* x_init,
-                           double* x_out, double* xa_host, dd4dvar_solve_report* rep) {
+                           double* x_out, double* xa_host, dd4dvar_solve_report* rep,
+                           dd4dvar_ctx* lo) {
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = nullptr;
   chk(hipDeviceSynchronize(), "sync");
@@ -1312,9 +1326,12 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
   double* xa_dev = B.get<double>(size_t(3) * c->plan.model.nlat * c->plan.model.nlon);
 
   struct MaskReset {
-    dd4dvar_ctx* c;
-    ~MaskReset() { c->eval_mask = nullptr; }
-  } reset{c};
+    dd4dvar_ctx *c, *lo;
+    ~MaskReset() {
+      c->eval_mask = nullptr;
+      if (lo) lo->eval_mask = nullptr;
+    }
+  } reset{c, lo};
 
   if (x_init) lb_from_x(L, x_init, st);
   else launch_fill(L.xi, N, 0.0, st);
@@ -1336,15 +1353,27 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
         chk(hipMemsetAsync(L.pending, 0, sizeof(int32_t), st), "memset");
         gn_count(G, st);
         if (read1(L.pending, st) == 0) break;
+        if (lo) {
+          // the products' linearization: lo's trajectory of the current x
+          lo->eval_mask = G.gn_on;
+          local_forward<float>(lo, L.xphys, st);
+          lo->eval_mask = nullptr;
+        }
         gn_cg_start(G, st);
         for (;;) {
           chk(hipMemsetAsync(L.pending, 0, sizeof(int32_t), st), "memset");
           gn_cg_count(G, st);
           if (read1(L.pending, st) == 0) break;
           gn_cg_dir(G, st);
-          c->eval_mask = G.cg_on;
-          gn_product<T>(c, G.dx, G.hv, st);
-          c->eval_mask = nullptr;
+          if (lo) {
+            lo->eval_mask = G.cg_on;
+            gn_product<float>(lo, G.dx, G.hv, st);
+            lo->eval_mask = nullptr;
+          } else {
+            c->eval_mask = G.cg_on;
+            gn_product<T>(c, G.dx, G.hv, st);
+            c->eval_mask = nullptr;
+          }
           ++products;
           gn_cg_update(G, st);
         }
@@ -1386,6 +1415,7 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
     // exchange (Alg. 1): integrate the new controls, refresh rings and targets
     lb_to_x(L, 0, 0, st);
     exchange_impl<T>(c, L.xphys, st);
+    if (lo) exchange_impl<float>(lo, L.xphys, st);
     const double mx = *std::max_element(step.begin(), step.end());
     if (!std::isfinite(mx)) {
       c->err = "non-finite iterate in the local solves";
@@ -1435,7 +1465,8 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
 }  // namespace
 
 dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* o, const double* x_init,
-                          double* x_out, double* xa_host, dd4dvar_solve_report* rep) {
+                          double* x_out, double* xa_host, dd4dvar_solve_report* rep,
+                          dd4dvar_ctx* lo) {
   if (o->lbfgs_m < 1 || o->lbfgs_m > kMaxPairs || o->max_iter < 0 || o->max_outer < 1 ||
       o->max_ls < 1 || !(o->grad_rtol >= 0) || !(o->outer_tol >= 0) || !(o->armijo_c1 > 0) ||
       !(o->armijo_c1 < 1) || !(o->j_noise_rtol >= 0) || !std::isfinite(o->j_noise_rtol) ||
@@ -1448,7 +1479,27 @@ dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* o, const d
     ctx->err = "the Gauss-Newton local solver needs every level stored (checkpoints on)";
     return DD4DVAR_E_INVALID;
   }
-  if (ctx->prec == DD4DVAR_FP64) return solve_typed<double>(ctx, o, x_init, x_out, xa_host, rep);
-  return solve_typed<float>(ctx, o, x_init, x_out, xa_host, rep);
+  if (lo) {
+    if (o->local_solver != 1 || ctx->prec != DD4DVAR_FP64 || lo->prec != DD4DVAR_FP32_STATE) {
+      ctx->err = "the mixed-precision solve is Gauss-Newton with an FP64 and an FP32-state context";
+      return DD4DVAR_E_INVALID;
+    }
+    if (lo->ckpt || lo->device != ctx->device || lo->nsub != ctx->nsub ||
+        lo->plan.ctrl_total != ctx->plan.ctrl_total || lo->plan.traj_total != ctx->plan.traj_total) {
+      ctx->err = "the two contexts of a mixed-precision solve need the same plan, device and no checkpoints";
+      return DD4DVAR_E_INVALID;
+    }
+    for (int s = 0; s < ctx->nsub; ++s) {
+      const SubDev &a = ctx->subs[s], &b = lo->subs[s];
+      if (a.ncell != b.ncell || a.nlev != b.nlev || a.ctrl_off != b.ctrl_off ||
+          a.traj_off != b.traj_off || a.row0 != b.row0 || a.col0 != b.col0 || a.lev0 != b.lev0) {
+        ctx->err = "the two contexts of a mixed-precision solve need the same plan";
+        return DD4DVAR_E_INVALID;
+      }
+    }
+    return solve_typed<double>(ctx, o, x_init, x_out, xa_host, rep, lo);
+  }
+  if (ctx->prec == DD4DVAR_FP64) return solve_typed<double>(ctx, o, x_init, x_out, xa_host, rep, nullptr);
+  return solve_typed<float>(ctx, o, x_init, x_out, xa_host, rep, nullptr);
 }
 }  // namespace dd4dvar

@@ -191,6 +191,56 @@ def test_gn_solve_fp32_against_fp64(prec):
     assert err <= 1e-4, err
 
 
+def test_gn_mixed_solve_reaches_the_fp64_stationary_point():
+    """Mixed precision (FP64 evaluations, FP32 normal-matrix products): the
+    local gradients fall below 1e-6 of their start like the FP64 solve's,
+    where the FP32-only solve stops at its rounding floor, and the analysis
+    is the FP64 solve's to 1e-7 of the increment."""
+    from paper_2205_06649_amd.context import Context
+    p = _prob("c2")
+    opts = dict(max_outer=2, max_iter=4, cg_max_iter=60, cg_rtol=1e-8, grad_rtol=1e-9,
+                outer_tol=0.0, local_solver="gn")
+    c64 = Context(p, "fp64")
+    xa64, r64, _, _ = c64.solve(**opts)
+    c32 = Context(p, "fp32")
+    c32.set_exec_mode(2)
+    xa32, r32, _, _ = c32.solve(**opts)
+    c64b = Context(p, "fp64")
+    xam, rm, _, _ = c64b.solve(products=c32, **opts)
+    print(f"gradient ratios: fp64 {r64.gnorm_ratio_max:.2e}, fp32 {r32.gnorm_ratio_max:.2e}, "
+          f"mixed {rm.gnorm_ratio_max:.2e}", flush=True)
+    assert r64.gnorm_ratio_max <= 1e-6 and rm.gnorm_ratio_max <= 1e-6
+    assert r32.gnorm_ratio_max > rm.gnorm_ratio_max
+    sb = p.sigma_b[:, None, None]
+    inc = np.linalg.norm((xa64 - p.xb0) / sb)
+    assert np.linalg.norm((xam - xa64) / sb) <= 1e-7 * inc
+    for c in (c64, c32, c64b):
+        c.close()
+
+
+def test_gn_mixed_rules():
+    from paper_2205_06649_amd import _lib as L
+    from paper_2205_06649_amd.context import Context
+    p = _prob("c1")
+    c64, c32, c32b = Context(p, "fp64"), Context(p, "fp32"), Context(p, "fp32")
+    other = Context(_prob("tiny1"), "fp32")
+    gn_opts = dict(max_outer=1, max_iter=1, cg_max_iter=2, local_solver="gn")
+    for ctx, lo, kw in ((c32b, c32, gn_opts), (c64, c64, gn_opts), (c64, other, gn_opts),
+                        (c64, c32, dict(max_outer=1, max_iter=1))):
+        with pytest.raises(L.DD4DVarError) as e:
+            ctx.solve(products=lo, **kw)
+        assert e.value.status == L.DD4DVAR_E_INVALID
+    c32.set_checkpointing(3)
+    with pytest.raises(L.DD4DVarError) as e:
+        c64.solve(products=c32, **gn_opts)
+    assert e.value.status == L.DD4DVAR_E_INVALID
+    c32.set_checkpointing(0)
+    xa, rep, st, _ = c64.solve(products=c32, **gn_opts)
+    assert np.all(np.isfinite(xa)) and rep.gn_products == 2
+    for c in (c64, c32, c32b, other):
+        c.close()
+
+
 def test_gn_rules():
     from paper_2205_06649_amd import _lib as L
     p, maps, bg, trajs, rings = _oracle_state("c1")
