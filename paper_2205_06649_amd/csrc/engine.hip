@@ -491,7 +491,7 @@ void exchange_impl(dd4dvar_ctx* c, const double* x, hipStream_t st) {
   local_forward<T>(c, x, st);
   Dom<T> D = local_dom<T>(c);
   launch_ring_from_local<T>(D, 0, c->nsub, c->ring_blocks, -1, st);
-  for (int n = 0; n < c->maxlev; ++n) launch_targets_from_local<T>(D, n, 0, c->ntiles, c->jc, st);
+  launch_targets_from_local<T>(D, -1, 0, c->ntiles, c->jc, st);   // every level
   launch_reduce_jconst(c->d_subs, c->nsub, c->jc, 0.5 * c->plan.model.mu_overlap, c->jconst, st);
   chk(hipGetLastError(), "exchange launch");
 }
@@ -553,6 +553,8 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
     S.ntile = int32_t((b.ncell() + kTile - 1) / kTile);
     S.nbr0 = int32_t(P.nbr_ptr[s]);
     S.nbr1 = int32_t(P.nbr_ptr[s + 1]);
+    if (S.nbr1 - S.nbr0 > 64)
+      throw DevError{DD4DVAR_E_INVALID, "a box overlaps more than 64 others (exchange limit)"};
     S.pad_ = 0;
     S.traj_off = b.traj_off;
     S.zoff = b.traj_off;

@@ -95,67 +95,86 @@ __global__ void k_ring_from_local(Dom<T> D, int box_base, int level) {
   }
 }
 
+// Overlap targets of one local level (level >= 0) or of every level (level
+// < 0) of the boxes of a tile range.  Each cell first marks, once, the
+// entries of its box's neighbour list whose extended boxes contain it in
+// space (one bit per entry, at most 64), then at each level takes the mean
+// and the spread of the marked neighbours that hold the level, in one pass
+// with sums shifted by the first value (the values of one cell differ little
+// between boxes, so the shifted sums lose nothing to cancellation).
 template <typename T>
-__global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int n, int tile_base,
+__global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int level, int tile_base,
                                                               double* __restrict__ jc) {
   __shared__ double red[kTile / 64];
   const int w = tile_base + xcd_tile(blockIdx.x, gridDim.x);
   const int2 wt = D.tiles[w];
   const SubDev S = D.subs[wt.x];
-  if (n >= S.nlev) return;                 // uniform over the block
+  const int n0 = level < 0 ? 0 : level, n1 = level < 0 ? S.nlev : level + 1;
+  if (n0 >= S.nlev) return;                 // uniform over the block
   const int m = wt.y * kTile + threadIdx.x;
-  double jloc = 0.0;
-  if (m < S.ncell) {
-    const int K = int(D.cover[S.cell_off + m]) * D.tcount[S.lev0 + n] - 1;
-    if (K > 0) {
-      const int r = m / S.nx, c = m - r * S.nx;
-      const int grow = S.row0 + r;
-      int gcol = S.col0 + c;
-      if (gcol >= D.nlon) gcol -= D.nlon;
-      const int gl = S.lev0 + n;
-      double sh = 0, su = 0, sv = 0;
-      int cnt = 0;
-      for (int q = S.nbr0; q < S.nbr1; ++q) {
-        const SubDev P = D.subs[D.nbr_idx[q]];
-        if (gl < P.lev0 || gl >= P.lev0 + P.nlev) continue;
-        const int rr = grow - P.row0;
-        if (rr < 0 || rr >= P.ny) continue;
-        int cc = gcol - P.col0;
-        if (cc < 0) cc += D.nlon;
-        if (cc >= P.nx) continue;
-        const T* Z = zlevel(D, P, gl - P.lev0) + int64_t(rr) * P.nx + cc;
-        sh += double(Z[0]);
-        su += double(Z[P.ncell]);
-        sv += double(Z[2 * P.ncell]);
-        ++cnt;
-      }
-      const double inv = cnt > 0 ? 1.0 / double(cnt) : 0.0;
-      const double mh = sh * inv, mu = su * inv, mv = sv * inv;
-      double dh = 0, du = 0, dv = 0;
-      for (int q = S.nbr0; q < S.nbr1; ++q) {
-        const SubDev P = D.subs[D.nbr_idx[q]];
-        if (gl < P.lev0 || gl >= P.lev0 + P.nlev) continue;
-        const int rr = grow - P.row0;
-        if (rr < 0 || rr >= P.ny) continue;
-        int cc = gcol - P.col0;
-        if (cc < 0) cc += D.nlon;
-        if (cc >= P.nx) continue;
-        const T* Z = zlevel(D, P, gl - P.lev0) + int64_t(rr) * P.nx + cc;
-        const double a = double(Z[0]) - mh, b = double(Z[P.ncell]) - mu, e = double(Z[2 * P.ncell]) - mv;
-        dh += a * a;
-        du += b * b;
-        dv += e * e;
-      }
-      const int64_t plane = S.ncell;
-      T* Tg = D.targ + S.traj_off + int64_t(n) * 3 * plane;
-      Tg[m] = T(mh);
-      Tg[plane + m] = T(mu);
-      Tg[2 * plane + m] = T(mv);
-      jloc = dh * D.isb2[0] + du * D.isb2[1] + dv * D.isb2[2];
-    }
+  const bool valid = m < S.ncell;
+  const int mm = valid ? m : 0;
+  const int r = mm / S.nx, c = mm - r * S.nx;
+  const int grow = S.row0 + r;
+  int gcol = S.col0 + c;
+  if (gcol >= D.nlon) gcol -= D.nlon;
+  uint64_t hits = 0;
+  for (int q = S.nbr0; q < S.nbr1; ++q) {
+    const SubDev P = D.subs[D.nbr_idx[q]];
+    const int rr = grow - P.row0;
+    int cc = gcol - P.col0;
+    if (cc < 0) cc += D.nlon;
+    if (valid && rr >= 0 && rr < P.ny && cc < P.nx) hits |= uint64_t(1) << (q - S.nbr0);
   }
-  const double tot = block_sum2(jloc, red);
-  if (threadIdx.x == 0) jc[w] = (n == 0) ? tot : jc[w] + tot;
+  const int64_t plane = S.ncell;
+  double acc = 0.0;                         // thread 0: the tile's sum over levels
+  for (int n = n0; n < n1; ++n) {
+    double jloc = 0.0;
+    const int K = valid ? int(D.cover[S.cell_off + mm]) * D.tcount[S.lev0 + n] - 1 : 0;
+    const int gl = S.lev0 + n;
+    double ch = 0, cu = 0, cv = 0;                 // shift: the first value
+    double ah = 0, au = 0, av = 0, bh = 0, bu = 0, bv = 0;
+    int cnt = 0;
+    for (int q = S.nbr0; q < S.nbr1; ++q) {
+      const SubDev P = D.subs[D.nbr_idx[q]];
+      if (gl < P.lev0 || gl >= P.lev0 + P.nlev) continue;   // uniform
+      if (!((hits >> (q - S.nbr0)) & 1)) continue;
+      const int rr = grow - P.row0;
+      int cc = gcol - P.col0;
+      if (cc < 0) cc += D.nlon;
+      const T* Z = zlevel(D, P, gl - P.lev0) + int64_t(rr) * P.nx + cc;
+      const double zh = double(Z[0]), zu = double(Z[P.ncell]), zv = double(Z[2 * P.ncell]);
+      if (cnt == 0) {
+        ch = zh;
+        cu = zu;
+        cv = zv;
+      }
+      const double dh = zh - ch, du = zu - cu, dv = zv - cv;
+      ah += dh;
+      au += du;
+      av += dv;
+      bh += dh * dh;
+      bu += du * du;
+      bv += dv * dv;
+      ++cnt;
+    }
+    if (K > 0 && cnt > 0) {
+      const double inv = 1.0 / double(cnt);
+      T* Tg = D.targ + S.traj_off + int64_t(n) * 3 * plane;
+      Tg[m] = T(ch + ah * inv);
+      Tg[plane + m] = T(cu + au * inv);
+      Tg[2 * plane + m] = T(cv + av * inv);
+      // sum over the neighbours of (value - mean)^2
+      const double sh = bh - ah * ah * inv, su = bu - au * au * inv, sv = bv - av * av * inv;
+      jloc = sh * D.isb2[0] + su * D.isb2[1] + sv * D.isb2[2];
+    }
+    // the level's tile sum, added in level order (as one launch per level
+    // adds them), so both ways give the same bits
+    __syncthreads();                        // red may still be read from the previous level
+    const double tot = block_sum2(jloc, red);
+    if (threadIdx.x == 0) acc = (n == n0) ? tot : acc + tot;
+  }
+  if (threadIdx.x == 0) jc[w] = (n0 == 0) ? acc : jc[w] + acc;
 }
 
 __global__ void k_reduce_jconst(const SubDev* __restrict__ subs, int nsub, const double* __restrict__ jc,
