@@ -98,19 +98,39 @@ __global__ void k_ring_from_local(Dom<T> D, int box_base, int level) {
 // Overlap targets of one local level (level >= 0) or of every level (level
 // < 0) of the boxes of a tile range.  Each cell first marks, once, the
 // entries of its box's neighbour list whose extended boxes contain it in
-// space (one bit per entry, at most 64), then at each level takes the mean
-// and the spread of the marked neighbours that hold the level, in one pass
-// with sums shifted by the first value (the values of one cell differ little
-// between boxes, so the shifted sums lose nothing to cancellation).
+// space (one bit per entry, at most 64; the list itself is staged in LDS),
+// then at each level visits the entries marked by some lane of its wave and
+// takes the mean and the spread of the marked neighbours that hold the
+// level, in one pass with sums shifted by the first value (the values of one
+// cell differ little between boxes, so the shifted sums lose nothing to
+// cancellation).
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int level, int tile_base,
                                                               double* __restrict__ jc) {
   __shared__ double red[kTile / 64];
+  // the box's neighbour list, staged once: first level, levels, first row
+  // and column, width, cells, state offset
+  __shared__ int nb_lev0[64], nb_nlev[64], nb_row0[64], nb_col0[64], nb_nx[64], nb_ny[64],
+      nb_ncell[64];
+  __shared__ int64_t nb_zoff[64];
   const int w = tile_base + xcd_tile(blockIdx.x, gridDim.x);
   const int2 wt = D.tiles[w];
   const SubDev S = D.subs[wt.x];
   const int n0 = level < 0 ? 0 : level, n1 = level < 0 ? S.nlev : level + 1;
   if (n0 >= S.nlev) return;                 // uniform over the block
+  const int nq = S.nbr1 - S.nbr0;           // <= 64 (checked at set-up)
+  for (int i = threadIdx.x; i < nq; i += kTile) {
+    const SubDev P = D.subs[D.nbr_idx[S.nbr0 + i]];
+    nb_lev0[i] = P.lev0;
+    nb_nlev[i] = P.nlev;
+    nb_row0[i] = P.row0;
+    nb_col0[i] = P.col0;
+    nb_nx[i] = P.nx;
+    nb_ny[i] = P.ny;
+    nb_ncell[i] = P.ncell;
+    nb_zoff[i] = P.zoff;
+  }
+  __syncthreads();
   const int m = wt.y * kTile + threadIdx.x;
   const bool valid = m < S.ncell;
   const int mm = valid ? m : 0;
@@ -118,14 +138,21 @@ __global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int leve
   const int grow = S.row0 + r;
   int gcol = S.col0 + c;
   if (gcol >= D.nlon) gcol -= D.nlon;
+  // per lane: the entries whose boxes contain the cell; per wave: their union
   uint64_t hits = 0;
-  for (int q = S.nbr0; q < S.nbr1; ++q) {
-    const SubDev P = D.subs[D.nbr_idx[q]];
-    const int rr = grow - P.row0;
-    int cc = gcol - P.col0;
+  for (int i = 0; i < nq; ++i) {
+    const int rr = grow - nb_row0[i];
+    int cc = gcol - nb_col0[i];
     if (cc < 0) cc += D.nlon;
-    if (valid && rr >= 0 && rr < P.ny && cc < P.nx) hits |= uint64_t(1) << (q - S.nbr0);
+    if (valid && rr >= 0 && rr < nb_ny[i] && cc < nb_nx[i])
+      hits |= uint64_t(1) << i;
   }
+  uint32_t wlo = uint32_t(hits), whi = uint32_t(hits >> 32);
+  for (int off = 32; off > 0; off >>= 1) {
+    wlo |= __shfl_xor(wlo, off, 64);
+    whi |= __shfl_xor(whi, off, 64);
+  }
+  const uint64_t wave_hits = (uint64_t(whi) << 32) | wlo;
   const int64_t plane = S.ncell;
   double acc = 0.0;                         // thread 0: the tile's sum over levels
   for (int n = n0; n < n1; ++n) {
@@ -135,15 +162,17 @@ __global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int leve
     double ch = 0, cu = 0, cv = 0;                 // shift: the first value
     double ah = 0, au = 0, av = 0, bh = 0, bu = 0, bv = 0;
     int cnt = 0;
-    for (int q = S.nbr0; q < S.nbr1; ++q) {
-      const SubDev P = D.subs[D.nbr_idx[q]];
-      if (gl < P.lev0 || gl >= P.lev0 + P.nlev) continue;   // uniform
-      if (!((hits >> (q - S.nbr0)) & 1)) continue;
-      const int rr = grow - P.row0;
-      int cc = gcol - P.col0;
+    for (uint64_t rem = wave_hits; rem; rem &= rem - 1) {     // entries in list order
+      const int i = __builtin_ctzll(rem);
+      const int pl = gl - nb_lev0[i];
+      if (pl < 0 || pl >= nb_nlev[i]) continue;                // uniform
+      if (!((hits >> i) & 1)) continue;
+      const int rr = grow - nb_row0[i];
+      int cc = gcol - nb_col0[i];
       if (cc < 0) cc += D.nlon;
-      const T* Z = zlevel(D, P, gl - P.lev0) + int64_t(rr) * P.nx + cc;
-      const double zh = double(Z[0]), zu = double(Z[P.ncell]), zv = double(Z[2 * P.ncell]);
+      const int64_t pc = nb_ncell[i];
+      const T* Z = D.traj + nb_zoff[i] + int64_t(D.zslot[pl]) * 3 * pc + int64_t(rr) * nb_nx[i] + cc;
+      const double zh = double(Z[0]), zu = double(Z[pc]), zv = double(Z[2 * pc]);
       if (cnt == 0) {
         ch = zh;
         cu = zu;
