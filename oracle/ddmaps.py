@@ -112,6 +112,9 @@ def build(prob) -> DDMaps:
     o, ot = prob.overlap_cells, prob.overlap_steps
     pieces = _pieces(prob)
     nspace = len(pieces)
+    if getattr(prob, "tz_p", 0) > 0 and nspace != 1:
+        raise ValueError("the Turkel-Zwas variant is built for time decompositions "
+                         "(one band of one piece)")
     tedges = np.asarray(prob.time_edges, dtype=np.int64)
     ntime = len(tedges) - 1
 

@@ -26,6 +26,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import model
 from .model import Grid
 
 
@@ -200,12 +201,23 @@ def increment_ad(geo: LocalGeometry, P, lam):
     return geo.fold(A)
 
 
+def _global_box(geo):
+    """The Turkel-Zwas variant runs on boxes that cover the whole sphere (time
+    decompositions): the local model is then the global one."""
+    b, g = geo.box, geo.g
+    if not (b.row0 == 0 and b.ny == g.nlat and b.col0 == 0 and b.nx == g.nlon):
+        raise ValueError("the Turkel-Zwas variant needs boxes covering the sphere")
+
+
 def forward(geo: LocalGeometry, x, ring):
     """Local trajectory [nlev][3][ny][nx] from control x and frozen ring.
 
     ``ring`` is [nlev][3][nring] (values as seen by the stencil, signs
     applied) or None when the box has no frozen positions.
     """
+    if geo.g.tz is not None:
+        _global_box(geo)
+        return model.forward(geo.g, x, geo.box.nlev - 1)
     L = geo.box.nlev - 1
     traj = np.empty((L + 1,) + x.shape, dtype=x.dtype)
     traj[0] = x
@@ -221,6 +233,9 @@ def forward(geo: LocalGeometry, x, ring):
 
 
 def tlm(geo: LocalGeometry, traj, ring, dx):
+    if geo.g.tz is not None:
+        _global_box(geo)
+        return model.tlm(geo.g, traj, dx)
     L = traj.shape[0] - 1
     d = np.empty_like(traj)
     d[0] = dx
@@ -237,6 +252,9 @@ def tlm(geo: LocalGeometry, traj, ring, dx):
 
 def adjoint(geo: LocalGeometry, traj, ring, forcing):
     """Transpose of ``tlm`` applied to per-level forcing; returns level 0."""
+    if geo.g.tz is not None:
+        _global_box(geo)
+        return model.adjoint(geo.g, traj, forcing)
     L = traj.shape[0] - 1
     a = forcing.copy()
 

@@ -26,14 +26,18 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import tz
+
 
 class Grid:
     """Per-row tables and Courant factors of the lat-lon grid."""
 
-    def __init__(self, nlat, nlon, dt, radius, gravity, omega, dtype=np.float64):
+    def __init__(self, nlat, nlon, dt, radius, gravity, omega, dtype=np.float64, tz=None):
         """``dtype`` is the arithmetic type of the tables and constants:
         float64 normally; np.longdouble gives an extended-precision reference
-        of the same computation (its inputs are still the FP64 values)."""
+        of the same computation (its inputs are still the FP64 values).
+        ``tz`` = (p, q, alpha) selects the Turkel-Zwas variant (``tz``
+        module); None the plain scheme."""
         if nlon % 2:
             raise ValueError("nlon must be even for the across-pole map")
         D = dtype
@@ -49,10 +53,13 @@ class Grid:
         self.fcor = D(2) * self.omega * np.sin(self.theta)
         self.sig_lon = self.dt / (self.radius * self.dlon)
         self.sig_lat = self.dt / (self.radius * self.dlat)
+        self.tz = None if tz is None else (int(tz[0]), int(tz[1]), D(tz[2]))
 
     @classmethod
     def of(cls, prob, dtype=np.float64):
-        return cls(prob.nlat, prob.nlon, prob.dt, prob.radius, prob.gravity, prob.omega, dtype)
+        p = int(getattr(prob, "tz_p", 0))
+        tz = (p, int(prob.tz_q), float(prob.tz_alpha)) if p > 0 else None
+        return cls(prob.nlat, prob.nlon, prob.dt, prob.radius, prob.gravity, prob.omega, dtype, tz)
 
 
 # --- neighbour operators on the global grid ---------------------------------
@@ -107,6 +114,8 @@ def _row(g, a):
 
 def increment(g: Grid, Z):
     """F(Z): the 2 dt increment (U, V, H) of the discrete SWE; returns (H, U, V)."""
+    if g.tz is not None:
+        return tz.increment(g, Z, *g.tz)
     h, u, v = Z
     c = g.cos[:, None]
     t = g.tan[:, None]
@@ -129,6 +138,8 @@ def increment(g: Grid, Z):
 
 def increment_tl(g: Grid, Z, dZ):
     """Tangent linear of ``increment`` at Z applied to dZ."""
+    if g.tz is not None:
+        return tz.increment_tl(g, Z, dZ, *g.tz)
     h, u, v = Z
     dh, du, dv = dZ
     c = g.cos[:, None]
@@ -164,6 +175,8 @@ def increment_ad(g: Grid, Z, lam):
     lam = (lamH, lamU, lamV) are the weights on the (H, U, V) outputs.  Each
     term of the tangent linear code is transposed in turn (scatter form).
     """
+    if g.tz is not None:
+        return tz.increment_ad(g, Z, lam, *g.tz)
     h, u, v = Z
     lH, lU, lV = lam
     c = g.cos[:, None]

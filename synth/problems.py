@@ -95,6 +95,11 @@ class Problem:
     obs_sigma: np.ndarray           # f64  [nobs]
     obs_noise: np.ndarray           # f64  [nobs] standard-normal draws
     seed: int
+    # discretization: tz_p = 0 the plain centred scheme; tz_p >= 1 the
+    # Turkel-Zwas variant with offsets (tz_p, tz_q) and averaging tz_alpha
+    tz_p: int = 0
+    tz_q: int = 1
+    tz_alpha: float = 0.0
 
     @property
     def nobs(self) -> int:
@@ -209,7 +214,8 @@ def make_spec(cfg, *, seed: Optional[int] = None, dt: Optional[float] = None,
     truth0 = _truth_snapshot(rngs["truth"], nlat, nlon, const["radius"],
                              const["gravity"], const["omega"], const["h_ref"])
     if dt is None:
-        dt = cfl_dt(truth0, nlat, nlon, const["radius"], const["gravity"])
+        dt = cfl_dt(truth0, nlat, nlon, const["radius"], const["gravity"]) * float(
+            cfg.get("dt_scale", 1.0))
     std = truth0.reshape(3, -1).std(axis=1)
     sigma_b = 0.05 * std
     sigma_o = 0.01 * std
@@ -264,7 +270,9 @@ def make_spec(cfg, *, seed: Optional[int] = None, dt: Optional[float] = None,
         overlap_steps=int(cfg["overlap_steps"]),
         truth0=truth0, xb0=xb0, sigma_b=sigma_b.astype(np.float64),
         obs_step=obs_step, obs_cell=obs_cell, obs_field=obs_field,
-        obs_value=None, obs_sigma=obs_sigma, obs_noise=obs_noise, seed=seed)
+        obs_value=None, obs_sigma=obs_sigma, obs_noise=obs_noise, seed=seed,
+        tz_p=int(cfg.get("tz", (0, 1, 0.0))[0]), tz_q=int(cfg.get("tz", (0, 1, 0.0))[1]),
+        tz_alpha=float(cfg.get("tz", (0, 1, 0.0))[2]))
 
 
 TruthForward = Callable[[Problem, np.ndarray, Sequence[int]], np.ndarray]

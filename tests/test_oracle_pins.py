@@ -590,6 +590,90 @@ def test_dd_solve_gauss_newton():
     assert np.linalg.norm((xa - xl) / sb) <= 1e-6 * np.linalg.norm((xl - p.xb0) / sb)
 
 
+# --- Turkel-Zwas variant (Sec. 7 discrete U, V, H with p, q, alpha) ---------
+TZ_VARIANTS = [(1, 1, 0.0), (2, 2, 0.5), (2, 1, 0.0), (1, 2, 1.0), (3, 2, 0.25)]
+
+
+def _tz_grid(p, tzv):
+    return model.Grid(p.nlat, p.nlon, p.dt, p.radius, p.gravity, p.omega, tz=tzv)
+
+
+@pytest.mark.parametrize("tzv", TZ_VARIANTS)
+def test_tz_rest_state_and_identities(rng, tzv):
+    """Rest state fixed; tangent linear equal to centred differences of the
+    (quadratic) increment; adjoint the transpose of the tangent linear, one
+    step and over a trajectory (adjoint definition, eq. adjProd)."""
+    p = problem("c1")
+    g = _tz_grid(p, tzv)
+    R = np.stack([np.full((p.nlat, p.nlon), p.h_ref), np.zeros((p.nlat, p.nlon)),
+                  np.zeros((p.nlat, p.nlon))])
+    assert np.all(model.increment(g, R) == 0.0)
+    Z = p.truth0
+    dZ = rng.standard_normal(Z.shape) * p.sigma_b[:, None, None]
+    lam = rng.standard_normal(Z.shape)
+    tl = model.increment_tl(g, Z, dZ)
+    fd = (model.increment(g, Z + 1e-3 * dZ) - model.increment(g, Z - 1e-3 * dZ)) / 2e-3
+    assert np.linalg.norm(fd - tl) <= 1e-9 * np.linalg.norm(tl)
+    lhs, rhs = np.sum(tl * lam), np.sum(dZ * model.increment_ad(g, Z, lam))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    traj = model.forward(g, Z, 6)
+    y = rng.standard_normal(traj.shape)
+    lhs = np.sum(model.tlm(g, traj, dZ) * y)
+    rhs = np.sum(dZ * model.adjoint(g, traj, y))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_tz_plain_offsets_against_the_plain_scheme():
+    """With p = q = 1 and alpha = 0 the U and V of the Turkel-Zwas scheme are
+    the plain scheme's exactly, and its advective H differs from the flux
+    form by the product-rule remainder
+    (s_lon/c)[(hE-h)(uE-u) - (hW-h)(uW-u)] + (s_lat/c)[(hN-h)(vN cN - v c) - (hS-h)(vS cS - v c)]."""
+    p = problem("c1")
+    g0 = model.Grid.of(p)
+    g1 = _tz_grid(p, (1, 1, 0.0))
+    Z = p.truth0
+    F0, F1 = model.increment(g0, Z), model.increment(g1, Z)
+    np.testing.assert_allclose(F1[1:], F0[1:], rtol=1e-13, atol=1e-13 * np.abs(F0[1:]).max())
+    h, u, v = Z
+    c = g0.cos[:, None]
+    cN = np.append(g0.cos[1:], g0.cos[-1])[:, None]
+    cS = np.insert(g0.cos[:-1], 0, g0.cos[0])[:, None]
+    E, W = (lambda x: np.roll(x, -1, -1)), (lambda x: np.roll(x, 1, -1))
+    hN, hS = model._north(h, 1.0), model._south(h, 1.0)
+    vN, vS = model._north(v, -1.0), model._south(v, -1.0)
+    rem = (g0.sig_lon / c) * ((E(h) - h) * (E(u) - u) - (W(h) - h) * (W(u) - u)) + \
+        (g0.sig_lat / c) * ((hN - h) * (vN * cN - v * c) - (hS - h) * (vS * cS - v * c))
+    np.testing.assert_allclose(F1[0] - F0[0], rem, rtol=1e-9, atol=1e-9 * np.abs(rem).max())
+
+
+@pytest.mark.parametrize("tzv", TZ_VARIANTS[1:])
+@pytest.mark.parametrize("omega,alpha", [(7.292e-5, 0.0), (0.0, math.pi / 4), (0.0, 0.3)])
+def test_tz_steady_flow_second_order(tzv, omega, alpha):
+    """The Turkel-Zwas increments of the solid-body rotations above vanish at
+    second order in the grid spacing too (consistency of the wide offsets,
+    the averaged Coriolis terms and the corner divergence)."""
+    res = []
+    for nlat in (32, 64, 128):
+        g, Z = _tc2(nlat, omega, alpha)
+        g.tz = tzv
+        F = model.increment(g, Z)
+        h = Z[0]
+        band = np.abs(g.theta) < math.pi / 3
+        scale = np.linalg.norm((g.sig_lat * g.gravity * (np.roll(h, -1, 0) - np.roll(h, 1, 0)))[band])
+        res.append(max(np.linalg.norm(F[k][band]) for k in range(3)) / scale)
+    assert 3.4 < res[0] / res[1] < 5.5 and 3.4 < res[1] / res[2] < 4.6, res
+
+
+def test_tz_needs_a_time_decomposition():
+    cfg = dict(synth.CONFIGS["c1"], tz=(2, 2, 0.5), index=120)
+    p = custom_problem(cfg)
+    with pytest.raises(ValueError):
+        ddmaps.build(p)
+    q = custom_problem(dict(cfg, bands=1, pieces=1, index=121))
+    maps = ddmaps.build(q)
+    assert all(b.ny == q.nlat and b.nx == q.nlon for b in maps.boxes)
+
+
 # --- P10: map invariants -----------------------------------------------------
 @pytest.mark.parametrize("which", ["c1", "c2", "small", "span", "mixed", "c3"])
 def test_map_invariants(which):
