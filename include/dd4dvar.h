@@ -69,6 +69,21 @@ typedef struct {
   double lambda_obs, mu_overlap;
   int32_t precision;
   int32_t weight_mode;
+  /* Turkel-Zwas variant (Sec. 7, discrete U, V, H with offsets p, q and
+   * averaging alpha): tz_p = 0 selects the plain scheme above (tz_q and
+   * tz_alpha ignored).  tz_p >= 1 takes the pressure-gradient, divergence and
+   * Coriolis terms over tz_p columns and tz_q rows, averaged with weight
+   * tz_alpha over the points (i +- p, j), (i, j +- q) and the corners
+   * (i +- p, j +- q); advection keeps offset one and H is the advective
+   * form with h / cos on both divergence terms.  Requires
+   * 1 <= tz_p <= nlon / 2, 1 <= tz_q <= nlat / 2, 0 <= tz_alpha <= 1 and a
+   * time decomposition (one band of one piece: every box covers the sphere,
+   * so the local model is the global one).  Such a context runs the step
+   * kernels only (execution modes 0 and 1; no persistent modes), and the
+   * tangent-linear, Gauss-Newton and mixed-precision entry points return
+   * E_INVALID. */
+  int32_t tz_p, tz_q;
+  double tz_alpha;
 } dd4dvar_model_desc;
 
 /* Space-time partition DD(Delta x Omega) (Def. domdecom, eqs. Eq-r, nlocx).

@@ -33,7 +33,8 @@ class dd4dvar_model_desc(C.Structure):
                 ("dt", C.c_double), ("radius", C.c_double), ("gravity", C.c_double),
                 ("omega", C.c_double), ("h_ref", C.c_double),
                 ("lambda_obs", C.c_double), ("mu_overlap", C.c_double),
-                ("precision", C.c_int32), ("weight_mode", C.c_int32)]
+                ("precision", C.c_int32), ("weight_mode", C.c_int32),
+                ("tz_p", C.c_int32), ("tz_q", C.c_int32), ("tz_alpha", C.c_double)]
 
 
 class dd4dvar_partition_desc(C.Structure):

@@ -76,6 +76,11 @@ struct dd4dvar_ctx {
   int box_kmin = 0;                     // passes that hold the largest box
   bool box_span = false;                // some box spans the circle
   int strip_k = 0;                      // rows per column strip of the strip adjoint (0: n/a)
+  // Turkel-Zwas variant (tz_p > 0): step kernels only, with the slot arena
+  // of their two-phase adjoint
+  int tz_p = 0, tz_q = 1;
+  double tz_alpha = 0;
+  void* tz_slots = nullptr;
   // state storage: every level (ckpt = 0), or checkpoint pairs every ckpt
   // levels plus one segment that the adjoint recomputes
   int ckpt = 0;
@@ -234,12 +239,34 @@ void fill_rows(const dd4dvar_model_desc& m, std::vector<RowCoef<T>>& rows, std::
   cosx[m.nlat + 1] = T(c[m.nlat - 1]);
 }
 
+// One forward and one adjoint step of the step kernels in the scheme that the
+// model selects (plain centred, or Turkel-Zwas)
+template <typename T>
+void fwd_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int ntiles, hipStream_t st) {
+  if (c->tz_p > 0)
+    launch_fwd_tz<T>(D, n, tile_base, ntiles, c->tz_p, c->tz_q, c->tz_alpha, st);
+  else
+    launch_fwd<T>(D, n, tile_base, ntiles, st);
+}
+
+template <typename T>
+void adj_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int ntiles, int mode,
+              const double* x, const double* forcing, double* out, hipStream_t st) {
+  if (c->tz_p > 0) {
+    if (mode == 3) throw DevError{DD4DVAR_E_INVALID, "no Gauss-Newton adjoint for the Turkel-Zwas variant"};
+    launch_adj_tz<T>(D, n, tile_base, ntiles, mode, c->tz_p, c->tz_q, c->tz_alpha,
+                     static_cast<T*>(c->tz_slots), x, c->xb, forcing, out, st);
+  } else {
+    launch_adj<T>(D, n, tile_base, ntiles, mode, x, c->xb, forcing, out, st);
+  }
+}
+
 // Global forward run (FP64) of x (device [3][ncell], full h) into traj
 // ([nsteps+1][3][ncell], h stored as an anomaly).
 void global_forward(dd4dvar_ctx* c, const double* x, double* traj, hipStream_t st) {
   Dom<double> G = global_dom(c, traj);
   launch_init<double>(G, x, 0, c->gtiles, st);
-  for (int n = 0; n < c->plan.model.nsteps; ++n) launch_fwd<double>(G, n, 0, c->gtiles, st);
+  for (int n = 0; n < c->plan.model.nsteps; ++n) fwd_step<double>(c, G, n, 0, c->gtiles, st);
   chk(hipGetLastError(), "global forward launch");
 }
 
@@ -262,7 +289,7 @@ void local_forward(dd4dvar_ctx* c, const double* x, hipStream_t st, double* traj
     launch_init<T>(D, x, tile_base, ntiles, st);
     if (per_level) launch_traj_out<T>(D, traj_out, tile_base, ntiles, 0, st);
     for (int n = 0; n + 1 < nlev; ++n) {
-      launch_fwd<T>(D, n, tile_base, ntiles, st);
+      fwd_step<T>(c, D, n, tile_base, ntiles, st);
       if (per_level) launch_traj_out<T>(D, traj_out, tile_base, ntiles, n + 1, st);
     }
   };
@@ -296,14 +323,14 @@ void local_adjoint(dd4dvar_ctx* c, int mode, const double* x, const double* forc
     const int cs = c->ckpt;
     if (cs == 0) {
       for (int n = lmax; n >= 0; --n)
-        launch_adj<T>(D, n, tile_base, ntiles, mode, x, c->xb, forcing, out, st);
+        adj_step<T>(c, D, n, tile_base, ntiles, mode, x, forcing, out, st);
       return;
     }
     for (int lo = (lmax / cs) * cs; lo >= 0; lo -= cs) {
       const int hi = std::min(lo + cs - 1, lmax);
-      for (int n = lo + 1; n < hi; ++n) launch_fwd<T>(D, n, tile_base, ntiles, st);
+      for (int n = lo + 1; n < hi; ++n) fwd_step<T>(c, D, n, tile_base, ntiles, st);
       for (int n = hi; n >= lo; --n)
-        launch_adj<T>(D, n, tile_base, ntiles, mode, x, c->xb, forcing, out, st);
+        adj_step<T>(c, D, n, tile_base, ntiles, mode, x, forcing, out, st);
     }
   };
   if (!ids && c->exec_mode != 1) {
@@ -399,7 +426,7 @@ void cost_grad_impl(dd4dvar_ctx* c, const std::vector<int32_t>* ids, const doubl
     for (int32_t s : *ids) {
       const SubDev& S = c->subs[s];
       launch_init<T>(D, x, S.tile0, S.ntile, st);
-      for (int n = 0; n + 1 < S.nlev; ++n) launch_fwd<T>(D, n, S.tile0, S.ntile, st);
+      for (int n = 0; n + 1 < S.nlev; ++n) fwd_step<T>(c, D, n, S.tile0, S.ntile, st);
     }
     chk(hipGetLastError(), "forward launch");
     c->have_forward = true;
@@ -465,7 +492,7 @@ void exchange_lockstep(dd4dvar_ctx* c, const double* x, hipStream_t st) {
   for (int g = 0; g <= P.model.nsteps; ++g) {
     for (int j = 0; j < ntm; ++j) {
       const int n = g - lev0[j];
-      if (n >= 1 && n < nlev[j]) launch_fwd<T>(D, n - 1, tb[j], nt[j], st);
+      if (n >= 1 && n < nlev[j]) fwd_step<T>(c, D, n - 1, tb[j], nt[j], st);
     }
     for (int j = 0; j < ntm; ++j) {
       const int n = g - lev0[j];
@@ -576,7 +603,7 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
   {
     size_t lds = 0;
     int kmax = 0;
-    bool ok = c->prec == DD4DVAR_FP32_STATE;
+    bool ok = c->prec == DD4DVAR_FP32_STATE && c->plan.model.tz_p == 0;
     int strip = 0;
     for (const SubDev& S : c->subs) {
       const int rs = box_strip_rows(S.ny, S.nx, S.nring, S.nlev);
@@ -748,6 +775,12 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
   c->ring_bytes = size_t(std::max<int64_t>(ring_off, 1)) * tsz;
   c->ring = dalloc<char>(c, c->ring_bytes);
   c->adj = dalloc<char>(c, size_t(std::max<int64_t>(adj_off, 1)) * tsz);
+  if (P.model.tz_p > 0) {
+    c->tz_p = P.model.tz_p;
+    c->tz_q = P.model.tz_q;
+    c->tz_alpha = P.model.tz_alpha;
+    c->tz_slots = dalloc<char>(c, size_t(P.ctrl_total) * tz_slot_planes() * tsz);
+  }
   chk(hipMemsetAsync(c->ring, 0, size_t(std::max<int64_t>(ring_off, 1)) * tsz, st), "memset ring");
   chk(hipMemsetAsync(c->targ, 0, size_t(P.traj_total) * tsz, st), "memset targets");
   chk(hipStreamSynchronize(st), "upload sync");
@@ -1122,6 +1155,8 @@ dd4dvar_status dd4dvar_tangent_linear(dd4dvar_ctx* ctx, const double* dx_dev, do
                                       void* stream) {
   if (!ctx || !dx_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
   if (ctx->ckpt) return fail(ctx, DD4DVAR_E_INVALID, "the tangent-linear model needs every level stored");
+  if (ctx->tz_p > 0)
+    return fail(ctx, DD4DVAR_E_INVALID, "no tangent-linear sweeps for the Turkel-Zwas variant");
   if (!ctx->have_forward) return fail(ctx, DD4DVAR_E_STATE, "tangent-linear model before any forward");
   API_GUARD(ctx, {
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1142,6 +1177,8 @@ dd4dvar_status dd4dvar_gn_hessvec(dd4dvar_ctx* ctx, const double* dx_dev, double
   if (!ctx || !dx_dev || !out_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
   if (dx_dev == out_dev) return fail(ctx, DD4DVAR_E_INVALID, "dx_dev and out_dev must differ");
   if (ctx->ckpt) return fail(ctx, DD4DVAR_E_INVALID, "Gauss-Newton products need every level stored");
+  if (ctx->tz_p > 0)
+    return fail(ctx, DD4DVAR_E_INVALID, "no Gauss-Newton products for the Turkel-Zwas variant");
   if (!ctx->have_forward) return fail(ctx, DD4DVAR_E_STATE, "Gauss-Newton product before any forward");
   API_GUARD(ctx, {
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1475,6 +1512,10 @@ dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* o, const d
       o->local_solver < 0 || o->local_solver > 1 || o->cg_max_iter < 0 || !(o->cg_rtol >= 0) ||
       !std::isfinite(o->cg_rtol)) {
     ctx->err = "bad solve options";
+    return DD4DVAR_E_INVALID;
+  }
+  if (o->local_solver == 1 && ctx->tz_p > 0) {
+    ctx->err = "no Gauss-Newton local solver for the Turkel-Zwas variant";
     return DD4DVAR_E_INVALID;
   }
   if (o->local_solver == 1 && ctx->ckpt) {

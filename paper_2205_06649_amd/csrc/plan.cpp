@@ -69,6 +69,12 @@ static void validate_and_copy(const dd4dvar_model_desc* m,
   require(m->precision == DD4DVAR_FP64 || m->precision == DD4DVAR_FP32_STATE,
           "unknown precision");
   require(m->weight_mode == 0 || m->weight_mode == 1, "unknown weight_mode");
+  if (m->tz_p != 0) {
+    require(m->tz_p >= 1 && m->tz_p <= m->nlon / 2, "tz_p must be 0 or in 1..nlon/2");
+    require(m->tz_q >= 1 && m->tz_q <= m->nlat / 2, "tz_q must be in 1..nlat/2");
+    require(std::isfinite(m->tz_alpha) && m->tz_alpha >= 0 && m->tz_alpha <= 1,
+            "tz_alpha must be in [0, 1]");
+  }
   plan->model = *m;
 
   const int nlat = m->nlat, nlon = m->nlon, nt = m->nsteps;
@@ -160,6 +166,8 @@ dd4dvar_status build_plan(const dd4dvar_model_desc* m, const dd4dvar_partition_d
       pos += np + 1;
     }
     const int nspace = int(pieces.size());
+    require(m->tz_p == 0 || nspace == 1,
+            "the Turkel-Zwas variant needs a time decomposition (one band of one piece)");
     const int ntime = p->n_time;
     plan->nspace = nspace;
     plan->ntime = ntime;

@@ -26,7 +26,9 @@ class Descriptors:
             nlat=prob.nlat, nlon=prob.nlon, nsteps=prob.nsteps, dt=prob.dt,
             radius=prob.radius, gravity=prob.gravity, omega=prob.omega, h_ref=prob.h_ref,
             lambda_obs=prob.lambda_obs, mu_overlap=prob.mu_overlap,
-            precision=int(precision), weight_mode=int(prob.weight_mode))
+            precision=int(precision), weight_mode=int(prob.weight_mode),
+            tz_p=int(getattr(prob, "tz_p", 0)), tz_q=int(getattr(prob, "tz_q", 1)),
+            tz_alpha=float(getattr(prob, "tz_alpha", 0.0)))
         be = arr(prob.band_lat_edges, np.int32)
         bn = arr(prob.band_npieces, np.int32)
         pe = arr(prob.piece_lon_edges, np.int32)

@@ -1,0 +1,178 @@
+"""Turkel-Zwas variant on the GPU (Sec. 7 discrete U, V, H with coarse
+offsets p, q and averaging alpha) on time decompositions (one band of one
+piece: every box is the whole sphere), against the oracle.
+
+* the global forward run and the local forward sweeps (trajectories);
+* local J and gradient of every box: FP64 state (J 1e-12, gradient 2e-12
+  against the oracle in extended precision) and FP32 state (1e-4), in
+  execution modes 0 (one launch per level over every box) and 1 (per box),
+  for offsets from (1, 1) up to the largest allowed (nlon/2, nlat/2), where
+  the two p-neighbours coincide and the q-offsets reach half the rows across
+  each pole, and alpha in {0, 1/4, 1/2, 1};
+* the adjoint sweep under a caller forcing (transpose of the oracle's
+  tangent linear, eq. adjProd);
+* a DD solve (Alg. 1, batched L-BFGS) against the oracle's, on the analysis;
+* the entry points the variant does not have return E_INVALID.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import custom_problem
+from oracle import dd, ddmaps, local, model
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-4}
+TOL_GRAD = {"fp64": 2e-12, "fp32": 1e-4}
+TZ_CFG = dict(synth.CONFIGS["c1"], bands=1, pieces=1, ntime=3, overlap_cells=0,
+              overlap_steps=2, index=130)
+VARIANTS = [(2, 2, 0.5), (1, 1, 0.0), (3, 2, 0.25), (1, 2, 1.0), (32, 16, 0.5)]
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.longdouble)
+    b = np.asarray(b, dtype=np.longdouble)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def _anom(Z, h_ref):
+    """Trajectory with h as its anomaly (so that the u, v errors count)."""
+    Z = np.array(Z, dtype=np.float64)
+    Z[..., 0, :, :] -= h_ref
+    return Z
+
+
+@functools.lru_cache(maxsize=None)
+def _state(tzv):
+    p = custom_problem(dict(TZ_CFG, tz=tzv))
+    maps = ddmaps.build(p)
+    bg, trajs = dd.background(p, maps)
+    rings, _ = dd.exchange(maps, trajs)
+    return p, maps, trajs, rings
+
+
+def _controls(p, maps, trajs, seed):
+    rng = np.random.default_rng(seed)
+    sb = p.sigma_b[:, None, None]
+    return [trajs[b.sub][0] + 0.3 * sb * rng.standard_normal(trajs[b.sub][0].shape)
+            for b in maps.boxes]
+
+
+def test_cases_are_time_decompositions():
+    for tzv in VARIANTS:
+        p, maps, _, _ = _state(tzv)
+        assert (p.tz_p, p.tz_q, p.tz_alpha) == tzv
+        assert len(maps.boxes) == 3
+        assert all(b.ny == p.nlat and b.nx == p.nlon for b in maps.boxes)
+    p, _, _, _ = _state(VARIANTS[-1])
+    assert p.tz_p == p.nlon // 2 and p.tz_q == p.nlat // 2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_forward_runs(prec):
+    from paper_2205_06649_amd.context import Context
+    tzv = VARIANTS[0]
+    p, maps, trajs, rings = _state(tzv)
+    g = model.Grid.of(p)
+    ctx = Context(p, prec)
+    import torch
+    # global run (FP64 in both precisions)
+    tg = ctx.forward_global(torch.tensor(p.xb0, device="cuda:0")).cpu().numpy()
+    ref = model.forward(g, p.xb0, p.nsteps)
+    assert _rel(_anom(tg, p.h_ref), _anom(ref, p.h_ref)) <= 1e-12
+    xs = _controls(p, maps, trajs, seed=1)
+    tr = ctx.unpack_traj(ctx.forward(ctx.pack_ctrl(xs)))
+    for b in maps.boxes:
+        lt = local.forward(local.LocalGeometry(g, maps, b.sub), xs[b.sub], rings[b.sub])
+        e = _rel(_anom(tr[b.sub], p.h_ref), _anom(lt, p.h_ref))
+        print(f"{prec} box {b.sub}: trajectory rel {e:.2e}", flush=True)
+        assert e <= (1e-12 if prec == "fp64" else 1e-5)
+    ctx.close()
+
+
+@pytest.mark.parametrize("tzv", VARIANTS)
+@pytest.mark.parametrize("prec,mode", [("fp64", 0), ("fp32", 0), ("fp64", 1)])
+def test_cost_grad_matches_oracle(tzv, prec, mode):
+    from paper_2205_06649_amd.context import Context
+    p, maps, trajs, rings = _state(tzv)
+    xs = _controls(p, maps, trajs, seed=2)
+    ctx = Context(p, prec)
+    ctx.set_exec_mode(mode)
+    J, g = ctx.cost_grad(ctx.pack_ctrl(xs))
+    J = J.cpu().numpy()
+    grads = ctx.unpack_ctrl(g)
+    ctx.close()
+    for b in maps.boxes:
+        s = b.sub
+        Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], rings[s],
+                                 {k: trajs[k] for k in maps.neighbors[s]},
+                                 dtype=np.longdouble if prec == "fp64" else np.float64)
+        ej, eg = float(abs(J[s] - Jr) / abs(Jr)), _rel(grads[s], gr)
+        print(f"tz {tzv} {prec} mode {mode} box {s}: J rel {ej:.2e}, grad rel {eg:.2e}", flush=True)
+        assert ej <= TOL[prec] and eg <= TOL_GRAD[prec], (s, ej, eg)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adjoint_under_forcing(prec):
+    from paper_2205_06649_amd.context import Context
+    tzv = VARIANTS[2]
+    p, maps, trajs, rings = _state(tzv)
+    g = model.Grid.of(p)
+    xs = _controls(p, maps, trajs, seed=3)
+    ctx = Context(p, prec)
+    ctx.forward(ctx.pack_ctrl(xs), with_traj=False)
+    rng = np.random.default_rng(4)
+    forcing = [rng.standard_normal((b.nlev, 3, b.ny, b.nx)) for b in maps.boxes]
+    adj = ctx.unpack_ctrl(ctx.adjoint(ctx.pack_traj(forcing)))
+    ctx.close()
+    for b in maps.boxes:
+        geo = local.LocalGeometry(g, maps, b.sub)
+        lt = local.forward(geo, xs[b.sub], rings[b.sub])
+        ref = local.adjoint(geo, lt, rings[b.sub], forcing[b.sub])
+        e = _rel(adj[b.sub], ref)
+        print(f"{prec} box {b.sub}: adjoint rel {e:.2e}", flush=True)
+        assert e <= (1e-12 if prec == "fp64" else 1e-5)
+
+
+def test_solve_matches_oracle():
+    from paper_2205_06649_amd.context import Context
+    p, maps, _, _ = _state(VARIANTS[0])
+    opts = dict(max_outer=2, max_iter=20)
+    ref, _ = dd.solve(p, maps, outer_tol=1e-12, **opts)
+    ctx = Context(p, "fp64")
+    xa, rep, status, _ = ctx.solve(outer_tol=1e-12, **opts)
+    ctx.close()
+    errs = [np.linalg.norm(xa[f] - ref[f]) / np.linalg.norm(ref[f] - ref[f].mean()) for f in range(3)]
+    e_b = np.linalg.norm((p.xb0 - p.truth0) / p.sigma_b[:, None, None])
+    e_a = np.linalg.norm((xa - p.truth0) / p.sigma_b[:, None, None])
+    print(f"tz solve: outer {rep.outer_iters} evals {rep.total_evals} analysis err {max(errs):.2e}, "
+          f"distance to truth {e_a:.3e} (background {e_b:.3e})", flush=True)
+    assert max(errs) <= 1e-7
+    assert e_a < e_b
+
+
+def test_unsupported_entry_points_rejected():
+    from paper_2205_06649_amd import _lib as L
+    from paper_2205_06649_amd.context import Context
+    p, maps, trajs, _ = _state(VARIANTS[0])
+    ctx = Context(p, "fp32")
+    for mode in (2, 3, 4):
+        with pytest.raises(L.DD4DVarError) as e:
+            ctx.set_exec_mode(mode)
+        assert e.value.status == L.DD4DVAR_E_INVALID
+    x = ctx.pack_ctrl(_controls(p, maps, trajs, seed=5))
+    ctx.forward(x, with_traj=False)
+    with pytest.raises(L.DD4DVarError) as e:
+        ctx.tangent_linear(x)
+    assert e.value.status == L.DD4DVAR_E_INVALID
+    with pytest.raises(L.DD4DVarError) as e:
+        ctx.gn_hessvec(x)
+    assert e.value.status == L.DD4DVAR_E_INVALID
+    with pytest.raises(L.DD4DVarError) as e:
+        ctx.solve(local_solver="gn")
+    assert e.value.status == L.DD4DVAR_E_INVALID
+    ctx.close()

@@ -92,9 +92,26 @@ def _bad(p, **kw):
     return p.replace(**kw)
 
 
+def _time_decomposition(p):
+    """The same problem on one band of one piece (boxes covering the sphere)."""
+    return p.replace(band_lat_edges=np.array([0, p.nlat], dtype=np.int32),
+                     band_npieces=np.array([1], dtype=np.int32),
+                     piece_lon_edges=np.array([0, p.nlon], dtype=np.int32), overlap_cells=0)
+
+
+def test_turkel_zwas_limits_accepted():
+    """The largest offsets (nlon/2, nlat/2) and alpha in {0, 1} plan on a time
+    decomposition; the plain scheme (tz_p = 0) ignores tz_q and tz_alpha."""
+    t = _time_decomposition(_with_values(synth.make_spec("c1")))
+    for kw in (dict(tz_p=32, tz_q=16, tz_alpha=1.0), dict(tz_p=1, tz_q=1, tz_alpha=0.0),
+               dict(tz_p=0, tz_q=-5, tz_alpha=7.0)):
+        Plan(t.replace(**kw)).close()
+
+
 @pytest.mark.parametrize("case", [
     "odd_nlon", "edges_not_tiling", "overlap_too_big", "sigma_nonpositive", "obs_cell_range",
-    "obs_step_range", "duplicate_obs", "nan_obs", "bad_field", "piece_wraps", "time_overlap"])
+    "obs_step_range", "duplicate_obs", "nan_obs", "bad_field", "piece_wraps", "time_overlap",
+    "tz_space_pieces", "tz_p_range", "tz_q_range", "tz_q_zero", "tz_alpha_range", "tz_alpha_nan"])
 def test_invalid_descriptors_rejected(case):
     p = _with_values(synth.make_spec("c1"))
     if case == "odd_nlon":
@@ -133,6 +150,14 @@ def test_invalid_descriptors_rejected(case):
                       overlap_cells=2)
     elif case == "time_overlap":
         q = p.replace(overlap_steps=11)
+    elif case == "tz_space_pieces":
+        q = p.replace(tz_p=2, tz_q=2, tz_alpha=0.5)
+    else:
+        t = _time_decomposition(p)
+        q = {"tz_p_range": dict(tz_p=33, tz_q=1), "tz_q_range": dict(tz_p=1, tz_q=17),
+             "tz_q_zero": dict(tz_p=1, tz_q=0), "tz_alpha_range": dict(tz_p=1, tz_q=1, tz_alpha=1.5),
+             "tz_alpha_nan": dict(tz_p=1, tz_q=1, tz_alpha=np.nan)}[case]
+        q = t.replace(**q)
     with pytest.raises(L.DD4DVarError) as e:
         Plan(q)
     assert e.value.status == L.DD4DVAR_E_INVALID
