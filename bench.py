@@ -18,7 +18,9 @@ graph replays; the timed steps are graph replays of that plan.
 Prints one JSON line.  Extra fields: the autotuner's candidates, the same
 plan launched eagerly, the plain per-subdomain FP64 path (one launch per
 subdomain per step) and the batched FP64 path, the FP32 error against FP64,
-phase timings, an FP32-vs-FP64 DD solve, and the oracle timed on host cores.
+phase timings, an FP32-vs-FP64 DD solve, the Gauss-Newton local solver, the
+Turkel-Zwas variant on a time decomposition of the same grid, and the oracle
+timed on host cores.
 """
 from __future__ import annotations
 
@@ -332,6 +334,103 @@ def gn_leg(prob, x, mode, passes, config, reps=10, solves=True):
     return out
 
 
+TZ_VARIANT = (2, 2, 0.5)
+
+
+def tz_bytes(ctx, prec_bytes):
+    """Compulsory HBM bytes of one Turkel-Zwas evaluation (step kernels).
+
+    Forward as the plain step kernels.  Adjoint at level n: the scatter
+    launch reads Z^n and lambda^{n+1} and writes one value of each of the 13
+    offsets' slot planes (for n < L); the gather launch reads the 13 slot
+    values that reach the cell, lambda^{n+1} and lambda^{n+2} where they
+    exist, Z^n, the overlap target where covered and the coverage byte, and
+    writes lambda^n (level 0: FP64 control and background read, FP64
+    gradient written); 20 B per observation.
+    """
+    from paper_2205_06649_amd import _lib as L
+    b3 = 3 * prec_bytes
+    tcount = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_TIME_COUNT, 0)
+    fwd = adj = 0.0
+    for s, inf in enumerate(ctx.info):
+        ncell, lev0, nlev = int(inf[1]) * int(inf[3]), int(inf[4]), int(inf[5])
+        L_ = nlev - 1
+        cover = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_COVER, s).astype(np.int64)
+        nobs = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_OBS_BIN, s).size
+        fwd += ncell * (24 + b3)
+        for n in range(L_):
+            fwd += ncell * b3 * (3 if n >= 1 else 2)
+        for n in range(L_, -1, -1):
+            has1, has2 = n + 1 <= L_, n + 2 <= L_
+            if has1:
+                adj += ncell * b3 * 15
+            nvec = 13 * has1 + has1 + has2 + 1 + (n > 0)
+            covered = int(np.count_nonzero(cover * tcount[lev0 + n] - 1 > 0))
+            adj += ncell * (nvec * b3 + 1) + covered * b3 + (ncell * 72 if n == 0 else 0)
+        adj += nobs * 20
+    return fwd, adj
+
+
+def tz_leg(spec, reps=5):
+    """Turkel-Zwas variant (Sec. 7 discrete U, V, H with offsets p, q and
+    averaging alpha) on a time decomposition of the benchmark's grid, window,
+    intervals and observation network: one box per interval, each covering
+    the sphere (the truth run that makes the observations uses the variant
+    too).  FP32 and FP64 evaluations with the step kernels, the sweep phases,
+    and the algorithmic rate of each sweep."""
+    import torch
+
+    import synth
+    from paper_2205_06649_amd.context import Context
+    p_, q_, a_ = TZ_VARIANT
+    tspec = spec.replace(band_lat_edges=np.array([0, spec.nlat], np.int32),
+                         band_npieces=np.array([1], np.int32),
+                         piece_lon_edges=np.array([0, spec.nlon], np.int32),
+                         overlap_cells=0, tz_p=p_, tz_q=q_, tz_alpha=a_)
+    prob = synth.finish_spec(tspec, gpu_truth_forward)
+    out = {"tz_p": p_, "tz_q": q_, "tz_alpha": a_,
+           "workload": f"{prob.nlat}x{prob.nlon}, {prob.nsteps} steps, "
+                       f"{len(prob.time_edges) - 1} intervals (boxes covering the sphere), "
+                       f"overlap {prob.overlap_steps} steps, {prob.nobs} obs"}
+    res = {}
+    for prec, b in (("fp32", 4), ("fp64", 8)):
+        ctx = Context(prob, prec)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(2205)
+        sb = torch.tensor(prob.sigma_b, dtype=torch.float64, device="cuda")
+        scale = torch.cat([sb[f].expand(int(i[1]) * int(i[3])) for i in ctx.info for f in range(3)])
+        x = ctx.background_controls() + 0.3 * scale * torch.randn(
+            ctx.ctrl_len, generator=gen, dtype=torch.float64, device="cuda")
+        ms, J, g = time_evals(ctx, x, reps, 2)
+        ctx.set_timing(True)
+        ctx.cost_grad(x, J, g)
+        ctx.get_timing()
+        for _ in range(reps):
+            ctx.cost_grad(x, J, g)
+        t = ctx.get_timing()
+        ctx.set_timing(False)
+        fwd_b, adj_b = tz_bytes(ctx, b)
+        fwd_ms, adj_ms = t["fwd_ms"] / t["calls"], t["adj_ms"] / t["calls"]
+        pts = sum(int(i[1]) * int(i[3]) * (int(i[5]) - 1) for i in ctx.info)
+        res[prec] = (J.cpu().numpy(), g.cpu().numpy())
+        out[prec] = {"ms_per_eval": ms, "local_point_steps_per_s": pts / (ms * 1e-3),
+                     "forward_ms": fwd_ms, "adjoint_ms": adj_ms,
+                     "forward_GBs": fwd_b / (fwd_ms * 1e-3) / 1e9,
+                     "adjoint_GBs": adj_b / (adj_ms * 1e-3) / 1e9,
+                     "adjoint_frac_of_hbm_peak": adj_b / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"turkel-zwas {prec}: {ms:.2f} ms/eval (forward {fwd_ms:.2f} ms, "
+            f"{out[prec]['forward_GBs']:.0f} GB/s; adjoint {adj_ms:.2f} ms, "
+            f"{out[prec]['adjoint_GBs']:.0f} GB/s)")
+        ctx.close()
+        del ctx, x, J, g
+        torch.cuda.empty_cache()
+    (J32, g32), (J64, g64) = res["fp32"], res["fp64"]
+    out["fp32_vs_fp64_rel_err"] = {
+        "J_max": float(np.max(np.abs(J32 - J64) / np.abs(J64))),
+        "grad_norm": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))}
+    return out
+
+
 def time_evals(ctx, x, steps, warmup):
     import torch
     J = torch.empty(ctx.nsub, dtype=torch.float64, device="cuda")
@@ -472,6 +571,8 @@ def main():
                     help="skip the Gauss-Newton leg (normal-matrix product, GN solves)")
     ap.add_argument("--no-gn-solve", action="store_true",
                     help="time the Gauss-Newton normal-matrix product only")
+    ap.add_argument("--no-tz", action="store_true",
+                    help="skip the Turkel-Zwas leg (time decomposition of the same grid)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -667,6 +768,8 @@ def main():
     if not args.no_gn:
         result["gauss_newton"] = gn_leg(prob, x, mode, passes, args.config,
                                         solves=not args.no_gn_solve)
+    if not args.no_tz:
+        result["turkel_zwas"] = tz_leg(spec)
 
     if cpu is not None:
         result["cpu_baseline"] = cpu
