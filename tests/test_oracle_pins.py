@@ -664,6 +664,38 @@ def test_tz_steady_flow_second_order(tzv, omega, alpha):
     assert 3.4 < res[0] / res[1] < 5.5 and 3.4 < res[1] / res[2] < 4.6, res
 
 
+def _max_wind_run(g, x0, steps, cap=1e3):
+    """Leapfrog run (Euler half start) of the global model; the step at which
+    the winds pass ``cap`` m/s (or ``steps``) and the largest wind seen."""
+    prev, cur = x0, x0 + 0.5 * model.increment(g, x0)
+    peak = float(np.abs(x0[1:]).max())
+    with np.errstate(all="ignore"):
+        for n in range(1, steps):
+            prev, cur = cur, prev + model.increment(g, cur)
+            a = float(np.abs(cur[1:]).max())
+            if not a <= cap:
+                return n, a
+            peak = max(peak, a)
+    return steps, peak
+
+
+def test_tz_larger_time_step():
+    """The point of the coarse offsets: the gravity-wave terms over p columns
+    and q rows relax the (polar) CFL limit.  At 2.5x the time step of the
+    synthetic problems the plain centred scheme blows up within 20 steps,
+    while the Turkel-Zwas scheme with p = q = 2 stays bounded over 400 steps,
+    and with alpha = 1/2 still at 4x."""
+    p = problem("c1")
+    w0 = float(np.abs(p.xb0[1:]).max())
+    g = model.Grid(p.nlat, p.nlon, 2.5 * p.dt, p.radius, p.gravity, p.omega)
+    n, _ = _max_wind_run(g, p.xb0, 400)
+    assert n < 20
+    for k, tzv in ((2.5, (2, 2, 0.0)), (2.5, (2, 2, 0.5)), (4.0, (2, 2, 0.5))):
+        g = _tz_grid(p.replace(dt=k * p.dt), tzv)
+        n, peak = _max_wind_run(g, p.xb0, 400)
+        assert n == 400 and peak < 2.0 * w0, (k, tzv, n, peak)
+
+
 def test_tz_needs_a_time_decomposition():
     cfg = dict(synth.CONFIGS["c1"], tz=(2, 2, 0.5), index=120)
     p = custom_problem(cfg)
