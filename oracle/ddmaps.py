@@ -21,6 +21,18 @@ intervals Delta_j = [t_j, t_{j+s_j}] (Sec. 3.2).  Readings:
   lies across the east/west seam or across a pole; it then reads the box
   itself.  Otherwise it is frozen and reads the core owner of the (pole-mapped)
   cell in the same time interval; u and v change sign across a pole;
+* under the Turkel-Zwas variant (offsets p, q) the stencil reads up to q rows
+  and p columns beyond the box, corners included, so the ring becomes a pad:
+  for a box of several pieces every position of the frame [-q, ny+q) x
+  [-p, nx+p) outside the box, numbered south block (rows -q..-1, columns
+  -p..nx+p-1, row-major), north block (rows ny..ny+q-1), west block (rows
+  0..ny-1, columns -p..-1), east block (columns nx..nx+p-1); for a box
+  spanning the circle only the south and north blocks over columns 0..nx-1
+  (its columns wrap onto itself).  A row beyond a pole maps to the row at
+  the same depth on the other side, half a circle further, u and v negated.
+  A position of a spanning box that maps into the box itself is internal;
+  every other position is frozen and reads the core owner of the mapped cell
+  in the same time interval;
 * restriction weights (Def. defrestrfun, applied to squared terms):
   c(n, cell) = number of extended space-time boxes containing (n, cell), which
   is the spatial count times the temporal count;
@@ -51,6 +63,8 @@ class Box:
     span: bool
     lev0: int          # S_j
     nlev: int          # E_j - S_j + 1
+    pad_p: int = 0     # Turkel-Zwas pad widths (0: the one-cell ring)
+    pad_q: int = 0
 
     @property
     def ncell(self):
@@ -58,7 +72,30 @@ class Box:
 
     @property
     def nring(self):
-        return 2 * self.nx + 2 * self.ny
+        p, q = self.pad_p, self.pad_q
+        if q == 0:
+            return 2 * self.nx + 2 * self.ny
+        if self.span:
+            return 2 * q * self.nx
+        return 2 * q * (self.nx + 2 * p) + 2 * p * self.ny
+
+
+def ring_coords(b: Box):
+    """Box-relative (row, col) of every ring (or pad) position, in order."""
+    ny, nx, p, q = b.ny, b.nx, b.pad_p, b.pad_q
+    if q == 0:
+        rr = np.concatenate([np.full(nx, -1), np.full(nx, ny), np.arange(ny), np.arange(ny)])
+        cc = np.concatenate([np.arange(nx), np.arange(nx), np.full(ny, -1), np.full(ny, nx)])
+        return rr, cc
+    cols = np.arange(nx) if b.span else np.arange(-p, nx + p)
+    south = np.arange(-q, 0)
+    north = np.arange(ny, ny + q)
+    rr = [np.repeat(south, cols.size), np.repeat(north, cols.size)]
+    cc = [np.tile(cols, q), np.tile(cols, q)]
+    if not b.span:
+        rr += [np.repeat(np.arange(ny), p), np.repeat(np.arange(ny), p)]
+        cc += [np.tile(np.arange(-p, 0), ny), np.tile(np.arange(nx, nx + p), ny)]
+    return np.concatenate(rr), np.concatenate(cc)
 
 
 @dataclasses.dataclass
@@ -112,9 +149,8 @@ def build(prob) -> DDMaps:
     o, ot = prob.overlap_cells, prob.overlap_steps
     pieces = _pieces(prob)
     nspace = len(pieces)
-    if getattr(prob, "tz_p", 0) > 0 and nspace != 1:
-        raise ValueError("the Turkel-Zwas variant is built for time decompositions "
-                         "(one band of one piece)")
+    tzp = int(getattr(prob, "tz_p", 0))
+    pp, pq = (tzp, int(prob.tz_q)) if tzp > 0 else (0, 0)
     tedges = np.asarray(prob.time_edges, dtype=np.int64)
     ntime = len(tedges) - 1
 
@@ -129,10 +165,12 @@ def build(prob) -> DDMaps:
                 col0, nx, span = 0, nlon, True
             else:
                 col0, nx, span = (c0 - o) % nlon, (c1 - c0) + 2 * o, False
+                if nx + 2 * pp > nlon:
+                    raise ValueError("a box and its pad columns must not wrap the circle")
             boxes.append(Box(sub=j * nspace + i, piece=i, interval=j, band=b,
                              core_row0=r0, core_row1=r1, core_col0=c0, core_col1=c1,
                              row0=br0, ny=br1 - br0, col0=col0, nx=nx, span=span,
-                             lev0=S, nlev=E - S + 1))
+                             lev0=S, nlev=E - S + 1, pad_p=pp, pad_q=pq))
 
     owner = np.full((nlat, nlon), -1, dtype=np.int64)
     for i, (b, r0, r1, c0, c1, npc) in enumerate(pieces):
@@ -154,8 +192,7 @@ def build(prob) -> DDMaps:
     for bx in boxes:
         ny, nx = bx.ny, bx.nx
         # box-relative (row, col) of each ring position
-        rr = np.concatenate([np.full(nx, -1), np.full(nx, ny), np.arange(ny), np.arange(ny)])
-        cc = np.concatenate([np.arange(nx), np.arange(nx), np.full(ny, -1), np.full(ny, nx)])
+        rr, cc = ring_coords(bx)
         src = np.empty(rr.size, dtype=np.int64)
         off = np.empty(rr.size, dtype=np.int64)
         sgn = np.ones(rr.size, dtype=np.int64)
@@ -166,17 +203,17 @@ def build(prob) -> DDMaps:
             if bx.span and (c < 0 or c >= nx):
                 src[k], off[k] = -1, r * nx + (c % nx)
                 continue
-            if bx.span and across:
-                rin = 0 if grow < 0 else ny - 1
-                src[k], off[k], sgn[k] = -1, rin * nx + (c + half) % nx, -1
+            # the row at the same depth beyond the pole, half a circle further
+            mrow = -1 - grow if grow < 0 else (2 * nlat - 1 - grow if grow >= nlat else grow)
+            if bx.span and across and bx.row0 <= mrow < bx.row0 + ny:
+                src[k], off[k], sgn[k] = -1, (mrow - bx.row0) * nx + (c + half) % nx, -1
                 continue
             gcol = (bx.col0 + c) % nlon
             if across:
-                mrow = 0 if grow < 0 else nlat - 1
                 mcol = (gcol + half) % nlon
                 sgn[k] = -1
             else:
-                mrow, mcol = grow, gcol
+                mcol = gcol
             sb = boxes[bx.interval * nspace + owner[mrow, mcol]]
             src[k] = sb.sub
             rel_r = mrow - sb.row0

@@ -26,7 +26,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import model
+from . import model, tz_local
 from .model import Grid
 
 
@@ -37,6 +37,10 @@ class LocalGeometry:
         b = maps.boxes[s]
         self.box = b
         self.g = g
+        # the Turkel-Zwas variant reads a wider frame (see tz_local)
+        self.tz = tz_local.TzGeometry(g, maps, s) if g.tz is not None else None
+        if self.tz is not None:
+            return
         ny, nx = b.ny, b.nx
         rows = b.row0 + np.arange(ny)
         cos_ext = np.concatenate([[g.cos[0]], g.cos, [g.cos[-1]]])
@@ -201,23 +205,14 @@ def increment_ad(geo: LocalGeometry, P, lam):
     return geo.fold(A)
 
 
-def _global_box(geo):
-    """The Turkel-Zwas variant runs on boxes that cover the whole sphere (time
-    decompositions): the local model is then the global one."""
-    b, g = geo.box, geo.g
-    if not (b.row0 == 0 and b.ny == g.nlat and b.col0 == 0 and b.nx == g.nlon):
-        raise ValueError("the Turkel-Zwas variant needs boxes covering the sphere")
-
-
 def forward(geo: LocalGeometry, x, ring):
     """Local trajectory [nlev][3][ny][nx] from control x and frozen ring.
 
     ``ring`` is [nlev][3][nring] (values as seen by the stencil, signs
     applied) or None when the box has no frozen positions.
     """
-    if geo.g.tz is not None:
-        _global_box(geo)
-        return model.forward(geo.g, x, geo.box.nlev - 1)
+    if geo.tz is not None:
+        return tz_local.forward(geo.tz, x, ring)
     L = geo.box.nlev - 1
     traj = np.empty((L + 1,) + x.shape, dtype=x.dtype)
     traj[0] = x
@@ -233,9 +228,8 @@ def forward(geo: LocalGeometry, x, ring):
 
 
 def tlm(geo: LocalGeometry, traj, ring, dx):
-    if geo.g.tz is not None:
-        _global_box(geo)
-        return model.tlm(geo.g, traj, dx)
+    if geo.tz is not None:
+        return tz_local.tlm(geo.tz, traj, ring, dx)
     L = traj.shape[0] - 1
     d = np.empty_like(traj)
     d[0] = dx
@@ -252,9 +246,8 @@ def tlm(geo: LocalGeometry, traj, ring, dx):
 
 def adjoint(geo: LocalGeometry, traj, ring, forcing):
     """Transpose of ``tlm`` applied to per-level forcing; returns level 0."""
-    if geo.g.tz is not None:
-        _global_box(geo)
-        return model.adjoint(geo.g, traj, forcing)
+    if geo.tz is not None:
+        return tz_local.adjoint(geo.tz, traj, ring, forcing)
     L = traj.shape[0] - 1
     a = forcing.copy()
 

@@ -13,7 +13,7 @@ import pytest
 
 import synth
 from conftest import custom_problem, problem
-from oracle import brute, dd, ddmaps, gn, lbfgs, local, model
+from oracle import brute, dd, ddmaps, gn, lbfgs, local, model, tz_local
 
 
 def _grid(p):
@@ -696,14 +696,98 @@ def test_tz_larger_time_step():
         assert n == 400 and peak < 2.0 * w0, (k, tzv, n, peak)
 
 
-def test_tz_needs_a_time_decomposition():
-    cfg = dict(synth.CONFIGS["c1"], tz=(2, 2, 0.5), index=120)
-    p = custom_problem(cfg)
+TZ_SPACE_CFGS = {
+    "c1": dict(synth.CONFIGS["c1"], index=140),
+    "span": dict(SPAN_CFG, index=141),
+    "mixed": dict(MIXED_CFG, index=142),
+    # five spanning bands: pads reaching across a pole partly into the box
+    # itself (internal) and partly into the polar band (frozen)
+    "deep": dict(index=145, nlat=16, nlon=32, nsteps=6, bands=5, pieces=1, ntime=2,
+                 overlap_cells=2, overlap_steps=1, obs_frac=0.1, obs_every=2),
+}
+
+
+@pytest.mark.parametrize("which", ["c1", "span", "mixed", "deep"])
+@pytest.mark.parametrize("tzv", [(2, 2, 0.5), (1, 3, 1.0)])
+def test_tz_restricted_model_with_exact_pad(rng, which, tzv):
+    """Spatial decompositions under the variant: with the pad of every level
+    taken from the global trajectory (one interval), the restricted model on
+    each box (pieces, spanning bands, bands touching a pole, pads reaching
+    across it, brick widths) reproduces the global trajectory on the box, and
+    the weighted local functionals sum to the global one (eq. restJ)."""
+    p = custom_problem(dict(TZ_SPACE_CFGS[which], ntime=1, tz=tzv))
+    g = _grid(p)
+    maps = ddmaps.build(p)
+    x = p.xb0 + p.sigma_b[:, None, None] * rng.standard_normal(p.xb0.shape)
+    gt = model.forward(g, x, p.nsteps)
+    trajs = {b.sub: local.restrict_global(maps, b.sub, gt) for b in maps.boxes}
+    xb0 = p.xb0[None]
+    total = 0.0
+    for b in maps.boxes:
+        assert b.nring == len(maps.halo_src[b.sub])
+        ring = local.ring_from_trajs(maps, b.sub, trajs)
+        lt = local.forward(local.LocalGeometry(g, maps, b.sub), trajs[b.sub][0], ring)
+        assert np.abs(lt - trajs[b.sub]).max() <= 1e-12 * np.abs(trajs[b.sub]).max(), b.sub
+        xbs = local.restrict_global(maps, b.sub, xb0)[0]
+        J = local.cost_grad(p, maps, b.sub, trajs[b.sub][0], xbs, ring,
+                            {k: trajs[k] for k in maps.neighbors[b.sub]}, with_grad=False)
+        total += J
+    Jg = model.cost_grad(p, x, with_grad=False)
+    assert abs(total - Jg) <= 1e-12 * Jg
+
+
+@pytest.mark.parametrize("which", ["c1", "span", "mixed", "deep"])
+def test_tz_local_dot_product_and_gradient(rng, which):
+    """Local tangent linear and adjoint with frozen pads (adjoint definition,
+    eq. adjProd), per step and over the window, on every box; the local
+    gradient against centred differences of the local functional."""
+    p = custom_problem(dict(TZ_SPACE_CFGS[which], tz=(2, 2, 0.5)))
+    g, maps, trajs, rings = _local_setup(p)
+    sb = p.sigma_b[:, None, None]
+    for s in range(len(maps.boxes)):
+        geo = local.LocalGeometry(g, maps, s)
+        x = trajs[s][0] + 0.3 * sb * rng.standard_normal(trajs[s][0].shape)
+        lt = local.forward(geo, x, rings[s])
+        dx = rng.standard_normal(x.shape)
+        y = rng.standard_normal(lt.shape)
+        lhs = np.sum(local.tlm(geo, lt, rings[s], dx) * y)
+        rhs = np.sum(dx * local.adjoint(geo, lt, rings[s], y))
+        assert abs(lhs - rhs) <= 1e-13 * abs(lhs), s
+        P, dP = geo.tz.pad(x, rings[s][0]), geo.tz.pad(dx, None)
+        lam = rng.standard_normal(x.shape)
+        lhs = np.sum(tz_local.increment_tl(geo.tz, P, dP) * lam)
+        rhs = np.sum(dx * geo.tz.fold(tz_local.increment_ad(geo.tz, P, lam)))
+        assert abs(lhs - rhs) <= 1e-13 * abs(lhs), s
+    s = len(maps.boxes) - 1
+    xb = trajs[s][0]
+    x = xb + 0.5 * sb * rng.standard_normal(xb.shape)
+    nb = {k: trajs[k] for k in maps.neighbors[s]}
+    J, gr = local.cost_grad(p, maps, s, x, xb, rings[s], nb)
+    d = sb * rng.standard_normal(xb.shape)
+    an = np.sum(gr * d)
+    eps = 5e-4
+    Jp = local.cost_grad(p, maps, s, x + eps * d, xb, rings[s], nb, with_grad=False)
+    Jm = local.cost_grad(p, maps, s, x - eps * d, xb, rings[s], nb, with_grad=False)
+    assert abs((Jp - Jm) / (2 * eps) - an) <= 1e-6 * abs(an)
+
+
+def test_tz_time_decomposition_box_is_the_global_model():
+    """A box covering the sphere: the padded-frame increment equals the
+    global model's (array shifts and pole reflection) bit for bit."""
+    p = custom_problem(dict(synth.CONFIGS["c1"], bands=1, pieces=1, ntime=2, overlap_cells=0,
+                            index=143, tz=(3, 2, 0.25)))
+    g = _grid(p)
+    maps = ddmaps.build(p)
+    geo = local.LocalGeometry(g, maps, 0)
+    assert geo.tz.frozen.size == 0
+    x = p.truth0
+    assert np.array_equal(tz_local.increment(geo.tz, geo.tz.pad(x, None)), model.increment(g, x))
+
+
+def test_tz_pad_columns_must_not_wrap():
+    cfg = dict(synth.CONFIGS["c1"], index=144, tz=(15, 1, 0.0))
     with pytest.raises(ValueError):
-        ddmaps.build(p)
-    q = custom_problem(dict(cfg, bands=1, pieces=1, index=121))
-    maps = ddmaps.build(q)
-    assert all(b.ny == q.nlat and b.nx == q.nlon for b in maps.boxes)
+        ddmaps.build(custom_problem(cfg))
 
 
 # --- P10: map invariants -----------------------------------------------------
