@@ -76,11 +76,12 @@ typedef struct {
    * tz_alpha over the points (i +- p, j), (i, j +- q) and the corners
    * (i +- p, j +- q); advection keeps offset one and H is the advective
    * form with h / cos on both divergence terms.  Requires
-   * 1 <= tz_p <= nlon / 2, 1 <= tz_q <= nlat / 2, 0 <= tz_alpha <= 1 and a
-   * time decomposition (one band of one piece: every box covers the sphere,
-   * so the local model is the global one).  Such a context runs the step
-   * kernels only (execution modes 0 and 1; no persistent modes), and the
-   * tangent-linear, Gauss-Newton and mixed-precision entry points return
+   * 1 <= tz_p <= nlon / 2, 1 <= tz_q <= nlat / 2, 0 <= tz_alpha <= 1, and
+   * for bands of several pieces box width + 2 tz_p <= nlon.  Each box then
+   * reads a frozen pad tz_q rows and tz_p columns wide, corners included
+   * (see HALO_SRC), in place of the one-cell ring.  Such a context runs the
+   * step kernels only (execution modes 0 and 1; no persistent modes), and
+   * the tangent-linear, Gauss-Newton and mixed-precision entry points return
    * E_INVALID. */
   int32_t tz_p, tz_q;
   double tz_alpha;
@@ -149,6 +150,13 @@ dd4dvar_status dd4dvar_plan_subdomain_info(const dd4dvar_plan* plan, int32_t s,
  *                when the position wraps inside the box.  Ring positions:
  *                south row (box row -1, cols 0..nx-1), north row (row ny),
  *                west column (col -1, rows 0..ny-1), east column (col nx).
+ *                Under the Turkel-Zwas variant (offsets p, q) the pad: south
+ *                block (rows -q..-1) and north block (rows ny..ny+q-1),
+ *                row-major over cols -p..nx+p-1 (0..nx-1 for a box spanning
+ *                the circle), then for other boxes the west block (rows
+ *                0..ny-1, cols -p..-1) and east block (cols nx..nx+p-1),
+ *                row-major.  A row beyond a pole maps to the row at the same
+ *                depth on the other side, half a circle further.
  *   1 HALO_OFF   per s, [nring]: cell offset in the source box (or in the box
  *                itself for internal positions)
  *   2 HALO_SIGN  per s, [nring]: +1, or -1 across a pole (applies to u, v)

@@ -244,7 +244,7 @@ void fill_rows(const dd4dvar_model_desc& m, std::vector<RowCoef<T>>& rows, std::
 template <typename T>
 void fwd_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int ntiles, hipStream_t st) {
   if (c->tz_p > 0)
-    launch_fwd_tz<T>(D, n, tile_base, ntiles, c->tz_p, c->tz_q, c->tz_alpha, st);
+    launch_fwd_tz<T>(D, n, tile_base, ntiles, c->tz_p, c->tz_q, c->tz_alpha, c->plan.model.nlat, st);
   else
     launch_fwd<T>(D, n, tile_base, ntiles, st);
 }
@@ -255,7 +255,7 @@ void adj_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int n
   if (c->tz_p > 0) {
     if (mode == 3) throw DevError{DD4DVAR_E_INVALID, "no Gauss-Newton adjoint for the Turkel-Zwas variant"};
     launch_adj_tz<T>(D, n, tile_base, ntiles, mode, c->tz_p, c->tz_q, c->tz_alpha,
-                     static_cast<T*>(c->tz_slots), x, c->xb, forcing, out, st);
+                     c->plan.model.nlat, static_cast<T*>(c->tz_slots), x, c->xb, forcing, out, st);
   } else {
     launch_adj<T>(D, n, tile_base, ntiles, mode, x, c->xb, forcing, out, st);
   }

@@ -46,6 +46,35 @@ int64_t mod(int64_t a, int64_t n) {
   int64_t r = a % n;
   return r < 0 ? r + n : r;
 }
+
+// Box-relative (row, col) of ring position k.  One-cell ring: south row,
+// north row, west column, east column.  Turkel-Zwas pad (offsets p, q): the
+// south block (rows -q..-1) and the north block (rows ny..ny+q-1), row-major
+// over columns -p..nx+p-1 (0..nx-1 for a box spanning the circle), then for
+// a box of several pieces the west block (rows 0..ny-1, columns -p..-1) and
+// the east block (columns nx..nx+p-1), row-major.
+void ring_coord(const BoxInfo& b, int k, int* r, int* c) {
+  const int ny = b.ny, nx = b.nx, p = b.pad_p, q = b.pad_q;
+  if (q == 0) {
+    if (k < nx) { *r = -1; *c = k; }
+    else if (k < 2 * nx) { *r = ny; *c = k - nx; }
+    else if (k < 2 * nx + ny) { *r = k - 2 * nx; *c = -1; }
+    else { *r = k - 2 * nx - ny; *c = nx; }
+    return;
+  }
+  const int w = b.span ? nx : nx + 2 * p, c0 = b.span ? 0 : -p;
+  if (k < 2 * q * w) {
+    const int row = k / w;
+    *r = row < q ? row - q : ny + (row - q);
+    *c = c0 + k % w;
+    return;
+  }
+  k -= 2 * q * w;
+  const int east = k >= ny * p;
+  if (east) k -= ny * p;
+  *r = k / p;
+  *c = east ? nx + k % p : -p + k % p;
+}
 }  // namespace
 
 void set_thread_error(const std::string& msg) { g_thread_error = msg; }
@@ -166,8 +195,6 @@ dd4dvar_status build_plan(const dd4dvar_model_desc* m, const dd4dvar_partition_d
       pos += np + 1;
     }
     const int nspace = int(pieces.size());
-    require(m->tz_p == 0 || nspace == 1,
-            "the Turkel-Zwas variant needs a time decomposition (one band of one piece)");
     const int ntime = p->n_time;
     plan->nspace = nspace;
     plan->ntime = ntime;
@@ -197,12 +224,21 @@ dd4dvar_status build_plan(const dd4dvar_model_desc* m, const dd4dvar_partition_d
           bx.col0 = 0; bx.nx = nlon; bx.span = 1;
         } else {
           bx.col0 = int(mod(pc.c0 - o, nlon)); bx.nx = pc.c1 - pc.c0 + 2 * o; bx.span = 0;
+          if (bx.nx + 2 * m->tz_p > nlon)
+            throw Invalid{"a box and its Turkel-Zwas pad columns must not wrap the circle"};
         }
         bx.pole_s = bx.span && bx.row0 == 0;
         bx.pole_n = bx.span && bx.row0 + bx.ny == nlat;
         bx.lev0 = S;
         bx.nlev = E - S + 1;
-        bx.nring = 2 * bx.nx + 2 * bx.ny;
+        bx.pad_p = m->tz_p > 0 ? m->tz_p : 0;
+        bx.pad_q = m->tz_p > 0 ? m->tz_q : 0;
+        if (bx.pad_q == 0)
+          bx.nring = 2 * bx.nx + 2 * bx.ny;
+        else if (bx.span)
+          bx.nring = 2 * bx.pad_q * bx.nx;
+        else
+          bx.nring = 2 * bx.pad_q * (bx.nx + 2 * bx.pad_p) + 2 * bx.pad_p * bx.ny;
         bx.ctrl_off = ctrl;
         bx.traj_off = traj;
         ctrl += 3 * bx.ncell();
@@ -253,10 +289,7 @@ dd4dvar_status build_plan(const dd4dvar_model_desc* m, const dd4dvar_partition_d
       const int64_t base = plan->ring_ptr[s];
       for (int k = 0; k < bx.nring; ++k) {
         int r, c;
-        if (k < bx.nx) { r = -1; c = k; }
-        else if (k < 2 * bx.nx) { r = bx.ny; c = k - bx.nx; }
-        else if (k < 2 * bx.nx + bx.ny) { r = k - 2 * bx.nx; c = -1; }
-        else { r = k - 2 * bx.nx - bx.ny; c = bx.nx; }
+        ring_coord(bx, k, &r, &c);
         const int grow = bx.row0 + r;
         const bool across = grow < 0 || grow >= nlat;
         if (bx.span && (c < 0 || c >= bx.nx)) {
@@ -264,17 +297,17 @@ dd4dvar_status build_plan(const dd4dvar_model_desc* m, const dd4dvar_partition_d
           plan->halo_off[base + k] = r * bx.nx + int(mod(c, bx.nx));
           continue;
         }
-        if (bx.span && across) {
-          const int rin = grow < 0 ? 0 : bx.ny - 1;
+        // the row at the same depth beyond the pole, half a circle further
+        const int mrow = grow < 0 ? -1 - grow : (grow >= nlat ? 2 * nlat - 1 - grow : grow);
+        if (bx.span && across && mrow >= bx.row0 && mrow < bx.row0 + bx.ny) {
           plan->halo_src[base + k] = -1;
-          plan->halo_off[base + k] = rin * bx.nx + int(mod(c + half, bx.nx));
+          plan->halo_off[base + k] = (mrow - bx.row0) * bx.nx + int(mod(c + half, bx.nx));
           plan->halo_sign[base + k] = -1;
           continue;
         }
         const int gcol = int(mod(bx.col0 + c, nlon));
-        int mrow = grow, mcol = gcol;
+        int mcol = gcol;
         if (across) {
-          mrow = grow < 0 ? 0 : nlat - 1;
           mcol = int(mod(gcol + half, nlon));
           plan->halo_sign[base + k] = -1;
         }

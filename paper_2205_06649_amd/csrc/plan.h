@@ -18,7 +18,8 @@ struct BoxInfo {
   int32_t span;          // box covers every longitude (band of one piece)
   int32_t pole_s, pole_n;  // span box touching the south / north pole row
   int32_t lev0, nlev;    // levels S_j .. S_j + nlev - 1
-  int32_t nring;         // 2 nx + 2 ny
+  int32_t nring;         // 2 nx + 2 ny, or the Turkel-Zwas pad (see ring_coord)
+  int32_t pad_p, pad_q;  // Turkel-Zwas pad widths (0: the one-cell ring)
   int64_t ctrl_off;      // packed FP64 control offset (elements)
   int64_t traj_off;      // packed FP64 trajectory offset (elements)
   int64_t ncell() const { return int64_t(ny) * nx; }

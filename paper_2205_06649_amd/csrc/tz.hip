@@ -1,7 +1,6 @@
 // Turkel-Zwas variant of the local sweeps (Sec. 7 discrete U, V, H with
-// coarse offsets p, q and averaging alpha), for boxes that cover the whole
-// sphere (time decompositions): step kernels over every box, one workgroup
-// per 256-cell tile.
+// coarse offsets p, q and averaging alpha): step kernels over every box, one
+// workgroup per 256-cell tile.
 //
 // The scheme reads 13 points: the cell, its four neighbours, (i +- p, j),
 // (i, j +- q) and the corners (i +- p, j +- q).  Rows beyond a pole are the
@@ -11,16 +10,25 @@
 // Coriolis terms take u, v, f, tan at the neighbour; 2 dt on the Coriolis
 // bracket; v differences for the meridional advection of v.
 //
+// Points outside the box (restricted model, eq. restricted) come from the
+// box's frozen pad, q rows and p columns wide with corners, whose values the
+// exchange writes with their signs applied: for a box of several pieces every
+// position of the frame [-q, ny+q) x [-p, nx+p) outside the box, numbered
+// south block, north block (row-major over columns -p..nx+p-1), west block,
+// east block (row-major); for a box spanning the circle, whose columns wrap
+// onto itself, the south and north blocks over columns 0..nx-1, and a point
+// beyond a pole that maps into the box itself is read there (u, v negated).
+//
 // Adjoint, deterministic and without atomics: for every cell k a first
 // kernel writes the transposed contribution of its increment to each of the
-// 13 points it reads (the partial derivatives of the increment at k with
+// in-box points it reads (the partial derivatives of the increment at k with
 // respect to the state there, applied to lambda^{n+1}(k)) into one slot
-// plane per offset; for a given offset the map from k to the point read is
-// one-to-one, except that a row within q of a pole is reached both directly
-// and across the pole, so contributions that cross a pole go to separate
-// planes.  A second kernel sums, for every cell, the planes that some cell's
-// offset reaches there, in a fixed order, and adds the forcing and
-// lambda^{n+2} (gather form of the same transpose).
+// plane per offset; frozen points get nothing.  For a given offset the map
+// from k to the point read is one-to-one, except that a row near a pole may
+// be reached both directly and across the pole, so contributions that cross a
+// pole go to separate planes.  A second kernel sums, for every cell, the
+// planes that some in-box cell's offset reaches there, in a fixed order, and
+// adds the forcing and lambda^{n+2} (gather form of the same transpose).
 #include "kernels.h"
 #include "launch.h"
 #include "stencil.h"
@@ -41,54 +49,80 @@ constexpr int kOffs = 13;
 constexpr int kPlanes = tz_slot_planes();
 
 struct Pt {
-  int idx;   // cell of the box
-  int sg;    // +1, or -1 across a pole (u, v)
-  int row;   // its row (coefficients)
-  bool across;
+  int idx;      // cell of the box, or position in the frozen pad
+  int sg;       // -1 for an in-box point reached across a pole (u, v)
+  int grow;     // global row whose coefficients apply
+  bool pad;     // frozen pad value (signs already applied)
+  bool across;  // in-box point reached across a pole
 };
 
-// point (r + dr, c + dc) of a box covering the sphere
-__device__ __forceinline__ Pt point(const SubDev& S, int r, int c, int dr, int dc, int half) {
-  int rr = r + dr, cc = c + dc, sg = 1;
-  bool across = false;
-  if (rr >= S.ny) {
-    rr = 2 * S.ny - 1 - rr;
-    cc += half;
-    sg = -1;
-    across = true;
-  } else if (rr < 0) {
-    rr = -1 - rr;
-    cc += half;
-    sg = -1;
-    across = true;
+// row offset and column offset of each of the 13 points, in slot-plane order
+__device__ __forceinline__ int off_r(int o, int q) {
+  return o == 3 ? 1 : o == 4 ? -1 : (o == 7 || o == 9 || o == 10) ? q : (o == 8 || o == 11 || o == 12) ? -q : 0;
+}
+__device__ __forceinline__ int off_c(int o, int p) {
+  return o == 1 ? 1 : o == 2 ? -1 : (o == 5 || o == 9 || o == 11) ? p : (o == 6 || o == 10 || o == 12) ? -p : 0;
+}
+
+// point (r + dr, c + dc) of box cell (r, c)
+__device__ __forceinline__ Pt point(const SubDev& S, int r, int c, int dr, int dc, int p, int q,
+                                    int half, int nlat) {
+  const int rr = r + dr;
+  int cc = c + dc;
+  const int g = S.row0 + rr;
+  const bool cross = g < 0 || g >= nlat;
+  Pt P;
+  P.grow = g < 0 ? -1 - g : (g >= nlat ? 2 * nlat - 1 - g : g);
+  P.sg = 1;
+  P.pad = false;
+  P.across = false;
+  if (S.span) {
+    cc = cc < 0 ? cc + S.nx : (cc >= S.nx ? cc - S.nx : cc);
+    if (rr >= 0 && rr < S.ny) {
+      P.idx = rr * S.nx + cc;
+    } else if (cross && P.grow >= S.row0 && P.grow < S.row0 + S.ny) {
+      int ca = cc + half;
+      ca = ca >= S.nx ? ca - S.nx : ca;
+      P.idx = (P.grow - S.row0) * S.nx + ca;
+      P.sg = -1;
+      P.across = true;
+    } else {
+      P.pad = true;
+      P.idx = (rr < 0 ? rr + q : q + rr - S.ny) * S.nx + cc;
+    }
+    return P;
   }
-  cc %= S.nx;
-  if (cc < 0) cc += S.nx;
-  return {rr * S.nx + cc, sg, rr, across};
+  if (rr >= 0 && rr < S.ny && cc >= 0 && cc < S.nx) {
+    P.idx = rr * S.nx + cc;
+    return P;
+  }
+  P.pad = true;
+  const int w = S.nx + 2 * p;
+  if (rr < 0)
+    P.idx = (rr + q) * w + cc + p;
+  else if (rr >= S.ny)
+    P.idx = (q + rr - S.ny) * w + cc + p;
+  else if (cc < 0)
+    P.idx = 2 * q * w + rr * p + cc + p;
+  else
+    P.idx = 2 * q * w + S.ny * p + rr * p + cc - S.nx;
+  return P;
 }
 
+// value at a point: the box state (sign across a pole) or the frozen pad
 template <typename T>
-__device__ __forceinline__ V3<T> ld_pt(const T* Z, int64_t plane, const Pt& p) {
-  const T s = T(p.sg);
-  return {Z[p.idx], s * Z[plane + p.idx], s * Z[2 * plane + p.idx]};
+__device__ __forceinline__ V3<T> ld_pt(const T* Z, const T* R, int64_t plane, int nring, const Pt& P) {
+  const T* base = P.pad ? R : Z;
+  const int64_t st = P.pad ? int64_t(nring) : plane;
+  const T s = T(P.sg);
+  return {base[P.idx], s * base[st + P.idx], s * base[2 * st + P.idx]};
 }
 
-// the 13 points of cell (r, c): offsets in the order of the slot planes
+// the 13 points of cell (r, c), in slot-plane order
 __device__ __forceinline__ void points(const SubDev& S, int r, int c, int p, int q, int half,
-                                       Pt* P) {
-  P[0] = point(S, r, c, 0, 0, half);
-  P[1] = point(S, r, c, 0, 1, half);
-  P[2] = point(S, r, c, 0, -1, half);
-  P[3] = point(S, r, c, 1, 0, half);
-  P[4] = point(S, r, c, -1, 0, half);
-  P[5] = point(S, r, c, 0, p, half);
-  P[6] = point(S, r, c, 0, -p, half);
-  P[7] = point(S, r, c, q, 0, half);
-  P[8] = point(S, r, c, -q, 0, half);
-  P[9] = point(S, r, c, q, p, half);
-  P[10] = point(S, r, c, q, -p, half);
-  P[11] = point(S, r, c, -q, p, half);
-  P[12] = point(S, r, c, -q, -p, half);
+                                       int nlat, Pt* P) {
+#pragma unroll
+  for (int o = 0; o < kOffs; ++o) P[o] = point(S, r, c, off_r(o, q), off_c(o, p), p, q, half, nlat);
 }
 
 // across-pole plane of offset o (o = 3, 4, 7 .. 12), else -1
@@ -104,21 +138,22 @@ struct State13 {
 };
 
 template <typename T>
-__device__ __forceinline__ State13<T> load13(const T* Z, int64_t plane, const Pt* P) {
+__device__ __forceinline__ State13<T> load13(const T* Z, const T* R, int64_t plane, int nring,
+                                             const Pt* P) {
   State13<T> s;
-  s.C = ld_pt(Z, plane, P[0]);
-  s.E = ld_pt(Z, plane, P[1]);
-  s.W = ld_pt(Z, plane, P[2]);
-  s.N = ld_pt(Z, plane, P[3]);
-  s.Sv = ld_pt(Z, plane, P[4]);
-  s.Ep = ld_pt(Z, plane, P[5]);
-  s.Wp = ld_pt(Z, plane, P[6]);
-  s.Nq = ld_pt(Z, plane, P[7]);
-  s.Sq = ld_pt(Z, plane, P[8]);
-  s.EN = ld_pt(Z, plane, P[9]);
-  s.WN = ld_pt(Z, plane, P[10]);
-  s.ES = ld_pt(Z, plane, P[11]);
-  s.WS = ld_pt(Z, plane, P[12]);
+  s.C = ld_pt(Z, R, plane, nring, P[0]);
+  s.E = ld_pt(Z, R, plane, nring, P[1]);
+  s.W = ld_pt(Z, R, plane, nring, P[2]);
+  s.N = ld_pt(Z, R, plane, nring, P[3]);
+  s.Sv = ld_pt(Z, R, plane, nring, P[4]);
+  s.Ep = ld_pt(Z, R, plane, nring, P[5]);
+  s.Wp = ld_pt(Z, R, plane, nring, P[6]);
+  s.Nq = ld_pt(Z, R, plane, nring, P[7]);
+  s.Sq = ld_pt(Z, R, plane, nring, P[8]);
+  s.EN = ld_pt(Z, R, plane, nring, P[9]);
+  s.WN = ld_pt(Z, R, plane, nring, P[10]);
+  s.ES = ld_pt(Z, R, plane, nring, P[11]);
+  s.WS = ld_pt(Z, R, plane, nring, P[12]);
   return s;
 }
 }  // namespace
@@ -126,7 +161,7 @@ __device__ __forceinline__ State13<T> load13(const T* Z, int64_t plane, const Pt
 // Z^{n+1} = Z^{n-1} + F(Z^n) (Z^1 = Z^0 + F(Z^0)/2) with the Turkel-Zwas F
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_fwd_tz(Dom<T> D, int n, int tile_base, int p, int q,
-                                                  T alpha) {
+                                                  T alpha, int nlat) {
   const int2 wt = D.tiles[tile_base + xcd_tile(blockIdx.x, gridDim.x)];
   if (D.active && !D.active[wt.x]) return;
   const SubDev S = D.subs[wt.x];
@@ -137,12 +172,13 @@ __global__ __launch_bounds__(kTile) void k_fwd_tz(Dom<T> D, int n, int tile_base
   const int64_t plane = S.ncell;
   const T* Z = zlevel(D, S, n);
   const T* B0 = n >= 1 ? zlevel(D, S, n - 1) : Z;
+  const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
   Pt P[kOffs];
-  points(S, r, c, p, q, D.half, P);
-  const State13<T> z = load13(Z, plane, P);
+  points(S, r, c, p, q, D.half, nlat, P);
+  const State13<T> z = load13(Z, R, plane, S.nring, P);
   const V3<T> B = ld_box(B0, plane, m, T(1));
   const RowCoef<T> rc = D.rows[S.row0 + r];
-  const RowCoef<T> rN = D.rows[S.row0 + P[7].row], rS = D.rows[S.row0 + P[8].row];
+  const RowCoef<T> rN = D.rows[P[7].grow], rS = D.rows[P[8].grow];
   const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
   const T tp = T(p), tq = T(q);
   const V3<T>& C = z.C;
@@ -170,7 +206,8 @@ __global__ __launch_bounds__(kTile) void k_fwd_tz(Dom<T> D, int n, int tile_base
 // at level n applied to lambda^{n+1}(k), one slot plane per offset
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_adj_tz_scatter(Dom<T> D, int n, int tile_base, int p,
-                                                          int q, T alpha, T* __restrict__ slots) {
+                                                          int q, T alpha, int nlat,
+                                                          T* __restrict__ slots) {
   const int2 wt = D.tiles[tile_base + xcd_tile(blockIdx.x, gridDim.x)];
   if (D.active && !D.active[wt.x]) return;
   const SubDev S = D.subs[wt.x];
@@ -181,12 +218,13 @@ __global__ __launch_bounds__(kTile) void k_adj_tz_scatter(Dom<T> D, int n, int t
   const int64_t plane = S.ncell;
   const T* Z = zlevel(D, S, n);
   const T* L1 = D.adj + S.adj_off + int64_t((n + 1) % 3) * 3 * plane;
+  const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
   Pt P[kOffs];
-  points(S, r, c, p, q, D.half, P);
-  const State13<T> z = load13(Z, plane, P);
+  points(S, r, c, p, q, D.half, nlat, P);
+  const State13<T> z = load13(Z, R, plane, S.nring, P);
   const V3<T> lam = ld_box(L1, plane, m, T(1));
   const RowCoef<T> rc = D.rows[S.row0 + r];
-  const RowCoef<T> rN = D.rows[S.row0 + P[7].row], rS = D.rows[S.row0 + P[8].row];
+  const RowCoef<T> rN = D.rows[P[7].grow], rS = D.rows[P[8].grow];
   const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
   const T tp = T(p), tq = T(q);
   const V3<T>& C = z.C;
@@ -227,6 +265,7 @@ __global__ __launch_bounds__(kTile) void k_adj_tz_scatter(Dom<T> D, int n, int t
   T* base = slots + S.ctrl_off * kPlanes;
 #pragma unroll
   for (int o = 0; o < kOffs; ++o) {
+    if (P[o].pad) continue;                  // frozen: not part of the local model
     const int pl = P[o].across ? across_plane(o) : o;
     const T sg = T(P[o].sg);
     T* sp = base + int64_t(pl) * 3 * plane;
@@ -239,7 +278,8 @@ __global__ __launch_bounds__(kTile) void k_adj_tz_scatter(Dom<T> D, int n, int t
 // second adjoint kernel: lambda^n (or the gradient) at every cell from the
 // slot planes that reach it, the forcing and lambda^{n+2}
 template <typename T, int MODE>
-__global__ __launch_bounds__(kTile) void k_adj_tz_gather(Dom<T> D, int n, int tile_base, int q,
+__global__ __launch_bounds__(kTile) void k_adj_tz_gather(Dom<T> D, int n, int tile_base, int p,
+                                                         int q, int nlat,
                                                          const T* __restrict__ slots,
                                                          const double* __restrict__ x,
                                                          const double* __restrict__ xb,
@@ -262,32 +302,38 @@ __global__ __launch_bounds__(kTile) void k_adj_tz_gather(Dom<T> D, int n, int ti
   const bool has1 = n + 1 <= L, has2 = n + 2 <= L;
   const T* L1 = A + int64_t((n + 1) % 3) * 3 * plane;
   const T* L2 = A + int64_t((n + 2) % 3) * 3 * plane;
-  const int r = mm / S.nx, ny = S.ny;
+  const int r = mm / S.nx, c = mm - r * S.nx, ny = S.ny;
   double jloc = 0.0;
-  // J_F(Z^n)^T lambda^{n+1}: the planes whose offset reaches this row
+  // J_F(Z^n)^T lambda^{n+1}: the planes of the in-box cells whose offset
+  // reaches this cell, directly (the reader is the cell minus the offset) or,
+  // in a box spanning the circle, across a pole (the reader's row lies the
+  // offset's depth from the pole on this side)
   double ah = 0, au = 0, av = 0;
   if (has1) {
     const T* base = slots + S.ctrl_off * kPlanes;
-    // rows reached directly by an offset of +k rows: r >= k; of -k: r + k < ny;
-    // across a pole by +k: r >= ny - k; by -k: r < k
-    const bool dir[kOffs] = {true, true, true, r >= 1, r + 1 < ny, true, true, r >= q, r + q < ny,
-                             r >= q, r >= q, r + q < ny, r + q < ny};
-    const bool acr[8] = {r >= ny - 1, r < 1, r >= ny - q, r < q, r >= ny - q, r >= ny - q, r < q, r < q};
+    const int g = S.row0 + r;
 #pragma unroll
     for (int o = 0; o < kOffs; ++o) {
-      if (!dir[o]) continue;
+      const int rk = r - off_r(o, q), ck = c - off_c(o, p);
+      if (rk < 0 || rk >= ny || (!S.span && (ck < 0 || ck >= S.nx))) continue;
       const T* sp = base + int64_t(o) * 3 * plane;
       ah += double(sp[mm]);
       au += double(sp[plane + mm]);
       av += double(sp[2 * plane + mm]);
     }
+    if (S.span) {
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      if (!acr[o]) continue;
-      const T* sp = base + int64_t(13 + o) * 3 * plane;
-      ah += double(sp[mm]);
-      au += double(sp[plane + mm]);
-      av += double(sp[2 * plane + mm]);
+      for (int a = 0; a < 8; ++a) {
+        const int o = a < 2 ? 3 + a : 5 + a;   // offsets 3, 4, 7 .. 12
+        const int dr = off_r(o, q);
+        const int gk = dr > 0 ? 2 * nlat - 1 - dr - g : -dr - 1 - g;
+        const bool reach = dr > 0 ? g >= nlat - dr : g <= -dr - 1;
+        if (!reach || gk < S.row0 || gk >= S.row0 + ny) continue;
+        const T* sp = base + int64_t(13 + a) * 3 * plane;
+        ah += double(sp[mm]);
+        au += double(sp[plane + mm]);
+        av += double(sp[2 * plane + mm]);
+      }
     }
   }
   V3<T> l0 = {T(0), T(0), T(0)}, l2 = {T(0), T(0), T(0)};
@@ -374,30 +420,32 @@ __global__ __launch_bounds__(kTile) void k_adj_tz_gather(Dom<T> D, int n, int ti
 
 template <typename T>
 void launch_fwd_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(k_fwd_tz<T>, dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q, T(alpha));
+                   int nlat, hipStream_t st) {
+  hipLaunchKernelGGL(k_fwd_tz<T>, dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q, T(alpha),
+                     nlat);
 }
 template <typename T>
 void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, int p, int q,
-                   double alpha, T* slots, const double* x, const double* xb,
+                   double alpha, int nlat, T* slots, const double* x, const double* xb,
                    const double* forcing, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_tz_scatter<T>, dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q,
-                     T(alpha), slots);
+                     T(alpha), nlat, slots);
   if (mode == 0)
-    hipLaunchKernelGGL((k_adj_tz_gather<T, 0>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, q,
-                       slots, x, xb, forcing, out);
+    hipLaunchKernelGGL((k_adj_tz_gather<T, 0>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p,
+                       q, nlat, slots, x, xb, forcing, out);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_adj_tz_gather<T, 1>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, q,
-                       slots, x, xb, forcing, out);
+    hipLaunchKernelGGL((k_adj_tz_gather<T, 1>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p,
+                       q, nlat, slots, x, xb, forcing, out);
   else
-    hipLaunchKernelGGL((k_adj_tz_gather<T, 2>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, q,
-                       slots, x, xb, forcing, out);
+    hipLaunchKernelGGL((k_adj_tz_gather<T, 2>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p,
+                       q, nlat, slots, x, xb, forcing, out);
 }
 
-#define DD4DVAR_INST(T)                                                                         \
-  template void launch_fwd_tz<T>(const Dom<T>&, int, int, int, int, int, double, hipStream_t); \
-  template void launch_adj_tz<T>(const Dom<T>&, int, int, int, int, int, int, double, T*,      \
-                                 const double*, const double*, const double*, double*,         \
+#define DD4DVAR_INST(T)                                                                        \
+  template void launch_fwd_tz<T>(const Dom<T>&, int, int, int, int, int, double, int,         \
+                                 hipStream_t);                                                 \
+  template void launch_adj_tz<T>(const Dom<T>&, int, int, int, int, int, int, double, int, T*, \
+                                 const double*, const double*, const double*, double*,        \
                                  hipStream_t);
 DD4DVAR_INST(DD4DVAR_TZ_T)
 #undef DD4DVAR_INST

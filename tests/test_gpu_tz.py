@@ -1,6 +1,10 @@
 """Turkel-Zwas variant on the GPU (Sec. 7 discrete U, V, H with coarse
-offsets p, q and averaging alpha) on time decompositions (one band of one
-piece: every box is the whole sphere), against the oracle.
+offsets p, q and averaging alpha), against the oracle.
+
+Time decompositions (one band of one piece: every box is the whole sphere)
+and spatial ones, whose boxes read frozen pads q rows and p columns wide:
+2 x 2 pieces, three spanning bands, a brick partition, and five thin
+spanning bands whose pads reach across a pole partly into the box itself.
 
 * the global forward run and the local forward sweeps (trajectories);
 * local J and gradient of every box: FP64 state (J 1e-12, gradient 2e-12
@@ -11,7 +15,8 @@ piece: every box is the whole sphere), against the oracle.
   each pole, and alpha in {0, 1/4, 1/2, 1};
 * the adjoint sweep under a caller forcing (transpose of the oracle's
   tangent linear, eq. adjProd);
-* a DD solve (Alg. 1, batched L-BFGS) against the oracle's, on the analysis;
+* DD solves (Alg. 1, batched L-BFGS, with the exchange of the pads and
+  overlap targets) against the oracle's, on the analysis;
 * the entry points the variant does not have return E_INVALID.
 """
 import functools
@@ -22,6 +27,7 @@ import pytest
 import synth
 from conftest import custom_problem
 from oracle import dd, ddmaps, local, model
+from test_oracle_pins import TZ_SPACE_CFGS
 
 pytestmark = pytest.mark.gpu
 
@@ -30,6 +36,9 @@ TOL_GRAD = {"fp64": 2e-12, "fp32": 1e-4}
 TZ_CFG = dict(synth.CONFIGS["c1"], bands=1, pieces=1, ntime=3, overlap_cells=0,
               overlap_steps=2, index=130)
 VARIANTS = [(2, 2, 0.5), (1, 1, 0.0), (3, 2, 0.25), (1, 2, 1.0), (32, 16, 0.5)]
+SPACE_VARIANTS = [(2, 2, 0.5), (1, 3, 1.0)]
+CASES = [("time", v) for v in VARIANTS] + [(w, v) for w in ("c1", "span", "mixed", "deep")
+                                           for v in SPACE_VARIANTS]
 
 
 def _rel(a, b):
@@ -47,8 +56,8 @@ def _anom(Z, h_ref):
 
 
 @functools.lru_cache(maxsize=None)
-def _state(tzv):
-    p = custom_problem(dict(TZ_CFG, tz=tzv))
+def _state(tzv, which="time"):
+    p = custom_problem(dict(TZ_CFG if which == "time" else TZ_SPACE_CFGS[which], tz=tzv))
     maps = ddmaps.build(p)
     bg, trajs = dd.background(p, maps)
     rings, _ = dd.exchange(maps, trajs)
@@ -70,6 +79,15 @@ def test_cases_are_time_decompositions():
         assert all(b.ny == p.nlat and b.nx == p.nlon for b in maps.boxes)
     p, _, _, _ = _state(VARIANTS[-1])
     assert p.tz_p == p.nlon // 2 and p.tz_q == p.nlat // 2
+    # spatial cases: frozen pad positions, and in-box positions across a pole
+    p, maps, _, _ = _state(SPACE_VARIANTS[1], "deep")
+    assert all(b.span for b in maps.boxes)
+    internal_across = [int(((maps.halo_src[b.sub] < 0) & (maps.halo_sign[b.sub] < 0)).sum())
+                       for b in maps.boxes]
+    frozen = [int((maps.halo_src[b.sub] >= 0).sum()) for b in maps.boxes]
+    assert any(i > 0 and f > 0 and 0 < b.row0 for i, f, b in zip(internal_across, frozen, maps.boxes))
+    p, maps, _, _ = _state(SPACE_VARIANTS[0], "mixed")
+    assert not any(b.span for b in maps.boxes) and len({b.nx for b in maps.boxes}) > 1
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -94,11 +112,11 @@ def test_forward_runs(prec):
     ctx.close()
 
 
-@pytest.mark.parametrize("tzv", VARIANTS)
+@pytest.mark.parametrize("which,tzv", CASES)
 @pytest.mark.parametrize("prec,mode", [("fp64", 0), ("fp32", 0), ("fp64", 1)])
-def test_cost_grad_matches_oracle(tzv, prec, mode):
+def test_cost_grad_matches_oracle(which, tzv, prec, mode):
     from paper_2205_06649_amd.context import Context
-    p, maps, trajs, rings = _state(tzv)
+    p, maps, trajs, rings = _state(tzv, which)
     xs = _controls(p, maps, trajs, seed=2)
     ctx = Context(p, prec)
     ctx.set_exec_mode(mode)
@@ -112,15 +130,17 @@ def test_cost_grad_matches_oracle(tzv, prec, mode):
                                  {k: trajs[k] for k in maps.neighbors[s]},
                                  dtype=np.longdouble if prec == "fp64" else np.float64)
         ej, eg = float(abs(J[s] - Jr) / abs(Jr)), _rel(grads[s], gr)
-        print(f"tz {tzv} {prec} mode {mode} box {s}: J rel {ej:.2e}, grad rel {eg:.2e}", flush=True)
+        print(f"tz {which} {tzv} {prec} mode {mode} box {s}: J rel {ej:.2e}, grad rel {eg:.2e}",
+              flush=True)
         assert ej <= TOL[prec] and eg <= TOL_GRAD[prec], (s, ej, eg)
 
 
+@pytest.mark.parametrize("which", ["time", "c1", "deep"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_adjoint_under_forcing(prec):
+def test_adjoint_under_forcing(prec, which):
     from paper_2205_06649_amd.context import Context
-    tzv = VARIANTS[2]
-    p, maps, trajs, rings = _state(tzv)
+    tzv = VARIANTS[2] if which == "time" else SPACE_VARIANTS[0]
+    p, maps, trajs, rings = _state(tzv, which)
     g = model.Grid.of(p)
     xs = _controls(p, maps, trajs, seed=3)
     ctx = Context(p, prec)
@@ -138,9 +158,10 @@ def test_adjoint_under_forcing(prec):
         assert e <= (1e-12 if prec == "fp64" else 1e-5)
 
 
-def test_solve_matches_oracle():
+@pytest.mark.parametrize("which", ["time", "c1"])
+def test_solve_matches_oracle(which):
     from paper_2205_06649_amd.context import Context
-    p, maps, _, _ = _state(VARIANTS[0])
+    p, maps, _, _ = _state(VARIANTS[0], which)
     opts = dict(max_outer=2, max_iter=20)
     ref, _ = dd.solve(p, maps, outer_tol=1e-12, **opts)
     ctx = Context(p, "fp64")
@@ -149,7 +170,7 @@ def test_solve_matches_oracle():
     errs = [np.linalg.norm(xa[f] - ref[f]) / np.linalg.norm(ref[f] - ref[f].mean()) for f in range(3)]
     e_b = np.linalg.norm((p.xb0 - p.truth0) / p.sigma_b[:, None, None])
     e_a = np.linalg.norm((xa - p.truth0) / p.sigma_b[:, None, None])
-    print(f"tz solve: outer {rep.outer_iters} evals {rep.total_evals} analysis err {max(errs):.2e}, "
+    print(f"tz {which} solve: outer {rep.outer_iters} evals {rep.total_evals} analysis err {max(errs):.2e}, "
           f"distance to truth {e_a:.3e} (background {e_b:.3e})", flush=True)
     assert max(errs) <= 1e-7
     assert e_a < e_b

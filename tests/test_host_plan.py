@@ -14,7 +14,7 @@ import synth
 from oracle import ddmaps
 from paper_2205_06649_amd import _lib as L
 from paper_2205_06649_amd.descriptors import Descriptors, Plan
-from test_oracle_pins import MIXED_CFG, SPAN_CFG
+from test_oracle_pins import MIXED_CFG, SPAN_CFG, TZ_SPACE_CFGS
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -36,6 +36,14 @@ def test_library_exports_every_declared_symbol():
 
 
 def _spec(which):
+    if which.startswith("tz_"):
+        # Turkel-Zwas pads: pieces, spanning bands, bricks, pole-crossing pads
+        name, tzv = {"tz_c1": ("c1", (2, 2, 0.5)), "tz_span": ("span", (1, 3, 1.0)),
+                     "tz_mixed": ("mixed", (3, 2, 0.25)), "tz_deep": ("deep", (1, 3, 0.5)),
+                     "tz_time": ("time", (2, 2, 0.5))}[which]
+        cfg = (dict(synth.CONFIGS["c1"], bands=1, pieces=1, overlap_cells=0, index=146)
+               if name == "time" else TZ_SPACE_CFGS[name])
+        return synth.make_spec(dict(cfg, tz=tzv))
     if which == "span":
         return synth.make_spec(SPAN_CFG)
     if which == "mixed":
@@ -48,7 +56,8 @@ def _with_values(p):
     return p.replace(obs_value=np.zeros(p.nobs))
 
 
-@pytest.mark.parametrize("which", ["tiny1", "tiny2", "small", "c1", "c2", "span", "mixed", "c3"])
+@pytest.mark.parametrize("which", ["tiny1", "tiny2", "small", "c1", "c2", "span", "mixed", "c3",
+                                   "tz_c1", "tz_span", "tz_mixed", "tz_deep", "tz_time"])
 def test_plan_maps_match_oracle_bitwise(which):
     p = _with_values(_spec(which))
     om = ddmaps.build(p)
@@ -111,7 +120,7 @@ def test_turkel_zwas_limits_accepted():
 @pytest.mark.parametrize("case", [
     "odd_nlon", "edges_not_tiling", "overlap_too_big", "sigma_nonpositive", "obs_cell_range",
     "obs_step_range", "duplicate_obs", "nan_obs", "bad_field", "piece_wraps", "time_overlap",
-    "tz_space_pieces", "tz_p_range", "tz_q_range", "tz_q_zero", "tz_alpha_range", "tz_alpha_nan"])
+    "tz_pad_wraps", "tz_p_range", "tz_q_range", "tz_q_zero", "tz_alpha_range", "tz_alpha_nan"])
 def test_invalid_descriptors_rejected(case):
     p = _with_values(synth.make_spec("c1"))
     if case == "odd_nlon":
@@ -150,8 +159,8 @@ def test_invalid_descriptors_rejected(case):
                       overlap_cells=2)
     elif case == "time_overlap":
         q = p.replace(overlap_steps=11)
-    elif case == "tz_space_pieces":
-        q = p.replace(tz_p=2, tz_q=2, tz_alpha=0.5)
+    elif case == "tz_pad_wraps":
+        q = p.replace(tz_p=15, tz_q=1, tz_alpha=0.5)
     else:
         t = _time_decomposition(p)
         q = {"tz_p_range": dict(tz_p=33, tz_q=1), "tz_q_range": dict(tz_p=1, tz_q=17),
