@@ -68,7 +68,7 @@ def gather(prob, maps, trajs, level=0):
 
 def solve(prob, maps=None, max_outer=5, outer_tol=1e-6, lbfgs_m=8, max_iter=50,
           grad_rtol=0.0, max_ls=30, c1=1e-4, verbose=False, local_solver="lbfgs",
-          cg_max_iter=50, cg_rtol=1e-6):
+          cg_max_iter=50, cg_rtol=1e-6, krylov="cg"):
     """Alg. 1.  ``local_solver`` "lbfgs" (the default) or "gn": Gauss-Newton
     (Alg. 5 / Alg. 6, see ``gn``) with ``max_iter`` updates per local solve and
     conjugate gradients of at most ``cg_max_iter`` iterations."""
@@ -97,7 +97,8 @@ def solve(prob, maps=None, max_outer=5, outer_tol=1e-6, lbfgs_m=8, max_iter=50,
             if local_solver == "gn":
                 res = gn.minimize(prob, maps, s, xs[s], xb[s], rings[s],
                                   {k: targets[k] for k in maps.neighbors[s]}, max_iter=max_iter,
-                                  grad_rtol=grad_rtol, cg_max_iter=cg_max_iter, cg_rtol=cg_rtol)
+                                  grad_rtol=grad_rtol, cg_max_iter=cg_max_iter, cg_rtol=cg_rtol,
+                                  krylov=krylov)
                 res["x"] = res["xi"].ravel()
                 report["cg_iters"] = report.get("cg_iters", 0) + res["cg_iters"]
             else:

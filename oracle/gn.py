@@ -28,7 +28,14 @@ B-preconditioned Krylov method, Alg. 7, but gives only its citation):
   identity of eq. Eq_matrixAV:1 when every restriction weight is one;
 * the Krylov method is textbook conjugate gradients from xi = 0, stopped
   after ``cg_max_iter`` iterations, when |r| <= cg_rtol |r_0|, or when the
-  curvature p^T A p is not positive;
+  curvature p^T A p is not positive; or, as Alg. 7 names, the Lanczos
+  method on the same B-preconditioned system (``krylov="lanczos"``): the
+  Lanczos basis v_1 = r_0 / |r_0|, ..., the tridiagonal T_j of its
+  recurrence coefficients, x_j = V_j y_j with T_j y_j = |r_0| e_1, whose
+  residual norm is beta_{j+1} |e_j^T y_j|; same caps and stop tests (T_j
+  not positive definite ends it at x_{j-1}).  It reaches the CG iterates in
+  exact arithmetic and also yields the Ritz values (eigenvalues of T_j) of
+  the preconditioned normal matrix;
 * the Gauss-Newton update u^{l+1} = u^l + delta u^l of Alg. 5 is taken in
   full (no line search), and the iteration stops after ``max_iter`` updates
   or when |V grad J_s| <= grad_rtol |V grad J_s(u^0)|, tested before each
@@ -112,8 +119,68 @@ def cg(apply, b, max_iter, rtol):
     return x, k
 
 
+def _tridiag_solve(a, b, rhs):
+    """Solve the symmetric tridiagonal system (diagonal a, off-diagonal b) by
+    its LDL^T factorization; None if a pivot is not positive."""
+    n = len(a)
+    d = np.empty(n)
+    lo = np.empty(max(n - 1, 0))
+    z = np.empty(n)
+    for i in range(n):
+        d[i] = a[i] - (lo[i - 1] ** 2 * d[i - 1] if i > 0 else 0.0)
+        if not d[i] > 0.0:
+            return None
+        if i < n - 1:
+            lo[i] = b[i] / d[i]
+        z[i] = rhs[i] - (lo[i - 1] * z[i - 1] if i > 0 else 0.0)
+    y = np.empty(n)
+    for i in range(n - 1, -1, -1):
+        y[i] = z[i] / d[i] - (lo[i] * y[i + 1] if i < n - 1 else 0.0)
+    return y
+
+
+def lanczos(apply, b, max_iter, rtol):
+    """Lanczos method for apply(x) = b (symmetric positive definite) from
+    x = 0.  Returns (x, iters, alpha, beta): x = V_j y_j after j = iters
+    products, and the recurrence coefficients of T_j (diagonal alpha[:j],
+    off-diagonal beta[1:j]; beta[0] = |b|)."""
+    beta0 = float(np.linalg.norm(b))
+    alpha, beta = [], [beta0]
+    if max_iter <= 0 or not beta0 > 0.0 or not beta0 > rtol * beta0:
+        return np.zeros_like(b), 0, np.array(alpha), np.array(beta)
+    V = [b / beta0]
+    y = None
+    j = 0
+    while j < max_iter:
+        w = apply(V[j])
+        if j > 0:
+            w = w - beta[j] * V[j - 1]
+        a = float(np.dot(w, V[j]))
+        w = w - a * V[j]
+        bn = float(np.linalg.norm(w))
+        yn = _tridiag_solve(alpha + [a], beta[1:j + 1], np.eye(j + 1)[0] * beta0)
+        if yn is None:
+            break
+        alpha.append(a)
+        beta.append(bn)
+        y = yn
+        j += 1
+        if bn * abs(y[-1]) <= rtol * beta0 or not bn > 0.0:
+            break
+        V.append(w / bn)
+    x = np.zeros_like(b) if y is None else sum(yi * vi for yi, vi in zip(y, V))
+    return x, j, np.array(alpha), np.array(beta)
+
+
+def ritz_values(alpha, beta):
+    """Eigenvalues of T_j (the Ritz values of the Lanczos run)."""
+    j = len(alpha)
+    T = np.diag(alpha) + np.diag(beta[1:j], 1) + np.diag(beta[1:j], -1)
+    return np.linalg.eigvalsh(T)
+
+
 def minimize(prob, maps, s, x0, xb, ring, nbr_trajs, max_iter=5, grad_rtol=0.0,
-             cg_max_iter=50, cg_rtol=1e-6):
+             cg_max_iter=50, cg_rtol=1e-6, krylov="cg"):
     """Gauss-Newton iterations on J_s from x0 (Alg. 5 with the normal
     equations solved as above).  Returns a dict like ``lbfgs.minimize``."""
     g = Grid.of(prob)
@@ -139,7 +206,12 @@ def minimize(prob, maps, s, x0, xb, ring, nbr_trajs, max_iter=5, grad_rtol=0.0,
         def apply(v):
             return (sb * hessvec(prob, maps, s, traj, ring, (sb * v.reshape(x.shape)), W)).ravel()
 
-        xi, k = cg(apply, -(sb * gr).ravel(), cg_max_iter, cg_rtol)
+        if krylov == "lanczos":
+            xi, k, al, be = lanczos(apply, -(sb * gr).ravel(), cg_max_iter, cg_rtol)
+            ritz = ritz_values(al, be) if k else np.zeros(0)
+        else:
+            xi, k = cg(apply, -(sb * gr).ravel(), cg_max_iter, cg_rtol)
+            ritz = np.zeros(0)
         cg_total += k
         xi_it = xi_it + xi.reshape(x.shape)
         x = xb + sb * xi_it
@@ -148,4 +220,4 @@ def minimize(prob, maps, s, x0, xb, ring, nbr_trajs, max_iter=5, grad_rtol=0.0,
         hist.append(J)
         it += 1
     return dict(x=x, xi=xi_it, J=J, grad=gr, iters=it, cg_iters=cg_total, nfev=it + 1, status=status,
-                history=hist, g0norm=g0, gnorm=gn)
+                history=hist, g0norm=g0, gnorm=gn, ritz=ritz if it else np.zeros(0))

@@ -590,6 +590,81 @@ def test_dd_solve_gauss_newton():
     assert np.linalg.norm((xa - xl) / sb) <= 1e-6 * np.linalg.norm((xl - p.xb0) / sb)
 
 
+# --- Lanczos on the B-preconditioned normal equations (Alg. 7) -------------
+def _spd(rng, n, cond):
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.geomspace(1.0, cond, n)
+    return (Q * lam) @ Q.T, lam
+
+
+def test_lanczos_matches_cg_and_exact_solve(rng):
+    """In exact arithmetic the Lanczos iterate x_j = V_j y_j is the j-th CG
+    iterate: the same vectors after every number of products (1e-9), the
+    solution of the system at a tight tolerance, and the same stop by
+    residual."""
+    A, lam = _spd(rng, 40, 1e3)
+    b = rng.standard_normal(40)
+    for k in range(1, 13):
+        xl, jl, _, _ = gn.lanczos(lambda v: A @ v, b, k, 0.0)
+        xc, jc = gn.cg(lambda v: A @ v, b, k, 0.0)
+        assert jl == jc == k
+        assert np.linalg.norm(xl - xc) <= 1e-9 * np.linalg.norm(xc), k
+    # run to a tight tolerance: the solution (finite precision costs a few
+    # more products than n once the basis loses orthogonality, as for CG)
+    x, j, _, _ = gn.lanczos(lambda v: A @ v, b, 400, 1e-12)
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+    # the residual estimate beta_{j+1} |e_j^T y_j| is the true residual: the
+    # same stop as CG while the basis stays orthogonal, and the tolerance met
+    for rtol in (3e-1, 1e-1):
+        xl, jl, _, _ = gn.lanczos(lambda v: A @ v, b, 100, rtol)
+        xc, jc = gn.cg(lambda v: A @ v, b, 100, rtol)
+        assert jl == jc
+    for rtol in (1e-2, 1e-5):
+        xl, jl, _, _ = gn.lanczos(lambda v: A @ v, b, 200, rtol)
+        assert np.linalg.norm(b - A @ xl) <= 1.01 * rtol * np.linalg.norm(b)
+
+
+def test_lanczos_ritz_values(rng):
+    """The eigenvalues of T_j interlace the spectrum and the extreme ones
+    converge to the extreme eigenvalues (well separated here)."""
+    A, lam = _spd(rng, 60, 1e2)
+    b = rng.standard_normal(60)
+    _, j, al, be = gn.lanczos(lambda v: A @ v, b, 30, 0.0)
+    r = gn.ritz_values(al, be)
+    assert j == 30 and r.size == 30
+    assert lam[0] * (1 - 1e-12) <= r.min() and r.max() <= lam[-1] * (1 + 1e-12)
+    assert abs(r.max() - lam[-1]) <= 1e-8 * lam[-1]
+
+
+def test_gn_lanczos_local_problem():
+    """Gauss-Newton with Lanczos on a local normal equation system (Alg. 6,
+    Alg. 7): the same updates as with CG, and Ritz values inside the spectrum
+    of the dense preconditioned normal matrix V A V, the largest converged
+    to its largest eigenvalue."""
+    p = problem("tiny2")
+    g, maps, trajs, rings = _local_setup(p)
+    s = 6
+    x0 = _perturbed_local(p, maps, trajs, s, seed=16)
+    xb = trajs[s][0]
+    nb = {k: trajs[k] for k in maps.neighbors[s]}
+    kw = dict(max_iter=3, cg_max_iter=40, cg_rtol=1e-6)
+    rc = gn.minimize(p, maps, s, x0, xb, rings[s], nb, **kw)
+    rl = gn.minimize(p, maps, s, x0, xb, rings[s], nb, krylov="lanczos", **kw)
+    sb = p.sigma_b[:, None, None]
+    assert rl["cg_iters"] == rc["cg_iters"]
+    assert np.linalg.norm((rl["x"] - rc["x"]) / sb) <= 1e-8 * np.linalg.norm((rc["x"] - x0) / sb)
+    # spectrum of V A V about x0, from one update with a long Lanczos run
+    res1 = gn.minimize(p, maps, s, x0, xb, rings[s], nb, krylov="lanczos", max_iter=1,
+                       cg_max_iter=80, cg_rtol=0.0)
+    A, _, _ = _dense_normal_matrix(p, maps, s, g, rings, x0)
+    v = (sb * np.ones_like(x0)).ravel()
+    ev = np.linalg.eigvalsh(v[:, None] * A * v[None, :])
+    r = res1["ritz"]
+    assert r.size > 0 and ev[0] * (1 - 1e-9) <= r.min() and r.max() <= ev[-1] * (1 + 1e-9)
+    assert abs(r.max() - ev[-1]) <= 1e-6 * ev[-1]
+
+
 # --- Turkel-Zwas variant (Sec. 7 discrete U, V, H with p, q, alpha) ---------
 TZ_VARIANTS = [(1, 1, 0.0), (2, 2, 0.5), (2, 1, 0.0), (1, 2, 1.0), (3, 2, 0.25)]
 
