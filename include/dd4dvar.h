@@ -367,6 +367,11 @@ typedef struct {
   int32_t cg_max_iter;  /* CG iterations per Gauss-Newton update (>= 0) */
   double cg_rtol;       /* CG stop at |r| <= cg_rtol |r0| (also stops when the
                            curvature p^T A p is not positive) */
+  int32_t krylov;       /* solver of the Gauss-Newton normal equations: 0 = CG,
+                           1 = Lanczos (Alg. 7): the same caps and stop tests,
+                           the CG iterates in exact arithmetic; keeps its basis
+                           (cg_max_iter vectors of the control length, FP64)
+                           and reports Ritz values; needs local_solver = 1 */
 } dd4dvar_solve_opts;
 
 typedef struct {
@@ -377,14 +382,20 @@ typedef struct {
   double J_final;            /* sum over subdomains of the final local J */
   double gnorm_ratio_max;    /* max_s |g_s| / |g_s,0| at the end */
   double seconds;
+  double ritz_min, ritz_max; /* Lanczos: smallest and largest Ritz value of the
+                                preconditioned normal matrices over the
+                                subdomains' last runs (0 otherwise) */
 } dd4dvar_solve_report;
 
 /* Runs Alg. 1 from x_init_dev (packed controls, NULL = background): batched
- * local solves (L-BFGS, or Gauss-Newton with conjugate gradients, see
- * local_solver) over all subdomains in xi = (x - x^b_s) / sigma_b, then forward,
- * exchange and the outer stop test; finally the partition-of-unity gather of
- * level 0 into xa_host [3][nlat][nlon].  x_out_dev (nullable) receives the
- * final packed controls.  Synchronous.  E_NOTCONVERGED when max_outer was
+ * local solves (L-BFGS, or Gauss-Newton with CG or Lanczos, see local_solver
+ * and krylov) over all subdomains in xi = (x - x^b_s) / sigma_b, then
+ * forward, exchange and the outer stop test; finally the partition-of-unity
+ * gather of level 0 into xa_host [3][nlat][nlon].  From NULL the halo rings
+ * and overlap targets are first reset to those of the background run; from
+ * given controls the solve continues with the rings and targets of the last
+ * exchange (or the background, before any).  x_out_dev (nullable) receives
+ * the final packed controls.  Synchronous.  E_NOTCONVERGED when max_outer was
  * reached without meeting outer_tol (outputs are written). */
 dd4dvar_status dd4dvar_solve(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* opts,
                              const double* x_init_dev, double* x_out_dev,

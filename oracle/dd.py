@@ -71,7 +71,8 @@ def solve(prob, maps=None, max_outer=5, outer_tol=1e-6, lbfgs_m=8, max_iter=50,
           cg_max_iter=50, cg_rtol=1e-6, krylov="cg"):
     """Alg. 1.  ``local_solver`` "lbfgs" (the default) or "gn": Gauss-Newton
     (Alg. 5 / Alg. 6, see ``gn``) with ``max_iter`` updates per local solve and
-    conjugate gradients of at most ``cg_max_iter`` iterations."""
+    ``krylov`` "cg" (conjugate gradients) or "lanczos" (Alg. 7) runs of at most
+    ``cg_max_iter`` products."""
     if maps is None:
         maps = ddm.build(prob)
     bg, trajs = background(prob, maps)
@@ -80,6 +81,7 @@ def solve(prob, maps=None, max_outer=5, outer_tol=1e-6, lbfgs_m=8, max_iter=50,
     rings, targets = exchange(maps, trajs)
     sb = prob.sigma_b[:, None, None]
     report = dict(outer=0, evals=0, history=[])
+    ritz_last = {}     # per subdomain: extreme Ritz values of its last Lanczos run
     for outer in range(1, max_outer + 1):
         new_xs = {}
         step = 0.0
@@ -101,6 +103,8 @@ def solve(prob, maps=None, max_outer=5, outer_tol=1e-6, lbfgs_m=8, max_iter=50,
                                   krylov=krylov)
                 res["x"] = res["xi"].ravel()
                 report["cg_iters"] = report.get("cg_iters", 0) + res["cg_iters"]
+                if res["ritz"].size:
+                    ritz_last[s] = (float(res["ritz"].min()), float(res["ritz"].max()))
             else:
                 res = lbfgs.minimize(fun, xi0, m=lbfgs_m, max_iter=max_iter,
                                      grad_rtol=grad_rtol, c1=c1, max_ls=max_ls)
@@ -117,4 +121,7 @@ def solve(prob, maps=None, max_outer=5, outer_tol=1e-6, lbfgs_m=8, max_iter=50,
         if step < outer_tol:
             break
     xa = gather(prob, maps, trajs, 0)
+    if ritz_last:
+        report["ritz_min"] = min(v[0] for v in ritz_last.values())
+        report["ritz_max"] = max(v[1] for v in ritz_last.values())
     return xa, dict(report, controls=xs, trajs=trajs, background=bg)

@@ -196,6 +196,7 @@ def minimize(prob, maps, s, x0, xb, ring, nbr_trajs, max_iter=5, grad_rtol=0.0,
     hist = [J]
     it = 0
     cg_total = 0
+    ritz = np.zeros(0)     # Ritz values of the last Lanczos run with a product
     status = "max_iter"
     while it < max_iter:
         if gn <= grad_rtol * g0:
@@ -208,10 +209,10 @@ def minimize(prob, maps, s, x0, xb, ring, nbr_trajs, max_iter=5, grad_rtol=0.0,
 
         if krylov == "lanczos":
             xi, k, al, be = lanczos(apply, -(sb * gr).ravel(), cg_max_iter, cg_rtol)
-            ritz = ritz_values(al, be) if k else np.zeros(0)
+            if k:
+                ritz = ritz_values(al, be)
         else:
             xi, k = cg(apply, -(sb * gr).ravel(), cg_max_iter, cg_rtol)
-            ritz = np.zeros(0)
         cg_total += k
         xi_it = xi_it + xi.reshape(x.shape)
         x = xb + sb * xi_it
@@ -220,4 +221,4 @@ def minimize(prob, maps, s, x0, xb, ring, nbr_trajs, max_iter=5, grad_rtol=0.0,
         hist.append(J)
         it += 1
     return dict(x=x, xi=xi_it, J=J, grad=gr, iters=it, cg_iters=cg_total, nfev=it + 1, status=status,
-                history=hist, g0norm=g0, gnorm=gn, ritz=ritz if it else np.zeros(0))
+                history=hist, g0norm=g0, gnorm=gn, ritz=ritz)

@@ -56,13 +56,15 @@ class dd4dvar_solve_opts(C.Structure):
     _fields_ = [("lbfgs_m", C.c_int32), ("max_iter", C.c_int32), ("max_outer", C.c_int32),
                 ("max_ls", C.c_int32), ("grad_rtol", C.c_double), ("outer_tol", C.c_double),
                 ("armijo_c1", C.c_double), ("j_noise_rtol", C.c_double),
-                ("local_solver", C.c_int32), ("cg_max_iter", C.c_int32), ("cg_rtol", C.c_double)]
+                ("local_solver", C.c_int32), ("cg_max_iter", C.c_int32), ("cg_rtol", C.c_double),
+                ("krylov", C.c_int32)]
 
 
 class dd4dvar_solve_report(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("total_evals", C.c_int32),
                 ("lbfgs_iters", C.c_int32), ("gn_products", C.c_int32), ("J_final", C.c_double),
-                ("gnorm_ratio_max", C.c_double), ("seconds", C.c_double)]
+                ("gnorm_ratio_max", C.c_double), ("seconds", C.c_double),
+                ("ritz_min", C.c_double), ("ritz_max", C.c_double)]
 
 
 class dd4dvar_tune_report(C.Structure):

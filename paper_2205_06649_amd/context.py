@@ -157,14 +157,17 @@ class Context:
     J_NOISE_RTOL = {"fp64": 0.0, "fp32": 1e-6}
 
     LOCAL_SOLVERS = {"lbfgs": 0, "gn": 1}
+    KRYLOV = {"cg": 0, "lanczos": 1}
 
     def solve(self, lbfgs_m=8, max_iter=50, max_outer=5, max_ls=30, grad_rtol=0.0,
               outer_tol=1e-6, armijo_c1=1e-4, x_init=None, want_controls=False,
               j_noise_rtol=None, local_solver="lbfgs", cg_max_iter=50, cg_rtol=1e-6,
-              products=None):
+              products=None, krylov="cg"):
         """Alg. 1.  products: an FP32-state Context of the same problem whose
         sweeps supply the Gauss-Newton normal-matrix products while this
-        (FP64) context evaluates J and the gradients (dd4dvar_solve_mixed)."""
+        (FP64) context evaluates J and the gradients (dd4dvar_solve_mixed).
+        krylov: "cg" or "lanczos" (Alg. 7) for the Gauss-Newton normal
+        equations; the report carries the Lanczos runs' extreme Ritz values."""
         p = self.prob
         if j_noise_rtol is None:
             j_noise_rtol = self.J_NOISE_RTOL[self.precision]
@@ -172,7 +175,8 @@ class Context:
                                     max_ls=max_ls, grad_rtol=grad_rtol, outer_tol=outer_tol,
                                     armijo_c1=armijo_c1, j_noise_rtol=j_noise_rtol,
                                     local_solver=self.LOCAL_SOLVERS[local_solver],
-                                    cg_max_iter=cg_max_iter, cg_rtol=cg_rtol)
+                                    cg_max_iter=cg_max_iter, cg_rtol=cg_rtol,
+                                    krylov=self.KRYLOV[krylov])
         xa = np.empty((3, p.nlat, p.nlon))
         xo = self.empty(self.ctrl_len) if want_controls else None
         if products is None:

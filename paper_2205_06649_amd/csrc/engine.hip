@@ -1361,6 +1361,21 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
     G.gn_on = B.get<uint8_t>(nsub);
     G.cg_on = B.get<uint8_t>(nsub);
     G.pending = L.pending;
+    G.krylov = o->krylov;
+    if (o->krylov == 1) {
+      // Lanczos basis (cg_max_iter vectors) and per-subdomain coefficients
+      const size_t K = size_t(std::max(o->cg_max_iter, 1));
+      G.lv = B.get<double>(K * size_t(N));
+      G.la = B.get<double>(size_t(nsub) * (K + 1));
+      G.lb = B.get<double>(size_t(nsub) * (K + 1));
+      G.ly = B.get<double>(size_t(nsub) * (K + 1));
+      G.ld = B.get<double>(size_t(nsub) * (K + 1));
+      G.lz = B.get<double>(size_t(nsub) * (K + 1));
+      G.ritz_lo = B.get<double>(nsub);
+      G.ritz_hi = B.get<double>(nsub);
+      launch_fill(G.ritz_lo, nsub, 0.0, st);
+      launch_fill(G.ritz_hi, nsub, 0.0, st);
+    }
   }
   double* xa_dev = B.get<double>(size_t(3) * c->plan.model.nlat * c->plan.model.nlon);
 
@@ -1372,8 +1387,15 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
     }
   } reset{c, lo};
 
-  if (x_init) lb_from_x(L, x_init, st);
-  else launch_fill(L.xi, N, 0.0, st);
+  if (x_init) {
+    lb_from_x(L, x_init, st);
+  } else {
+    // Alg. 1 from the background: halo rings and overlap targets of the
+    // background run, whatever an earlier solve left in them
+    background_impl<T>(c, st);
+    if (lo) background_impl<float>(lo, st);
+    launch_fill(L.xi, N, 0.0, st);
+  }
   int evals = 0, outer = 0, lbfgs_iters = 0, products = 0;
   bool met = false;
   std::vector<int32_t> iters_h(nsub);
@@ -1398,7 +1420,8 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
           local_forward<float>(lo, L.xphys, st);
           lo->eval_mask = nullptr;
         }
-        gn_cg_start(G, st);
+        if (G.krylov == 1) gn_lz_start(G, st);
+        else gn_cg_start(G, st);
         for (;;) {
           chk(hipMemsetAsync(L.pending, 0, sizeof(int32_t), st), "memset");
           gn_cg_count(G, st);
@@ -1414,8 +1437,10 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
             c->eval_mask = nullptr;
           }
           ++products;
-          gn_cg_update(G, st);
+          if (G.krylov == 1) gn_lz_update(G, st);
+          else gn_cg_update(G, st);
         }
+        if (G.krylov == 1) gn_lz_finish(G, st);
         gn_update(G, st);
         lb_to_x(L, 0, 0, st);
         c->eval_mask = G.gn_on;
@@ -1480,6 +1505,11 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
   chk(hipMemcpyAsync(J.data(), L.J, nsub * sizeof(double), hipMemcpyDeviceToHost, st), "read J");
   chk(hipMemcpyAsync(gn.data(), L.gnorm, nsub * sizeof(double), hipMemcpyDeviceToHost, st), "read g");
   chk(hipMemcpyAsync(g0.data(), L.g0norm, nsub * sizeof(double), hipMemcpyDeviceToHost, st), "read g0");
+  std::vector<double> rlo(nsub, 0.0), rhi(nsub, 0.0);
+  if (use_gn && G.krylov == 1) {
+    chk(hipMemcpyAsync(rlo.data(), G.ritz_lo, nsub * sizeof(double), hipMemcpyDeviceToHost, st), "read ritz");
+    chk(hipMemcpyAsync(rhi.data(), G.ritz_hi, nsub * sizeof(double), hipMemcpyDeviceToHost, st), "read ritz");
+  }
   chk(hipStreamSynchronize(st), "sync");
   if (rep) {
     rep->outer_iters = outer;
@@ -1493,6 +1523,17 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
     }
     rep->J_final = js;
     rep->gnorm_ratio_max = ratio;
+    // extreme Ritz values over the subdomains' last Lanczos runs
+    double rmin = 0, rmax = 0;
+    bool any = false;
+    for (int s = 0; s < nsub; ++s) {
+      if (!(rhi[s] > 0)) continue;
+      rmin = any ? std::min(rmin, rlo[s]) : rlo[s];
+      rmax = any ? std::max(rmax, rhi[s]) : rhi[s];
+      any = true;
+    }
+    rep->ritz_min = rmin;
+    rep->ritz_max = rmax;
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   if (!met) {
@@ -1510,6 +1551,7 @@ dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* o, const d
       o->max_ls < 1 || !(o->grad_rtol >= 0) || !(o->outer_tol >= 0) || !(o->armijo_c1 > 0) ||
       !(o->armijo_c1 < 1) || !(o->j_noise_rtol >= 0) || !std::isfinite(o->j_noise_rtol) ||
       o->local_solver < 0 || o->local_solver > 1 || o->cg_max_iter < 0 || !(o->cg_rtol >= 0) ||
+      o->krylov < 0 || o->krylov > 1 || (o->krylov == 1 && o->local_solver != 1) ||
       !std::isfinite(o->cg_rtol)) {
     ctx->err = "bad solve options";
     return DD4DVAR_E_INVALID;

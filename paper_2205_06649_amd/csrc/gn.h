@@ -24,6 +24,14 @@ struct GnState {
   int32_t *status, *iters, *cg_k, *cg_total;
   uint8_t *gn_on, *cg_on;   // evaluation masks: in the GN loop, in CG
   int32_t* pending;         // device counter
+  // Lanczos (krylov = 1): basis vectors V[j] at lv + j N (j < cg_max_iter),
+  // per subdomain the recurrence coefficients la[j] (diagonal of T) and
+  // lb[j] (lb[0] = |r_0|, lb[j] couples V[j-1] and V[j]), the coefficients
+  // y of x = sum_j y_j V[j] (stride cg_max_iter + 1) and the extreme Ritz
+  // values of the last run with at least one product
+  int krylov;
+  double *lv, *la, *lb, *ly, *ritz_lo, *ritz_hi;
+  double *ld, *lz;          // per-subdomain scratch of the L D L^T solve
 };
 
 void gn_to_x(const GnState& G, hipStream_t st);
@@ -34,6 +42,9 @@ void gn_cg_start(const GnState& G, hipStream_t st);
 void gn_cg_count(const GnState& G, hipStream_t st);
 void gn_cg_dir(const GnState& G, hipStream_t st);
 void gn_cg_update(const GnState& G, hipStream_t st);
+void gn_lz_start(const GnState& G, hipStream_t st);
+void gn_lz_update(const GnState& G, hipStream_t st);
+void gn_lz_finish(const GnState& G, hipStream_t st);
 void gn_update(const GnState& G, hipStream_t st);
 void gn_after(const GnState& G, hipStream_t st);
 void gn_step(const GnState& G, hipStream_t st);

@@ -172,6 +172,63 @@ def test_gn_solve_matches_oracle(which, opts):
     ctx.close()
 
 
+@pytest.mark.parametrize("which,opts", [
+    ("tiny2", dict(max_outer=2, max_iter=2, cg_max_iter=30)),
+    ("c1", dict(max_outer=1, max_iter=2, cg_max_iter=20)),
+])
+def test_gn_lanczos_solve_matches_oracle(which, opts):
+    """Gauss-Newton local solves whose normal equations are solved by the
+    Lanczos method (Alg. 7), FP64, against the oracle's: analysis and local
+    controls, product counts, the extreme Ritz values of the local
+    preconditioned normal matrices; and against the device CG solve."""
+    from paper_2205_06649_amd import _lib as L
+    p, maps, bg, trajs, rings = _oracle_state(which)
+    kw = dict(outer_tol=0.0, local_solver="gn", cg_rtol=0.0, **opts)
+    xa_ref, rep_ref = dd.solve(p, maps, krylov="lanczos", **kw)
+    ctx = _ctx(which, "fp64")
+    xa, rep, st, xo = ctx.solve(krylov="lanczos", want_controls=True, **kw)
+    sb = p.sigma_b[:, None, None]
+    inc = np.linalg.norm((xa_ref - p.xb0) / sb)
+    assert np.linalg.norm((xa - xa_ref) / sb) <= 1e-8 * inc
+    xs = ctx.unpack_ctrl(xo)
+    for b in maps.boxes:
+        ref = rep_ref["controls"][b.sub]
+        d = _rel((xs[b.sub] - trajs[b.sub][0]) / sb, (ref - trajs[b.sub][0]) / sb)
+        assert d <= 1e-8, (b.sub, d)
+    assert rep.gn_products == opts["max_outer"] * opts["max_iter"] * opts["cg_max_iter"]
+    rmax = rep_ref["ritz_max"]
+    print(f"{which}: Ritz values {rep.ritz_min:.6e} .. {rep.ritz_max:.6e} "
+          f"(oracle {rep_ref['ritz_min']:.6e} .. {rmax:.6e})", flush=True)
+    assert 0.0 < rep.ritz_min <= rep.ritz_max
+    assert abs(rep.ritz_max - rmax) <= 1e-6 * rmax
+    assert abs(rep.ritz_min - rep_ref["ritz_min"]) <= 1e-6 * rmax
+    xc, repc, _, _ = ctx.solve(**kw)
+    assert repc.ritz_min == 0.0 and repc.ritz_max == 0.0
+    assert np.linalg.norm((xa - xc) / sb) <= 1e-6 * inc
+    with pytest.raises(L.DD4DVarError) as e:
+        ctx.solve(max_outer=1, max_iter=1, krylov="lanczos")
+    assert e.value.status == L.DD4DVAR_E_INVALID
+    ctx.close()
+
+
+def test_gn_lanczos_fp32_products():
+    """Lanczos with FP32 state sweeps (persistent kernels) against the FP64
+    Lanczos solve: analysis within the FP32 bar."""
+    opts = dict(max_outer=2, max_iter=3, cg_max_iter=30, cg_rtol=1e-8, outer_tol=0.0,
+                local_solver="gn", krylov="lanczos")
+    res = {}
+    for pr in ("fp64", "fp32-box"):
+        ctx = _ctx("c2", pr)
+        xa, rep, st, _ = ctx.solve(**opts)
+        res[pr] = (xa, rep.ritz_max)
+        ctx.close()
+    ref = res["fp64"][0]
+    err = max(np.linalg.norm(res["fp32-box"][0][f] - ref[f]) / np.linalg.norm(ref[f] - ref[f].mean())
+              for f in range(3))
+    assert err <= 1e-4, err
+    assert abs(res["fp32-box"][1] - res["fp64"][1]) <= 1e-3 * res["fp64"][1]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp32-box"])
 def test_gn_solve_fp32_against_fp64(prec):
     """FP32 state sweeps (step kernels, or the persistent per-box kernels)
