@@ -324,8 +324,31 @@ def gn_leg(prob, x, mode, passes, config, reps=10, solves=True):
     ctx32.close()
     del ctx64, ctx32
     torch.cuda.empty_cache()
+    # the Lanczos solver of the normal equations (Alg. 7), FP32 sweeps: same
+    # products as CG, and the extreme Ritz values of the local preconditioned
+    # normal matrices
+    ctx = Context(prob, "fp32")
+    ctx.set_exec_mode(mode)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    a, rep, st, _ = ctx.solve(local_solver="gn", krylov="lanczos", **GN_OPTS)
+    sec = time.perf_counter() - t
+    xa["lanczos_fp32"] = a
+    out["lanczos_fp32"] = {"seconds": sec, "evaluations": int(rep.total_evals),
+                           "gn_iters": int(rep.lbfgs_iters), "products": int(rep.gn_products),
+                           "J_final": float(rep.J_final),
+                           "gnorm_ratio_max": float(rep.gnorm_ratio_max),
+                           "ritz_min": float(rep.ritz_min), "ritz_max": float(rep.ritz_max)}
+    log(f"fp32 gauss-newton solve with lanczos: {sec:.2f} s, {rep.gn_products} products, "
+        f"Ritz values {rep.ritz_min:.3e} .. {rep.ritz_max:.3e}")
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
     ref = xa["fp64"]
-    for k in ("fp32", "mixed"):
+    out["lanczos_fp32_vs_cg_fp32_rel_err"] = float(max(
+        np.linalg.norm(xa["lanczos_fp32"][f] - xa["fp32"][f]) / np.linalg.norm(ref[f] - ref[f].mean())
+        for f in range(3)))
+    for k in ("fp32", "mixed", "lanczos_fp32"):
         out[f"{k}_analysis_rel_err"] = float(max(
             np.linalg.norm(xa[k][f] - ref[f]) / np.linalg.norm(ref[f] - ref[f].mean())
             for f in range(3)))
@@ -335,40 +358,6 @@ def gn_leg(prob, x, mode, passes, config, reps=10, solves=True):
 
 
 TZ_VARIANT = (2, 2, 0.5)
-
-
-def tz_bytes(ctx, prec_bytes):
-    """Compulsory HBM bytes of one Turkel-Zwas evaluation (step kernels).
-
-    Forward as the plain step kernels.  Adjoint at level n: the scatter
-    launch reads Z^n and lambda^{n+1} and writes one value of each of the 13
-    offsets' slot planes (for n < L); the gather launch reads the 13 slot
-    values that reach the cell, lambda^{n+1} and lambda^{n+2} where they
-    exist, Z^n, the overlap target where covered and the coverage byte, and
-    writes lambda^n (level 0: FP64 control and background read, FP64
-    gradient written); 20 B per observation.
-    """
-    from paper_2205_06649_amd import _lib as L
-    b3 = 3 * prec_bytes
-    tcount = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_TIME_COUNT, 0)
-    fwd = adj = 0.0
-    for s, inf in enumerate(ctx.info):
-        ncell, lev0, nlev = int(inf[1]) * int(inf[3]), int(inf[4]), int(inf[5])
-        L_ = nlev - 1
-        cover = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_COVER, s).astype(np.int64)
-        nobs = L.dd4dvar_plan_get_map(ctx.plan, L.MAP_OBS_BIN, s).size
-        fwd += ncell * (24 + b3)
-        for n in range(L_):
-            fwd += ncell * b3 * (3 if n >= 1 else 2)
-        for n in range(L_, -1, -1):
-            has1, has2 = n + 1 <= L_, n + 2 <= L_
-            if has1:
-                adj += ncell * b3 * 15
-            nvec = 13 * has1 + has1 + has2 + 1 + (n > 0)
-            covered = int(np.count_nonzero(cover * tcount[lev0 + n] - 1 > 0))
-            adj += ncell * (nvec * b3 + 1) + covered * b3 + (ncell * 72 if n == 0 else 0)
-        adj += nobs * 20
-    return fwd, adj
 
 
 def tz_leg(spec, reps=5):
@@ -409,7 +398,9 @@ def tz_leg(spec, reps=5):
             ctx.cost_grad(x, J, g)
         t = ctx.get_timing()
         ctx.set_timing(False)
-        fwd_b, adj_b = tz_bytes(ctx, b)
+        # compulsory bytes as for the plain step kernels: the 13-point
+        # neighbourhoods are re-reads of the same levels through the caches
+        fwd_b, adj_b, _ = algorithmic_bytes(ctx, b)
         fwd_ms, adj_ms = t["fwd_ms"] / t["calls"], t["adj_ms"] / t["calls"]
         pts = sum(int(i[1]) * int(i[3]) * (int(i[5]) - 1) for i in ctx.info)
         res[prec] = (J.cpu().numpy(), g.cpu().numpy())

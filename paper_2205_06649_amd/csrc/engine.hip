@@ -76,11 +76,9 @@ struct dd4dvar_ctx {
   int box_kmin = 0;                     // passes that hold the largest box
   bool box_span = false;                // some box spans the circle
   int strip_k = 0;                      // rows per column strip of the strip adjoint (0: n/a)
-  // Turkel-Zwas variant (tz_p > 0): step kernels only, with the slot arena
-  // of their two-phase adjoint
+  // Turkel-Zwas variant (tz_p > 0): step kernels only
   int tz_p = 0, tz_q = 1;
   double tz_alpha = 0;
-  void* tz_slots = nullptr;
   // state storage: every level (ckpt = 0), or checkpoint pairs every ckpt
   // levels plus one segment that the adjoint recomputes
   int ckpt = 0;
@@ -255,7 +253,7 @@ void adj_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int n
   if (c->tz_p > 0) {
     if (mode == 3) throw DevError{DD4DVAR_E_INVALID, "no Gauss-Newton adjoint for the Turkel-Zwas variant"};
     launch_adj_tz<T>(D, n, tile_base, ntiles, mode, c->tz_p, c->tz_q, c->tz_alpha,
-                     c->plan.model.nlat, static_cast<T*>(c->tz_slots), x, c->xb, forcing, out, st);
+                     c->plan.model.nlat, x, c->xb, forcing, out, st);
   } else {
     launch_adj<T>(D, n, tile_base, ntiles, mode, x, c->xb, forcing, out, st);
   }
@@ -779,7 +777,6 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
     c->tz_p = P.model.tz_p;
     c->tz_q = P.model.tz_q;
     c->tz_alpha = P.model.tz_alpha;
-    c->tz_slots = dalloc<char>(c, size_t(P.ctrl_total) * tz_slot_planes() * tsz);
   }
   chk(hipMemsetAsync(c->ring, 0, size_t(std::max<int64_t>(ring_off, 1)) * tsz, st), "memset ring");
   chk(hipMemsetAsync(c->targ, 0, size_t(P.traj_total) * tsz, st), "memset targets");

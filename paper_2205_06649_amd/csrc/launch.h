@@ -50,15 +50,13 @@ template <typename T>
 void launch_dz_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hipStream_t st);
 
 // tz.hip: Turkel-Zwas step kernels (boxes with frozen pads q rows and p
-// columns wide); the adjoint uses a slot arena of tz_slot_planes() x 3 x
-// (cells of every box) values
-constexpr int tz_slot_planes() { return 21; }
+// columns wide)
 template <typename T>
 void launch_fwd_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
                    int nlat, hipStream_t st);
 template <typename T>
 void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, int p, int q,
-                   double alpha, int nlat, T* slots, const double* x, const double* xb,
+                   double alpha, int nlat, const double* x, const double* xb,
                    const double* forcing, double* out, hipStream_t st);
 
 // box.hip: persistent per-box sweeps (FP32 state)

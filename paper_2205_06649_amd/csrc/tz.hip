@@ -19,16 +19,15 @@
 // onto itself, the south and north blocks over columns 0..nx-1, and a point
 // beyond a pole that maps into the box itself is read there (u, v negated).
 //
-// Adjoint, deterministic and without atomics: for every cell k a first
-// kernel writes the transposed contribution of its increment to each of the
-// in-box points it reads (the partial derivatives of the increment at k with
-// respect to the state there, applied to lambda^{n+1}(k)) into one slot
-// plane per offset; frozen points get nothing.  For a given offset the map
-// from k to the point read is one-to-one, except that a row near a pole may
-// be reached both directly and across the pole, so contributions that cross a
-// pole go to separate planes.  A second kernel sums, for every cell, the
-// planes that some in-box cell's offset reaches there, in a fixed order, and
-// adds the forcing and lambda^{n+2} (gather form of the same transpose).
+// Adjoint (adjoint definition of Sec. 2, eq. adjProd), gather form, one
+// launch per level: every cell x sums the transposed contributions of the
+// in-box cells k whose increment reads it, the partial derivative of the
+// increment at k with respect to the state at x applied to lambda^{n+1}(k),
+// evaluated from k's state, lambda and row coefficients: the cell itself
+// (its whole 13-point neighbourhood), the readers k = x - offset of the other
+// 12 offsets, and in a box spanning the circle the readers whose offset
+// reaches x across a pole (u, v components negated).  Frozen pad values get
+// nothing.  The sum runs in a fixed order (deterministic, no atomics).
 #include "kernels.h"
 #include "launch.h"
 #include "stencil.h"
@@ -42,11 +41,8 @@ namespace dd4dvar {
 using namespace stencil;
 
 namespace {
-// offsets: the cell, E1, W1, N1, S1, Ep, Wp, Nq, Sq, EpNq, WpNq, EpSq, WpSq;
-// planes 13.. hold the across-pole contributions of N1, S1, Nq, Sq and the
-// four corners
+// offsets: the cell, E1, W1, N1, S1, Ep, Wp, Nq, Sq, EpNq, WpNq, EpSq, WpSq
 constexpr int kOffs = 13;
-constexpr int kPlanes = tz_slot_planes();
 
 struct Pt {
   int idx;      // cell of the box, or position in the frozen pad
@@ -56,7 +52,7 @@ struct Pt {
   bool across;  // in-box point reached across a pole
 };
 
-// row offset and column offset of each of the 13 points, in slot-plane order
+// row offset and column offset of each of the 13 points
 __device__ __forceinline__ int off_r(int o, int q) {
   return o == 3 ? 1 : o == 4 ? -1 : (o == 7 || o == 9 || o == 10) ? q : (o == 8 || o == 11 || o == 12) ? -q : 0;
 }
@@ -118,18 +114,11 @@ __device__ __forceinline__ V3<T> ld_pt(const T* Z, const T* R, int64_t plane, in
   return {base[P.idx], s * base[st + P.idx], s * base[2 * st + P.idx]};
 }
 
-// the 13 points of cell (r, c), in slot-plane order
+// the 13 points of cell (r, c)
 __device__ __forceinline__ void points(const SubDev& S, int r, int c, int p, int q, int half,
                                        int nlat, Pt* P) {
 #pragma unroll
   for (int o = 0; o < kOffs; ++o) P[o] = point(S, r, c, off_r(o, q), off_c(o, p), p, q, half, nlat);
-}
-
-// across-pole plane of offset o (o = 3, 4, 7 .. 12), else -1
-__device__ __forceinline__ int across_plane(int o) {
-  if (o == 3 || o == 4) return 13 + (o - 3);
-  if (o >= 7) return 15 + (o - 7);
-  return -1;
 }
 
 template <typename T>
@@ -202,89 +191,52 @@ __global__ __launch_bounds__(kTile) void k_fwd_tz(Dom<T> D, int n, int tile_base
   out[2 * plane + m] = B.v + wgt * V;
 }
 
-// first adjoint kernel: the transposed contributions of cell k's increment
-// at level n applied to lambda^{n+1}(k), one slot plane per offset
+// transposed contribution of reader k through offset o (1 .. 12) to the
+// point x it reads there: lk = lambda^{n+1}(k), hk, uk, vk its state (h as
+// the anomaly), K its row coefficients, X those of x's row, ux, vx the
+// values k reads at x (sign applied across a pole)
 template <typename T>
-__global__ __launch_bounds__(kTile) void k_adj_tz_scatter(Dom<T> D, int n, int tile_base, int p,
-                                                          int q, T alpha, int nlat,
-                                                          T* __restrict__ slots) {
-  const int2 wt = D.tiles[tile_base + xcd_tile(blockIdx.x, gridDim.x)];
-  if (D.active && !D.active[wt.x]) return;
-  const SubDev S = D.subs[wt.x];
-  if (n + 1 > S.nlev - 1) return;
-  const int m = wt.y * kTile + threadIdx.x;
-  if (m >= S.ncell) return;
-  const int r = m / S.nx, c = m - r * S.nx;
-  const int64_t plane = S.ncell;
-  const T* Z = zlevel(D, S, n);
-  const T* L1 = D.adj + S.adj_off + int64_t((n + 1) % 3) * 3 * plane;
-  const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
-  Pt P[kOffs];
-  points(S, r, c, p, q, D.half, nlat, P);
-  const State13<T> z = load13(Z, R, plane, S.nring, P);
-  const V3<T> lam = ld_box(L1, plane, m, T(1));
-  const RowCoef<T> rc = D.rows[S.row0 + r];
-  const RowCoef<T> rN = D.rows[P[7].grow], rS = D.rows[P[8].grow];
-  const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
-  const T tp = T(p), tq = T(q);
-  const V3<T>& C = z.C;
-  const T hh = h0 + C.h;
-  const T lH = lam.h, lU = lam.u, lV = lam.v;
-  const T Dl = ((one - al) * (z.Ep.u - z.Wp.u) + half * al * (z.EN.u - z.WN.u + z.ES.u - z.WS.u)) / tp;
-  const T Dt = ((one - al) * (z.Nq.v * rN.c - z.Sq.v * rS.c) + half * al * (z.EN.v * rN.c - z.ES.v * rS.c) +
-                half * al * (z.WN.v * rN.c - z.WS.v * rS.c)) / tq;
-  const T a1u = rc.a1 * C.u, stv = st * C.v;
-  const T dn = half * al * rc.a1 * hh / tp;          // corner weight of u in H
-  const T cqN = rc.a3 * hh * rN.c / tq, cqS = rc.a3 * hh * rS.c / tq;
-  V3<T> g[kOffs];
-  // the cell itself
-  g[0].h = -lH * (rc.a1 * Dl + rc.a3 * Dt);
-  g[0].u = lU * (-rc.a1 * (z.E.u - z.W.u) + (one - al) * rc.ct * C.v) +
-           lV * (-rc.a1 * (z.E.v - z.W.v) - (one - al) * (rc.cf + T(2) * rc.ct * C.u)) -
-           lH * rc.a1 * (z.E.h - z.W.h);
-  g[0].v = lU * (-st * (z.N.u - z.Sv.u) + (one - al) * (rc.cf + rc.ct * C.u)) - lV * st * (z.N.v - z.Sv.v) -
-           lH * st * (z.N.h - z.Sv.h);
-  // advection neighbours (offset one)
-  g[1] = {-lH * a1u, -lU * a1u, -lV * a1u};
-  g[2] = {lH * a1u, lU * a1u, lV * a1u};
-  g[3] = {-lH * stv, -lU * stv, -lV * stv};
-  g[4] = {lH * stv, lU * stv, lV * stv};
-  // (i +- p, j): pressure gradient and averaged Coriolis of U, divergence of H
-  g[5] = {-lU * rc.a2 / tp, lU * half * al * rc.ct * z.Ep.v - lH * (one - al) * rc.a1 * hh / tp,
-          lU * half * al * (rc.cf + rc.ct * z.Ep.u)};
-  g[6] = {lU * rc.a2 / tp, lU * half * al * rc.ct * z.Wp.v + lH * (one - al) * rc.a1 * hh / tp,
-          lU * half * al * (rc.cf + rc.ct * z.Wp.u)};
-  // (i, j +- q): pressure gradient and averaged Coriolis of V, divergence of H
-  g[7] = {-lV * stg / tq, -lV * half * al * (rN.cf + T(2) * rN.ct * z.Nq.u), -lH * (one - al) * cqN};
-  g[8] = {lV * stg / tq, -lV * half * al * (rS.cf + T(2) * rS.ct * z.Sq.u), lH * (one - al) * cqS};
-  // corners: the averaged divergence of H
-  g[9] = {T(0), -lH * dn, -lH * half * al * cqN};
-  g[10] = {T(0), lH * dn, -lH * half * al * cqN};
-  g[11] = {T(0), -lH * dn, lH * half * al * cqS};
-  g[12] = {T(0), lH * dn, lH * half * al * cqS};
-  T* base = slots + S.ctrl_off * kPlanes;
-#pragma unroll
-  for (int o = 0; o < kOffs; ++o) {
-    if (P[o].pad) continue;                  // frozen: not part of the local model
-    const int pl = P[o].across ? across_plane(o) : o;
-    const T sg = T(P[o].sg);
-    T* sp = base + int64_t(pl) * 3 * plane;
-    sp[P[o].idx] = g[o].h;
-    sp[plane + P[o].idx] = sg * g[o].u;
-    sp[2 * plane + P[o].idx] = sg * g[o].v;
+__device__ __forceinline__ V3<T> reader_term(int o, const V3<T>& lk, T hk, T uk, T vk,
+                                             const RowCoef<T>& K, const RowCoef<T>& X, T ux,
+                                             T vx, T st, T stg, T h0, T al, T tp, T tq) {
+  const T one = T(1), half = T(0.5), hh = h0 + hk;
+  switch (o) {
+    case 1: case 2: {
+      const T a = (o == 1 ? -K.a1 : K.a1) * uk;
+      return {lk.h * a, lk.u * a, lk.v * a};
+    }
+    case 3: case 4: {
+      const T a = (o == 3 ? -st : st) * vk;
+      return {lk.h * a, lk.u * a, lk.v * a};
+    }
+    case 5: case 6: {
+      const T sgn = o == 5 ? T(-1) : T(1);
+      return {sgn * lk.u * K.a2 / tp, lk.u * half * al * K.ct * vx + sgn * lk.h * (one - al) * K.a1 * hh / tp,
+              lk.u * half * al * (K.cf + K.ct * ux)};
+    }
+    case 7: case 8: {
+      const T sgn = o == 7 ? T(-1) : T(1);
+      return {sgn * lk.v * stg / tq, -lk.v * half * al * (X.cf + T(2) * X.ct * ux),
+              sgn * lk.h * (one - al) * K.a3 * hh * X.c / tq};
+    }
+    default: {
+      const T dn = half * al * K.a1 * hh / tp, cq = half * al * K.a3 * hh * X.c / tq;
+      const T su = (o == 9 || o == 11) ? T(-1) : T(1), sv = (o == 9 || o == 10) ? T(-1) : T(1);
+      return {T(0), su * lk.h * dn, sv * lk.h * cq};
+    }
   }
 }
 
-// second adjoint kernel: lambda^n (or the gradient) at every cell from the
-// slot planes that reach it, the forcing and lambda^{n+2}
+// lambda^n (or the gradient at level 0) of every cell:
+//   mode 0: cost forcing (observations + overlap), gradient and J at level 0
+//   mode 1: caller forcing (packed FP64, trajectory layout), adj0 at level 0
+//   mode 2: cost forcing, adj0 at level 0 (no background term)
 template <typename T, int MODE>
-__global__ __launch_bounds__(kTile) void k_adj_tz_gather(Dom<T> D, int n, int tile_base, int p,
-                                                         int q, int nlat,
-                                                         const T* __restrict__ slots,
-                                                         const double* __restrict__ x,
-                                                         const double* __restrict__ xb,
-                                                         const double* __restrict__ forcing,
-                                                         double* __restrict__ out) {
+__global__ __launch_bounds__(kTile) void k_adj_tz(Dom<T> D, int n, int tile_base, int p, int q,
+                                                  T alpha, int nlat, const double* __restrict__ x,
+                                                  const double* __restrict__ xb,
+                                                  const double* __restrict__ forcing,
+                                                  double* __restrict__ out) {
   __shared__ double fo[3][kTile];
   __shared__ double red[kTile / 64];
   const int w = tile_base + xcd_tile(blockIdx.x, gridDim.x);
@@ -304,24 +256,50 @@ __global__ __launch_bounds__(kTile) void k_adj_tz_gather(Dom<T> D, int n, int ti
   const T* L2 = A + int64_t((n + 2) % 3) * 3 * plane;
   const int r = mm / S.nx, c = mm - r * S.nx, ny = S.ny;
   double jloc = 0.0;
-  // J_F(Z^n)^T lambda^{n+1}: the planes of the in-box cells whose offset
-  // reaches this cell, directly (the reader is the cell minus the offset) or,
-  // in a box spanning the circle, across a pole (the reader's row lies the
-  // offset's depth from the pole on this side)
+  // J_F(Z^n)^T lambda^{n+1} at this cell
   double ah = 0, au = 0, av = 0;
-  if (has1) {
-    const T* base = slots + S.ctrl_off * kPlanes;
-    const int g = S.row0 + r;
-#pragma unroll
-    for (int o = 0; o < kOffs; ++o) {
-      const int rk = r - off_r(o, q), ck = c - off_c(o, p);
-      if (rk < 0 || rk >= ny || (!S.span && (ck < 0 || ck >= S.nx))) continue;
-      const T* sp = base + int64_t(o) * 3 * plane;
-      ah += double(sp[mm]);
-      au += double(sp[plane + mm]);
-      av += double(sp[2 * plane + mm]);
+  if (has1 && valid) {
+    const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
+    Pt P[kOffs];
+    points(S, r, c, p, q, D.half, nlat, P);
+    const State13<T> z = load13(Z, R, plane, S.nring, P);
+    const V3<T> lam = ld_box(L1, plane, mm, T(1));
+    const RowCoef<T> rc = D.rows[S.row0 + r];
+    const RowCoef<T> rN = D.rows[P[7].grow], rS = D.rows[P[8].grow];
+    const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
+    const T tp = T(p), tq = T(q);
+    const V3<T>& C = z.C;
+    // the cell itself
+    {
+      const T Dl = ((one - al) * (z.Ep.u - z.Wp.u) + half * al * (z.EN.u - z.WN.u + z.ES.u - z.WS.u)) / tp;
+      const T Dt = ((one - al) * (z.Nq.v * rN.c - z.Sq.v * rS.c) + half * al * (z.EN.v * rN.c - z.ES.v * rS.c) +
+                    half * al * (z.WN.v * rN.c - z.WS.v * rS.c)) / tq;
+      ah += double(-lam.h * (rc.a1 * Dl + rc.a3 * Dt));
+      au += double(lam.u * (-rc.a1 * (z.E.u - z.W.u) + (one - al) * rc.ct * C.v) +
+                   lam.v * (-rc.a1 * (z.E.v - z.W.v) - (one - al) * (rc.cf + T(2) * rc.ct * C.u)) -
+                   lam.h * rc.a1 * (z.E.h - z.W.h));
+      av += double(lam.u * (-st * (z.N.u - z.Sv.u) + (one - al) * (rc.cf + rc.ct * C.u)) -
+                   lam.v * st * (z.N.v - z.Sv.v) - lam.h * st * (z.N.h - z.Sv.h));
     }
+    // in-box readers k = x - offset
+#pragma unroll
+    for (int o = 1; o < kOffs; ++o) {
+      const int rk = r - off_r(o, q);
+      int ck = c - off_c(o, p);
+      if (rk < 0 || rk >= ny) continue;
+      if (S.span) ck = ck < 0 ? ck + S.nx : (ck >= S.nx ? ck - S.nx : ck);
+      else if (ck < 0 || ck >= S.nx) continue;
+      const int k = rk * S.nx + ck;
+      const V3<T> lk = ld_box(L1, plane, k, T(1));
+      const V3<T> t = reader_term(o, lk, Z[k], Z[plane + k], Z[2 * plane + k], D.rows[S.row0 + rk], rc,
+                                  C.u, C.v, st, stg, h0, al, tp, tq);
+      ah += double(t.h);
+      au += double(t.u);
+      av += double(t.v);
+    }
+    // readers across a pole (a box spanning the circle): u, v negated
     if (S.span) {
+      const int g = S.row0 + r;
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
         const int o = a < 2 ? 3 + a : 5 + a;   // offsets 3, 4, 7 .. 12
@@ -329,10 +307,15 @@ __global__ __launch_bounds__(kTile) void k_adj_tz_gather(Dom<T> D, int n, int ti
         const int gk = dr > 0 ? 2 * nlat - 1 - dr - g : -dr - 1 - g;
         const bool reach = dr > 0 ? g >= nlat - dr : g <= -dr - 1;
         if (!reach || gk < S.row0 || gk >= S.row0 + ny) continue;
-        const T* sp = base + int64_t(13 + a) * 3 * plane;
-        ah += double(sp[mm]);
-        au += double(sp[plane + mm]);
-        av += double(sp[2 * plane + mm]);
+        int ck = c - off_c(o, p) - D.half;
+        ck = ((ck % S.nx) + S.nx) % S.nx;
+        const int k = (gk - S.row0) * S.nx + ck;
+        const V3<T> lk = ld_box(L1, plane, k, T(1));
+        const V3<T> t = reader_term(o, lk, Z[k], Z[plane + k], Z[2 * plane + k], D.rows[gk], rc,
+                                    -C.u, -C.v, st, stg, h0, al, tp, tq);
+        ah += double(t.h);
+        au -= double(t.u);
+        av -= double(t.v);
       }
     }
   }
@@ -426,25 +409,23 @@ void launch_fwd_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int
 }
 template <typename T>
 void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, int p, int q,
-                   double alpha, int nlat, T* slots, const double* x, const double* xb,
+                   double alpha, int nlat, const double* x, const double* xb,
                    const double* forcing, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_tz_scatter<T>, dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q,
-                     T(alpha), nlat, slots);
   if (mode == 0)
-    hipLaunchKernelGGL((k_adj_tz_gather<T, 0>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p,
-                       q, nlat, slots, x, xb, forcing, out);
+    hipLaunchKernelGGL((k_adj_tz<T, 0>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q,
+                       T(alpha), nlat, x, xb, forcing, out);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_adj_tz_gather<T, 1>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p,
-                       q, nlat, slots, x, xb, forcing, out);
+    hipLaunchKernelGGL((k_adj_tz<T, 1>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q,
+                       T(alpha), nlat, x, xb, forcing, out);
   else
-    hipLaunchKernelGGL((k_adj_tz_gather<T, 2>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p,
-                       q, nlat, slots, x, xb, forcing, out);
+    hipLaunchKernelGGL((k_adj_tz<T, 2>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q,
+                       T(alpha), nlat, x, xb, forcing, out);
 }
 
 #define DD4DVAR_INST(T)                                                                        \
   template void launch_fwd_tz<T>(const Dom<T>&, int, int, int, int, int, double, int,         \
                                  hipStream_t);                                                 \
-  template void launch_adj_tz<T>(const Dom<T>&, int, int, int, int, int, int, double, int, T*, \
+  template void launch_adj_tz<T>(const Dom<T>&, int, int, int, int, int, int, double, int,     \
                                  const double*, const double*, const double*, double*,        \
                                  hipStream_t);
 DD4DVAR_INST(DD4DVAR_TZ_T)
