@@ -80,9 +80,8 @@ typedef struct {
    * for bands of several pieces box width + 2 tz_p <= nlon.  Each box then
    * reads a frozen pad tz_q rows and tz_p columns wide, corners included
    * (see HALO_SRC), in place of the one-cell ring.  Such a context runs the
-   * step kernels only (execution modes 0 and 1; no persistent modes), and
-   * the tangent-linear, Gauss-Newton and mixed-precision entry points return
-   * E_INVALID. */
+   * step kernels only (execution modes 0 and 1; the persistent modes return
+   * E_INVALID), the tangent-linear and Gauss-Newton entry points included. */
   int32_t tz_p, tz_q;
   double tz_alpha;
 } dd4dvar_model_desc;

@@ -251,7 +251,6 @@ template <typename T>
 void adj_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int ntiles, int mode,
               const double* x, const double* forcing, double* out, hipStream_t st) {
   if (c->tz_p > 0) {
-    if (mode == 3) throw DevError{DD4DVAR_E_INVALID, "no Gauss-Newton adjoint for the Turkel-Zwas variant"};
     launch_adj_tz<T>(D, n, tile_base, ntiles, mode, c->tz_p, c->tz_q, c->tz_alpha,
                      c->plan.model.nlat, x, c->xb, forcing, out, st);
   } else {
@@ -367,7 +366,12 @@ void local_tlm(dd4dvar_ctx* c, const double* dx, hipStream_t st) {
   }
   auto sweep = [&](int tile_base, int ntiles, int nlev) {
     launch_tlm_init<T>(D, dx, tile_base, ntiles, st);
-    for (int n = 0; n + 1 < nlev; ++n) launch_tlm<T>(D, n, tile_base, ntiles, st);
+    for (int n = 0; n + 1 < nlev; ++n) {
+      if (c->tz_p > 0)
+        launch_tlm_tz<T>(D, n, tile_base, ntiles, c->tz_p, c->tz_q, c->tz_alpha, c->plan.model.nlat, st);
+      else
+        launch_tlm<T>(D, n, tile_base, ntiles, st);
+    }
   };
   if (c->exec_mode != 1) {
     sweep(0, c->ntiles, c->maxlev);
@@ -1152,8 +1156,6 @@ dd4dvar_status dd4dvar_tangent_linear(dd4dvar_ctx* ctx, const double* dx_dev, do
                                       void* stream) {
   if (!ctx || !dx_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
   if (ctx->ckpt) return fail(ctx, DD4DVAR_E_INVALID, "the tangent-linear model needs every level stored");
-  if (ctx->tz_p > 0)
-    return fail(ctx, DD4DVAR_E_INVALID, "no tangent-linear sweeps for the Turkel-Zwas variant");
   if (!ctx->have_forward) return fail(ctx, DD4DVAR_E_STATE, "tangent-linear model before any forward");
   API_GUARD(ctx, {
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1174,8 +1176,6 @@ dd4dvar_status dd4dvar_gn_hessvec(dd4dvar_ctx* ctx, const double* dx_dev, double
   if (!ctx || !dx_dev || !out_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
   if (dx_dev == out_dev) return fail(ctx, DD4DVAR_E_INVALID, "dx_dev and out_dev must differ");
   if (ctx->ckpt) return fail(ctx, DD4DVAR_E_INVALID, "Gauss-Newton products need every level stored");
-  if (ctx->tz_p > 0)
-    return fail(ctx, DD4DVAR_E_INVALID, "no Gauss-Newton products for the Turkel-Zwas variant");
   if (!ctx->have_forward) return fail(ctx, DD4DVAR_E_STATE, "Gauss-Newton product before any forward");
   API_GUARD(ctx, {
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1551,10 +1551,6 @@ dd4dvar_status solve_impl(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* o, const d
       o->krylov < 0 || o->krylov > 1 || (o->krylov == 1 && o->local_solver != 1) ||
       !std::isfinite(o->cg_rtol)) {
     ctx->err = "bad solve options";
-    return DD4DVAR_E_INVALID;
-  }
-  if (o->local_solver == 1 && ctx->tz_p > 0) {
-    ctx->err = "no Gauss-Newton local solver for the Turkel-Zwas variant";
     return DD4DVAR_E_INVALID;
   }
   if (o->local_solver == 1 && ctx->ckpt) {

@@ -58,6 +58,9 @@ template <typename T>
 void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, int p, int q,
                    double alpha, int nlat, const double* x, const double* xb,
                    const double* forcing, double* out, hipStream_t st);
+template <typename T>
+void launch_tlm_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
+                   int nlat, hipStream_t st);
 
 // box.hip: persistent per-box sweeps (FP32 state)
 size_t box_lds_bytes(int ny, int nx, int nring, int nlev);

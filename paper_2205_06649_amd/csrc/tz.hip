@@ -121,6 +121,16 @@ __device__ __forceinline__ void points(const SubDev& S, int r, int c, int p, int
   for (int o = 0; o < kOffs; ++o) P[o] = point(S, r, c, off_r(o, q), off_c(o, p), p, q, half, nlat);
 }
 
+// perturbation at a point: the box value (sign across a pole), zero on a
+// frozen pad position (the pad does not depend on the control)
+template <typename T>
+__device__ __forceinline__ V3<T> ld_dpt(const T* dZ, int64_t plane, int m, const Pt& P) {
+  const int i = P.pad ? m : P.idx;
+  const T s = T(P.sg);
+  const T h = dZ[i], u = dZ[plane + i], v = dZ[2 * plane + i];
+  return {P.pad ? T(0) : h, P.pad ? T(0) : s * u, P.pad ? T(0) : s * v};
+}
+
 template <typename T>
 struct State13 {
   V3<T> C, E, W, N, Sv, Ep, Wp, Nq, Sq, EN, WN, ES, WS;
@@ -191,6 +201,62 @@ __global__ __launch_bounds__(kTile) void k_fwd_tz(Dom<T> D, int n, int tile_base
   out[2 * plane + m] = B.v + wgt * V;
 }
 
+// tangent linear (the TLM step of Alg. 6):
+// dZ^{n+1} = dZ^{n-1} + F'(Z^n) dZ^n (dZ^1 = dZ^0 + F'(Z^0) dZ^0 / 2)
+template <typename T>
+__global__ __launch_bounds__(kTile) void k_tlm_tz(Dom<T> D, int n, int tile_base, int p, int q,
+                                                  T alpha, int nlat) {
+  const int2 wt = D.tiles[tile_base + xcd_tile(blockIdx.x, gridDim.x)];
+  if (D.active && !D.active[wt.x]) return;
+  const SubDev S = D.subs[wt.x];
+  if (n >= S.nlev - 1) return;
+  const int m = wt.y * kTile + threadIdx.x;
+  if (m >= S.ncell) return;
+  const int r = m / S.nx, c = m - r * S.nx;
+  const int64_t plane = S.ncell;
+  const T* Z = zlevel(D, S, n);
+  const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
+  const T* dZ = D.dz + S.zoff + int64_t(n) * 3 * plane;
+  const T* dB = n >= 1 ? D.dz + S.zoff + int64_t(n - 1) * 3 * plane : dZ;
+  Pt P[kOffs];
+  points(S, r, c, p, q, D.half, nlat, P);
+  const State13<T> z = load13(Z, R, plane, S.nring, P);
+  V3<T> d[kOffs];
+#pragma unroll
+  for (int o = 0; o < kOffs; ++o) d[o] = ld_dpt(dZ, plane, m, P[o]);
+  const V3<T> B = ld_box(dB, plane, m, T(1));
+  const RowCoef<T> rc = D.rows[S.row0 + r];
+  const RowCoef<T> rN = D.rows[P[7].grow], rS = D.rows[P[8].grow];
+  const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
+  const T tp = T(p), tq = T(q);
+  const V3<T>& C = z.C;
+  const V3<T>& dC = d[0];
+  const T hh = h0 + C.h;
+  const T dU = -rc.a1 * (dC.u * (z.E.u - z.W.u) + C.u * (d[1].u - d[2].u)) -
+               st * (dC.v * (z.N.u - z.Sv.u) + C.v * (d[3].u - d[4].u)) - rc.a2 / tp * (d[5].h - d[6].h) +
+               ((one - al) * (rc.ct * dC.u * C.v + (rc.cf + rc.ct * C.u) * dC.v) +
+                half * al * (rc.ct * d[5].u * z.Ep.v + (rc.cf + rc.ct * z.Ep.u) * d[5].v) +
+                half * al * (rc.ct * d[6].u * z.Wp.v + (rc.cf + rc.ct * z.Wp.u) * d[6].v));
+  const T dV = -rc.a1 * (dC.u * (z.E.v - z.W.v) + C.u * (d[1].v - d[2].v)) -
+               st * (dC.v * (z.N.v - z.Sv.v) + C.v * (d[3].v - d[4].v)) - stg / tq * (d[7].h - d[8].h) -
+               ((one - al) * (rc.cf + T(2) * rc.ct * C.u) * dC.u +
+                half * al * (rN.cf + T(2) * rN.ct * z.Nq.u) * d[7].u +
+                half * al * (rS.cf + T(2) * rS.ct * z.Sq.u) * d[8].u);
+  const T Dl = ((one - al) * (z.Ep.u - z.Wp.u) + half * al * (z.EN.u - z.WN.u + z.ES.u - z.WS.u)) / tp;
+  const T Dt = ((one - al) * (z.Nq.v * rN.c - z.Sq.v * rS.c) + half * al * (z.EN.v * rN.c - z.ES.v * rS.c) +
+                half * al * (z.WN.v * rN.c - z.WS.v * rS.c)) / tq;
+  const T dDl = ((one - al) * (d[5].u - d[6].u) + half * al * (d[9].u - d[10].u + d[11].u - d[12].u)) / tp;
+  const T dDt = ((one - al) * (d[7].v * rN.c - d[8].v * rS.c) + half * al * (d[9].v * rN.c - d[11].v * rS.c) +
+                 half * al * (d[10].v * rN.c - d[12].v * rS.c)) / tq;
+  const T dH = -rc.a1 * (dC.u * (z.E.h - z.W.h) + C.u * (d[1].h - d[2].h) + dC.h * Dl + hh * dDl) -
+               (st * (dC.v * (z.N.h - z.Sv.h) + C.v * (d[3].h - d[4].h)) + rc.a3 * (dC.h * Dt + hh * dDt));
+  const T wgt = n == 0 ? T(0.5) : T(1);
+  T* out = D.dz + S.zoff + int64_t(n + 1) * 3 * plane;
+  out[m] = B.h + wgt * dH;
+  out[plane + m] = B.u + wgt * dU;
+  out[2 * plane + m] = B.v + wgt * dV;
+}
+
 // transposed contribution of reader k through offset o (1 .. 12) to the
 // point x it reads there: lk = lambda^{n+1}(k), hk, uk, vk its state (h as
 // the anomaly), K its row coefficients, X those of x's row, ux, vx the
@@ -231,6 +297,8 @@ __device__ __forceinline__ V3<T> reader_term(int o, const V3<T>& lk, T hk, T uk,
 //   mode 0: cost forcing (observations + overlap), gradient and J at level 0
 //   mode 1: caller forcing (packed FP64, trajectory layout), adj0 at level 0
 //   mode 2: cost forcing, adj0 at level 0 (no background term)
+//   mode 3: Gauss-Newton forcing W dZ^n from the tangent-linear trajectory
+//           (eq. line5and7), adj0 at level 0, no cost
 template <typename T, int MODE>
 __global__ __launch_bounds__(kTile) void k_adj_tz(Dom<T> D, int n, int tile_base, int p, int q,
                                                   T alpha, int nlat, const double* __restrict__ x,
@@ -341,9 +409,10 @@ __global__ __launch_bounds__(kTile) void k_adj_tz(Dom<T> D, int n, int tile_base
       for (int o = o0 + int(threadIdx.x); o < o1; o += kTile) {
         const int code = D.obs_code[o];
         const int loc = code >> 2, f = code & 3;
-        const double rr = double(Z[f * plane + loc]) - D.obs_val[o];
+        const double rr = MODE == 3 ? double(D.dz[S.zoff + int64_t(n) * 3 * plane + f * plane + loc])
+                                    : double(Z[f * plane + loc]) - D.obs_val[o];
         const double qo = D.obs_q[o];
-        jloc += 0.5 * qo * rr * rr;
+        if (MODE != 3) jloc += 0.5 * qo * rr * rr;
         fo[f][loc - wt.y * kTile] = qo * rr;
       }
       __syncthreads();
@@ -359,16 +428,20 @@ __global__ __launch_bounds__(kTile) void k_adj_tz(Dom<T> D, int n, int tile_base
       av = double(l0.v) + 0.5 * av;
     }
     if (MODE != 1) {
+      // overlap misfit, or in mode 3 the perturbation in its place
       const V3<T> C = ld_box(Z, plane, m, T(1));
-      const V3<T> tg = ld_box(D.targ + S.traj_off + int64_t(n) * 3 * plane, plane, K > 0 ? m : 0, T(1));
-      const double eh = double(C.h) - double(tg.h);
-      const double eu = double(C.u) - double(tg.u);
-      const double ev = double(C.v) - double(tg.v);
+      const V3<T> tg = MODE == 3 ? ld_box(D.dz + S.zoff + int64_t(n) * 3 * plane, plane, m, T(1))
+                                 : ld_box(D.targ + S.traj_off + int64_t(n) * 3 * plane, plane,
+                                          K > 0 ? m : 0, T(1));
+      const double eh = MODE == 3 ? double(tg.h) : double(C.h) - double(tg.h);
+      const double eu = MODE == 3 ? double(tg.u) : double(C.u) - double(tg.u);
+      const double ev = MODE == 3 ? double(tg.v) : double(C.v) - double(tg.v);
       const double mk = D.mu * double(K);
       fh += mk * eh * D.isb2[0];
       fu += mk * eu * D.isb2[1];
       fv += mk * ev * D.isb2[2];
-      jloc += 0.5 * mk * (eh * eh * D.isb2[0] + eu * eu * D.isb2[1] + ev * ev * D.isb2[2]);
+      if (MODE != 3)
+        jloc += 0.5 * mk * (eh * eh * D.isb2[0] + eu * eu * D.isb2[1] + ev * ev * D.isb2[2]);
     }
     const double bh = fh + ah + double(l2.h);
     const double bu = fu + au + double(l2.u);
@@ -417,9 +490,18 @@ void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, 
   else if (mode == 1)
     hipLaunchKernelGGL((k_adj_tz<T, 1>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q,
                        T(alpha), nlat, x, xb, forcing, out);
-  else
+  else if (mode == 2)
     hipLaunchKernelGGL((k_adj_tz<T, 2>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q,
                        T(alpha), nlat, x, xb, forcing, out);
+  else
+    hipLaunchKernelGGL((k_adj_tz<T, 3>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q,
+                       T(alpha), nlat, x, xb, forcing, out);
+}
+template <typename T>
+void launch_tlm_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
+                   int nlat, hipStream_t st) {
+  hipLaunchKernelGGL(k_tlm_tz<T>, dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q, T(alpha),
+                     nlat);
 }
 
 #define DD4DVAR_INST(T)                                                                        \
@@ -427,6 +509,8 @@ void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, 
                                  hipStream_t);                                                 \
   template void launch_adj_tz<T>(const Dom<T>&, int, int, int, int, int, int, double, int,     \
                                  const double*, const double*, const double*, double*,        \
+                                 hipStream_t);                                                 \
+  template void launch_tlm_tz<T>(const Dom<T>&, int, int, int, int, int, double, int,         \
                                  hipStream_t);
 DD4DVAR_INST(DD4DVAR_TZ_T)
 #undef DD4DVAR_INST

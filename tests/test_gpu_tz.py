@@ -17,7 +17,10 @@ spanning bands whose pads reach across a pole partly into the box itself.
   tangent linear, eq. adjProd);
 * DD solves (Alg. 1, batched L-BFGS, with the exchange of the pads and
   overlap targets) against the oracle's, on the analysis;
-* the entry points the variant does not have return E_INVALID.
+* the tangent-linear sweep and the Gauss-Newton normal-matrix product
+  (frozen pads unperturbed), and a DD solve with Gauss-Newton local solves;
+* the persistent execution modes, which the variant does not have, return
+  E_INVALID.
 """
 import functools
 
@@ -26,7 +29,7 @@ import pytest
 
 import synth
 from conftest import custom_problem
-from oracle import dd, ddmaps, local, model
+from oracle import dd, ddmaps, gn, local, model
 from test_oracle_pins import TZ_SPACE_CFGS
 
 pytestmark = pytest.mark.gpu
@@ -176,7 +179,55 @@ def test_solve_matches_oracle(which):
     assert e_a < e_b
 
 
-def test_unsupported_entry_points_rejected():
+@pytest.mark.parametrize("which,tzv", [("c1", (2, 2, 0.5)), ("deep", (1, 3, 0.5)),
+                                       ("time", (32, 16, 0.5))])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tangent_linear_and_gn_product(which, tzv, prec):
+    """dZ = M' dx (the TLM step of Alg. 6 under the variant, pads
+    unperturbed) and (B_w^-1 + M'^T W M') dx against the oracle; FP64 1e-12,
+    FP32 1e-4."""
+    from paper_2205_06649_amd.context import Context
+    p, maps, trajs, rings = _state(tzv, which)
+    rng = np.random.default_rng(31)
+    sb = p.sigma_b[:, None, None]
+    xs = _controls(p, maps, trajs, seed=30)
+    dxs = [sb * rng.standard_normal(trajs[b.sub][0].shape) for b in maps.boxes]
+    ctx = Context(p, prec)
+    ctx.forward(ctx.pack_ctrl(xs), with_traj=False)
+    dt = ctx.unpack_traj(ctx.tangent_linear(ctx.pack_ctrl(dxs)))
+    hv = ctx.unpack_ctrl(ctx.gn_hessvec(ctx.pack_ctrl(dxs)))
+    ctx.close()
+    g = model.Grid.of(p)
+    tol = 1e-12 if prec == "fp64" else 1e-4
+    for b in maps.boxes:
+        geo = local.LocalGeometry(g, maps, b.sub)
+        lt = local.forward(geo, xs[b.sub], rings[b.sub])
+        e1 = _rel(dt[b.sub], local.tlm(geo, lt, rings[b.sub], dxs[b.sub]))
+        e2 = _rel(hv[b.sub], gn.hessvec(p, maps, b.sub, lt, rings[b.sub], dxs[b.sub]))
+        print(f"tz {which} {prec} box {b.sub}: TLM rel {e1:.2e}, GN product rel {e2:.2e}", flush=True)
+        assert e1 <= tol and e2 <= tol, (b.sub, e1, e2)
+
+
+def test_gn_solve_matches_oracle():
+    """Alg. 1 with Gauss-Newton local solves (fixed update and CG counts)
+    under the variant, FP64, against the oracle's analysis."""
+    from paper_2205_06649_amd.context import Context
+    p, maps, _, _ = _state((2, 2, 0.5), "c1")
+    opts = dict(max_outer=2, max_iter=2, cg_max_iter=15, cg_rtol=0.0, outer_tol=0.0,
+                local_solver="gn")
+    ref, _ = dd.solve(p, maps, **opts)
+    ctx = Context(p, "fp64")
+    xa, rep, status, _ = ctx.solve(**opts)
+    ctx.close()
+    sb = p.sigma_b[:, None, None]
+    inc = np.linalg.norm((ref - p.xb0) / sb)
+    err = np.linalg.norm((xa - ref) / sb) / inc
+    print(f"tz gauss-newton solve: {rep.gn_products} products, analysis rel {err:.2e}", flush=True)
+    assert err <= 1e-8
+    assert rep.gn_products == 2 * 2 * 15
+
+
+def test_persistent_modes_rejected():
     from paper_2205_06649_amd import _lib as L
     from paper_2205_06649_amd.context import Context
     p, maps, trajs, _ = _state(VARIANTS[0])
@@ -185,15 +236,4 @@ def test_unsupported_entry_points_rejected():
         with pytest.raises(L.DD4DVarError) as e:
             ctx.set_exec_mode(mode)
         assert e.value.status == L.DD4DVAR_E_INVALID
-    x = ctx.pack_ctrl(_controls(p, maps, trajs, seed=5))
-    ctx.forward(x, with_traj=False)
-    with pytest.raises(L.DD4DVarError) as e:
-        ctx.tangent_linear(x)
-    assert e.value.status == L.DD4DVAR_E_INVALID
-    with pytest.raises(L.DD4DVarError) as e:
-        ctx.gn_hessvec(x)
-    assert e.value.status == L.DD4DVAR_E_INVALID
-    with pytest.raises(L.DD4DVarError) as e:
-        ctx.solve(local_solver="gn")
-    assert e.value.status == L.DD4DVAR_E_INVALID
     ctx.close()
