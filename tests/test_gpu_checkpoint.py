@@ -9,14 +9,22 @@ that follow an exchange), whole solves, and the autograd backward."""
 import numpy as np
 import pytest
 
-from conftest import problem
+import synth
+from conftest import custom_problem, problem
 
 pytestmark = pytest.mark.gpu
+
+# the Turkel-Zwas variant (offsets 2, 2; frozen pads) on the c1 decomposition
+TZ_CFG = dict(synth.CONFIGS["c1"], index=140, tz=(2, 2, 0.5))
+
+
+def _problem(which):
+    return custom_problem(TZ_CFG) if which == "tz" else problem(which)
 
 
 def _pair(which, prec, stride):
     from paper_2205_06649_amd.context import Context
-    p = problem(which)
+    p = _problem(which)
     full = Context(p, prec)
     ck = Context(p, prec)
     nb_full = full.set_checkpointing(0)
@@ -36,7 +44,7 @@ def _x(p, ctx, seed):
 
 @pytest.mark.parametrize("stride", [3, 5])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("which", ["c1", "small", "c2"])
+@pytest.mark.parametrize("which", ["c1", "small", "c2", "tz"])
 def test_checkpointed_equals_stored(which, prec, stride):
     import torch
     p, full, ck, nb_full, nb_ck = _pair(which, prec, stride)

@@ -8,7 +8,8 @@ timed, and the plan it picks must still meet the parity bars."""
 import numpy as np
 import pytest
 
-from conftest import problem
+import synth
+from conftest import custom_problem, problem
 from oracle import dd, ddmaps, local
 
 pytestmark = pytest.mark.gpu
@@ -17,7 +18,9 @@ pytestmark = pytest.mark.gpu
 def _setup(which, prec, seed=0):
     import torch
     from paper_2205_06649_amd.context import Context
-    p = problem(which)
+    # "tz": the Turkel-Zwas variant (offsets 2, 2; frozen pads) on the c1 decomposition
+    p = (custom_problem(dict(synth.CONFIGS["c1"], index=140, tz=(2, 2, 0.5))) if which == "tz"
+         else problem(which))
     ctx = Context(p, prec)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
@@ -31,8 +34,12 @@ def _setup(which, prec, seed=0):
     return p, ctx, draw, torch
 
 
-@pytest.mark.parametrize("prec,mode", [("fp64", 0), ("fp32", 0), ("fp32", 2), ("fp32", 3)])
-@pytest.mark.parametrize("which", ["c1", "small"])
+PLANS = [("fp64", 0), ("fp32", 0), ("fp32", 2), ("fp32", 3)]
+
+
+# the Turkel-Zwas variant runs the step kernels only (modes 0 and 1)
+@pytest.mark.parametrize("which,prec,mode", [(w, pr, m) for w in ("c1", "small") for pr, m in PLANS]
+                         + [("tz", "fp64", 0), ("tz", "fp32", 0), ("tz", "fp64", 1)])
 def test_graph_replays_match_eager(which, prec, mode):
     p, ctx, draw, torch = _setup(which, prec)
     ctx.set_exec_mode(mode)
