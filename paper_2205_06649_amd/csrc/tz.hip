@@ -114,9 +114,23 @@ __device__ __forceinline__ V3<T> ld_pt(const T* Z, const T* R, int64_t plane, in
   return {base[P.idx], s * base[st + P.idx], s * base[2 * st + P.idx]};
 }
 
-// the 13 points of cell (r, c)
+// the 13 points of cell (r, c): plain index arithmetic for cells whose
+// neighbourhood lies inside the box (nearly all), the general mapping else
 __device__ __forceinline__ void points(const SubDev& S, int r, int c, int p, int q, int half,
                                        int nlat, Pt* P) {
+  const bool inner = r >= q && r + q < S.ny && c >= p && c + p < S.nx;
+  if (inner) {
+    const int m = r * S.nx + c;
+#pragma unroll
+    for (int o = 0; o < kOffs; ++o) {
+      P[o].idx = m + off_r(o, q) * S.nx + off_c(o, p);
+      P[o].sg = 1;
+      P[o].grow = S.row0 + r + off_r(o, q);
+      P[o].pad = false;
+      P[o].across = false;
+    }
+    return;
+  }
 #pragma unroll
   for (int o = 0; o < kOffs; ++o) P[o] = point(S, r, c, off_r(o, q), off_c(o, p), p, q, half, nlat);
 }
