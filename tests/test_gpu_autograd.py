@@ -8,7 +8,8 @@ background spread, centred: truncation ~1e-8, rounding ~1e-10)."""
 import numpy as np
 import pytest
 
-from conftest import problem
+import synth
+from conftest import custom_problem, problem
 from oracle import dd, ddmaps, local, model
 
 pytestmark = pytest.mark.gpu
@@ -25,7 +26,9 @@ def _rel(a, b):
 def _setup(which, prec, seed=0):
     import torch
     from paper_2205_06649_amd.context import Context
-    p = problem(which)
+    # "tz": the Turkel-Zwas variant (offsets 2, 2; frozen pads) on the c1 decomposition
+    p = (custom_problem(dict(synth.CONFIGS["c1"], index=140, tz=(2, 2, 0.5))) if which == "tz"
+         else problem(which))
     maps = ddmaps.build(p)
     bg, trajs = dd.background(p, maps)
     rings, _ = dd.exchange(maps, trajs)
@@ -38,7 +41,7 @@ def _setup(which, prec, seed=0):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("which", ["c1", "small"])
+@pytest.mark.parametrize("which", ["c1", "small", "tz"])
 def test_local_sweep_backward_is_the_adjoint(which, prec):
     from paper_2205_06649_amd.autograd import local_sweep
     p, maps, rings, ctx, xs, x, torch = _setup(which, prec)
@@ -58,7 +61,7 @@ def test_local_sweep_backward_is_the_adjoint(which, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("which", ["c1", "small"])
+@pytest.mark.parametrize("which", ["c1", "small", "tz"])
 def test_local_sweep_forward_mode_is_the_tlm(which, prec):
     """Forward-mode AD of LocalSweep (a dual tensor through the sweep) is the
     tangent-linear model: against the oracle's TLM per box, and consistent

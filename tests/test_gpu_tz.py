@@ -227,6 +227,29 @@ def test_gn_solve_matches_oracle():
     assert rep.gn_products == 2 * 2 * 15
 
 
+def test_mixed_precision_gn_solve():
+    """Mixed precision under the variant (FP64 evaluations, FP32 normal-matrix
+    products): the analysis of the FP64 Gauss-Newton solve to 1e-6 of the
+    increment, the local gradients reduced like the FP64 solve's."""
+    from paper_2205_06649_amd.context import Context
+    p, maps, _, _ = _state((2, 2, 0.5), "c1")
+    opts = dict(max_outer=2, max_iter=3, cg_max_iter=30, cg_rtol=1e-8, outer_tol=0.0,
+                local_solver="gn", grad_rtol=0.0)
+    c64 = Context(p, "fp64")
+    x64, r64, _, _ = c64.solve(**opts)
+    c32 = Context(p, "fp32")
+    xm, rm, _, _ = c64.solve(products=c32, **opts)
+    c64.close()
+    c32.close()
+    sb = p.sigma_b[:, None, None]
+    inc = np.linalg.norm((x64 - p.xb0) / sb)
+    err = np.linalg.norm((xm - x64) / sb) / inc
+    print(f"tz mixed solve: analysis rel {err:.2e}, gradient ratio {rm.gnorm_ratio_max:.2e} "
+          f"(fp64 {r64.gnorm_ratio_max:.2e})", flush=True)
+    assert err <= 1e-6
+    assert rm.gnorm_ratio_max <= max(10 * r64.gnorm_ratio_max, 1e-6)
+
+
 def test_persistent_modes_rejected():
     from paper_2205_06649_amd import _lib as L
     from paper_2205_06649_amd.context import Context
