@@ -366,7 +366,8 @@ def tz_leg(spec, reps=5):
     intervals and observation network: one box per interval, each covering
     the sphere (the truth run that makes the observations uses the variant
     too).  FP32 and FP64 evaluations with the step kernels, the sweep phases,
-    and the algorithmic rate of each sweep."""
+    and the algorithmic rate of each sweep; then the benchmark's own space-time
+    decomposition under the variant (frozen pads), FP32."""
     import torch
 
     import synth
@@ -419,6 +420,37 @@ def tz_leg(spec, reps=5):
     out["fp32_vs_fp64_rel_err"] = {
         "J_max": float(np.max(np.abs(J32 - J64) / np.abs(J64))),
         "grad_norm": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))}
+    # the benchmark's own space-time decomposition (2048 boxes) under the
+    # variant: every box reads a frozen pad q rows and p columns wide, which
+    # the exchange refreshes; FP32 step kernels
+    sspec = spec.replace(tz_p=p_, tz_q=q_, tz_alpha=a_)
+    sprob = synth.finish_spec(sspec, gpu_truth_forward)
+    ctx = Context(sprob, "fp32")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2205)
+    sb = torch.tensor(sprob.sigma_b, dtype=torch.float64, device="cuda")
+    scale = torch.cat([sb[f].expand(int(i[1]) * int(i[3])) for i in ctx.info for f in range(3)])
+    x = ctx.background_controls() + 0.3 * scale * torch.randn(
+        ctx.ctrl_len, generator=gen, dtype=torch.float64, device="cuda")
+    ms, J, g = time_evals(ctx, x, reps, 2)
+    for _ in range(2):
+        ctx.exchange(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.exchange(x)
+    e1.record()
+    e1.synchronize()
+    pts = sum(int(i[1]) * int(i[3]) * (int(i[5]) - 1) for i in ctx.info)
+    out["spatial_fp32"] = {"subdomains": ctx.nsub, "ms_per_eval": ms,
+                           "local_point_steps_per_s": pts / (ms * 1e-3),
+                           "pad_positions_per_box": int(ctx.info[0][9]),
+                           "exchange_ms": e0.elapsed_time(e1) / reps}
+    log(f"turkel-zwas on {ctx.nsub} boxes, fp32: {ms:.2f} ms/eval, exchange "
+        f"{out['spatial_fp32']['exchange_ms']:.2f} ms")
+    ctx.close()
+    del ctx, x, J, g
+    torch.cuda.empty_cache()
     return out
 
 
