@@ -38,44 +38,38 @@ def shift_lon_T(y, k):
     return np.roll(y, k, axis=-1)
 
 
-def _src_row(nlat, j, k):
-    """Source row of row j + k and whether it lies across a pole."""
-    s = j + k
-    if s >= nlat:
-        return 2 * nlat - 1 - s, True
-    if s < 0:
-        return -1 - s, True
-    return s, False
+def _src_rows(nlat, k):
+    """Source row of every row j + k, and whether it lies across a pole (the
+    row at the same depth on the other side)."""
+    s = np.arange(nlat) + k
+    across = (s >= nlat) | (s < 0)
+    return np.where(s >= nlat, 2 * nlat - 1 - s, np.where(s < 0, -1 - s, s)), across
 
 
 def shift_lat(x, k, sign):
     """Value at row j + k; rows beyond a pole come from across it, shifted by
     half a circle and multiplied by ``sign`` (-1 for u, v)."""
     nlat, nlon = x.shape[-2], x.shape[-1]
-    out = np.empty_like(x)
-    for j in range(nlat):
-        s, across = _src_row(nlat, j, k)
-        out[j] = sign * np.roll(x[s], -(nlon // 2)) if across else x[s]
+    src, across = _src_rows(nlat, k)
+    out = x[src].copy()
+    out[across] = sign * np.roll(out[across], -(nlon // 2), axis=-1)
     return out
 
 
 def shift_lat_T(y, k, sign):
     """Transpose of ``shift_lat``."""
     nlat, nlon = y.shape[-2], y.shape[-1]
+    src, across = _src_rows(nlat, k)
+    contrib = y.copy()
+    contrib[across] = sign * np.roll(y[across], nlon // 2, axis=-1)
     out = np.zeros_like(y)
-    for j in range(nlat):
-        s, across = _src_row(nlat, j, k)
-        if across:
-            out[s] += sign * np.roll(y[j], nlon // 2)
-        else:
-            out[s] += y[j]
+    np.add.at(out, src, contrib)
     return out
 
 
 def row_at(a, k):
     """Per-row table at row j + k (the source row's value beyond a pole)."""
-    nlat = a.shape[0]
-    return np.array([a[_src_row(nlat, j, k)[0]] for j in range(nlat)])[:, None]
+    return a[_src_rows(a.shape[0], k)[0]][:, None]
 
 
 class _Nbrs:

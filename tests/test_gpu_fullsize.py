@@ -75,6 +75,61 @@ def test_fullsize_sampled_subdomains(prec, tol):
     ctx.close()
 
 
+@functools.lru_cache(maxsize=None)
+def _fullsize_tz():
+    """The 2048-box decomposition under the Turkel-Zwas variant (offsets
+    2, 2, alpha 1/2; frozen pads), with the rest state as background: the
+    rest state is a fixed point of the variant (pinned), so the background
+    trajectory is the rest state at every level and costs no model run; the
+    controls are drawn around it, so the sweeps are exercised in full."""
+    spec = synth.make_spec("c5").replace(tz_p=2, tz_q=2, tz_alpha=0.5)
+    rest = np.zeros_like(spec.xb0)
+    rest[0] = spec.h_ref
+    flat = spec.truth0.reshape(3, -1)
+    vals = flat[spec.obs_field.astype(np.int64), spec.obs_cell.astype(np.int64)] + \
+        spec.obs_sigma * spec.obs_noise
+    p = spec.replace(obs_value=vals, xb0=rest)
+    maps = ddmaps.build(p)
+    sample = [0, 17, 130, 255]      # polar, interior, interior, polar (interval 0)
+    lmax = max(maps.boxes[s].nlev for s in sample) - 1
+    bg = np.broadcast_to(rest, (lmax + 1,) + rest.shape)
+    return p, maps, sample, bg
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp64", 1e-12)])
+def test_fullsize_tz_sampled_subdomains(prec, tol):
+    """Sampled boxes of the full-size decomposition under the Turkel-Zwas
+    variant, in the launch configuration the benchmark times (all 2048 boxes
+    per call, step kernels), against the oracle."""
+    from paper_2205_06649_amd.context import Context
+    p, maps, sample, bg = _fullsize_tz()
+    print(f"full-size turkel-zwas parity {prec}: sample {sample}", flush=True)
+    ctx = Context(p, prec)
+    xb = ctx.background_controls()
+    rng = np.random.default_rng(12)
+    xs = ctx.unpack_ctrl(xb)
+    xs = [x + 0.3 * p.sigma_b[:, None, None] * rng.standard_normal(x.shape) for x in xs]
+    J, grad = ctx.cost_grad(ctx.pack_ctrl(xs))
+    J = J.cpu().numpy()
+    g = grad.cpu().numpy()
+    assert np.all(np.isfinite(J)) and np.all(np.isfinite(g))
+    grads = ctx.unpack_ctrl(g)
+    ctx.close()
+    trajs = {}
+    for s in sample:
+        need = set(maps.neighbors[s].tolist()) | {int(k) for k in maps.halo_src[s] if k >= 0} | {s}
+        for k in need:
+            if k not in trajs:
+                trajs[k] = local.restrict_global(maps, k, bg)
+        ring = local.ring_from_trajs(maps, s, trajs)
+        Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], ring,
+                                 {k: trajs[k] for k in maps.neighbors[s]},
+                                 dtype=np.longdouble if prec == "fp64" else np.float64)
+        ej, eg = float(abs(J[s] - Jr) / abs(Jr)), _rel(grads[s], gr)
+        print(f"  subdomain {s}: J rel {ej:.2e}, grad rel {eg:.2e}", flush=True)
+        assert ej <= tol and eg <= (2 * tol if prec == "fp64" else tol), (s, ej, eg)
+
+
 @pytest.mark.parametrize("which", ["c2", "c3"])
 def test_gpu_gradient_finite_differences(which):
     """Centred differences of the GPU J (FP64) along a random direction agree
