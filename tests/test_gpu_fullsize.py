@@ -248,8 +248,9 @@ def test_fullsize_gn_solve_fp32_against_fp64():
     iterations of three updates, CG to 1e-4 or 20 iterations): the FP32
     analysis (persistent kernels) within 1e-4 of the FP64 one; the
     mixed-precision solve (FP64 evaluations, FP32 products) reduces every
-    local gradient below 1e-6 of its start; all closer to the truth than the
-    background."""
+    local gradient below 1e-6 of its start; the FP32 solve with Lanczos in
+    place of CG lands on the FP32 CG analysis (1e-5); all closer to the truth
+    than the background."""
     import time
     import torch
     from paper_2205_06649_amd.context import Context
@@ -285,8 +286,25 @@ def test_fullsize_gn_solve_fp32_against_fp64():
     ctx32.close()
     del ctx64, ctx32
     torch.cuda.empty_cache()
+    # Lanczos (Alg. 7) in place of CG, FP32 persistent products: the FP32 CG
+    # solve's analysis (the same iterates in exact arithmetic) and Ritz values
+    # inside the spectrum bounds of the preconditioned normal matrices
+    ctx = Context(p, "fp32")
+    ctx.set_exec_mode(2)
+    xa, rep, st, _ = ctx.solve(krylov="lanczos", **opts)
+    print(f"  lanczos fp32: {rep.gn_products} products, Ritz values {rep.ritz_min:.3e} .. "
+          f"{rep.ritz_max:.3e}", flush=True)
+    assert 0.0 < rep.ritz_min < rep.ritz_max
+    res["lanczos"] = xa
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    scale = [np.linalg.norm(res["fp64"][f] - res["fp64"][f].mean()) for f in range(3)]
+    d = max(np.linalg.norm(res["lanczos"][f] - res["fp32"][f]) / scale[f] for f in range(3))
+    print(f"  lanczos vs cg (fp32): {d:.2e}", flush=True)
+    assert d <= 1e-5
     ref = res["fp64"]
-    for k in ("fp32", "mixed"):
+    for k in ("fp32", "mixed", "lanczos"):
         err = max(np.linalg.norm(res[k][f] - ref[f]) / np.linalg.norm(ref[f] - ref[f].mean())
                   for f in range(3))
         print(f"  {k} analysis error vs fp64: {err:.2e}", flush=True)
