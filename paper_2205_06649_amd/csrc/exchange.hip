@@ -15,6 +15,9 @@
 namespace dd4dvar {
 
 namespace {
+// neighbour entries of a level whose loads are issued together
+constexpr int kGather = 8;
+
 __device__ __forceinline__ double block_sum2(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -25,6 +28,7 @@ __device__ __forceinline__ double block_sum2(double v, double* sh) {
     for (int i = 0; i < int(blockDim.x >> 6); ++i) r += sh[i];
   return r;
 }
+
 }  // namespace
 
 // targets (and backgrounds at level 0) from the global FP64 trajectory, whose
@@ -152,33 +156,57 @@ __global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int leve
     wlo |= __shfl_xor(wlo, off, 64);
     whi |= __shfl_xor(whi, off, 64);
   }
-  const uint64_t wave_hits = (uint64_t(whi) << 32) | wlo;
+  // the union is the same in every lane: keep it in scalar registers
+  const uint64_t wave_hits = (uint64_t(__builtin_amdgcn_readfirstlane(whi)) << 32) |
+                             uint32_t(__builtin_amdgcn_readfirstlane(wlo));
+  // lane i < nq holds entry i's level range, for one ballot per level
+  const int lane = threadIdx.x & 63;
+  const int my_lev0 = lane < nq ? nb_lev0[lane] : 0, my_nlev = lane < nq ? nb_nlev[lane] : 0;
+  const int cov = valid ? int(D.cover[S.cell_off + mm]) : 0;
   const int64_t plane = S.ncell;
   double acc = 0.0;                         // thread 0: the tile's sum over levels
   for (int n = n0; n < n1; ++n) {
     double jloc = 0.0;
-    const int K = valid ? int(D.cover[S.cell_off + mm]) * D.tcount[S.lev0 + n] - 1 : 0;
+    const int K = cov * D.tcount[S.lev0 + n] - 1;
     const int gl = S.lev0 + n;
+    // entries that some lane of the wave hits and that hold the level, in
+    // list order; the first kGather of them are loaded together, before any
+    // is used, then summed in list order
+    const int my_pl = gl - my_lev0;
+    uint64_t rem = wave_hits & uint64_t(__ballot(my_pl >= 0 && my_pl < my_nlev));
+    T zh[kGather], zu[kGather], zv[kGather];
+    bool hk[kGather];
+#pragma unroll
+    for (int k = 0; k < kGather; ++k) {
+      hk[k] = false;
+      zh[k] = zu[k] = zv[k] = T(0);
+      if (rem) {                                               // uniform
+        const int i = __builtin_ctzll(rem);
+        rem &= rem - 1;
+        hk[k] = (hits >> i) & 1;
+        if (hk[k]) {
+          const int pl = gl - nb_lev0[i];
+          const int rr = grow - nb_row0[i];
+          int cc = gcol - nb_col0[i];
+          if (cc < 0) cc += D.nlon;
+          const int64_t pc = nb_ncell[i];
+          const T* Z = D.traj + nb_zoff[i] + int64_t(D.zslot[pl]) * 3 * pc + int64_t(rr) * nb_nx[i] + cc;
+          zh[k] = Z[0];
+          zu[k] = Z[pc];
+          zv[k] = Z[2 * pc];
+        }
+      }
+    }
     double ch = 0, cu = 0, cv = 0;                 // shift: the first value
     double ah = 0, au = 0, av = 0, bh = 0, bu = 0, bv = 0;
     int cnt = 0;
-    for (uint64_t rem = wave_hits; rem; rem &= rem - 1) {     // entries in list order
-      const int i = __builtin_ctzll(rem);
-      const int pl = gl - nb_lev0[i];
-      if (pl < 0 || pl >= nb_nlev[i]) continue;                // uniform
-      if (!((hits >> i) & 1)) continue;
-      const int rr = grow - nb_row0[i];
-      int cc = gcol - nb_col0[i];
-      if (cc < 0) cc += D.nlon;
-      const int64_t pc = nb_ncell[i];
-      const T* Z = D.traj + nb_zoff[i] + int64_t(D.zslot[pl]) * 3 * pc + int64_t(rr) * nb_nx[i] + cc;
-      const double zh = double(Z[0]), zu = double(Z[pc]), zv = double(Z[2 * pc]);
+    auto add = [&](double z0, double z1, double z2) {
       if (cnt == 0) {
-        ch = zh;
-        cu = zu;
-        cv = zv;
+        ch = z0;
+        cu = z1;
+        cv = z2;
       }
-      const double dh = zh - ch, du = zu - cu, dv = zv - cv;
+      const double dh = z0 - ch, du = z1 - cu, dv = z2 - cv;
       ah += dh;
       au += du;
       av += dv;
@@ -186,6 +214,20 @@ __global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int leve
       bu += du * du;
       bv += dv * dv;
       ++cnt;
+    };
+#pragma unroll
+    for (int k = 0; k < kGather; ++k)
+      if (hk[k]) add(double(zh[k]), double(zu[k]), double(zv[k]));
+    for (; rem; rem &= rem - 1) {                              // beyond kGather entries
+      const int i = __builtin_ctzll(rem);
+      if (!((hits >> i) & 1)) continue;
+      const int pl = gl - nb_lev0[i];
+      const int rr = grow - nb_row0[i];
+      int cc = gcol - nb_col0[i];
+      if (cc < 0) cc += D.nlon;
+      const int64_t pc = nb_ncell[i];
+      const T* Z = D.traj + nb_zoff[i] + int64_t(D.zslot[pl]) * 3 * pc + int64_t(rr) * nb_nx[i] + cc;
+      add(double(Z[0]), double(Z[pc]), double(Z[2 * pc]));
     }
     if (K > 0 && cnt > 0) {
       const double inv = 1.0 / double(cnt);
