@@ -19,6 +19,9 @@ TZ_CFG = dict(synth.CONFIGS["c1"], index=140, tz=(2, 2, 0.5))
 
 
 def _problem(which):
+    if which == "dense":
+        from test_gpu_parity import DENSE_CFG
+        return custom_problem(DENSE_CFG)
     return custom_problem(TZ_CFG) if which == "tz" else problem(which)
 
 
@@ -44,7 +47,7 @@ def _x(p, ctx, seed):
 
 @pytest.mark.parametrize("stride", [3, 5])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("which", ["c1", "small", "c2", "tz"])
+@pytest.mark.parametrize("which", ["c1", "small", "c2", "tz", "dense"])
 def test_checkpointed_equals_stored(which, prec, stride):
     import torch
     p, full, ck, nb_full, nb_ck = _pair(which, prec, stride)

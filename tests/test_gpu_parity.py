@@ -43,7 +43,15 @@ WIDE_CFG = dict(index=112, nlat=48, nlon=128, nsteps=8, bands=3, pieces=1, ntime
                 overlap_cells=2, overlap_steps=1, obs_frac=0.05, obs_every=2)
 
 
+# heavy overlap: up to 11 other space-time boxes cover a cell at a level, so the
+# target kernel's batched loads (8 neighbours of a level) are exceeded
+DENSE_CFG = dict(index=113, nlat=24, nlon=48, nsteps=24, bands=4, pieces=4, ntime=3,
+                 overlap_cells=5, overlap_steps=3, obs_frac=0.1, obs_every=2)
+
+
 def _prob(which):
+    if which == "dense":
+        return custom_problem(DENSE_CFG)
     if which == "span":
         return custom_problem(SPAN_CFG)
     if which == "mixed":
@@ -208,10 +216,16 @@ def test_adjoint_integrate_random_forcing(which, prec):
         assert _rel(adj[b.sub], ref) <= TOL[prec], b.sub
 
 
-def test_exchange_then_cost_grad():
-    """After an exchange, rings and targets come from the local trajectories."""
-    p, maps, bg, trajs, rings = _oracle_state("c1")
-    ctx = _ctx("c1", "fp64")
+@pytest.mark.parametrize("which,prec", [("c1", "fp64"), ("dense", "fp64"), ("dense", "fp32")])
+def test_exchange_then_cost_grad(which, prec):
+    """After an exchange, rings and targets come from the local trajectories
+    (also where more boxes cover a cell than the target kernel loads at once)."""
+    p, maps, bg, trajs, rings = _oracle_state(which)
+    if which == "dense":       # some cell-level is covered by more than 8 other boxes
+        assert max(int((maps.cover_sp[b.row0:b.row0 + b.ny][:, (b.col0 + np.arange(b.nx)) % p.nlon]
+                        ).max()) * int(maps.time_count[b.lev0:b.lev0 + b.nlev].max())
+                   for b in maps.boxes) - 1 > 8
+    ctx = _ctx(which, prec)
     xa = _perturbed(p, maps, trajs, seed=5)
     ctx.exchange(ctx.pack_ctrl(xa))
     g = model.Grid.of(p)
@@ -225,9 +239,9 @@ def test_exchange_then_cost_grad():
     for b in maps.boxes:
         s = b.sub
         Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], new_rings[s],
-                                 {k: new[k] for k in maps.neighbors[s]}, dtype=np.longdouble)
+                                 {k: new[k] for k in maps.neighbors[s]}, dtype=REF_DTYPE[prec])
         ej, eg = float(abs(J[s] - Jr) / abs(Jr)), float(_rel(grads[s], gr))
-        assert ej <= TOL["fp64"] and eg <= TOL_GRAD["fp64"], (s, ej, eg)
+        assert ej <= TOL[prec] and eg <= TOL_GRAD[prec], (s, ej, eg)
 
 
 def test_gather_partition_of_unity():
