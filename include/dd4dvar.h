@@ -180,7 +180,10 @@ const char* dd4dvar_last_error(const dd4dvar_ctx* ctx);
 /* Builds the plan, allocates the device arena on the current HIP device,
  * copies the inputs, runs the background model over the whole window in FP64
  * (Alg. 1, first step) and fills the frozen halo rings, overlap targets and
- * per-subdomain backgrounds from it.  Synchronous. */
+ * per-subdomain backgrounds from it.  Synchronous.  E_INVALID (with
+ * dd4dvar_last_error(NULL) naming the cause) for an invalid descriptor, or when a
+ * box overlaps more than 64 other space-time boxes (the overlap-target
+ * kernel keeps one bit per neighbour in a 64-bit mask). */
 dd4dvar_status dd4dvar_create(const dd4dvar_model_desc* model,
                               const dd4dvar_partition_desc* part,
                               const dd4dvar_data_desc* data, void* stream,

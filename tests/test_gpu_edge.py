@@ -6,7 +6,8 @@
 * the largest box the persistent kernels take (80 x 136 cells, 159.7 KB of
   LDS, 11 passes), where the column-strip adjoint does not apply (12 rows
   per strip) and is refused;
-* one-step intervals (local windows of 3 or 4 levels).
+* one-step intervals (local windows of 3 or 4 levels);
+* a box overlapping more than 64 others is refused at create.
 
 Bars as in the parity tests: FP64 J 1e-12, gradients 2e-12; FP32 1e-4.
 Execution modes: 0 (step kernels) for both precisions, 2 and 4 (persistent)
@@ -123,3 +124,24 @@ def test_case_shapes():
     assert min(b.nlev for b in maps.boxes) == 3 and max(b.nlev for b in maps.boxes) == 4
     p, maps, _, _ = _state("no_obs")
     assert p.nobs == 0 and all(maps.obs_bin[b.sub].size == 0 for b in maps.boxes)
+
+
+def test_too_many_neighbours_refused():
+    """A box that overlaps more than 64 other space-time boxes (here 74, with
+    an overlap of 6 cells around 6 x 8 cores and of 3 steps around 4-step
+    intervals) is refused at create with E_INVALID: the overlap-target kernel
+    keeps one bit per neighbour."""
+    from paper_2205_06649_amd import _lib as L
+    from paper_2205_06649_amd.context import Context
+    cfg = dict(index=117, nlat=48, nlon=64, nsteps=12, bands=8, pieces=8, ntime=3,
+               overlap_cells=6, overlap_steps=3, obs_frac=0.05, obs_every=2)
+    p = custom_problem(cfg)
+    assert max(len(v) for v in ddmaps.build(p).neighbors) > 64
+    with pytest.raises(L.DD4DVarError) as e:
+        Context(p, precision="fp32")
+    assert e.value.status == L.DD4DVAR_E_INVALID and "64" in str(e.value)
+    # with an overlap of 4 cells (at most 64 neighbours) the same cores are accepted
+    p4 = custom_problem(dict(cfg, overlap_cells=4, index=118))
+    assert max(len(v) for v in ddmaps.build(p4).neighbors) <= 64
+    ctx = Context(p4, precision="fp32")
+    assert ctx.nsub == 192
