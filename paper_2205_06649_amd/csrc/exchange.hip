@@ -15,8 +15,10 @@
 namespace dd4dvar {
 
 namespace {
-// neighbour entries of a level whose loads are issued together
-constexpr int kGather = 8;
+// neighbour entries of a level whose loads are issued together (FP64 values
+// take twice the registers)
+template <typename T>
+constexpr int kGather = sizeof(T) == 4 ? 8 : 4;
 
 __device__ __forceinline__ double block_sum2(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -170,14 +172,14 @@ __global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int leve
     const int K = cov * D.tcount[S.lev0 + n] - 1;
     const int gl = S.lev0 + n;
     // entries that some lane of the wave hits and that hold the level, in
-    // list order; the first kGather of them are loaded together, before any
+    // list order; the first kGather<T> of them are loaded together, before any
     // is used, then summed in list order
     const int my_pl = gl - my_lev0;
     uint64_t rem = wave_hits & uint64_t(__ballot(my_pl >= 0 && my_pl < my_nlev));
-    T zh[kGather], zu[kGather], zv[kGather];
-    bool hk[kGather];
+    T zh[kGather<T>], zu[kGather<T>], zv[kGather<T>];
+    bool hk[kGather<T>];
 #pragma unroll
-    for (int k = 0; k < kGather; ++k) {
+    for (int k = 0; k < kGather<T>; ++k) {
       hk[k] = false;
       zh[k] = zu[k] = zv[k] = T(0);
       if (rem) {                                               // uniform
@@ -216,9 +218,9 @@ __global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int leve
       ++cnt;
     };
 #pragma unroll
-    for (int k = 0; k < kGather; ++k)
+    for (int k = 0; k < kGather<T>; ++k)
       if (hk[k]) add(double(zh[k]), double(zu[k]), double(zv[k]));
-    for (; rem; rem &= rem - 1) {                              // beyond kGather entries
+    for (; rem; rem &= rem - 1) {                              // beyond kGather<T> entries
       const int i = __builtin_ctzll(rem);
       if (!((hits >> i) & 1)) continue;
       const int pl = gl - nb_lev0[i];
