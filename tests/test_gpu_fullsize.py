@@ -75,6 +75,41 @@ def test_fullsize_sampled_subdomains(prec, tol):
     ctx.close()
 
 
+def test_fullsize_exchange_fp32_against_fp64():
+    """The exchange in the benchmark's launch configuration (all 2048 boxes
+    integrated from perturbed controls, rings and overlap targets taken from
+    the local trajectories), FP32 state against FP64: afterwards every box's
+    J and gradient agree to the FP32 bar.  The two precisions run separate
+    instantiations of the exchange kernels (the target kernel gathers 8
+    neighbours at a time in FP32, 4 in FP64), and the FP64 one is held to
+    the oracle on the small decompositions."""
+    import torch
+    from paper_2205_06649_amd.context import Context
+    p, maps, sample, bg = _fullsize()
+    print("full-size exchange, fp32 against fp64", flush=True)
+    ctx64, ctx32 = Context(p, "fp64"), Context(p, "fp32")
+    xb = ctx64.background_controls()
+    sb = torch.tensor(p.sigma_b, dtype=torch.float64, device="cuda")
+    scale = torch.cat([sb[f].expand(int(inf[1]) * int(inf[3])) for inf in ctx64.info for f in range(3)])
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(12)
+    xa = xb + 0.3 * scale * torch.randn(ctx64.ctrl_len, generator=gen, dtype=torch.float64, device="cuda")
+    x = xb + 0.3 * scale * torch.randn(ctx64.ctrl_len, generator=gen, dtype=torch.float64, device="cuda")
+    out = {}
+    for name, ctx in (("fp64", ctx64), ("fp32", ctx32)):
+        ctx.exchange(xa)
+        J, g = ctx.cost_grad(x)
+        out[name] = (J.cpu().numpy().copy(), ctx.unpack_ctrl(g.cpu().numpy()))
+    J64, g64 = out["fp64"]
+    J32, g32 = out["fp32"]
+    ej = np.abs(J32 - J64) / np.abs(J64)
+    eg = np.array([_rel(a, b) for a, b in zip(g32, g64)])
+    print(f"  max J rel {ej.max():.2e}, max grad rel {eg.max():.2e}", flush=True)
+    assert np.all(np.isfinite(J32)) and ej.max() <= 1e-4 and eg.max() <= 1e-4
+    ctx64.close()
+    ctx32.close()
+
+
 @functools.lru_cache(maxsize=None)
 def _fullsize_tz():
     """The 2048-box decomposition under the Turkel-Zwas variant (offsets
