@@ -253,7 +253,11 @@ dd4dvar_status dd4dvar_gn_hessvec(dd4dvar_ctx* ctx, const double* dx_dev,
 
 /* Exchange (Alg. 1): integrates every subdomain from the packed controls
  * x_dev, then refreshes the frozen halo rings from the owners' trajectories
- * and the overlap targets from the neighbours' trajectories.  Asynchronous. */
+ * and the overlap targets from the neighbours' trajectories (each target the
+ * mean of the other boxes holding the cell and level, summed in neighbour
+ * list order; the spread around it goes into the cost constant).  The
+ * result is deterministic: with checkpointing on, where the levels are
+ * exchanged one at a time, it is the same bits.  Asynchronous. */
 dd4dvar_status dd4dvar_exchange(dd4dvar_ctx* ctx, const double* x_dev,
                                 void* stream);
 
