@@ -29,9 +29,15 @@ from . import local
 from . import model
 
 
-def background(prob, maps):
-    g = model.Grid.of(prob)
-    bg = model.forward(g, prob.xb0, prob.nsteps)
+def background(prob, maps, dtype=np.float64):
+    """Global background run from x_b0 and every box's restriction of it.
+
+    ``dtype`` np.longdouble runs the same steps in extended precision from the
+    same FP64 initial state (a reference for FP64 evaluations: the observation
+    and overlap residuals are differences of nearly equal depths, so the
+    rounding of an FP64 run reaches the gradient amplified)."""
+    g = model.Grid.of(prob, dtype)
+    bg = model.forward(g, np.asarray(prob.xb0, dtype), prob.nsteps)
     trajs = {b.sub: local.restrict_global(maps, b.sub, bg) for b in maps.boxes}
     return bg, trajs
 

@@ -85,10 +85,11 @@ def background_weight(prob, maps, s):
     return wb.reshape(1, b.ny, b.nx) / (prob.sigma_b ** 2)[:, None, None]
 
 
-def hessvec(prob, maps, s, traj, ring, dx, W=None):
+def hessvec(prob, maps, s, traj, ring, dx, W=None, dtype=np.float64):
     """A(x) dx with A the Gauss-Newton normal matrix about the local
-    trajectory ``traj`` of x (eq. line5and7)."""
-    g = Grid.of(prob)
+    trajectory ``traj`` of x (eq. line5and7).  ``dtype`` np.longdouble runs
+    the same steps in extended precision."""
+    g = Grid.of(prob, dtype)
     geo = local.LocalGeometry(g, maps, s)
     if W is None:
         W = residual_weights(prob, maps, s)

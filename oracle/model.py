@@ -288,15 +288,18 @@ def adjoint(g: Grid, traj, forcing):
 
 
 # --- global 4D-Var functional (Def. "4D-Var DA problem", eq. min3sec) --------
-def cost_grad(prob, x, with_grad=True):
+def cost_grad(prob, x, with_grad=True, dtype=np.float64):
     """J(x) = 1/2 ||x - xb||^2_{B^-1} + lambda/2 sum_k ||H_k M_k(x) - v_k||^2_{R^-1}.
 
     Reading: both norms are squared and J carries a factor 1/2 (the Gauss-
     Newton footnote of Sec. 4 uses J = 1/2 F^T F); B and R are diagonal.
+    ``dtype`` np.longdouble evaluates the same function of the same FP64
+    inputs in extended precision.
     """
-    g = Grid.of(prob)
+    g = Grid.of(prob, dtype)
+    x = np.asarray(x, dtype)
     sb2 = prob.sigma_b[:, None, None] ** 2
-    dxb = x - prob.xb0
+    dxb = x - np.asarray(prob.xb0, dtype)
     Jb = 0.5 * np.sum(dxb * dxb / sb2)
     traj = forward(g, x, prob.nsteps)
     flat = traj.reshape(prob.nsteps + 1, 3, -1)
