@@ -264,6 +264,35 @@ def test_fp64_rounding_floor_against_extended_precision(rng):
     assert worst_g > 1e-15     # the extended evaluation really is different
 
 
+def test_fp64_pipeline_floor_against_extended_pipeline(rng):
+    """The whole pipeline in extended precision (background run, rings,
+    overlap targets, background controls and evaluation, from the same FP64
+    x_b0, observations and controls) is the FP64 parity reference.  The FP64
+    pipeline lands up to a few 1e-12 from it: its background run carries the
+    full depth (1e4 m), so its rounding (~1e-12 m) enters the observation and
+    overlap residuals, which are metre-sized differences of depths.  An
+    evaluation that keeps h - h_ref avoids most of that."""
+    p = problem("c1")
+    g, maps, trajs, rings = _local_setup(p)
+    _, trajs_e = dd.background(p, maps, np.longdouble)
+    rings_e, _ = dd.exchange(maps, trajs_e)
+    bg = np.stack([trajs[s][0] for s in range(len(maps.boxes))])
+    bg_e = np.stack([trajs_e[s][0] for s in range(len(maps.boxes))])
+    d_anom = float(np.abs(bg[:, 0] - bg_e[:, 0]).max())
+    assert 1e-14 < d_anom < 1e-10            # rounding of the FP64 run, in metres
+    sb = p.sigma_b[:, None, None]
+    worst = 0.0
+    for s in range(len(maps.boxes)):
+        x = trajs[s][0] + 0.3 * sb * rng.standard_normal(trajs[s][0].shape)
+        J, gr = local.cost_grad(p, maps, s, x, trajs[s][0], rings[s],
+                                {k: trajs[k] for k in maps.neighbors[s]})
+        JE, gE = local.cost_grad(p, maps, s, x, trajs_e[s][0], rings_e[s],
+                                 {k: trajs_e[k] for k in maps.neighbors[s]}, dtype=np.longdouble)
+        assert float(abs(J - JE) / abs(JE)) < 1e-12
+        worst = max(worst, float(np.linalg.norm(gr - gE) / np.linalg.norm(gE)))
+    assert 1e-14 < worst < 4e-12, worst
+
+
 # --- P12: brute-force Jacobian of a tiny box vs adjoint rows ----------------
 def test_bruteforce_jacobian_tiny_box():
     p = problem("tiny2")
@@ -940,6 +969,35 @@ def test_map_invariants(which):
         assert len(hits) == maps.cover_sp[cell // nn, cell % nn] * maps.time_count[k]
 
 
+DENSE_PIN_CFG = dict(index=113, nlat=24, nlon=48, nsteps=24, bands=4, pieces=4, ntime=3,
+                     overlap_cells=5, overlap_steps=3, obs_frac=0.1, obs_every=2)
+
+
+@pytest.mark.parametrize("which", ["c1", "small", "span", "mixed", "dense"])
+def test_neighbour_sets_by_brute_force(which):
+    """Overlap neighbour sets (eqs. overl, ospatial, otime; reading R7: every
+    other box whose extended space-time box intersects): each box's set of
+    (global level, global cell) points is enumerated as an occupancy array
+    over the whole window, and two boxes are neighbours exactly when their
+    arrays share a point."""
+    cfg = {"span": SPAN_CFG, "mixed": MIXED_CFG, "dense": DENSE_PIN_CFG}.get(which, which)
+    p = synth.make_spec(cfg)
+    maps = ddmaps.build(p)
+    nb = len(maps.boxes)
+    occ = np.zeros((nb, p.nsteps + 1, p.nlat, p.nlon), dtype=bool)
+    for b in maps.boxes:
+        for r in range(b.row0, b.row0 + b.ny):
+            for c in range(b.col0, b.col0 + b.nx):
+                occ[b.sub, b.lev0:b.lev0 + b.nlev, r, c % p.nlon] = True
+    flat = occ.reshape(nb, -1).astype(np.int64)
+    shared = flat @ flat.T                     # points each pair of boxes shares
+    for b in maps.boxes:
+        want = sorted(int(k) for k in np.nonzero(shared[b.sub])[0] if k != b.sub)
+        assert sorted(int(k) for k in maps.neighbors[b.sub]) == want, b.sub
+    if which == "dense":                       # diagonal and far neighbours occur
+        assert max(len(maps.neighbors[b.sub]) for b in maps.boxes) > 20
+
+
 def test_box_sizes_at_benchmark_configs():
     """Extended sizes from the problem-size arithmetic (eqs. Eq-r, nlocx)."""
     p = synth.make_spec("c5")
@@ -965,6 +1023,34 @@ def test_lbfgs_quadratic(rng):
     assert res["status"] == "converged"
     xs = np.linalg.solve(A, bvec)
     assert np.linalg.norm(res["x"] - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_dd_solve_one_box_is_global_4dvar():
+    """Alg. 1 with P = Q = 1 and no overlap: one local solve whose functional
+    is global 4D-Var (eq. min3sec).  Its analysis is a stationary point of the
+    independently written global functional (gradient reduced to 1e-7 of its
+    value at the background), and it coincides with L-BFGS run directly on
+    the global functional in the same variables to the accuracy both stop
+    tests leave (1e-6 of the increment)."""
+    p = custom_problem(dict(synth.CONFIGS["c1"], bands=1, pieces=1, ntime=1, overlap_cells=0,
+                            overlap_steps=0, index=119))
+    maps = ddmaps.build(p)
+    assert len(maps.boxes) == 1 and maps.boxes[0].span
+    opts = dict(max_iter=400, grad_rtol=1e-9)
+    xa, rep = dd.solve(p, maps, max_outer=1, outer_tol=0.0, **opts)
+    sb = p.sigma_b[:, None, None]
+    _, g0 = model.cost_grad(p, p.xb0)
+    _, ga = model.cost_grad(p, xa)
+    assert np.linalg.norm(sb * ga) <= 1e-7 * np.linalg.norm(sb * g0)
+
+    def fun(xi):
+        J, gr = model.cost_grad(p, p.xb0 + sb * xi.reshape(p.xb0.shape))
+        return J, (sb * gr).ravel()
+
+    res = lbfgs.minimize(fun, np.zeros(p.xb0.size), **opts)
+    xg = p.xb0 + sb * res["x"].reshape(p.xb0.shape)
+    inc = np.linalg.norm((xg - p.xb0) / sb)
+    assert inc > 0 and np.linalg.norm((xa - xg) / sb) <= 1e-6 * inc
 
 
 def test_dd_solve_improves_on_background():
