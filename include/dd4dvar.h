@@ -45,7 +45,8 @@ typedef enum {
   DD4DVAR_E_INVALID = 1,       /* bad descriptor or argument; nothing was done */
   DD4DVAR_E_NOMEM = 2,         /* device or host allocation failed */
   DD4DVAR_E_DEVICE = 3,        /* a HIP call failed; last_error holds its text */
-  DD4DVAR_E_NONFINITE = 4,     /* NaN/Inf met in a cost or gradient */
+  DD4DVAR_E_NONFINITE = 4,     /* NaN/Inf met in a cost or gradient (reported
+                                  by dd4dvar_synchronize and dd4dvar_autotune) */
   DD4DVAR_E_NOTCONVERGED = 5,  /* iteration cap hit; outputs are still written */
   DD4DVAR_E_STATE = 6          /* call order violated (e.g. adjoint before forward) */
 } dd4dvar_status;
@@ -204,7 +205,10 @@ dd4dvar_status dd4dvar_background_controls(dd4dvar_ctx* ctx, double* x_dev,
  * per subdomain, entries of unlisted subdomains untouched) and grad_dev
  * (packed FP64).  Runs the forward sweep, the observation and overlap misfits
  * and the adjoint sweep; the local trajectories are kept for
- * dd4dvar_adjoint_integrate.  Asynchronous. */
+ * dd4dvar_adjoint_integrate.  Asynchronous: a NaN or Inf in any J_s or
+ * gradient entry (for example from a non-finite control, or a time step
+ * beyond the scheme's stability limit) sets the context's device flag,
+ * which dd4dvar_synchronize reports as E_NONFINITE. */
 dd4dvar_status dd4dvar_local_cost_grad(dd4dvar_ctx* ctx, int32_t nsub,
                                        const int32_t* sub_ids,
                                        const double* x_dev, double* J_dev,
@@ -291,6 +295,29 @@ dd4dvar_status dd4dvar_gather(dd4dvar_ctx* ctx, int32_t level, double* out_dev,
  * for an unknown mode or for modes 2 to 4 where they do not apply.  The sub_ids form of
  * local_cost_grad always uses the step kernels. */
 dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode);
+
+/* Execution plan with an explicit pass count: mode as for
+ * dd4dvar_set_exec_mode; passes (modes 2 to 4) is the number of 1024-cell
+ * passes the persistent forward and box-mapped adjoint are compiled for,
+ * 0 = the smallest that holds the largest box, otherwise between that and
+ * 11 (E_INVALID outside).  dd4dvar_set_exec_mode(ctx, m) equals
+ * dd4dvar_set_exec_plan(ctx, m, 0).  The autotuner chooses among such
+ * plans; this call pins one, for tests and measurement. */
+dd4dvar_status dd4dvar_set_exec_plan(dd4dvar_ctx* ctx, int32_t mode, int32_t passes);
+
+/* The plan in use: out[4] = {execution mode, pass count of the persistent
+ * kernels (0 when they do not apply), rows per column strip of the mode-4
+ * adjoint (0 when it does not apply), 1 if the persistent modes apply}. */
+dd4dvar_status dd4dvar_get_exec_plan(const dd4dvar_ctx* ctx, int32_t out[4]);
+
+/* Waits for the work queued on stream, then reads and clears the context's
+ * non-finite flag: E_NONFINITE if any cost J_s, gradient entry, or
+ * first-level adjoint entry (adjoint_integrate, gn_hessvec) computed since
+ * the last check was NaN or Inf, else OK.  The flag is also read and cleared
+ * by dd4dvar_autotune (which returns E_NONFINITE for it) and cleared by
+ * dd4dvar_solve / dd4dvar_solve_mixed, whose line search meets overflowing
+ * trial steps by design and checks its own iterates. */
+dd4dvar_status dd4dvar_synchronize(dd4dvar_ctx* ctx, void* stream);
 
 /* Storage of the local trajectories for the adjoint (Sec. 2 adjoint model;
  * square-root checkpointing of the forward states).  stride = 0 (default):

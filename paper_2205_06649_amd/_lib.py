@@ -96,6 +96,9 @@ _SIGS = {
     "dd4dvar_exchange": (C.c_int, [_VP, _VP, _VP]),
     "dd4dvar_gather": (C.c_int, [_VP, C.c_int32, _VP, _VP]),
     "dd4dvar_set_exec_mode": (C.c_int, [_VP, C.c_int32]),
+    "dd4dvar_set_exec_plan": (C.c_int, [_VP, C.c_int32, C.c_int32]),
+    "dd4dvar_get_exec_plan": (C.c_int, [_VP, C.POINTER(C.c_int32)]),
+    "dd4dvar_synchronize": (C.c_int, [_VP, _VP]),
     "dd4dvar_set_timing": (C.c_int, [_VP, C.c_int32]),
     "dd4dvar_set_graph": (C.c_int, [_VP, C.c_int32]),
     "dd4dvar_set_checkpointing": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int64)]),
@@ -242,6 +245,20 @@ def dd4dvar_gather(ctx, level, out_dev, stream=None):
 
 def dd4dvar_set_exec_mode(ctx, mode):
     check(lib().dd4dvar_set_exec_mode(ctx, mode), ctx)
+
+
+def dd4dvar_set_exec_plan(ctx, mode, passes):
+    check(lib().dd4dvar_set_exec_plan(ctx, mode, passes), ctx)
+
+
+def dd4dvar_get_exec_plan(ctx):
+    out = (C.c_int32 * 4)()
+    check(lib().dd4dvar_get_exec_plan(ctx, out), ctx)
+    return {"mode": out[0], "passes": out[1], "strip_rows": out[2], "persistent": bool(out[3])}
+
+
+def dd4dvar_synchronize(ctx, stream=None):
+    check(lib().dd4dvar_synchronize(ctx, stream), ctx)
 
 
 def dd4dvar_set_timing(ctx, on):

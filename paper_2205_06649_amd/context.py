@@ -38,6 +38,9 @@ class Context:
         # bumped by every call that integrates the local models and so
         # replaces the stored trajectories the adjoint linearizes around
         self.traj_generation = 0
+        # bumped by every call that replaces the frozen halo rings and overlap
+        # targets (exchange, solve), which the local model itself depends on
+        self.ring_generation = 0
 
     # -- plumbing -----------------------------------------------------------
     def _stream(self):
@@ -63,6 +66,18 @@ class Context:
 
     def set_exec_mode(self, mode):
         L.dd4dvar_set_exec_mode(self.handle, mode)
+
+    def set_exec_plan(self, mode, passes=0):
+        L.dd4dvar_set_exec_plan(self.handle, mode, passes)
+
+    def exec_plan(self):
+        """{mode, passes, strip_rows, persistent} of the plan in use."""
+        return L.dd4dvar_get_exec_plan(self.handle)
+
+    def synchronize(self):
+        """Wait for the queued work; raises DD4DVarError (E_NONFINITE) if a
+        cost or gradient computed since the last check was NaN or Inf."""
+        L.dd4dvar_synchronize(self.handle, self._stream())
 
     def set_checkpointing(self, stride):
         """0: keep every level; stride >= 3: keep checkpoint pairs every
@@ -145,6 +160,7 @@ class Context:
     def exchange(self, x):
         L.dd4dvar_exchange(self.handle, x.data_ptr(), self._stream())
         self.traj_generation += 1
+        self.ring_generation += 1
 
     def gather(self, level):
         p = self.prob
@@ -185,7 +201,9 @@ class Context:
             st, rep = L.dd4dvar_solve_mixed(self.handle, products.handle, opts, self.ptr(x_init),
                                             self.ptr(xo), xa)
             products.traj_generation += 1
+            products.ring_generation += 1
         self.traj_generation += 1
+        self.ring_generation += 1
         return xa, rep, st, xo
 
     # -- layout helpers (host side) -----------------------------------------

@@ -736,14 +736,19 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
             const double dh = x[o] - xb[o];
             const double du = x[o + plane] - xb[o + plane];
             const double dv = x[o + 2 * plane] - xb[o + 2 * plane];
-            out[o] = wb * dh * D.isb2[0] + double(bh);
-            out[o + plane] = wb * du * D.isb2[1] + double(bu);
-            out[o + 2 * plane] = wb * dv * D.isb2[2] + double(bv);
+            const double gh = wb * dh * D.isb2[0] + double(bh);
+            const double gu = wb * du * D.isb2[1] + double(bu);
+            const double gv = wb * dv * D.isb2[2] + double(bv);
+            out[o] = gh;
+            out[o + plane] = gu;
+            out[o + 2 * plane] = gv;
+            flag_nonfinite(D.nonfinite, !(isfinite(gh) && isfinite(gu) && isfinite(gv)));
             jloc += 0.5 * wb * (dh * dh * D.isb2[0] + du * du * D.isb2[1] + dv * dv * D.isb2[2]);
           } else {
             out[o] = double(bh);
             out[o + plane] = double(bu);
             out[o + 2 * plane] = double(bv);
+            flag_nonfinite(D.nonfinite, !(isfinite(bh) && isfinite(bu) && isfinite(bv)));
           }
         }
       }
@@ -1032,14 +1037,19 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
             const double dh = x[o] - xb[o];
             const double du = x[o + plane] - xb[o + plane];
             const double dv = x[o + 2 * plane] - xb[o + 2 * plane];
-            out[o] = wb * dh * D.isb2[0] + double(bh);
-            out[o + plane] = wb * du * D.isb2[1] + double(bu);
-            out[o + 2 * plane] = wb * dv * D.isb2[2] + double(bv);
+            const double gh = wb * dh * D.isb2[0] + double(bh);
+            const double gu = wb * du * D.isb2[1] + double(bu);
+            const double gv = wb * dv * D.isb2[2] + double(bv);
+            out[o] = gh;
+            out[o + plane] = gu;
+            out[o + 2 * plane] = gv;
+            flag_nonfinite(D.nonfinite, !(isfinite(gh) && isfinite(gu) && isfinite(gv)));
             jloc += 0.5 * wb * (dh * dh * D.isb2[0] + du * du * D.isb2[1] + dv * dv * D.isb2[2]);
           } else {
             out[o] = double(bh);
             out[o + plane] = double(bu);
             out[o + 2 * plane] = double(bv);
+            flag_nonfinite(D.nonfinite, !(isfinite(bh) && isfinite(bu) && isfinite(bv)));
           }
         }
       }

@@ -184,6 +184,7 @@ Dom<T> local_dom(const dd4dvar_ctx* c) {
   D.hsign = c->hsign;
   D.hgcell = c->hgcell;
   D.active = c->eval_mask;
+  D.nonfinite = c->nonfinite;
   D.zslot = c->d_zslot;
   D.st = T(c->st);
   D.stg = T(c->stg);
@@ -790,6 +791,18 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
   else background_impl<float>(c, st);
 }
 
+// reads and clears the context's non-finite flag after the stream's work
+bool take_nonfinite(dd4dvar_ctx* c, hipStream_t st) {
+  uint32_t h = 0;
+  chk(hipMemcpyAsync(&h, c->nonfinite, sizeof(uint32_t), hipMemcpyDeviceToHost, st), "read flag");
+  chk(hipStreamSynchronize(st), "sync");
+  if (h) {
+    chk(hipMemsetAsync(c->nonfinite, 0, sizeof(uint32_t), st), "clear flag");
+    chk(hipStreamSynchronize(st), "sync");
+  }
+  return h != 0;
+}
+
 dd4dvar_status fail(dd4dvar_ctx* c, dd4dvar_status s, const std::string& msg) {
   if (c) c->err = msg;
   else set_thread_error(msg);
@@ -906,7 +919,38 @@ dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode) {
   if (mode >= 2 && ctx->ckpt)
     return fail(ctx, DD4DVAR_E_INVALID, "persistent per-box sweeps store every level (checkpoints on)");
   ctx->exec_mode = mode;
+  if (mode >= 2) ctx->box_k = ctx->box_kmin;
   return DD4DVAR_OK;
+}
+
+dd4dvar_status dd4dvar_set_exec_plan(dd4dvar_ctx* ctx, int32_t mode, int32_t passes) {
+  if (!ctx) return fail(ctx, DD4DVAR_E_INVALID, "null context");
+  if (passes != 0 && (mode < 2 || mode > 4 || !ctx->box_ok || passes < ctx->box_kmin ||
+                      passes > box_passes_max()))
+    return fail(ctx, DD4DVAR_E_INVALID, "passes must be 0 or hold the largest box (modes 2 to 4)");
+  const dd4dvar_status s = dd4dvar_set_exec_mode(ctx, mode);
+  if (s != DD4DVAR_OK) return s;
+  if (mode >= 2) ctx->box_k = passes ? passes : ctx->box_kmin;
+  return DD4DVAR_OK;
+}
+
+dd4dvar_status dd4dvar_get_exec_plan(const dd4dvar_ctx* ctx, int32_t out[4]) {
+  if (!ctx || !out) return fail(const_cast<dd4dvar_ctx*>(ctx), DD4DVAR_E_INVALID, "null argument");
+  out[0] = ctx->exec_mode;
+  out[1] = ctx->box_ok ? ctx->box_k : 0;
+  out[2] = ctx->strip_k;
+  out[3] = ctx->box_ok ? 1 : 0;
+  return DD4DVAR_OK;
+}
+
+dd4dvar_status dd4dvar_synchronize(dd4dvar_ctx* ctx, void* stream) {
+  if (!ctx) return fail(ctx, DD4DVAR_E_INVALID, "null context");
+  API_GUARD(ctx, {
+    if (take_nonfinite(ctx, static_cast<hipStream_t>(stream)))
+      return fail(ctx, DD4DVAR_E_NONFINITE,
+                  "a cost, gradient or first-level adjoint entry was NaN or Inf since the last check");
+    return DD4DVAR_OK;
+  })
 }
 
 dd4dvar_status dd4dvar_set_timing(dd4dvar_ctx* ctx, int32_t on) {
@@ -1108,6 +1152,8 @@ dd4dvar_status dd4dvar_autotune(dd4dvar_ctx* ctx, const double* x_dev, double* J
     ctx->exec_mode = report->mode[report->chosen];
     ctx->box_k = cand[report->chosen].second;
     ctx->timing = timing0;
+    if (take_nonfinite(ctx, st))
+      return fail(ctx, DD4DVAR_E_NONFINITE, "a cost or gradient entry at x was NaN or Inf");
     return DD4DVAR_OK;
   })
 }
@@ -1228,7 +1274,12 @@ dd4dvar_status dd4dvar_solve(dd4dvar_ctx* ctx, const dd4dvar_solve_opts* opts,
                              const double* x_init_dev, double* x_out_dev, double* xa_host,
                              dd4dvar_solve_report* report) {
   if (!ctx || !opts || !xa_host) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
-  API_GUARD(ctx, { return solve_impl(ctx, opts, x_init_dev, x_out_dev, xa_host, report, nullptr); })
+  API_GUARD(ctx, {
+    const dd4dvar_status r = solve_impl(ctx, opts, x_init_dev, x_out_dev, xa_host, report, nullptr);
+    // trial steps of the line search may overflow; the solve handles them
+    (void)take_nonfinite(ctx, nullptr);
+    return r;
+  })
 }
 
 dd4dvar_status dd4dvar_solve_mixed(dd4dvar_ctx* ctx, dd4dvar_ctx* ctx_lo,
@@ -1237,7 +1288,12 @@ dd4dvar_status dd4dvar_solve_mixed(dd4dvar_ctx* ctx, dd4dvar_ctx* ctx_lo,
                                    dd4dvar_solve_report* report) {
   if (!ctx || !ctx_lo || !opts || !xa_host) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
   if (ctx == ctx_lo) return fail(ctx, DD4DVAR_E_INVALID, "the two contexts must differ");
-  API_GUARD(ctx, { return solve_impl(ctx, opts, x_init_dev, x_out_dev, xa_host, report, ctx_lo); })
+  API_GUARD(ctx, {
+    const dd4dvar_status r = solve_impl(ctx, opts, x_init_dev, x_out_dev, xa_host, report, ctx_lo);
+    (void)take_nonfinite(ctx, nullptr);
+    (void)take_nonfinite(ctx_lo, nullptr);
+    return r;
+  })
 }
 
 }  // extern "C"

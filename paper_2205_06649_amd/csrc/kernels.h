@@ -71,6 +71,8 @@ struct Dom {
   const int32_t* hsign;
   const int32_t* hgcell;
   const uint8_t* active;     // per subdomain, 0 = skip (nullptr = all active)
+  uint32_t* nonfinite;       // set to 1 when a cost or first-level adjoint / gradient
+                             // entry is NaN or Inf (read and cleared by the host)
   // slot of the state arena holding each local level: the level itself when
   // every level is stored; with checkpoints, level pairs n = kc, kc+1 keep
   // their own slots and the others share a segment that the adjoint refills
@@ -80,6 +82,11 @@ struct Dom {
   double isb2[3];            // 1 / sigma_b^2
   int32_t nlon, half, maxlev, weight_mode;
 };
+
+// flags a non-finite output value (no store while every value is finite)
+__device__ __forceinline__ void flag_nonfinite(uint32_t* flag, bool bad) {
+  if (bad && flag) atomicOr(flag, 1u);
+}
 
 // state of local level n of subdomain S
 template <typename T>

@@ -471,15 +471,20 @@ __global__ __launch_bounds__(kTile) void k_adj_tz(Dom<T> D, int n, int tile_base
       const double dh = x[o] - xb[o];
       const double du = x[o + plane] - xb[o + plane];
       const double dv = x[o + 2 * plane] - xb[o + 2 * plane];
-      out[o] = wb * dh * D.isb2[0] + bh;
-      out[o + plane] = wb * du * D.isb2[1] + bu;
-      out[o + 2 * plane] = wb * dv * D.isb2[2] + bv;
+      const double gh = wb * dh * D.isb2[0] + bh;
+      const double gu = wb * du * D.isb2[1] + bu;
+      const double gv = wb * dv * D.isb2[2] + bv;
+      out[o] = gh;
+      out[o + plane] = gu;
+      out[o + 2 * plane] = gv;
+      flag_nonfinite(D.nonfinite, !(isfinite(gh) && isfinite(gu) && isfinite(gv)));
       jloc += 0.5 * wb * (dh * dh * D.isb2[0] + du * du * D.isb2[1] + dv * dv * D.isb2[2]);
     } else {
       const int64_t o = S.ctrl_off + m;
       out[o] = bh;
       out[o + plane] = bu;
       out[o + 2 * plane] = bv;
+      flag_nonfinite(D.nonfinite, !(isfinite(bh) && isfinite(bu) && isfinite(bv)));
     }
   }
   if (MODE == 0 || MODE == 2) {
