@@ -21,7 +21,11 @@ the incoming weight of its J.
 Both keep the device trajectory that the adjoint linearizes around inside the
 library context.  When another call has replaced it before backward runs,
 backward integrates the saved controls again first (recomputation instead of
-storing a second trajectory).
+storing a second trajectory).  The local model also depends on the frozen
+halo rings of the last exchange: when an exchange or a solve has replaced
+them between forward and backward, the forward's trajectory can no longer be
+recomputed, and backward (or the forward-mode derivative) raises instead of
+returning the derivative of another function.
 """
 from __future__ import annotations
 
@@ -48,14 +52,22 @@ class LocalSweep(torch.autograd.Function):
         traj = dd.forward(x)
         fctx.dd = dd
         fctx.gen = dd.traj_generation
+        fctx.ring_gen = dd.ring_generation
         fctx.save_for_backward(x)
         fctx.save_for_forward(x)
         return traj
 
     @staticmethod
+    def _check_rings(fctx):
+        if fctx.dd.ring_generation != fctx.ring_gen:
+            raise RuntimeError("the frozen halo rings were replaced (exchange or solve) after "
+                               "LocalSweep.forward: its derivative is no longer available")
+
+    @staticmethod
     def jvp(fctx, x_t, dd_t):
         dd = fctx.dd
         (x,) = fctx.saved_tensors
+        LocalSweep._check_rings(fctx)
         if dd.traj_generation != fctx.gen:
             dd.forward(x, with_traj=False)
             fctx.gen = dd.traj_generation
@@ -65,6 +77,7 @@ class LocalSweep(torch.autograd.Function):
     def backward(fctx, g):
         dd = fctx.dd
         (x,) = fctx.saved_tensors
+        LocalSweep._check_rings(fctx)
         if dd.traj_generation != fctx.gen:
             dd.forward(x, with_traj=False)
         return dd.adjoint(g.to(torch.float64).contiguous()), None

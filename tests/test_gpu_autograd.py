@@ -131,6 +131,38 @@ def test_local_sweep_recomputes_a_replaced_trajectory():
     assert torch.equal(x1.grad, x2.grad)
 
 
+def test_local_sweep_refuses_replaced_rings():
+    """An exchange (or a solve) between forward and backward replaces the
+    frozen halo rings the local model depends on, so the forward's trajectory
+    cannot be recomputed: backward and the forward-mode derivative raise
+    instead of returning the derivative about another trajectory."""
+    import torch.autograd.forward_ad as fwAD
+    from paper_2205_06649_amd.autograd import local_sweep
+    p, maps, rings, ctx, xs, x, torch = _setup("small", "fp64", seed=7)
+    W = torch.randn(ctx.traj_len, dtype=torch.float64, device="cuda")
+    xr = x.clone().requires_grad_(True)
+    t = local_sweep(ctx, xr)
+    ctx.exchange(x + 1e-3 * W[:ctx.ctrl_len].abs())
+    with pytest.raises(RuntimeError, match="halo rings"):
+        (t * W).sum().backward()
+    xr2 = x.clone().requires_grad_(True)
+    t2 = local_sweep(ctx, xr2)
+    ctx.solve(max_iter=2, max_outer=1)
+    with pytest.raises(RuntimeError, match="halo rings"):
+        (t2 * W).sum().backward()
+    with fwAD.dual_level():
+        xd = fwAD.make_dual(x, torch.ones_like(x))
+        yd = local_sweep(ctx, xd)
+        fwAD.unpack_dual(yd).tangent          # same rings: fine
+    # with the rings unchanged since forward, a replaced trajectory is
+    # recomputed (the exchange and the solve above left the current rings)
+    xr3 = x.clone().requires_grad_(True)
+    t3 = local_sweep(ctx, xr3)
+    ctx.cost_grad(ctx.background_controls())
+    (t3 * W).sum().backward()
+    assert torch.isfinite(xr3.grad).all()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_local_cost_backward_is_the_fused_gradient(prec):
     from paper_2205_06649_amd.autograd import local_cost
