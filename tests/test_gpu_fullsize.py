@@ -3,13 +3,20 @@ finite-difference checks of the gradient.
 
 Full size: the 1024 x 2048, 200-step, 16 x 16 x 8 decomposition with overlap
 4 cells / 4 steps and 999,999 observations, evaluated for all 2048 subdomains
-in one batched call (FP32 state and FP64), exactly as the benchmark times it.
-The oracle then recomputes sampled first-interval subdomains one by one.
-Because the oracle's global run costs about a second per step at this size,
-the observation values of this case are the truth snapshot at each observed
-point plus the drawn noise (no model run); over the 9 s window the truth
-moves by a small fraction of a cell, so values keep the workload's
-distribution.  The background run covers only the sampled interval.
+in one batched call (FP32 state and FP64), in every plan the benchmark's
+autotuner chooses between (step kernels; persistent box-mapped adjoint with
+10 or 11 passes; persistent strip adjoint with 11-row strips) and in the plan
+it picks.  The oracle then recomputes sampled subdomains one by one: polar
+and interior boxes of the first interval and of the fourth (steps 71..104,
+overlapping the third and fifth intervals).  Because the oracle's global run
+costs about half a second per step at this size, the observation values of
+this case are the truth snapshot at each observed point plus the drawn noise
+(no model run); over the 9 s window the truth moves by a small fraction of a
+cell, so values keep the workload's distribution.  The oracle's background
+run covers the levels the sampled boxes and their neighbours share, and the
+sampled boxes' controls are that background at their first level plus
+noise.  Errors are reported norm-wise and per field element-wise (largest
+error over the field's largest value).
 """
 import functools
 
@@ -28,6 +35,27 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+# sampled boxes: interval 0 (polar, interior, interior, polar) and interval 3
+# (polar, interior), whose windows start at step 71 and overlap intervals 2 and 4
+SAMPLE = [0, 17, 130, 255, 768, 885]
+
+
+class _Window:
+    """Global trajectory levels lo..hi (inclusive) indexed by global level."""
+
+    def __init__(self, lo, levels):
+        self.lo, self.levels = lo, levels
+
+    def box(self, maps, s):
+        """Box trajectory of s from its first level on, cut at the window's end."""
+        b = maps.boxes[s]
+        assert b.lev0 >= self.lo, (s, b.lev0, self.lo)
+        a = b.lev0 - self.lo
+        rows = b.row0 + np.arange(b.ny)
+        cols = (b.col0 + np.arange(b.nx)) % maps.nlon
+        return self.levels[a:a + b.nlev][:, :, rows][:, :, :, cols]
+
+
 @functools.lru_cache(maxsize=None)
 def _fullsize():
     spec = synth.make_spec("c5")
@@ -36,42 +64,135 @@ def _fullsize():
         spec.obs_sigma * spec.obs_noise
     p = spec.replace(obs_value=vals)
     maps = ddmaps.build(p)
-    sample = [0, 17, 130, 255]      # polar, interior, interior, polar (interval 0)
-    lmax = max(maps.boxes[s].nlev for s in sample) - 1
-    bg = model.forward(model.Grid.of(p), p.xb0, lmax)
-    return p, maps, sample, bg
+    # the oracle's background run over every level a sampled box, its ring
+    # owners or its overlap neighbours share with it
+    need = set()
+    for s in SAMPLE:
+        b = maps.boxes[s]
+        need |= {s} | {int(k) for k in maps.neighbors[s]}
+    lo = min(maps.boxes[k].lev0 for k in need)
+    hi = max(b.lev0 + b.nlev - 1 for b in (maps.boxes[s] for s in SAMPLE))
+    steps = [n for n in range(hi + 1)
+             if any(maps.boxes[k].lev0 <= n < maps.boxes[k].lev0 + maps.boxes[k].nlev for k in need)]
+    print(f"oracle background run to step {hi} ({len(steps)} levels kept)", flush=True)
+    kept = model.forward_at(model.Grid.of(p), p.xb0, steps)
+    windows = []
+    # contiguous runs of kept steps
+    i = 0
+    while i < len(steps):
+        j = i
+        while j + 1 < len(steps) and steps[j + 1] == steps[j] + 1:
+            j += 1
+        windows.append(_Window(steps[i], kept[i:j + 1]))
+        i = j + 1
+    return p, maps, windows
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp64", 1e-12)])
-def test_fullsize_sampled_subdomains(prec, tol):
+# FP64 is compared with the oracle pipeline in extended precision (the
+# background run included); that run costs about 1.4 s per step here, so the
+# FP64 sample is the first interval's boxes (steps 0..29)
+SAMPLE_EXT = [0, 17, 130, 255]
+
+
+@functools.lru_cache(maxsize=None)
+def _fullsize_ext():
+    p, maps, _ = _fullsize()
+    hi = max(maps.boxes[s].lev0 + maps.boxes[s].nlev - 1 for s in SAMPLE_EXT)
+    print(f"extended-precision oracle background run to step {hi}", flush=True)
+    bg = model.forward(model.Grid.of(p, np.longdouble), np.asarray(p.xb0, np.longdouble), hi)
+    return [_Window(0, bg)]
+
+
+def _box_traj(maps, windows, s):
+    b = maps.boxes[s]
+    for w in windows:
+        if w.lo <= b.lev0 < w.lo + len(w.levels):
+            return w.box(maps, s)
+    raise KeyError(s)
+
+
+def _controls(p, maps, windows, ctx, seed):
+    """Controls of every box: the oracle's background at each sampled box's
+    first level plus noise; the other boxes (not compared) start from the
+    context's background controls plus noise."""
+    rng = np.random.default_rng(seed)
+    xs = ctx.unpack_ctrl(ctx.background_controls())
+    out = []
+    for b, x in zip(maps.boxes, xs):
+        base = _box_traj(maps, windows, b.sub)[0] if b.sub in SAMPLE else x
+        out.append(base + 0.3 * p.sigma_b[:, None, None] * rng.standard_normal(x.shape))
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_sampled(dtype_name):
+    """The oracle's J and gradient of every sampled box at the controls of
+    _controls (seed 11): FP64, or the same FP64 inputs in extended precision."""
+    p, maps, windows = _fullsize()
+    dtype = {"f64": np.float64, "ext": np.longdouble}[dtype_name]
     from paper_2205_06649_amd.context import Context
-    p, maps, sample, bg = _fullsize()
-    print(f"full-size parity {prec}: {len(maps.boxes)} subdomains, sample {sample}", flush=True)
+    out = {}
+    ctx = Context(p, "fp32")
+    xs = _controls(p, maps, windows, ctx, 11)
+    ctx.close()
+    sample = SAMPLE
+    if dtype_name == "ext":
+        windows, sample = _fullsize_ext(), SAMPLE_EXT
+    for s in sample:
+        need = set(maps.neighbors[s].tolist()) | {int(k) for k in maps.halo_src[s] if k >= 0} | {s}
+        trajs = {k: _box_traj(maps, windows, k) for k in need}
+        ring = local.ring_from_trajs(maps, s, {k: trajs[k] for k in need
+                                                if maps.boxes[k].interval == maps.boxes[s].interval})
+        Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], ring,
+                                 {k: trajs[k] for k in maps.neighbors[s]}, dtype=dtype)
+        out[s] = (Jr, gr)
+        print(f"  oracle ({dtype_name}) subdomain {s} done", flush=True)
+    return xs, out
+
+
+def _field_rel(a, b):
+    """max over fields of max |a - b| / max |b| (element-wise, per field)."""
+    a = np.asarray(a, dtype=np.longdouble)
+    b = np.asarray(b, dtype=np.longdouble)
+    return max(float(np.abs(a[f] - b[f]).max() / np.abs(b[f]).max()) for f in range(3))
+
+
+# FP32 plans: the step kernels, the autotuner's two persistent candidates
+# (strip adjoint with 11-row strips, box-mapped adjoint with 10 or 11 passes)
+# and whatever the autotuner picks on this input
+PLANS = [("fp32", 0, 0), ("fp32", 4, 0), ("fp32", 2, 10), ("fp32", 2, 11), ("fp32", "auto", 0),
+         ("fp64", 0, 0)]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,mode,passes", PLANS)
+def test_fullsize_sampled_subdomains(prec, mode, passes):
+    from paper_2205_06649_amd.context import Context
+    p, maps, windows = _fullsize()
+    xs, ref = _oracle_sampled("ext" if prec == "fp64" else "f64")
+    print(f"full-size parity {prec} plan {mode}/{passes}: {len(maps.boxes)} subdomains, "
+          f"sample {SAMPLE}", flush=True)
     ctx = Context(p, prec)
-    xb = ctx.background_controls()
-    rng = np.random.default_rng(11)
-    xs = ctx.unpack_ctrl(xb)
-    xs = [x + 0.3 * p.sigma_b[:, None, None] * rng.standard_normal(x.shape) for x in xs]
-    J, grad = ctx.cost_grad(ctx.pack_ctrl(xs))
+    x = ctx.pack_ctrl(xs)
+    if mode == "auto":
+        rep = ctx.autotune(x, reps=2)
+        print(f"  autotuned: {rep}", flush=True)
+    else:
+        ctx.set_exec_plan(mode, passes)
+    J, grad = ctx.cost_grad(x)
+    ctx.synchronize()
     J = J.cpu().numpy()
     assert np.all(np.isfinite(J))
-    # every subdomain's gradient entry count and finiteness
     g = grad.cpu().numpy()
     assert np.all(np.isfinite(g))
     grads = ctx.unpack_ctrl(g)
-    trajs = {}
-    for s in sample:
-        need = set(maps.neighbors[s].tolist()) | {int(k) for k in maps.halo_src[s] if k >= 0} | {s}
-        for k in need:
-            if k not in trajs:
-                trajs[k] = local.restrict_global(maps, k, bg)
-        ring = local.ring_from_trajs(maps, s, trajs)
-        xbs = trajs[s][0]
-        Jr, gr = local.cost_grad(p, maps, s, xs[s], xbs, ring, {k: trajs[k] for k in maps.neighbors[s]},
-                                 dtype=np.longdouble if prec == "fp64" else np.float64)
-        ej, eg = float(abs(J[s] - Jr) / abs(Jr)), _rel(grads[s], gr)
-        print(f"  subdomain {s}: J rel {ej:.2e}, grad rel {eg:.2e}", flush=True)
-        assert ej <= tol and eg <= (2 * tol if prec == "fp64" else tol), (s, ej, eg)
+    for s in sorted(ref):
+        Jr, gr = ref[s]
+        ej, eg, ef = float(abs(J[s] - Jr) / abs(Jr)), _rel(grads[s], gr), _field_rel(grads[s], gr)
+        print(f"  subdomain {s}: J rel {ej:.2e}, grad rel {eg:.2e}, per-field max {ef:.2e}",
+              flush=True)
+        tol = 1e-4 if prec == "fp32" else 1e-12
+        assert ej <= tol and eg <= tol and ef <= 10 * tol, (s, ej, eg, ef)
     ctx.close()
 
 
@@ -85,7 +206,7 @@ def test_fullsize_exchange_fp32_against_fp64():
     the oracle on the small decompositions."""
     import torch
     from paper_2205_06649_amd.context import Context
-    p, maps, sample, bg = _fullsize()
+    p, maps, _ = _fullsize()
     print("full-size exchange, fp32 against fp64", flush=True)
     ctx64, ctx32 = Context(p, "fp64"), Context(p, "fp32")
     xb = ctx64.background_controls()
@@ -142,8 +263,11 @@ def test_fullsize_tz_sampled_subdomains(prec, tol):
     ctx = Context(p, prec)
     xb = ctx.background_controls()
     rng = np.random.default_rng(12)
-    xs = ctx.unpack_ctrl(xb)
-    xs = [x + 0.3 * p.sigma_b[:, None, None] * rng.standard_normal(x.shape) for x in xs]
+    # sampled boxes start from the oracle's background; the others (not
+    # compared) from the context's
+    xs = [(local.restrict_global(maps, b.sub, bg)[0] if b.sub in sample else x) +
+          0.3 * p.sigma_b[:, None, None] * rng.standard_normal(x.shape)
+          for b, x in zip(maps.boxes, ctx.unpack_ctrl(xb))]
     J, grad = ctx.cost_grad(ctx.pack_ctrl(xs))
     J = J.cpu().numpy()
     g = grad.cpu().numpy()
@@ -155,6 +279,7 @@ def test_fullsize_tz_sampled_subdomains(prec, tol):
         need = set(maps.neighbors[s].tolist()) | {int(k) for k in maps.halo_src[s] if k >= 0} | {s}
         for k in need:
             if k not in trajs:
+                # the rest state: the same numbers in any precision
                 trajs[k] = local.restrict_global(maps, k, bg)
         ring = local.ring_from_trajs(maps, s, trajs)
         Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], ring,
@@ -162,7 +287,7 @@ def test_fullsize_tz_sampled_subdomains(prec, tol):
                                  dtype=np.longdouble if prec == "fp64" else np.float64)
         ej, eg = float(abs(J[s] - Jr) / abs(Jr)), _rel(grads[s], gr)
         print(f"  subdomain {s}: J rel {ej:.2e}, grad rel {eg:.2e}", flush=True)
-        assert ej <= tol and eg <= (2 * tol if prec == "fp64" else tol), (s, ej, eg)
+        assert ej <= tol and eg <= tol, (s, ej, eg)
 
 
 @pytest.mark.parametrize("which", ["c2", "c3"])
@@ -211,7 +336,7 @@ def test_fullsize_solve_fp32_against_fp64():
     import time
     import torch
     from paper_2205_06649_amd.context import Context
-    p, maps, sample, bg = _fullsize()
+    p, maps, _ = _fullsize()
     res = {}
     for prec in ("fp64", "fp32"):
         print(f"full-size solve {prec}", flush=True)
@@ -241,37 +366,40 @@ def test_fullsize_solve_fp32_against_fp64():
         assert np.linalg.norm((xa - p.truth0) / sb) < np.linalg.norm((p.xb0 - p.truth0) / sb)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp64", 2e-12)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp64", 1e-12)])
 def test_fullsize_gn_product_sampled_subdomains(prec, tol):
     """The Gauss-Newton normal-matrix product (eq. line5and7) of all 2048
     local functionals in one batched call, against the oracle's product on
     sampled first-interval boxes (FP32: the persistent kernels of mode 2)."""
     from oracle import gn
     from paper_2205_06649_amd.context import Context
-    p, maps, sample, bg = _fullsize()
-    print(f"full-size Gauss-Newton product {prec}, sample {sample}", flush=True)
+    p, maps, windows = _fullsize()
+    sample = SAMPLE
     ctx = Context(p, prec)
+    xs = _controls(p, maps, windows, ctx, 12)
+    D = np.float64
     if prec == "fp32":
         ctx.set_exec_mode(2)
-    rng = np.random.default_rng(12)
-    xs = [x + 0.3 * p.sigma_b[:, None, None] * rng.standard_normal(x.shape)
-          for x in ctx.unpack_ctrl(ctx.background_controls())]
+    else:
+        windows, sample, D = _fullsize_ext(), SAMPLE_EXT, np.longdouble
+    print(f"full-size Gauss-Newton product {prec}, sample {sample}", flush=True)
+    rng = np.random.default_rng(13)
     dxs = [p.sigma_b[:, None, None] * rng.standard_normal(x.shape) for x in xs]
     ctx.forward(ctx.pack_ctrl(xs), with_traj=False)
     hv = ctx.gn_hessvec(ctx.pack_ctrl(dxs)).cpu().numpy()
     assert np.all(np.isfinite(hv))
     hvs = ctx.unpack_ctrl(hv)
-    g = model.Grid.of(p)
+    g = model.Grid.of(p, D)
     trajs = {}
     for s in sample:
-        need = set(maps.neighbors[s].tolist()) | {int(k) for k in maps.halo_src[s] if k >= 0} | {s}
+        need = {int(k) for k in maps.halo_src[s] if k >= 0} | {s}
         for k in need:
             if k not in trajs:
-                trajs[k] = local.restrict_global(maps, k, bg)
-        ring = local.ring_from_trajs(maps, s, trajs)
+                trajs[k] = _box_traj(maps, windows, k)
+        ring = local.ring_from_trajs(maps, s, {k: trajs[k] for k in need})
         geo = local.LocalGeometry(g, maps, s)
-        lt = local.forward(geo, xs[s], ring)
-        ref = gn.hessvec(p, maps, s, lt, ring, dxs[s])
+        lt = local.forward(geo, np.asarray(xs[s], D), ring)
+        ref = gn.hessvec(p, maps, s, lt, ring, np.asarray(dxs[s], D), dtype=D)
         e = _rel(hvs[s], ref)
         print(f"  subdomain {s}: product rel {e:.2e}", flush=True)
         assert e <= tol, (s, e)
@@ -289,7 +417,7 @@ def test_fullsize_gn_solve_fp32_against_fp64():
     import time
     import torch
     from paper_2205_06649_amd.context import Context
-    p, maps, sample, bg = _fullsize()
+    p, maps, _ = _fullsize()
     opts = dict(max_outer=2, max_iter=3, cg_max_iter=20, cg_rtol=1e-4, grad_rtol=1e-6,
                 outer_tol=0.0, local_solver="gn")
     res = {}
@@ -365,21 +493,32 @@ def _long_window():
     return p, maps, sample, bg
 
 
-# FP64 gradients on the ~105-step windows: the FP64 oracle itself lands
-# 9.7e-13 from its extended-precision evaluation on box 27 (against 3e-13 to
-# 9e-13 on the 33-step windows), so the bar is 3e-12 here; J keeps 1e-12.
-@pytest.mark.parametrize("prec,tol,tol_grad", [("fp32", 1e-4, 1e-4), ("fp64", 1e-12, 3e-12)])
+@functools.lru_cache(maxsize=None)
+def _long_window_ext():
+    """The same background run in extended precision (the FP64 reference)."""
+    p, maps, sample, bg = _long_window()
+    lmax = bg.shape[0] - 1
+    return model.forward(model.Grid.of(p, np.longdouble), np.asarray(p.xb0, np.longdouble), lmax)
+
+
+# FP64 against the oracle pipeline in extended precision, as on the shorter
+# windows: J and gradients 1e-12 on the ~105-step windows too
+@pytest.mark.parametrize("prec,tol,tol_grad", [("fp32", 1e-4, 1e-4), ("fp64", 1e-12, 1e-12)])
 def test_long_window_sampled_subdomains(prec, tol, tol_grad):
     from paper_2205_06649_amd.context import Context
     p, maps, sample, bg = _long_window()
+    bg_ref = _long_window_ext() if prec == "fp64" else bg
     print(f"long-window parity {prec}: {len(maps.boxes)} subdomains, sample {sample}", flush=True)
     ctx = Context(p, prec)
     if prec == "fp32":
         ctx.set_exec_mode(2)            # persistent per-box sweeps over the long windows
     xb = ctx.background_controls()
     rng = np.random.default_rng(12)
-    xs = ctx.unpack_ctrl(xb)
-    xs = [x + 0.3 * p.sigma_b[:, None, None] * rng.standard_normal(x.shape) for x in xs]
+    # sampled boxes start from the oracle's background; the others (not
+    # compared) from the context's
+    xs = [(local.restrict_global(maps, b.sub, bg)[0] if b.sub in sample else x) +
+          0.3 * p.sigma_b[:, None, None] * rng.standard_normal(x.shape)
+          for b, x in zip(maps.boxes, ctx.unpack_ctrl(xb))]
     J, grad = ctx.cost_grad(ctx.pack_ctrl(xs))
     J = J.cpu().numpy()
     g = grad.cpu().numpy()
@@ -390,7 +529,7 @@ def test_long_window_sampled_subdomains(prec, tol, tol_grad):
         need = set(maps.neighbors[s].tolist()) | {int(k) for k in maps.halo_src[s] if k >= 0} | {s}
         for k in need:
             if k not in trajs:
-                trajs[k] = local.restrict_global(maps, k, bg)
+                trajs[k] = local.restrict_global(maps, k, bg_ref)
         ring = local.ring_from_trajs(maps, s, trajs)
         Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], ring,
                                  {k: trajs[k] for k in maps.neighbors[s]},

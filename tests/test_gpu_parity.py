@@ -1,7 +1,14 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
 Tolerances (norm-wise relative errors, per subdomain):
-  FP64 mode: 1e-12 for trajectories, J and gradients.
+  FP64 mode: 1e-12 for trajectories, J and gradients, against the oracle
+  pipeline in extended precision: the background run (and with it the frozen
+  rings, overlap targets and x^b_s) and the local evaluation in long double
+  from the same FP64 inputs (x_b0, observations, controls).  The observation
+  and overlap residuals are differences of nearly equal depths (metres out
+  of 1e4 m), so any FP64 evaluation carrying the full depth, the oracle's
+  own included, lands up to ~2e-12 from the exact gradient (pinned in the
+  oracle tests); the device stores h - h_ref and lands within ~3e-14.
   FP32 state mode: 2e-5 for trajectories (h as its anomaly), 1e-4 for J and
   gradients -- float rounding (6e-8) amplified by at most a few hundred over
   the <= 40 leapfrog steps of these cases; observation/overlap residuals and
@@ -20,14 +27,10 @@ from test_oracle_pins import MIXED_CFG, SPAN_CFG
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "fp32": 1e-4}
-TOL_GRAD = {"fp64": 2e-12, "fp32": 1e-4}
+TOL_GRAD = {"fp64": 1e-12, "fp32": 1e-4}
 TOL_TRAJ = {"fp64": 1e-12, "fp32": 2e-5}
-# FP64 results are compared with the oracle evaluated in extended precision.
-# J and trajectories are held to 1e-12.  Gradients are held to 2e-12: the
-# leapfrog adjoint amplifies per-step rounding (1e-15) by ~1e3 over these
-# windows, and the FP64 oracle itself lands up to 9e-13 from the
-# extended-precision gradient (see the rounding-floor pin), so 1e-12 is the
-# floor of any FP64 evaluation, not a margin.
+# FP64 results are compared with the oracle pipeline in extended precision
+# (see the module docstring), FP32 results with the FP64 oracle.
 REF_DTYPE = {"fp64": np.longdouble, "fp32": np.float64}
 
 
@@ -70,6 +73,24 @@ def _oracle_state(which):
     return p, maps, bg, trajs, rings
 
 
+@functools.lru_cache(maxsize=None)
+def _oracle_ext(which):
+    """Background run, box trajectories and rings in extended precision."""
+    p = _prob(which)
+    maps = ddmaps.build(p)
+    bg, trajs = dd.background(p, maps, np.longdouble)
+    rings, _ = dd.exchange(maps, trajs)
+    return trajs, rings
+
+
+def _reference(which, prec):
+    """(box trajectories, rings) of the reference pipeline for a precision."""
+    if prec == "fp64":
+        return _oracle_ext(which)
+    p, maps, bg, trajs, rings = _oracle_state(which)
+    return trajs, rings
+
+
 def _ctx(which, prec):
     from paper_2205_06649_amd.context import Context
     return Context(_prob(which), precision=prec)
@@ -106,45 +127,60 @@ def test_global_forward_fp64(which):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("which", ["tiny1", "c1", "small", "span", "mixed"])
 def test_local_forward(which, prec):
-    p, maps, bg, trajs, rings = _oracle_state(which)
+    p, maps, bg, trajs, _ = _oracle_state(which)
+    _, rings = _reference(which, prec)
     ctx = _ctx(which, prec)
     xs = _perturbed(p, maps, trajs)
-    g = model.Grid.of(p)
+    g = model.Grid.of(p, REF_DTYPE[prec])
     traj = ctx.unpack_traj(ctx.forward(ctx.pack_ctrl(xs)))
     for b in maps.boxes:
         geo = local.LocalGeometry(g, maps, b.sub)
-        ref = local.forward(geo, xs[b.sub], rings[b.sub])
+        ref = local.forward(geo, np.asarray(xs[b.sub], REF_DTYPE[prec]), rings[b.sub])
         assert _rel(_anom(traj[b.sub], p.h_ref), _anom(ref, p.h_ref)) <= TOL_TRAJ[prec], b.sub
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("which", ["tiny1", "c1", "small", "span", "mixed"])
+@pytest.mark.parametrize("which", ["tiny1", "c1", "small", "span", "mixed", "c2"])
 def test_local_cost_grad(which, prec):
-    p, maps, bg, trajs, rings = _oracle_state(which)
+    """J and gradient of every box; also per field, element-wise (largest
+    error over the field's largest reference value)."""
+    from test_gpu_strips import field_errors
+    p, maps, bg, trajs0, _ = _oracle_state(which)
+    trajs, rings = _reference(which, prec)
     ctx = _ctx(which, prec)
-    xs = _perturbed(p, maps, trajs, seed=1)
+    xs = _perturbed(p, maps, trajs0, seed=1)
     J, grad = ctx.cost_grad(ctx.pack_ctrl(xs))
+    ctx.synchronize()
     J = J.cpu().numpy()
     grads = ctx.unpack_ctrl(grad)
+    worst = 0.0
     for b in maps.boxes:
         s = b.sub
         Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], rings[s],
                                  {k: trajs[k] for k in maps.neighbors[s]}, dtype=REF_DTYPE[prec])
         ej, eg = float(abs(J[s] - Jr) / abs(Jr)), float(_rel(grads[s], gr))
-        assert ej <= TOL[prec] and eg <= TOL_GRAD[prec], (s, ej, eg)
+        ef = max(e for pair in field_errors(grads[s], gr) for e in pair)
+        worst = max(worst, eg, ef)
+        # per field element-wise: 10x the norm-wise bar (a field's largest
+        # value can sit far below the norm of all three)
+        assert ej <= TOL[prec] and eg <= TOL_GRAD[prec] and ef <= 10 * TOL_GRAD[prec], \
+            (s, ej, eg, ef)
+    print(f"{which} {prec}: worst gradient error {worst:.2e}")
 
 
 def test_cost_grad_at_background_and_subsets():
     """At x = x_b the background term vanishes; subset calls equal full calls;
     the one-launch-per-subdomain mode equals the batched mode bit for bit."""
     p, maps, bg, trajs, rings = _oracle_state("c1")
+    trajs_e, rings_e = _oracle_ext("c1")
     ctx = _ctx("c1", "fp64")
     xb = ctx.background_controls()
     J, grad = ctx.cost_grad(xb)
     J = J.cpu().numpy()
     for b in maps.boxes:
-        Jr, gr = local.cost_grad(p, maps, b.sub, trajs[b.sub][0], trajs[b.sub][0], rings[b.sub],
-                                 {k: trajs[k] for k in maps.neighbors[b.sub]}, dtype=np.longdouble)
+        Jr, gr = local.cost_grad(p, maps, b.sub, trajs_e[b.sub][0], trajs_e[b.sub][0],
+                                 rings_e[b.sub], {k: trajs_e[k] for k in maps.neighbors[b.sub]},
+                                 dtype=np.longdouble)
         assert float(abs(J[b.sub] - Jr) / abs(Jr)) <= 1e-12
     xs = ctx.pack_ctrl(_perturbed(p, maps, trajs, seed=2))
     J1, g1 = ctx.cost_grad(xs)
@@ -201,18 +237,20 @@ def test_persistent_strip_adjoint_fp32(which):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("which", ["c1", "span", "mixed"])
 def test_adjoint_integrate_random_forcing(which, prec):
-    p, maps, bg, trajs, rings = _oracle_state(which)
+    p, maps, bg, trajs, _ = _oracle_state(which)
+    _, rings = _reference(which, prec)
+    D = REF_DTYPE[prec]
     ctx = _ctx(which, prec)
     xs = _perturbed(p, maps, trajs, seed=3)
     ctx.forward(ctx.pack_ctrl(xs), with_traj=False)
     rng = np.random.default_rng(4)
     forcing = [rng.standard_normal((b.nlev, 3, b.ny, b.nx)) for b in maps.boxes]
     adj = ctx.unpack_ctrl(ctx.adjoint(ctx.pack_traj(forcing)))
-    g = model.Grid.of(p)
+    g = model.Grid.of(p, D)
     for b in maps.boxes:
         geo = local.LocalGeometry(g, maps, b.sub)
-        lt = local.forward(geo, xs[b.sub], rings[b.sub])
-        ref = local.adjoint(geo, lt, rings[b.sub], forcing[b.sub])
+        lt = local.forward(geo, np.asarray(xs[b.sub], D), rings[b.sub])
+        ref = local.adjoint(geo, lt, rings[b.sub], np.asarray(forcing[b.sub], D))
         assert _rel(adj[b.sub], ref) <= TOL[prec], b.sub
 
 
@@ -228,8 +266,11 @@ def test_exchange_then_cost_grad(which, prec):
     ctx = _ctx(which, prec)
     xa = _perturbed(p, maps, trajs, seed=5)
     ctx.exchange(ctx.pack_ctrl(xa))
-    g = model.Grid.of(p)
-    new = {b.sub: local.forward(local.LocalGeometry(g, maps, b.sub), xa[b.sub], rings[b.sub])
+    D = REF_DTYPE[prec]
+    ref_trajs, ref_rings = _reference(which, prec)
+    g = model.Grid.of(p, D)
+    new = {b.sub: local.forward(local.LocalGeometry(g, maps, b.sub), np.asarray(xa[b.sub], D),
+                                ref_rings[b.sub])
            for b in maps.boxes}
     new_rings, _ = dd.exchange(maps, new)
     xs = _perturbed(p, maps, trajs, seed=6)
@@ -238,8 +279,8 @@ def test_exchange_then_cost_grad(which, prec):
     grads = ctx.unpack_ctrl(grad)
     for b in maps.boxes:
         s = b.sub
-        Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], new_rings[s],
-                                 {k: new[k] for k in maps.neighbors[s]}, dtype=REF_DTYPE[prec])
+        Jr, gr = local.cost_grad(p, maps, s, xs[s], ref_trajs[s][0], new_rings[s],
+                                 {k: new[k] for k in maps.neighbors[s]}, dtype=D)
         ej, eg = float(abs(J[s] - Jr) / abs(Jr)), float(_rel(grads[s], gr))
         assert ej <= TOL[prec] and eg <= TOL_GRAD[prec], (s, ej, eg)
 
@@ -301,3 +342,57 @@ def test_persistent_box_sweeps_fp32(which, mode):
     with pytest.raises(L.DD4DVarError) as e:
         ctx64.set_exec_mode(mode)
     assert e.value.status == L.DD4DVAR_E_INVALID
+
+
+@functools.lru_cache(maxsize=None)
+def _c3_sampled(dtype_name):
+    """The 256 x 512 brick decomposition: sampled boxes of every size class
+    and of the first, a middle and the last interval, with the trajectories
+    of the background run (FP64, or extended precision) that they, their
+    ring owners and their overlap neighbours need."""
+    p = _prob("c3")
+    maps = ddmaps.build(p)
+    sizes = sorted(maps.boxes, key=lambda b: b.ncell)
+    sample = sorted({sizes[0].sub, sizes[len(sizes) // 2].sub, sizes[-1].sub,
+                     next(b.sub for b in maps.boxes if b.interval == 3),
+                     next(b.sub for b in maps.boxes if b.interval == 7 and b.band == 4)})
+    D = {"f64": np.float64, "ext": np.longdouble}[dtype_name]
+    bg = model.forward(model.Grid.of(p, D), np.asarray(p.xb0, D), p.nsteps)
+    need = set(sample)
+    for s in sample:
+        need |= {int(k) for k in maps.neighbors[s]} | {int(k) for k in maps.halo_src[s] if k >= 0}
+    trajs = {k: local.restrict_global(maps, k, bg) for k in need}
+    rings = {s: local.ring_from_trajs(maps, s, trajs) for s in sample}
+    return p, maps, sample, trajs, rings
+
+
+@pytest.mark.parametrize("prec,mode", [("fp64", 0), ("fp32", 0), ("fp32", 2), ("fp32", 4)])
+def test_c3_sampled_subdomains(prec, mode):
+    """The 256 x 512, 200-step brick decomposition (512 boxes of 945 to 8466
+    cells) evaluated in one batched call; sampled boxes against the oracle,
+    norm-wise and per field element-wise."""
+    from test_gpu_strips import field_errors
+    p, maps, sample, trajs0, _ = _c3_sampled("f64")
+    _, _, _, trajs, rings = _c3_sampled("ext" if prec == "fp64" else "f64")
+    rng = np.random.default_rng(31)
+    ctx = _ctx("c3", prec)
+    xb = ctx.unpack_ctrl(ctx.background_controls())
+    xs = [(trajs0[b.sub][0] if b.sub in sample else x) +
+          0.3 * p.sigma_b[:, None, None] * rng.standard_normal(x.shape)
+          for b, x in zip(maps.boxes, xb)]
+    ctx.set_exec_mode(mode)
+    J, grad = ctx.cost_grad(ctx.pack_ctrl(xs))
+    ctx.synchronize()
+    J = J.cpu().numpy()
+    grads = ctx.unpack_ctrl(grad)
+    for s in sample:
+        Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], rings[s],
+                                 {k: trajs[k] for k in maps.neighbors[s]}, dtype=REF_DTYPE[prec])
+        ej, eg = float(abs(J[s] - Jr) / abs(Jr)), float(_rel(grads[s], gr))
+        ef = max(e for pair in field_errors(grads[s], gr) for e in pair)
+        b = maps.boxes[s]
+        print(f"c3 {prec} mode {mode} box {s} ({b.ny}x{b.nx}, interval {b.interval}): "
+              f"J {ej:.2e} grad {eg:.2e} per-field {ef:.2e}", flush=True)
+        assert ej <= TOL[prec] and eg <= TOL_GRAD[prec] and ef <= 10 * TOL_GRAD[prec], \
+            (s, ej, eg, ef)
+    ctx.close()
