@@ -214,6 +214,23 @@ dd4dvar_status dd4dvar_local_cost_grad(dd4dvar_ctx* ctx, int32_t nsub,
                                        const double* x_dev, double* J_dev,
                                        double* grad_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * dd4dvar_local_cost_grad over all subdomains, the same kernels and results
+ * bit for bit, allocating nothing.  The per-tile FP64 cost partials, which
+ * local_cost_grad keeps in the context's arena, live in a static device
+ * array of the library instead: 131072 tiles (1 MiB) per GPU, held by each
+ * GPU the library runs on until the process ends; a decomposition with more
+ * tiles of 256 box cells (more than ~33.5 M box cells) gets E_INVALID.  The
+ * array's address is looked up once per device by dd4dvar_create.  Every
+ * call on a GPU shares that GPU's array (each call writes every partial it
+ * reads), so calls that overlap on one GPU, from any context or stream,
+ * race.  Runs eagerly: graph mode and phase timing do not apply.
+ * Asynchronous; the non-finite flag as for local_cost_grad. */
+dd4dvar_status dd4dvar_local_cost_grad_noalloc(dd4dvar_ctx* ctx, const double* x_dev,
+                                               double* J_dev, double* grad_dev,
+                                               void* stream);
+
 /* Forward model.  scope 0: the whole grid from x_dev = [3][nlat][nlon] over
  * all nsteps, traj_dev = [nsteps+1][3][nlat][nlon] (required), FP64 always.
  * scope 1: every subdomain's restricted model (eq. restricted) from packed

@@ -89,6 +89,7 @@ _SIGS = {
     "dd4dvar_ctx_plan": (_VP, [_VP]),
     "dd4dvar_background_controls": (C.c_int, [_VP, _VP, _VP]),
     "dd4dvar_local_cost_grad": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32), _VP, _VP, _VP, _VP]),
+    "dd4dvar_local_cost_grad_noalloc": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "dd4dvar_forward_integrate": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP]),
     "dd4dvar_adjoint_integrate": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP]),
     "dd4dvar_tangent_linear": (C.c_int, [_VP, _VP, _VP, _VP]),
@@ -217,6 +218,10 @@ def dd4dvar_local_cost_grad(ctx, x_dev, J_dev, grad_dev, stream=None, sub_ids=No
         st = lib().dd4dvar_local_cost_grad(ctx, int(ids.size), _ptr(ids, C.c_int32), x_dev, J_dev,
                                            grad_dev, stream)
     check(st, ctx)
+
+
+def dd4dvar_local_cost_grad_noalloc(ctx, x_dev, J_dev, grad_dev, stream=None):
+    check(lib().dd4dvar_local_cost_grad_noalloc(ctx, x_dev, J_dev, grad_dev, stream), ctx)
 
 
 def dd4dvar_forward_integrate(ctx, scope, x_dev, traj_dev, stream=None):

@@ -17,6 +17,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -64,6 +66,10 @@ struct dd4dvar_ctx {
   int32_t *obs_ptr = nullptr, *obs_code = nullptr;
   double *obs_val = nullptr, *obs_q = nullptr;
   double *jpart = nullptr, *jc = nullptr, *jconst = nullptr;
+  // per-tile cost partials in use: jpart, or the device's static scratch
+  // during dd4dvar_local_cost_grad_noalloc
+  double* jpart_use = nullptr;
+  double* scratch = nullptr;            // this device's static scratch array
   int32_t *nbr_idx = nullptr, *hsrc = nullptr, *hoff = nullptr, *hsign = nullptr, *hgcell = nullptr;
   double* xb = nullptr;
   int32_t *cptr = nullptr, *cpiece = nullptr;
@@ -130,6 +136,17 @@ struct dd4dvar_ctx {
 
 namespace {
 
+// Static scratch of dd4dvar_local_cost_grad_noalloc: the per-tile FP64 cost
+// partials of one evaluation (1 MiB: 131072 tiles of 256 cells, 33.5 M box
+// cells).  Each GPU the library runs on holds its own copy until the process
+// ends.  In host code the array's name is only a stand-in: its device
+// address is looked up once per device (with that device current) and kept.
+constexpr int64_t kScratchTiles = 131072;
+__device__ __align__(256) double scratch[kScratchTiles];
+
+std::mutex scratch_mu;
+std::map<int, double*> scratch_addr;   // device -> address of its scratch
+
 struct DevError {
   dd4dvar_status st;
   std::string msg;
@@ -177,7 +194,7 @@ Dom<T> local_dom(const dd4dvar_ctx* c) {
   D.obs_code = c->obs_code;
   D.obs_val = c->obs_val;
   D.obs_q = c->obs_q;
-  D.jpart = c->jpart;
+  D.jpart = c->jpart_use ? c->jpart_use : c->jpart;
   D.nbr_idx = c->nbr_idx;
   D.hsrc = c->hsrc;
   D.hoff = c->hoff;
@@ -415,7 +432,7 @@ void cost_grad_impl(dd4dvar_ctx* c, const std::vector<int32_t>* ids, const doubl
       c->have_forward = true;
       mark(c, 1, st);
       mark(c, 2, st);
-      launch_reduce_j(c->d_subs, c->nsub, nullptr, c->jpart, c->jconst, J, c->nonfinite, st);
+      launch_reduce_j(c->d_subs, c->nsub, nullptr, D.jpart, c->jconst, J, c->nonfinite, st);
       chk(hipGetLastError(), "reduce launch");
       mark(c, 3, st);
       if (c->timing) {
@@ -445,9 +462,9 @@ void cost_grad_impl(dd4dvar_ctx* c, const std::vector<int32_t>* ids, const doubl
     chk(hipMemcpyAsync(c->d_ids, ids->data(), ids->size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
         "ids upload");
     chk(hipStreamSynchronize(st), "ids upload sync");
-    launch_reduce_j(c->d_subs, int(ids->size()), c->d_ids, c->jpart, c->jconst, J, c->nonfinite, st);
+    launch_reduce_j(c->d_subs, int(ids->size()), c->d_ids, D.jpart, c->jconst, J, c->nonfinite, st);
   } else {
-    launch_reduce_j(c->d_subs, c->nsub, nullptr, c->jpart, c->jconst, J, c->nonfinite, st);
+    launch_reduce_j(c->d_subs, c->nsub, nullptr, D.jpart, c->jconst, J, c->nonfinite, st);
   }
   chk(hipGetLastError(), "reduce launch");
   mark(c, 3, st);
@@ -565,6 +582,17 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
   c->nsub = P.nsub;
   const size_t tsz = c->prec == DD4DVAR_FP64 ? sizeof(double) : sizeof(float);
   chk(hipGetDevice(&c->device), "hipGetDevice");
+  {
+    // this device's static scratch (set-up of the no-allocation entry point)
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    auto it = scratch_addr.find(c->device);
+    if (it == scratch_addr.end()) {
+      void* ptr = nullptr;
+      chk(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+      it = scratch_addr.emplace(c->device, static_cast<double*>(ptr)).first;
+    }
+    c->scratch = it->second;
+  }
 
   // subdomain table and tiles
   int64_t ring_off = 0, adj_off = 0;
@@ -1017,6 +1045,37 @@ dd4dvar_status dd4dvar_local_cost_grad(dd4dvar_ctx* ctx, int32_t nsub, const int
     } else {
       cost_grad_impl<float>(ctx, &ids, x_dev, J_dev, grad_dev, st);
     }
+    return DD4DVAR_OK;
+  })
+}
+
+dd4dvar_status dd4dvar_local_cost_grad_noalloc(dd4dvar_ctx* ctx, const double* x_dev,
+                                               double* J_dev, double* grad_dev, void* stream) {
+  if (!ctx || !x_dev || !J_dev || !grad_dev) return fail(ctx, DD4DVAR_E_INVALID, "null argument");
+  if (int64_t(ctx->ntiles) > kScratchTiles)
+    return fail(ctx, DD4DVAR_E_INVALID,
+                "the no-allocation evaluation holds at most " + std::to_string(kScratchTiles) +
+                    " tile partials; this decomposition has " + std::to_string(ctx->ntiles));
+  if (!ctx->scratch) return fail(ctx, DD4DVAR_E_STATE, "no static scratch address for this device");
+  API_GUARD(ctx, {
+    // the same launches as local_cost_grad over all subdomains, eagerly (no
+    // graph, no timing events), with the tile partials in the static scratch;
+    // every partial is written before it is read, so nothing is cleared
+    struct Restore {
+      dd4dvar_ctx* c;
+      bool timing;
+      ~Restore() {
+        c->jpart_use = nullptr;
+        c->timing = timing;
+      }
+    } restore{ctx, ctx->timing};
+    ctx->jpart_use = ctx->scratch;
+    ctx->timing = false;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (ctx->prec == DD4DVAR_FP64)
+      cost_grad_impl<double>(ctx, nullptr, x_dev, J_dev, grad_dev, st);
+    else
+      cost_grad_impl<float>(ctx, nullptr, x_dev, J_dev, grad_dev, st);
     return DD4DVAR_OK;
   })
 }
