@@ -160,15 +160,15 @@ def gn_product_bytes(ctx, prec_bytes, persistent=False):
 # digest of the kernel sources they were measured on: a changed kernel (or
 # another workload) reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    "k_adj": ("sweep", "50119dc3cd847849", 1169127424),
-    "k_adj_box/10": ("box", "5163a4f8ff7c089b", 16116062003),
-    "k_adj_box/11": ("box", "5163a4f8ff7c089b", 16126791782),
-    "k_adj_strip/11": ("box", "5163a4f8ff7c089b", 17811491430),
-    "k_eval_box/10": ("box", "5163a4f8ff7c089b", 30707271168),
+    "k_adj": ("sweep", "a3890750a10c1e04", 1158224896),
+    "k_adj_box/10": ("box", "7ffac9ed169463fc", 16090328166),
+    "k_adj_box/11": ("box", "7ffac9ed169463fc", 16085872845),
+    "k_adj_strip/11": ("box", "7ffac9ed169463fc", 18003660902),
+    "k_eval_box/10": ("box", "7ffac9ed169463fc", 50101914931),
     # Gauss-Newton normal-matrix product: tangent-linear sweep (10 passes)
     # and the adjoint with the Gauss-Newton forcing (column strips, 11 rows)
-    "k_tlm_box/10": ("box", "5163a4f8ff7c089b", 16795425178),
-    "k_adj_strip_gn/11": ("box", "5163a4f8ff7c089b", 16550709862),
+    "k_tlm_box/10": ("box", "7ffac9ed169463fc", 16797900186),
+    "k_adj_strip_gn/11": ("box", "7ffac9ed169463fc", 16994204877),
 }
 KERNEL_SOURCES = {"sweep": ("sweep.hip", "kernels.h", "stencil.h"),
                   "box": ("box.hip", "kernels.h", "stencil.h")}

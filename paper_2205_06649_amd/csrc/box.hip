@@ -537,9 +537,11 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
   float* rowtab = lds + 3 * npad;          // [ny][8]
   float* zring = rowtab + 8 * ny;          // [2 levels][nring][3]: state on the ring
   uint8_t* covl = reinterpret_cast<uint8_t*>(zring + 6 * nring);   // [ny*nx] coverage
-  // per level: intervals covering it, observation entries of the box
+  // per level: intervals covering it, and where the box's observation
+  // entries of the level start ([nlev + 1]: level n's are lvl_ob[n] ..
+  // lvl_ob[n + 1] - 1, one contiguous range of the bins)
   int* lvl_tc = reinterpret_cast<int*>(covl + ((ncell + 3) & ~3));
-  int* lvl_obs = lvl_tc + S.nlev;
+  int* lvl_ob = lvl_tc + S.nlev;
   const int64_t plane = ncell;
   const int32_t* hsrc = D.hsrc + S.hmap_off;
   const int32_t* hoff = D.hoff + S.hmap_off;
@@ -569,15 +571,9 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
   for (int i = tid; i < ncell; i += kBoxThreads) covl[i] = D.cover[S.cell_off + i];
   // per-level tables, so that no level waits on a global load at its start
   // or before its barrier
-  for (int n = tid; n < S.nlev; n += kBoxThreads) {
-    lvl_tc[n] = (MODE != 1) ? D.tcount[S.lev0 + n] : 0;
-    int cnt = 0;
-    if (MODE != 1)
-      for (int t = 0; t < S.ntile; ++t) {
-        const int64_t key = int64_t(S.tile0 + t) * D.maxlev + n;
-        cnt += D.obs_ptr[key + 1] - D.obs_ptr[key];
-      }
-    lvl_obs[n] = cnt;
+  for (int n = tid; n <= S.nlev; n += kBoxThreads) {
+    if (n < S.nlev) lvl_tc[n] = (MODE != 1) ? D.tcount[S.lev0 + n] : 0;
+    lvl_ob[n] = (MODE != 1) ? D.obs_ptr[obs_key(S.tile0, S.ntile, D.maxlev, 0, n)] : 0;
   }
   // this thread's ring position: the source of its value at every level
   // (frozen ring entry, or the box's own cell with the across-pole sign)
@@ -756,7 +752,8 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
       cur = nxt;
     }
     // observations of this box at level n
-    const bool any_obs = MODE != 1 && lvl_obs[n] > 0;
+    const int ob0 = lvl_ob[n], ob1 = lvl_ob[n + 1];
+    const bool any_obs = MODE != 1 && ob1 > ob0;
     __syncthreads();                                   // all reads of lambda^{n+1} done
     if (ring_thread) {
       float* Zq = zring + ((n - 1) & 1) * 3 * nring + 3 * tid;
@@ -784,23 +781,22 @@ __device__ __forceinline__ void adj_box_body(const Dom<float>& D, const double* 
     }
     if (MODE != 1 && any_obs) {
       __syncthreads();                                   // lambda^n (or the gradient) complete
-      for (int t = 0; t < S.ntile; ++t) {
-        const int64_t key = int64_t(S.tile0 + t) * D.maxlev + n;
-        const int o0 = D.obs_ptr[key], o1 = D.obs_ptr[key + 1];
-        for (int o = o0 + tid; o < o1; o += kBoxThreads) {
-          const int code = D.obs_code[o];
-          const int loc = code >> 2, f = code & 3;
-          const double rr = MODE == 3 ? double(D.dz[S.zoff + int64_t(n) * 3 * plane + f * plane + loc])
-                                      : double(Z[f * plane + loc]) - D.obs_val[o];
-          const double qo = D.obs_q[o];
-          if (MODE != 3) jloc += 0.5 * qo * rr * rr;
-          if (n > 0) {
-            const int lr = loc / nx, lc = loc - lr * nx;
-            float* Lf = Lm + 3 * ((lr + 1) * nxp + lc + 1) + f;
-            *Lf = float(double(*Lf) + qo * rr);
-          } else {
-            out[S.ctrl_off + f * plane + loc] += qo * rr;
-          }
+      // the level's entries of every tile of the box in one range; a cell
+      // and field occur at most once per level (duplicate observations are
+      // rejected), so the updates of the frame never collide
+      for (int o = ob0 + tid; o < ob1; o += kBoxThreads) {
+        const int code = D.obs_code[o];
+        const int loc = code >> 2, f = code & 3;
+        const double rr = MODE == 3 ? double(D.dz[S.zoff + int64_t(n) * 3 * plane + f * plane + loc])
+                                    : double(Z[f * plane + loc]) - D.obs_val[o];
+        const double qo = D.obs_q[o];
+        if (MODE != 3) jloc += 0.5 * qo * rr * rr;
+        if (n > 0) {
+          const int lr = loc / nx, lc = loc - lr * nx;
+          float* Lf = Lm + 3 * ((lr + 1) * nxp + lc + 1) + f;
+          *Lf = float(double(*Lf) + qo * rr);
+        } else {
+          out[S.ctrl_off + f * plane + loc] += qo * rr;
         }
       }
     }
@@ -855,7 +851,7 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
   float* zring = rowtab + 8 * ny;          // [2 levels][nring][3]: state on the ring
   uint8_t* covl = reinterpret_cast<uint8_t*>(zring + 6 * nring);   // [ny*nx] coverage
   int* lvl_tc = reinterpret_cast<int*>(covl + ((ncell + 3) & ~3));
-  int* lvl_obs = lvl_tc + S.nlev;
+  int* lvl_ob = lvl_tc + S.nlev;           // [nlev + 1], as in the box mapping
   const int64_t plane = ncell;
   const int32_t* hsrc = D.hsrc + S.hmap_off;
   const int32_t* hoff = D.hoff + S.hmap_off;
@@ -891,15 +887,9 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
     Zr[0] = gv.h; Zr[1] = gv.u; Zr[2] = gv.v;
   }
   for (int i = tid; i < ncell; i += kBoxThreads) covl[i] = D.cover[S.cell_off + i];
-  for (int n = tid; n < S.nlev; n += kBoxThreads) {
-    lvl_tc[n] = (MODE != 1) ? D.tcount[S.lev0 + n] : 0;
-    int cnt = 0;
-    if (MODE != 1)
-      for (int t = 0; t < S.ntile; ++t) {
-        const int64_t key = int64_t(S.tile0 + t) * D.maxlev + n;
-        cnt += D.obs_ptr[key + 1] - D.obs_ptr[key];
-      }
-    lvl_obs[n] = cnt;
+  for (int n = tid; n <= S.nlev; n += kBoxThreads) {
+    if (n < S.nlev) lvl_tc[n] = (MODE != 1) ? D.tcount[S.lev0 + n] : 0;
+    lvl_ob[n] = (MODE != 1) ? D.obs_ptr[obs_key(S.tile0, S.ntile, D.maxlev, 0, n)] : 0;
   }
   const bool ring_thread0 = tid < nring;
   bool rfrozen = true;
@@ -1061,7 +1051,8 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
       __builtin_amdgcn_sched_barrier(0);
       cur = nxt;
     }
-    const bool any_obs = MODE != 1 && lvl_obs[n] > 0;
+    const int ob0 = lvl_ob[n], ob1 = lvl_ob[n + 1];
+    const bool any_obs = MODE != 1 && ob1 > ob0;
     __syncthreads();                                   // all reads of lambda^{n+1} done
     if (ring_thread) {
       float* Zq = zring + ((n - 1) & 1) * 3 * nring + 3 * tid;
@@ -1087,23 +1078,22 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
     }
     if (MODE != 1 && any_obs) {
       __syncthreads();
-      for (int t = 0; t < S.ntile; ++t) {
-        const int64_t key = int64_t(S.tile0 + t) * D.maxlev + n;
-        const int o0 = D.obs_ptr[key], o1 = D.obs_ptr[key + 1];
-        for (int o = o0 + tid; o < o1; o += kBoxThreads) {
-          const int code = D.obs_code[o];
-          const int loc = code >> 2, f = code & 3;
-          const double rr = MODE == 3 ? double(D.dz[S.zoff + int64_t(n) * 3 * plane + f * plane + loc])
-                                      : double(Z[f * plane + loc]) - D.obs_val[o];
-          const double qo = D.obs_q[o];
-          if (MODE != 3) jloc += 0.5 * qo * rr * rr;
-          if (n > 0) {
-            const int lr = loc / nx, lcc = loc - lr * nx;
-            float* Lf = Lm + 3 * ((lr + 1) * nxp + lcc + 1) + f;
-            *Lf = float(double(*Lf) + qo * rr);
-          } else {
-            out[S.ctrl_off + f * plane + loc] += qo * rr;
-          }
+      // the level's entries of every tile of the box in one range; a cell
+      // and field occur at most once per level (duplicate observations are
+      // rejected), so the updates of the frame never collide
+      for (int o = ob0 + tid; o < ob1; o += kBoxThreads) {
+        const int code = D.obs_code[o];
+        const int loc = code >> 2, f = code & 3;
+        const double rr = MODE == 3 ? double(D.dz[S.zoff + int64_t(n) * 3 * plane + f * plane + loc])
+                                    : double(Z[f * plane + loc]) - D.obs_val[o];
+        const double qo = D.obs_q[o];
+        if (MODE != 3) jloc += 0.5 * qo * rr * rr;
+        if (n > 0) {
+          const int lr = loc / nx, lcc = loc - lr * nx;
+          float* Lf = Lm + 3 * ((lr + 1) * nxp + lcc + 1) + f;
+          *Lf = float(double(*Lf) + qo * rr);
+        } else {
+          out[S.ctrl_off + f * plane + loc] += qo * rr;
         }
       }
     }
@@ -1182,7 +1172,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_eval_box(Dom<float> D, const do
 // coverage byte of every cell and two ints per level
 size_t box_lds_bytes(int ny, int nx, int nring, int nlev) {
   return size_t(3 * (ny + 2) * (nx + 2) + 8 * ny + 6 * nring) * sizeof(float) +
-         ((size_t(ny) * nx + 3) & ~size_t(3)) + 2 * size_t(nlev) * sizeof(int);
+         ((size_t(ny) * nx + 3) & ~size_t(3)) + (2 * size_t(nlev) + 1) * sizeof(int);
 }
 
 // passes of 1024 cells the persistent kernels run for a box (0 when the box

@@ -704,7 +704,8 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
     if (cc < 0) cc += nlon;
     const int loc = (row - b.row0) * b.nx + cc;
     *loc_out = loc;
-    return int64_t(c->subs[s].tile0 + loc / kTile) * c->maxlev + (P.obs_step[k] - b.lev0);
+    const SubDev& S = c->subs[s];
+    return obs_key(S.tile0, S.ntile, c->maxlev, loc / kTile, P.obs_step[k] - b.lev0);
   };
   for (int s = 0; s < P.nsub; ++s)
     for (int64_t q = P.obs_ptr[s]; q < P.obs_ptr[s + 1]; ++q) {

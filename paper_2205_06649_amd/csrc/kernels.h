@@ -19,6 +19,16 @@ __device__ __forceinline__ int xcd_tile(int i, int nblocks) {
   return x * per + (x < rem ? x : rem) + k;
 }
 
+// Key of the observation bin of (tile t_local of a box, level n) in the CSR
+// over bins.  A box's bins are ordered by level, then by tile: the entries of
+// one tile at one level form one range (the step kernels), and so do the
+// entries of the whole box at one level (the per-box kernels:
+// obs_key(.., 0, n) .. obs_key(.., 0, n + 1)).  Bijective from [0, maxlev) x
+// [0, ntile) onto the box's keys [tile0 maxlev, (tile0 + ntile) maxlev).
+__host__ __device__ inline int64_t obs_key(int tile0, int ntile, int maxlev, int t_local, int n) {
+  return int64_t(tile0) * maxlev + int64_t(n) * ntile + t_local;
+}
+
 // One subdomain (or the whole grid) as the kernels see it.
 struct SubDev {
   int32_t row0, ny, col0, nx;
@@ -60,7 +70,7 @@ struct Dom {
   const T* cosx;             // [nlat+2]: cos of rows -1..nlat (pole-mapped)
   const uint8_t* cover;      // spatial coverage count per box cell
   const int32_t* tcount;     // temporal coverage count per global level
-  const int32_t* obs_ptr;    // CSR over (tile, level)
+  const int32_t* obs_ptr;    // CSR over the (tile, level) bins, keyed by obs_key
   const int32_t* obs_code;   // local cell * 4 + field
   const double* obs_val;     // value (h as anomaly)
   const double* obs_q;       // lambda * w_o / sigma_o^2

@@ -413,7 +413,7 @@ __global__ __launch_bounds__(kTile) void k_adj_tz(Dom<T> D, int n, int tile_base
     fu = Fz[plane + mm];
     fv = Fz[2 * plane + mm];
   } else {
-    const int64_t key = int64_t(w) * D.maxlev + n;
+    const int64_t key = obs_key(S.tile0, S.ntile, D.maxlev, wt.y, n);
     const int o0 = D.obs_ptr[key], o1 = D.obs_ptr[key + 1];
     if (o1 > o0) {
       fo[0][threadIdx.x] = 0.0;
