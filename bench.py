@@ -161,14 +161,14 @@ def gn_product_bytes(ctx, prec_bytes, persistent=False):
 # another workload) reports null until it is measured again.
 MEASURED_TRAFFIC = {
     "k_adj": ("sweep", "a3890750a10c1e04", 1158224896),
-    "k_adj_box/10": ("box", "7ffac9ed169463fc", 16090328166),
-    "k_adj_box/11": ("box", "7ffac9ed169463fc", 16085872845),
-    "k_adj_strip/11": ("box", "7ffac9ed169463fc", 18003660902),
-    "k_eval_box/10": ("box", "7ffac9ed169463fc", 50101914931),
+    "k_adj_box/10": ("box", "727178289b323131", 16096635494),
+    "k_adj_box/11": ("box", "727178289b323131", 16092319027),
+    "k_adj_strip/11": ("box", "727178289b323131", 16662557491),
+    "k_eval_box/10": ("box", "727178289b323131", 50178714931),
     # Gauss-Newton normal-matrix product: tangent-linear sweep (10 passes)
     # and the adjoint with the Gauss-Newton forcing (column strips, 11 rows)
-    "k_tlm_box/10": ("box", "7ffac9ed169463fc", 16797900186),
-    "k_adj_strip_gn/11": ("box", "7ffac9ed169463fc", 16994204877),
+    "k_tlm_box/10": ("box", "727178289b323131", 16795245773),
+    "k_adj_strip_gn/11": ("box", "727178289b323131", 15643503104),
 }
 KERNEL_SOURCES = {"sweep": ("sweep.hip", "kernels.h", "stencil.h"),
                   "box": ("box.hip", "kernels.h", "stencil.h")}

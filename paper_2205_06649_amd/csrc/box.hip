@@ -19,6 +19,8 @@
 // tracks the row and column of its cell incrementally from pass to pass.
 // These kernels need every level stored (no checkpoints): level n of a box
 // sits at slot n of its state arena.
+#include <type_traits>
+
 #include "kernels.h"
 #include "launch.h"
 #include "stencil.h"
@@ -833,8 +835,9 @@ __global__ __launch_bounds__(kBoxThreads) void k_fwd_box(Dom<float> D, const dou
 // a cell costs 10 buffer loads (its north state, east and west u, v, the
 // overlap target) instead of 14 and 9 LDS reads of lambda instead of 15; a
 // thread's column and its east/west edge masks are fixed for the whole
-// sweep.  Arithmetic, forcing, ring staging, observations and outputs as in
-// adj_box_body.
+// sweep.  Waves none of whose lanes has a row left skip the loads of the
+// remaining passes.  Arithmetic, forcing, ring staging, observations and
+// outputs as in adj_box_body.
 template <int K, int MODE, bool SPAN>
 __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double* __restrict__ x,
                                                const double* __restrict__ xb,
@@ -847,7 +850,7 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
   const int L = S.nlev - 1;
   const int tid = threadIdx.x;
   float* Lm = lds;                         // [npad][3]: lambda^{n+1}
-  float* rowtab = lds + 3 * npad;          // [ny][8]
+  float* rowtab = lds + 3 * npad;          // [ny][8], see below
   float* zring = rowtab + 8 * ny;          // [2 levels][nring][3]: state on the ring
   uint8_t* covl = reinterpret_cast<uint8_t*>(zring + 6 * nring);   // [ny*nx] coverage
   int* lvl_tc = reinterpret_cast<int*>(covl + ((ncell + 3) & ~3));
@@ -879,7 +882,16 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
   const bool w_in = c > 0, e_in = c + 1 < nx;
   const uint64_t mw = __builtin_amdgcn_ballot_w64(w_in), me = __builtin_amdgcn_ballot_w64(e_in);
 
-  fill_rowtab(rowtab, D, S);
+  // per-row coefficients of the gather: a1, a2, a3, cf, ct, c, and a3 of the
+  // rows the north and south terms take (the row itself at the box edge)
+  for (int r = tid; r < ny; r += kBoxThreads) {
+    const int j = S.row0 + r;
+    const RowCoef<float> rc = D.rows[j];
+    float* q = rowtab + 8 * r;
+    q[0] = rc.a1; q[1] = rc.a2; q[2] = rc.a3; q[3] = rc.cf; q[4] = rc.ct; q[5] = rc.c;
+    q[6] = D.rows[r + 1 < ny ? j + 1 : j].a3;
+    q[7] = D.rows[r > 0 ? j - 1 : j].a3;
+  }
   for (int i = tid; i < 3 * npad; i += kBoxThreads) Lm[i] = 0.0f;   // lambda^{L+1} = 0
   for (int k = tid; k < nring; k += kBoxThreads) {
     const V3<float> gv = ring_value(D, S, k, L);
@@ -907,43 +919,56 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
   for (int k = 0; k < K; ++k) ln[0][k] = ln[1][k] = ln[2][k] = 0.0f;
   // byte offset of (r0, c) and LDS frame index of (ra, c)
   const int v00 = (r0 * nx + c) * 4, f00 = 3 * ((ra + 1) * nxp + c + 1);
+  // staged ring positions (float index) of the thread's column to the south
+  // (north: nx positions on) and of its first row to the west (east: ny
+  // positions on).  Every lane reads them for its rows inside the box, all
+  // valid positions; lanes inside the box discard the values.
+  const int zS = 3 * c, zW = 3 * (2 * nx + r0);
 
-  for (int n = L; n >= 0; --n) {
+  // one level of the sweep; the first level of the window (n = 0: the
+  // adjoint of the forward start's half step, and the gradient output) is a
+  // copy of its own, so that the passes of the other levels test nothing
+  auto level = [&](const int n, auto last_tag) {
+    constexpr bool LAST = decltype(last_tag)::value;
     const float* Z = D.traj + S.zoff + int64_t(n) * 3 * plane;
     const int so = __builtin_amdgcn_readfirstlane(n * lvb);
     const float* Zr = zring + (n & 1) * 3 * nring;
-    const int tcount = lvl_tc[n];
+    // overlap weight mu K of a cell with coverage byte cov: K = cov tcount - 1
+    // other boxes hold it at this level (exact in FP32, as K is an integer
+    // below 2^24)
+    const float tcf = float(lvl_tc[n]);
     V3<float> gnext = {0.f, 0.f, 0.f};
-    const bool ring_thread = ring_thread0 && n > 0;
+    const bool ring_thread = ring_thread0 && !LAST;
     if (ring_thread) {
       const float* src = rfrozen ? D.ring + S.ring_off + int64_t(n - 1) * 3 * nring + roff
                                  : D.traj + S.zoff + int64_t(n - 1) * 3 * plane + roff;
       const int64_t fs = rfrozen ? int64_t(nring) : plane;
       gnext = {src[0], rsg * src[fs], rsg * src[2 * fs]};
     }
-    // loads of the pass for row r: the state of row r+1 (clamped to row r on
-    // the last row), east and west u, v (clamped at the box edge) and the
-    // overlap target where covered; past the box end in-range and unused
+    // loads of the pass for the row at byte offset v: the state of the row
+    // to the north, east and west u, v, and the overlap target where covered.
+    // The neighbour offsets ride on the scalar offset (one row on, one cell
+    // either way); a neighbour outside the box (north of the last row, east
+    // of the last column, west of the first) is read at the position those
+    // offsets reach inside the arena and replaced by the staged ring.  Rows
+    // past the box are read the same way and discarded.
     struct RowLoads {
       V3<float> Cn, tg;
-      float Eu, Ev, Wu, Wv;
-      int Kc;
+      float Eu, Ev, Wu, Wv, mk;
     };
-    auto issue = [&](int r, int v) {
+    auto issue = [&](int v) {
       RowLoads Q;
-      const int vn = r + 1 < ny ? v + nx4 : v;
-      Q.Cn = bload3(zrs, vn, so, fp);
-      const int ve = e_in ? v + 4 : v, vw = w_in ? v - 4 : v;
-      Q.Eu = bload(zrs, ve, so + fp);
-      Q.Ev = bload(zrs, ve, so + 2 * fp);
-      Q.Wu = bload(zrs, vw, so + fp);
-      Q.Wv = bload(zrs, vw, so + 2 * fp);
-      Q.Kc = 0;
+      Q.Cn = bload3(zrs, v, so + nx4, fp);
+      Q.Eu = bload(zrs, v, so + fp + 4);
+      Q.Ev = bload(zrs, v, so + 2 * fp + 4);
+      Q.Wu = bload(zrs, v, so + fp - 4);
+      Q.Wv = bload(zrs, v, so + 2 * fp - 4);
+      Q.mk = 0.f;
       Q.tg = {0.f, 0.f, 0.f};
       if (MODE != 1) {
         const int mc = v >> 2;
-        Q.Kc = int(covl[mc < ncell ? mc : ncell - 1]) * tcount - 1;
-        Q.tg = bload3(trs, Q.Kc > 0 ? v : 0, so, fp);
+        Q.mk = mu_f * __builtin_fmaf(float(covl[mc < ncell ? mc : ncell - 1]), tcf, -1.0f);
+        Q.tg = bload3(trs, Q.mk > 0.f ? v : 0, so, fp);
       }
       return Q;
     };
@@ -957,13 +982,16 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
     V3<float> Cc = bload3(zrs, v0, so, fp);
     const float* L0 = Lm + fb;
     V3<float> lp = lds3(L0, -n3), lc = lds3(L0, 0);   // lambda^{n+1} of rows r0-1, r0
-    RowLoads cur = issue(rb, v0);
+    // waves none of whose lanes has a row left issue no loads
+    RowLoads cur{};
+    if (__builtin_amdgcn_ballot_w64(0 < nr) != 0) cur = issue(v0);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int r = rb + k;
       const int v = v0 + k * nx4;
-      RowLoads nxt = cur;
-      if (k + 1 < K) nxt = issue(r + 1, v + nx4);
+      // (zero in a wave without rows left: never used there)
+      RowLoads nxt{};
+      if (k + 1 < K && __builtin_amdgcn_ballot_w64(k + 1 < nr) != 0) nxt = issue(v + nx4);
       __builtin_amdgcn_sched_barrier(0);
       const float* Lc = L0 + (k < kk ? k : kk) * n3;
       const V3<float> ln1 = lds3(Lc, n3);            // lambda^{n+1} of row r+1
@@ -971,18 +999,17 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
         const int m = v >> 2;
         const bool n_in = r + 1 < ny, s_in = r > 0;
         const float* rw = rowtab + 8 * r;
-        const RowK rk = {rw[0], rw[1], rw[3], rw[4], rw[5], rowtab[8 * (n_in ? r + 1 : r) + 2],
-                         rowtab[8 * (s_in ? r - 1 : r) + 2]};
+        const RowK rk = {rw[0], rw[1], rw[3], rw[4], rw[5], rw[6], rw[7]};
         const V3<float> C = Cc;
-        const V3<float> rE = lds3(Zr, e_in ? 0 : 3 * (2 * nx + ny + r));
-        const V3<float> rW = lds3(Zr, w_in ? 0 : 3 * (2 * nx + r));
+        const V3<float> rE = lds3(Zr + 3 * ny, zW + 3 * k);
+        const V3<float> rW = lds3(Zr, zW + 3 * k);
         const V3<float> E = pick3({0.f, cur.Eu, cur.Ev}, rE, me);
         const V3<float> W = pick3({0.f, cur.Wu, cur.Wv}, rW, mw);
         V3<float> N = cur.Cn, Sv = Cs;
         // rows at the box's south or north edge (wave-uniform test)
         if (__builtin_amdgcn_ballot_w64(!n_in || !s_in) != 0) {
-          N = pick3(N, lds3(Zr, n_in ? 0 : 3 * (nx + c)), __builtin_amdgcn_ballot_w64(n_in));
-          Sv = pick3(Sv, lds3(Zr, s_in ? 0 : 3 * c), __builtin_amdgcn_ballot_w64(s_in));
+          N = pick3(N, lds3(Zr + 3 * nx, zS), __builtin_amdgcn_ballot_w64(n_in));
+          Sv = pick3(Sv, lds3(Zr, zS), __builtin_amdgcn_ballot_w64(s_in));
         }
         const float sn = (SPAN && !n_in && S.pole_n) ? -1.0f : 1.0f;
         const float ss = (SPAN && !s_in && S.pole_s) ? -1.0f : 1.0f;
@@ -990,7 +1017,7 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
         const V3<float> gth = gather_cell(rk, st, stg, D.h0, C, E, W, N, Sv, l0, kE, kW, ln1, lp,
                                           sn, ss);
         float ah = gth.h, au = gth.u, av = gth.v;
-        if (n == 0) {
+        if (LAST) {
           au = l0.u + 0.5f * au;
           av = l0.v + 0.5f * av;
           ah = l0.h + 0.5f * ah;
@@ -1006,7 +1033,7 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
           const float eh = MODE == 3 ? tg.h : C.h - tg.h;
           const float eu = MODE == 3 ? tg.u : C.u - tg.u;
           const float ev = MODE == 3 ? tg.v : C.v - tg.v;
-          const float mk = mu_f * float(cur.Kc);
+          const float mk = cur.mk;
           fh = mk * ib_h * eh;
           fu = mk * ib_u * eu;
           fv = mk * ib_v * ev;
@@ -1016,7 +1043,7 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
         const float bh = fh + ah + ln[0][k];
         const float bu = fu + au + ln[1][k];
         const float bv = fv + av + ln[2][k];
-        if (n > 0) {
+        if (!LAST) {
           ln[0][k] = bh;
           ln[1][k] = bu;
           ln[2][k] = bv;
@@ -1058,7 +1085,7 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
       float* Zq = zring + ((n - 1) & 1) * 3 * nring + 3 * tid;
       Zq[0] = gnext.h; Zq[1] = gnext.u; Zq[2] = gnext.v;
     }
-    if (n > 0) {
+    if (!LAST) {
       // lambda^n into LDS; lambda^{n+1} into the registers
       int fs = f00, ns = nrows;
       asm volatile("" : "+v"(fs), "+v"(ns));
@@ -1088,7 +1115,7 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
                                     : double(Z[f * plane + loc]) - D.obs_val[o];
         const double qo = D.obs_q[o];
         if (MODE != 3) jloc += 0.5 * qo * rr * rr;
-        if (n > 0) {
+        if (!LAST) {
           const int lr = loc / nx, lcc = loc - lr * nx;
           float* Lf = Lm + 3 * ((lr + 1) * nxp + lcc + 1) + f;
           *Lf = float(double(*Lf) + qo * rr);
@@ -1098,11 +1125,13 @@ __device__ __forceinline__ void adj_strip_body(const Dom<float>& D, const double
       }
     }
     __syncthreads();
-    if (wraps && n > 0) {
+    if (wraps && !LAST) {
       fill_wraps(Lm, hsrc, hoff, hsgn, nring, nx, ny, false);
       __syncthreads();
     }
-  }
+  };
+  for (int n = L; n > 0; --n) level(n, std::false_type{});
+  level(0, std::true_type{});
   if (MODE == 0 || MODE == 2) {
     const double tot = block_sum_box(jloc, red);
     for (int t = tid + 1; t < S.ntile; t += kBoxThreads) D.jpart[S.tile0 + t] = 0.0;

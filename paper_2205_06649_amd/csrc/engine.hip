@@ -365,7 +365,7 @@ void local_adjoint(dd4dvar_ctx* c, int mode, const double* x, const double* forc
 void ensure_dz(dd4dvar_ctx* c) {
   if (c->dz) return;
   const size_t tsz = c->prec == DD4DVAR_FP64 ? sizeof(double) : sizeof(float);
-  c->dz = dalloc<char>(c, size_t(c->plan.traj_total) * tsz);
+  c->dz = dalloc<char>(c, size_t(c->plan.traj_total) * tsz + kBoxArenaTail);
 }
 
 // tangent-linear sweeps of every box (or of the boxes in c->eval_mask) about
@@ -802,8 +802,8 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
   chk(hipMemsetAsync(c->nonfinite, 0, sizeof(uint32_t), st), "memset");
   // large arenas
   c->traj_bytes = size_t(P.traj_total) * tsz;
-  c->traj = dalloc<char>(c, c->traj_bytes);
-  c->targ = dalloc<char>(c, size_t(P.traj_total) * tsz);
+  c->traj = dalloc<char>(c, c->traj_bytes + kBoxArenaTail);
+  c->targ = dalloc<char>(c, size_t(P.traj_total) * tsz + kBoxArenaTail);
   c->ring_bytes = size_t(std::max<int64_t>(ring_off, 1)) * tsz;
   c->ring = dalloc<char>(c, c->ring_bytes);
   c->adj = dalloc<char>(c, size_t(std::max<int64_t>(adj_off, 1)) * tsz);
@@ -1120,7 +1120,7 @@ dd4dvar_status dd4dvar_set_checkpointing(dd4dvar_ctx* ctx, int32_t stride, int64
     }
     ctx->graphs.clear();
     void* fresh = nullptr;
-    chk(hipMalloc(&fresh, bytes), "hipMalloc state arena");
+    chk(hipMalloc(&fresh, bytes + kBoxArenaTail), "hipMalloc state arena");
     auto& owned = ctx->mem.owned;
     owned.erase(std::remove(owned.begin(), owned.end(), ctx->traj), owned.end());
     (void)hipFree(ctx->traj);

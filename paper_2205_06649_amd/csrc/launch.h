@@ -63,6 +63,16 @@ void launch_tlm_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int
                    int nlat, hipStream_t st);
 
 // box.hip: persistent per-box sweeps (FP32 state)
+//
+// Their loads of the state, target and tangent-linear arenas may reach past
+// a box's last level: lanes whose rows or cells lie past the box read at
+// addresses that follow the pattern of the lanes inside it, and discard the
+// values.  The offset past the last level's end is below (1024 div nx + K +
+// 2) rows of nx cells plus one cell (column strips) or 1024 + nx + 1 cells
+// (cells t + 1024 k), under 64 KiB for nx <= 1022 and K <= 11; every arena
+// those kernels read is allocated with this many bytes after its end, so
+// that all their loads stay inside the allocation.
+constexpr size_t kBoxArenaTail = size_t(64) * 1024;
 size_t box_lds_bytes(int ny, int nx, int nring, int nlev);
 int box_passes(int ny, int nx, int nring, int nlev);
 int box_passes_max();
