@@ -85,6 +85,12 @@ struct dd4dvar_ctx {
   // Turkel-Zwas variant (tz_p > 0): step kernels only
   int tz_p = 0, tz_q = 1;
   double tz_alpha = 0;
+  // column-walk adjoint of the variant (q = 2): work list of every box's
+  // waves (box by box), each box's range in it, available / in use
+  TzWork* tz_work = nullptr;
+  int tz_nwork = 0;
+  std::vector<int> tz_work_box;
+  bool tz_col_ok = false, tz_col = false;
   // state storage: every level (ckpt = 0), or checkpoint pairs every ckpt
   // levels plus one segment that the adjoint recomputes
   int ckpt = 0;
@@ -269,8 +275,26 @@ template <typename T>
 void adj_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int ntiles, int mode,
               const double* x, const double* forcing, double* out, hipStream_t st) {
   if (c->tz_p > 0) {
+    // the column-walk kernel takes the waves of the launched boxes: all of
+    // them, or those of the one box whose tiles these are
+    const TzWork* work = nullptr;
+    int nwork = 0;
+    if (c->tz_col) {
+      if (tile_base == 0 && ntiles == c->ntiles) {
+        work = c->tz_work;
+        nwork = c->tz_nwork;
+      } else {
+        for (size_t s = 0; s < c->subs.size(); ++s)
+          if (c->subs[s].tile0 == tile_base) {
+            work = c->tz_work + c->tz_work_box[s];
+            nwork = c->tz_work_box[s + 1] - c->tz_work_box[s];
+            break;
+          }
+        if (!work) throw DevError{DD4DVAR_E_INVALID, "adjoint launch over an unknown tile range"};
+      }
+    }
     launch_adj_tz<T>(D, n, tile_base, ntiles, mode, c->tz_p, c->tz_q, c->tz_alpha,
-                     c->plan.model.nlat, x, c->xb, forcing, out, st);
+                     c->plan.model.nlat, x, c->xb, forcing, out, work, nwork, st);
   } else {
     launch_adj<T>(D, n, tile_base, ntiles, mode, x, c->xb, forcing, out, st);
   }
@@ -811,6 +835,50 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
     c->tz_p = P.model.tz_p;
     c->tz_q = P.model.tz_q;
     c->tz_alpha = P.model.tz_alpha;
+    // column-walk adjoint (q = 2, p <= 8): each box in column blocks of
+    // 64 - 2p outputs and row strips of at least 16 rows, at most one wave
+    // per 256-cell tile of the box (each wave owns one J slot of the box)
+    if (c->tz_q == 2 && c->tz_p <= 8) {
+      const int cw = 64 - 2 * c->tz_p;
+      std::vector<TzWork> wl;
+      std::vector<int> wb(c->subs.size() + 1, 0);
+      bool ok = true;
+      for (size_t s = 0; s < c->subs.size() && ok; ++s) {
+        const SubDev& S = c->subs[s];
+        wb[s] = int(wl.size());
+        const int ncb = (S.nx + cw - 1) / cw;
+        if (ncb > S.ntile) {
+          ok = false;
+          break;
+        }
+        const int maxstrips = S.ntile / ncb;
+        const int R = std::max(16, (S.ny + maxstrips - 1) / maxstrips);
+        const int nstr = (S.ny + R - 1) / R;
+        int j = 0;
+        for (int cb = 0; cb < ncb; ++cb)
+          for (int k = 0; k < nstr; ++k, ++j) {
+            TzWork w{};
+            w.box = int32_t(s);
+            w.c0 = cb * cw;
+            w.r0 = k * R;
+            w.r1 = std::min(S.ny, (k + 1) * R);
+            w.slot = S.tile0 + j;
+            w.zero0 = w.zero1 = 0;
+            if (j == 0) {
+              w.zero0 = S.tile0 + ncb * nstr;
+              w.zero1 = S.tile0 + S.ntile;
+            }
+            wl.push_back(w);
+          }
+      }
+      if (ok && !wl.empty()) {
+        wb.back() = int(wl.size());
+        c->tz_work = upload(c, wl, st);
+        c->tz_nwork = int(wl.size());
+        c->tz_work_box = wb;
+        c->tz_col_ok = c->tz_col = true;
+      }
+    }
   }
   chk(hipMemsetAsync(c->ring, 0, size_t(std::max<int64_t>(ring_off, 1)) * tsz, st), "memset ring");
   chk(hipMemsetAsync(c->targ, 0, size_t(P.traj_total) * tsz, st), "memset targets");
@@ -960,6 +1028,22 @@ dd4dvar_status dd4dvar_set_exec_plan(dd4dvar_ctx* ctx, int32_t mode, int32_t pas
   const dd4dvar_status s = dd4dvar_set_exec_mode(ctx, mode);
   if (s != DD4DVAR_OK) return s;
   if (mode >= 2) ctx->box_k = passes ? passes : ctx->box_kmin;
+  return DD4DVAR_OK;
+}
+
+dd4dvar_status dd4dvar_set_tz_adjoint(dd4dvar_ctx* ctx, int32_t kind) {
+  if (!ctx || kind < 0 || kind > 1) return fail(ctx, DD4DVAR_E_INVALID, "bad Turkel-Zwas adjoint kind");
+  if (kind == 1 && !ctx->tz_col_ok)
+    return fail(ctx, DD4DVAR_E_INVALID,
+                "the column-walk adjoint needs the Turkel-Zwas variant with q = 2 and p <= 8");
+  ctx->tz_col = kind == 1;
+  return DD4DVAR_OK;
+}
+
+dd4dvar_status dd4dvar_get_tz_adjoint(const dd4dvar_ctx* ctx, int32_t out[2]) {
+  if (!ctx || !out) return fail(const_cast<dd4dvar_ctx*>(ctx), DD4DVAR_E_INVALID, "null argument");
+  out[0] = ctx->tz_col ? 1 : 0;
+  out[1] = ctx->tz_col_ok ? 1 : 0;
   return DD4DVAR_OK;
 }
 

@@ -54,10 +54,19 @@ void launch_dz_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hipS
 template <typename T>
 void launch_fwd_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
                    int nlat, hipStream_t st);
+// one wave's share of the column-walk Turkel-Zwas adjoint (offset q = 2):
+// box, first column of its outputs' block (c0, lanes p .. 63 - p), rows
+// r0 .. r1 - 1, its J slot, and the box's J slots no wave writes
+// [zero0, zero1) (set on the box's first wave only)
+struct TzWork {
+  int32_t box, c0, r0, r1, slot, zero0, zero1, pad_;
+};
+// work == nullptr: the gather kernel (one thread per cell, any p, q)
 template <typename T>
 void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, int p, int q,
                    double alpha, int nlat, const double* x, const double* xb,
-                   const double* forcing, double* out, hipStream_t st);
+                   const double* forcing, double* out, const TzWork* work, int nwork,
+                   hipStream_t st);
 template <typename T>
 void launch_tlm_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
                    int nlat, hipStream_t st);

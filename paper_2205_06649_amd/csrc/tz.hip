@@ -493,6 +493,328 @@ __global__ __launch_bounds__(kTile) void k_adj_tz(Dom<T> D, int n, int tile_base
   }
 }
 
+// ---------------------------------------------------------------------------
+// Column-walk adjoint for the q = 2 offset.  One wave owns the columns
+// c0 - p .. c0 + 63 - p of one box (its outputs are the columns of the box
+// among lanes p .. 63 - p) and walks the rows r0 .. r1 - 1.  Every lane keeps,
+// for its column, the state and lambda^{n+1} of the rows r - 2 .. r + 2 in
+// registers: the values the 13-point stencil reads there (box cells, frozen
+// pad values, or box cells across a pole with u, v negated), and lambda only
+// at box cells (zero elsewhere: no reader lives there).  It loads one new row
+// per step, one step ahead, and takes the other columns from the lanes p
+// (through the LDS crossbar) and 1 (DPP wave shifts) to either side; the
+// forcing's loads of a step (lambda^{n+2}, the overlap target) are issued
+// before its arithmetic, with the coverage byte fetched one step ahead.  The
+// 12 in-box readers of a cell are the points of its
+// own stencil at the opposite offsets, so the window serves both, and a
+// reader outside the box contributes zero.  Arithmetic and its order as in
+// k_adj_tz (own terms, readers 1 .. 12, readers across a pole, summed in
+// FP64); the observation forcing is added afterwards by k_obs_tz, and each
+// wave's share of J goes to its own slot of the box's tile accumulators.
+constexpr int kColQ = 2;
+constexpr int kColThreads = 256;
+
+template <typename T>
+struct WinRow {
+  V3<T> z, l;
+};
+
+// window entry of box row rr (-2 .. ny + 1) and column col (wrapped into the
+// box for a box spanning the circle, -p .. nx + p - 1 otherwise)
+template <typename T>
+__device__ __forceinline__ WinRow<T> win_load(const SubDev& S, const T* Z, const T* R, const T* L1,
+                                              int64_t plane, int rr, int col, bool col_ok,
+                                              bool has1, int p, int half, int nlat) {
+  WinRow<T> w;
+  w.z = {T(0), T(0), T(0)};
+  w.l = {T(0), T(0), T(0)};
+  if (col_ok) {
+    const Pt P = point(S, rr, col, 0, 0, p, kColQ, half, nlat);
+    w.z = ld_pt(Z, R, plane, S.nring, P);
+    if (has1 && !P.pad && !P.across) w.l = ld_box(L1, plane, P.idx, T(1));
+  }
+  return w;
+}
+
+template <typename T>
+__device__ __forceinline__ WinRow<T> win_shfl(const WinRow<T>& w, int src) {
+  WinRow<T> o;
+  o.z = {__shfl(w.z.h, src, 64), __shfl(w.z.u, src, 64), __shfl(w.z.v, src, 64)};
+  o.l = {__shfl(w.l.h, src, 64), __shfl(w.l.u, src, 64), __shfl(w.l.v, src, 64)};
+  return o;
+}
+
+
+// value of the lane one above (wave_shl:1) or one below (wave_shr:1) in the wave
+template <typename T>
+__device__ __forceinline__ T lane_next(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+  } else {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x130, 0xf, 0xf, false);
+    return __builtin_bit_cast(T, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+  }
+}
+template <typename T>
+__device__ __forceinline__ T lane_prev(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+  } else {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x138, 0xf, 0xf, false);
+    return __builtin_bit_cast(T, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+  }
+}
+template <typename T>
+__device__ __forceinline__ WinRow<T> win_next(const WinRow<T>& w) {
+  return {{lane_next(w.z.h), lane_next(w.z.u), lane_next(w.z.v)}, {lane_next(w.l.h), lane_next(w.l.u), lane_next(w.l.v)}};
+}
+template <typename T>
+__device__ __forceinline__ WinRow<T> win_prev(const WinRow<T>& w) {
+  return {{lane_prev(w.z.h), lane_prev(w.z.u), lane_prev(w.z.v)}, {lane_prev(w.l.h), lane_prev(w.l.u), lane_prev(w.l.v)}};
+}
+// coefficient row of box row rr, mirrored across a pole
+__device__ __forceinline__ int grow_of(const SubDev& S, int rr, int nlat) {
+  const int g = S.row0 + rr;
+  return g < 0 ? -1 - g : (g >= nlat ? 2 * nlat - 1 - g : g);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kColThreads) void k_adj_tz_col(Dom<T> D, int n,
+                                                            const TzWork* __restrict__ work,
+                                                            int nwork, int p, T alpha, int nlat,
+                                                            const double* __restrict__ x,
+                                                            const double* __restrict__ xb,
+                                                            const double* __restrict__ forcing,
+                                                            double* __restrict__ out) {
+  // consecutive work items (the strips of one box column) on one XCD
+  // (uniform over the wave: its work item, box and rows live in scalar registers)
+  const int wv = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * (kColThreads / 64) +
+                                                int(threadIdx.x >> 6));
+  if (wv >= nwork) return;                 // whole waves; no workgroup barrier below
+  const TzWork wk = work[wv];
+  if (D.active && !D.active[wk.box]) return;
+  const SubDev S = D.subs[wk.box];
+  const int L = S.nlev - 1;
+  if (n > L) return;
+  const int lane = int(threadIdx.x & 63);
+  const int nx = S.nx, ny = S.ny;
+  const int c = wk.c0 + lane - p;           // this lane's column
+  const bool out_lane = lane >= p && lane < 64 - p && c < nx;
+  const bool col_ok = S.span || c < nx + p;
+  const int colw = S.span ? ((c % nx) + nx) % nx : c;
+  const int64_t plane = S.ncell;
+  const T* Z = zlevel(D, S, n);
+  const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
+  T* A = D.adj + S.adj_off;
+  const bool has1 = n + 1 <= L, has2 = n + 2 <= L;
+  const T* L1 = A + int64_t((n + 1) % 3) * 3 * plane;
+  const T* L2 = A + int64_t((n + 2) % 3) * 3 * plane;
+  const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
+  const T tp = T(p), tq = T(kColQ);
+  const int q = kColQ;
+  const int hl = D.half;
+  const int lEp = min(lane + p, 63), lWp = max(lane - p, 0);
+  double jloc = 0.0;
+
+  WinRow<T> w[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+    w[i] = win_load(S, Z, R, L1, plane, wk.r0 - 2 + i, colw, col_ok, has1, p, hl, nlat);
+  WinRow<T> pf = w[4];
+  // coverage byte of the lane's cell in the step's row, one step ahead
+  const int tcn = MODE != 1 ? D.tcount[S.lev0 + n] : 0;
+  int cov = (MODE != 1 && out_lane) ? int(D.cover[S.cell_off + wk.r0 * nx + c]) : 0;
+  for (int r = wk.r0; r < wk.r1; ++r) {
+    if (r > wk.r0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[i] = w[i + 1];
+      w[4] = pf;
+    }
+    const int cov_r = cov;
+    if (r + 1 < wk.r1) {
+      pf = win_load(S, Z, R, L1, plane, r + 3, colw, col_ok, has1, p, hl, nlat);
+      if (MODE != 1 && out_lane) cov = int(D.cover[S.cell_off + (r + 1) * nx + c]);
+    }
+    // the other columns' values: row r at lanes +-1 and +-p, rows r +- q at
+    // lanes +-p (every lane takes part in the exchange)
+    const WinRow<T> E1 = win_next(w[2]), W1 = win_prev(w[2]);
+    const WinRow<T> Ep = win_shfl(w[2], lEp), Wp = win_shfl(w[2], lWp);
+    const WinRow<T> EN = win_shfl(w[4], lEp), WN = win_shfl(w[4], lWp);
+    const WinRow<T> ES = win_shfl(w[0], lEp), WS = win_shfl(w[0], lWp);
+    if (!out_lane) continue;
+    const int m = r * nx + c;
+    // the forcing's loads, issued before the step's arithmetic
+    V3<T> l2 = {T(0), T(0), T(0)};
+    if (has2) l2 = ld_box(L2, plane, m, T(1));
+    const int K = cov_r * tcn - 1;
+    V3<T> tg = {T(0), T(0), T(0)};
+    if (MODE == 3) tg = ld_box(D.dz + S.zoff + int64_t(n) * 3 * plane, plane, m, T(1));
+    else if (MODE != 1) tg = ld_box(D.targ + S.traj_off + int64_t(n) * 3 * plane, plane, K > 0 ? m : 0, T(1));
+    const RowCoef<T> rc = D.rows[S.row0 + r];
+    const RowCoef<T> rN = D.rows[grow_of(S, r + q, nlat)], rS = D.rows[grow_of(S, r - q, nlat)];
+    // rows of the readers above and below (clamped into the box: a reader
+    // outside it has lambda zero)
+    const RowCoef<T> rKs = D.rows[S.row0 + max(r - q, 0)], rKn = D.rows[S.row0 + min(r + q, ny - 1)];
+    const V3<T> C = w[2].z;
+    double ah = 0, au = 0, av = 0;
+    if (has1) {
+      const V3<T> lam = w[2].l;
+      {
+        const T Dl = ((one - al) * (Ep.z.u - Wp.z.u) + half * al * (EN.z.u - WN.z.u + ES.z.u - WS.z.u)) / tp;
+        const T Dt = ((one - al) * (w[4].z.v * rN.c - w[0].z.v * rS.c) +
+                      half * al * (EN.z.v * rN.c - ES.z.v * rS.c) +
+                      half * al * (WN.z.v * rN.c - WS.z.v * rS.c)) / tq;
+        ah += double(-lam.h * (rc.a1 * Dl + rc.a3 * Dt));
+        au += double(lam.u * (-rc.a1 * (E1.z.u - W1.z.u) + (one - al) * rc.ct * C.v) +
+                     lam.v * (-rc.a1 * (E1.z.v - W1.z.v) - (one - al) * (rc.cf + T(2) * rc.ct * C.u)) -
+                     lam.h * rc.a1 * (E1.z.h - W1.z.h));
+        av += double(lam.u * (-st * (w[3].z.u - w[1].z.u) + (one - al) * (rc.cf + rc.ct * C.u)) -
+                     lam.v * st * (w[3].z.v - w[1].z.v) - lam.h * st * (w[3].z.h - w[1].z.h));
+      }
+      // readers k = x - offset o: the stencil point at the opposite offset
+#pragma unroll
+      for (int o = 1; o < kOffs; ++o) {
+        const WinRow<T>& k = o == 1 ? W1 : o == 2 ? E1 : o == 3 ? w[1] : o == 4 ? w[3]
+                           : o == 5 ? Wp : o == 6 ? Ep : o == 7 ? w[0] : o == 8 ? w[4]
+                           : o == 9 ? WS : o == 10 ? ES : o == 11 ? WN : EN;
+        const RowCoef<T>& K = (o == 7 || o == 9 || o == 10) ? rKs : (o == 8 || o == 11 || o == 12) ? rKn : rc;
+        const V3<T> t = reader_term(o, k.l, k.z.h, k.z.u, k.z.v, K, rc, C.u, C.v, st, stg, h0, al, tp, tq);
+        ah += double(t.h);
+        au += double(t.u);
+        av += double(t.v);
+      }
+      // readers across a pole (a box spanning the circle): u, v negated
+      if (S.span) {
+        const int g = S.row0 + r;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const int o = a < 2 ? 3 + a : 5 + a;   // offsets 3, 4, 7 .. 12
+          const int dr = off_r(o, q);
+          const int gk = dr > 0 ? 2 * nlat - 1 - dr - g : -dr - 1 - g;
+          const bool reach = dr > 0 ? g >= nlat - dr : g <= -dr - 1;
+          if (!reach || gk < S.row0 || gk >= S.row0 + ny) continue;
+          int ck = c - off_c(o, p) - hl;
+          ck = ((ck % nx) + nx) % nx;
+          const int kk = (gk - S.row0) * nx + ck;
+          const V3<T> lk = ld_box(L1, plane, kk, T(1));
+          const V3<T> t = reader_term(o, lk, Z[kk], Z[plane + kk], Z[2 * plane + kk], D.rows[gk], rc,
+                                      -C.u, -C.v, st, stg, h0, al, tp, tq);
+          ah += double(t.h);
+          au -= double(t.u);
+          av -= double(t.v);
+        }
+      }
+    }
+    const V3<T> l0 = w[2].l;
+    double fh = 0, fu = 0, fv = 0;
+    if (MODE == 1) {
+      const double* Fz = forcing + S.traj_off + int64_t(n) * 3 * plane;
+      fh = Fz[m];
+      fu = Fz[plane + m];
+      fv = Fz[2 * plane + m];
+    }
+    if (n == 0) {
+      ah = double(l0.h) + 0.5 * ah;
+      au = double(l0.u) + 0.5 * au;
+      av = double(l0.v) + 0.5 * av;
+    }
+    if (MODE != 1) {
+      // overlap misfit, or in mode 3 the perturbation in its place
+      const double eh = MODE == 3 ? double(tg.h) : double(C.h) - double(tg.h);
+      const double eu = MODE == 3 ? double(tg.u) : double(C.u) - double(tg.u);
+      const double ev = MODE == 3 ? double(tg.v) : double(C.v) - double(tg.v);
+      const double mk = D.mu * double(K);
+      fh += mk * eh * D.isb2[0];
+      fu += mk * eu * D.isb2[1];
+      fv += mk * ev * D.isb2[2];
+      if (MODE != 3)
+        jloc += 0.5 * mk * (eh * eh * D.isb2[0] + eu * eu * D.isb2[1] + ev * ev * D.isb2[2]);
+    }
+    const double bh = fh + ah + double(l2.h);
+    const double bu = fu + au + double(l2.u);
+    const double bv = fv + av + double(l2.v);
+    if (n > 0) {
+      T* Bn = A + int64_t(n % 3) * 3 * plane;
+      Bn[m] = T(bh);
+      Bn[plane + m] = T(bu);
+      Bn[2 * plane + m] = T(bv);
+    } else if (MODE == 0) {
+      const int64_t o = S.ctrl_off + m;
+      const double wb = D.weight_mode ? 1.0 : 1.0 / double(D.cover[S.cell_off + m]);
+      const double dh = x[o] - xb[o];
+      const double du = x[o + plane] - xb[o + plane];
+      const double dv = x[o + 2 * plane] - xb[o + 2 * plane];
+      const double gh = wb * dh * D.isb2[0] + bh;
+      const double gu = wb * du * D.isb2[1] + bu;
+      const double gv = wb * dv * D.isb2[2] + bv;
+      out[o] = gh;
+      out[o + plane] = gu;
+      out[o + 2 * plane] = gv;
+      flag_nonfinite(D.nonfinite, !(isfinite(gh) && isfinite(gu) && isfinite(gv)));
+      jloc += 0.5 * wb * (dh * dh * D.isb2[0] + du * du * D.isb2[1] + dv * dv * D.isb2[2]);
+    } else {
+      const int64_t o = S.ctrl_off + m;
+      out[o] = bh;
+      out[o + plane] = bu;
+      out[o + 2 * plane] = bv;
+      flag_nonfinite(D.nonfinite, !(isfinite(bh) && isfinite(bu) && isfinite(bv)));
+    }
+  }
+  if (MODE == 0 || MODE == 2) {
+    // the wave's share of J (fixed reduction order) into its slot; at the
+    // box's first level the slots of no wave are cleared
+    double v = jloc;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) D.jpart[wk.slot] = (n == L) ? v : D.jpart[wk.slot] + v;
+    if (n == L)
+      for (int t = wk.zero0 + lane; t < wk.zero1; t += 64) D.jpart[t] = 0.0;
+  }
+}
+
+// observation forcing of the column-walk adjoint at level n: for every entry
+// of a (tile, level) bin, q_o (Z - y) (or q_o dZ in mode 3) added to
+// lambda^n, or at level 0 to the gradient / adj0; its share of J added to
+// the tile's accumulator.  A cell and field occur at most once per level.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kTile) void k_obs_tz(Dom<T> D, int n, int tile_base,
+                                                  double* __restrict__ out) {
+  __shared__ double red[kTile / 64];
+  const int w = tile_base + xcd_tile(blockIdx.x, gridDim.x);
+  const int2 wt = D.tiles[w];
+  if (D.active && !D.active[wt.x]) return;
+  const SubDev S = D.subs[wt.x];
+  if (n > S.nlev - 1) return;
+  const int64_t key = obs_key(S.tile0, S.ntile, D.maxlev, wt.y, n);
+  const int o0 = D.obs_ptr[key], o1 = D.obs_ptr[key + 1];
+  if (o1 <= o0) return;                    // uniform over the block
+  const int64_t plane = S.ncell;
+  const T* Z = zlevel(D, S, n);
+  T* An = D.adj + S.adj_off + int64_t(n % 3) * 3 * plane;
+  double jloc = 0.0;
+  for (int o = o0 + int(threadIdx.x); o < o1; o += kTile) {
+    const int code = D.obs_code[o];
+    const int loc = code >> 2, f = code & 3;
+    const double rr = MODE == 3 ? double(D.dz[S.zoff + int64_t(n) * 3 * plane + f * plane + loc])
+                                : double(Z[f * plane + loc]) - D.obs_val[o];
+    const double qo = D.obs_q[o];
+    if (MODE != 3) jloc += 0.5 * qo * rr * rr;
+    if (n > 0) {
+      T* a = An + f * plane + loc;
+      *a = T(double(*a) + qo * rr);
+    } else {
+      out[S.ctrl_off + f * plane + loc] += qo * rr;
+    }
+  }
+  if (MODE == 0 || MODE == 2) {
+    const double tot = block_sum(jloc, red);
+    if (threadIdx.x == 0) D.jpart[w] += tot;
+  }
+}
+
 template <typename T>
 void launch_fwd_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
                    int nlat, hipStream_t st) {
@@ -502,7 +824,32 @@ void launch_fwd_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int
 template <typename T>
 void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, int p, int q,
                    double alpha, int nlat, const double* x, const double* xb,
-                   const double* forcing, double* out, hipStream_t st) {
+                   const double* forcing, double* out, const TzWork* work, int nwork,
+                   hipStream_t st) {
+  if (work) {
+    // column walk (q = 2), then the observation forcing of the level
+    const int nb = (nwork + kColThreads / 64 - 1) / (kColThreads / 64);
+    if (nb == 0) return;
+    if (mode == 0)
+      hipLaunchKernelGGL((k_adj_tz_col<T, 0>), dim3(nb), dim3(kColThreads), 0, st, D, n, work, nwork,
+                         p, T(alpha), nlat, x, xb, forcing, out);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_adj_tz_col<T, 1>), dim3(nb), dim3(kColThreads), 0, st, D, n, work, nwork,
+                         p, T(alpha), nlat, x, xb, forcing, out);
+    else if (mode == 2)
+      hipLaunchKernelGGL((k_adj_tz_col<T, 2>), dim3(nb), dim3(kColThreads), 0, st, D, n, work, nwork,
+                         p, T(alpha), nlat, x, xb, forcing, out);
+    else
+      hipLaunchKernelGGL((k_adj_tz_col<T, 3>), dim3(nb), dim3(kColThreads), 0, st, D, n, work, nwork,
+                         p, T(alpha), nlat, x, xb, forcing, out);
+    if (mode == 0)
+      hipLaunchKernelGGL((k_obs_tz<T, 0>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, out);
+    else if (mode == 2)
+      hipLaunchKernelGGL((k_obs_tz<T, 2>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, out);
+    else if (mode == 3)
+      hipLaunchKernelGGL((k_obs_tz<T, 3>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, out);
+    return;
+  }
   if (mode == 0)
     hipLaunchKernelGGL((k_adj_tz<T, 0>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q,
                        T(alpha), nlat, x, xb, forcing, out);
@@ -528,7 +875,7 @@ void launch_tlm_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int
                                  hipStream_t);                                                 \
   template void launch_adj_tz<T>(const Dom<T>&, int, int, int, int, int, int, double, int,     \
                                  const double*, const double*, const double*, double*,        \
-                                 hipStream_t);                                                 \
+                                 const TzWork*, int, hipStream_t);                            \
   template void launch_tlm_tz<T>(const Dom<T>&, int, int, int, int, int, double, int,         \
                                  hipStream_t);
 DD4DVAR_INST(DD4DVAR_TZ_T)

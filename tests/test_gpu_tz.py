@@ -21,7 +21,12 @@ spanning bands whose pads reach across a pole partly into the box itself.
 * the tangent-linear sweep and the Gauss-Newton normal-matrix product
   (frozen pads unperturbed), and a DD solve with Gauss-Newton local solves;
 * the persistent execution modes, which the variant does not have, return
-  E_INVALID.
+  E_INVALID;
+* the two adjoint kernels (gather form for any p, q; column walk for q = 2,
+  p <= 8, the default where it applies) against each other on the same
+  inputs: J and gradients, the adjoint of a caller forcing, the Gauss-Newton
+  product (every q = 2 case above also runs the column walk against the
+  oracle).
 """
 import functools
 
@@ -272,3 +277,77 @@ def test_persistent_modes_rejected():
             ctx.set_exec_mode(mode)
         assert e.value.status == L.DD4DVAR_E_INVALID
     ctx.close()
+
+
+def _field_err(a, b):
+    """max over fields h, u, v of max |a - b| / max |b| (arrays [..., 3, ny, nx])."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return max(float(np.abs(a[..., f, :, :] - b[..., f, :, :]).max() /
+                     max(np.abs(b[..., f, :, :]).max(), 1e-300)) for f in range(3))
+
+
+@pytest.mark.parametrize("which,tzv", [("time", v) for v in VARIANTS] +
+                         [(w, v) for w in ("c1", "span", "mixed", "deep") for v in SPACE_VARIANTS])
+def test_column_walk_applies_where_documented(which, tzv):
+    from paper_2205_06649_amd import _lib as L
+    from paper_2205_06649_amd.context import Context
+    p, maps, _, _ = _state(tzv, which)
+    ctx = Context(p, "fp32")
+    applies = tzv[1] == 2 and tzv[0] <= 8
+    assert ctx.tz_adjoint() == {"kind": int(applies), "column_walk_applies": applies}
+    ctx.set_tz_adjoint(0)
+    assert ctx.tz_adjoint()["kind"] == 0
+    if applies:
+        ctx.set_tz_adjoint(1)
+        assert ctx.tz_adjoint()["kind"] == 1
+    else:
+        with pytest.raises(L.DD4DVarError) as e:
+            ctx.set_tz_adjoint(1)
+        assert e.value.status == L.DD4DVAR_E_INVALID
+    with pytest.raises(L.DD4DVarError) as e:
+        ctx.set_tz_adjoint(2)
+    assert e.value.status == L.DD4DVAR_E_INVALID
+    ctx.close()
+
+
+COLUMN_CASES = [("time", (2, 2, 0.5)), ("time", (3, 2, 0.25))] + \
+    [(w, (2, 2, 0.5)) for w in ("c1", "span", "mixed", "deep")]
+
+
+@pytest.mark.parametrize("which,tzv", COLUMN_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_column_walk_matches_gather(which, tzv, prec):
+    """Both adjoint kernels run the same terms in the same order; they differ
+    by the rounding of the observation forcing into the adjoint state (added
+    after it is rounded to the state precision in the column walk) and by
+    the partial sums of J: FP64 1e-13, FP32 1e-5 per field, J 1e-13 / 1e-6
+    relative."""
+    import torch
+    from paper_2205_06649_amd.context import Context
+    p, maps, trajs, rings = _state(tzv, which)
+    xs = _controls(p, maps, trajs, seed=5)
+    rng = np.random.default_rng(6)
+    forcing = [rng.standard_normal((b.nlev, 3, b.ny, b.nx)) for b in maps.boxes]
+    dxs = [p.sigma_b[:, None, None] * rng.standard_normal(x.shape) for x in xs]
+    ctx = Context(p, prec)
+    xp, fp, dp = ctx.pack_ctrl(xs), ctx.pack_traj(forcing), ctx.pack_ctrl(dxs)
+    res = {}
+    for kind in (0, 1):
+        ctx.set_tz_adjoint(kind)
+        J, g = ctx.cost_grad(xp)
+        ctx.forward(xp, with_traj=False)
+        a = ctx.adjoint(fp)
+        h = ctx.gn_hessvec(dp)
+        ctx.synchronize()
+        res[kind] = (J.cpu().numpy(), [ctx.unpack_ctrl(v) for v in (g, a, h)])
+    ctx.close()
+    tol = 1e-13 if prec == "fp64" else 1e-5
+    tol_j = 1e-13 if prec == "fp64" else 1e-6
+    (J0, r0), (J1, r1) = res[0], res[1]
+    ej = float(np.max(np.abs(J1 - J0) / np.abs(J0)))
+    errs = [max(_field_err(r1[k][b.sub], r0[k][b.sub]) for b in maps.boxes) for k in range(3)]
+    print(f"tz {which} {tzv} {prec}: J {ej:.2e}, gradient {errs[0]:.2e}, adjoint {errs[1]:.2e}, "
+          f"Gauss-Newton product {errs[2]:.2e}", flush=True)
+    assert ej <= tol_j
+    assert max(errs) <= tol, errs
