@@ -520,20 +520,52 @@ struct WinRow {
 };
 
 // window entry of box row rr (-2 .. ny + 1) and column col (wrapped into the
-// box for a box spanning the circle, -p .. nx + p - 1 otherwise)
+// box for a box spanning the circle, -p .. nx + p - 1 otherwise; a lane with
+// no such column reads column 0 and serves no output), as loaded: the
+// stencil's state, and lambda^{n+1} read at a box cell in any case, with the
+// flag that it is one (zero otherwise).  Every load is issued without a
+// branch around it, so that none is waited for before the row enters the
+// window one step later (win_take applies the flag then).
 template <typename T>
-__device__ __forceinline__ WinRow<T> win_load(const SubDev& S, const T* Z, const T* R, const T* L1,
-                                              int64_t plane, int rr, int col, bool col_ok,
-                                              bool has1, int p, int half, int nlat) {
-  WinRow<T> w;
-  w.z = {T(0), T(0), T(0)};
-  w.l = {T(0), T(0), T(0)};
-  if (col_ok) {
-    const Pt P = point(S, rr, col, 0, 0, p, kColQ, half, nlat);
-    w.z = ld_pt(Z, R, plane, S.nring, P);
-    if (has1 && !P.pad && !P.across) w.l = ld_box(L1, plane, P.idx, T(1));
-  }
+struct WinLoad {
+  V3<T> z, l;
+  bool lin;
+};
+template <typename T>
+__device__ __forceinline__ WinLoad<T> win_issue(const SubDev& S, const T* Z, const T* R, const T* L1,
+                                                int64_t plane, int rr, int col, bool col_ok,
+                                                bool has1, int p, int half, int nlat) {
+  const Pt P = point(S, rr, col_ok ? col : 0, 0, 0, p, kColQ, half, nlat);
+  WinLoad<T> w;
+  w.z = ld_pt(Z, R, plane, S.nring, P);
+  const bool in_box = !P.pad && !P.across;
+  w.l = ld_box(L1, plane, in_box ? P.idx : 0, T(1));
+  w.lin = col_ok && has1 && in_box;
   return w;
+}
+
+// per lane a (lanes in mask) or b, as one v_cndmask per 32 bits written out
+// (a select left to the compiler can become a branch that waits for a)
+__device__ __forceinline__ float pick_lane(float a, float b, uint64_t mask) {
+  float r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+  return r;
+}
+__device__ __forceinline__ double pick_lane(double a, double b, uint64_t mask) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const float lo = pick_lane(__builtin_bit_cast(float, uint32_t(ua)), __builtin_bit_cast(float, uint32_t(ub)), mask);
+  const float hi = pick_lane(__builtin_bit_cast(float, uint32_t(ua >> 32)),
+                             __builtin_bit_cast(float, uint32_t(ub >> 32)), mask);
+  return __builtin_bit_cast(double, (uint64_t(__builtin_bit_cast(uint32_t, hi)) << 32) |
+                                        __builtin_bit_cast(uint32_t, lo));
+}
+template <typename T>
+__device__ __forceinline__ V3<T> pick3_lane(const V3<T>& a, uint64_t mask) {
+  return {pick_lane(a.h, T(0), mask), pick_lane(a.u, T(0), mask), pick_lane(a.v, T(0), mask)};
+}
+template <typename T>
+__device__ __forceinline__ WinRow<T> win_take(const WinLoad<T>& w) {
+  return {w.z, pick3_lane(w.l, __builtin_amdgcn_ballot_w64(w.lin))};
 }
 
 template <typename T>
@@ -582,8 +614,10 @@ __device__ __forceinline__ int grow_of(const SubDev& S, int rr, int nlat) {
   return g < 0 ? -1 - g : (g >= nlat ? 2 * nlat - 1 - g : g);
 }
 
+// (occupancy: four waves per SIMD in FP32, two in FP64, each within its
+// register budget)
 template <typename T, int MODE>
-__global__ __launch_bounds__(kColThreads) void k_adj_tz_col(Dom<T> D, int n,
+__global__ __launch_bounds__(kColThreads, sizeof(T) == 4 ? 4 : 2) void k_adj_tz_col(Dom<T> D, int n,
                                                             const TzWork* __restrict__ work,
                                                             int nwork, int p, T alpha, int nlat,
                                                             const double* __restrict__ x,
@@ -623,22 +657,41 @@ __global__ __launch_bounds__(kColThreads) void k_adj_tz_col(Dom<T> D, int n,
   WinRow<T> w[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i)
-    w[i] = win_load(S, Z, R, L1, plane, wk.r0 - 2 + i, colw, col_ok, has1, p, hl, nlat);
-  WinRow<T> pf = w[4];
-  // coverage byte of the lane's cell in the step's row, one step ahead
+    w[i] = win_take(win_issue(S, Z, R, L1, plane, wk.r0 - 2 + i, colw, col_ok, has1, p, hl, nlat));
+  WinLoad<T> pf;
+  // coverage byte of the lane's cell in the step's row, one step ahead (a
+  // lane without an output reads cell 0)
   const int tcn = MODE != 1 ? D.tcount[S.lev0 + n] : 0;
-  int cov = (MODE != 1 && out_lane) ? int(D.cover[S.cell_off + wk.r0 * nx + c]) : 0;
+  int cov = MODE != 1 ? int(D.cover[S.cell_off + (out_lane ? wk.r0 * nx + c : 0)]) : 0;
   for (int r = wk.r0; r < wk.r1; ++r) {
+    // coefficient rows of the step: own, pole-mirrored north and south, and
+    // the readers' north and south rows clamped into the box (a reader
+    // outside it has lambda zero), loaded first: the loads of a wave complete
+    // in order, so that waiting for them leaves the later ones in flight
+    const RowCoef<T> rc = D.rows[__builtin_amdgcn_readfirstlane(S.row0 + r)];
+    const RowCoef<T> rN = D.rows[__builtin_amdgcn_readfirstlane(grow_of(S, r + q, nlat))];
+    const RowCoef<T> rS = D.rows[__builtin_amdgcn_readfirstlane(grow_of(S, r - q, nlat))];
+    const RowCoef<T> rKs = D.rows[__builtin_amdgcn_readfirstlane(S.row0 + max(r - q, 0))];
+    const RowCoef<T> rKn = D.rows[__builtin_amdgcn_readfirstlane(S.row0 + min(r + q, ny - 1))];
     if (r > wk.r0) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) w[i] = w[i + 1];
-      w[4] = pf;
+      w[4] = win_take(pf);
     }
+    // this step's loads, by every lane and before any arithmetic: the
+    // window's next row and coverage byte, lambda^{n+2} and the target (or
+    // dZ) of the step's cell
+    // (on the strip's last step they read rows the window never takes, kept
+    // inside the pad and the box)
     const int cov_r = cov;
-    if (r + 1 < wk.r1) {
-      pf = win_load(S, Z, R, L1, plane, r + 3, colw, col_ok, has1, p, hl, nlat);
-      if (MODE != 1 && out_lane) cov = int(D.cover[S.cell_off + (r + 1) * nx + c]);
-    }
+    pf = win_issue(S, Z, R, L1, plane, min(r + 3, ny + kColQ - 1), colw, col_ok, has1, p, hl, nlat);
+    if (MODE != 1) cov = int(D.cover[S.cell_off + (out_lane ? min(r + 1, ny - 1) * nx + c : 0)]);
+    const int m = out_lane ? r * nx + c : 0;
+    const int K = cov_r * tcn - 1;
+    const V3<T> l2raw = ld_box(L2, plane, m, T(1));
+    V3<T> tg = {T(0), T(0), T(0)};
+    if (MODE == 3) tg = ld_box(D.dz + S.zoff + int64_t(n) * 3 * plane, plane, m, T(1));
+    else if (MODE != 1) tg = ld_box(D.targ + S.traj_off + int64_t(n) * 3 * plane, plane, K > 0 ? m : 0, T(1));
     // the other columns' values: row r at lanes +-1 and +-p, rows r +- q at
     // lanes +-p (every lane takes part in the exchange)
     const WinRow<T> E1 = win_next(w[2]), W1 = win_prev(w[2]);
@@ -646,19 +699,6 @@ __global__ __launch_bounds__(kColThreads) void k_adj_tz_col(Dom<T> D, int n,
     const WinRow<T> EN = win_shfl(w[4], lEp), WN = win_shfl(w[4], lWp);
     const WinRow<T> ES = win_shfl(w[0], lEp), WS = win_shfl(w[0], lWp);
     if (!out_lane) continue;
-    const int m = r * nx + c;
-    // the forcing's loads, issued before the step's arithmetic
-    V3<T> l2 = {T(0), T(0), T(0)};
-    if (has2) l2 = ld_box(L2, plane, m, T(1));
-    const int K = cov_r * tcn - 1;
-    V3<T> tg = {T(0), T(0), T(0)};
-    if (MODE == 3) tg = ld_box(D.dz + S.zoff + int64_t(n) * 3 * plane, plane, m, T(1));
-    else if (MODE != 1) tg = ld_box(D.targ + S.traj_off + int64_t(n) * 3 * plane, plane, K > 0 ? m : 0, T(1));
-    const RowCoef<T> rc = D.rows[S.row0 + r];
-    const RowCoef<T> rN = D.rows[grow_of(S, r + q, nlat)], rS = D.rows[grow_of(S, r - q, nlat)];
-    // rows of the readers above and below (clamped into the box: a reader
-    // outside it has lambda zero)
-    const RowCoef<T> rKs = D.rows[S.row0 + max(r - q, 0)], rKn = D.rows[S.row0 + min(r + q, ny - 1)];
     const V3<T> C = w[2].z;
     double ah = 0, au = 0, av = 0;
     if (has1) {
@@ -710,6 +750,7 @@ __global__ __launch_bounds__(kColThreads) void k_adj_tz_col(Dom<T> D, int n,
       }
     }
     const V3<T> l0 = w[2].l;
+    const V3<T> l2 = has2 ? l2raw : V3<T>{T(0), T(0), T(0)};
     double fh = 0, fu = 0, fv = 0;
     if (MODE == 1) {
       const double* Fz = forcing + S.traj_off + int64_t(n) * 3 * plane;
