@@ -90,6 +90,9 @@ struct dd4dvar_ctx {
   TzWork* tz_work = nullptr;
   int tz_nwork = 0;
   std::vector<int> tz_work_box;
+  // per local level, the tiles with observation entries there (CSR)
+  int32_t* tz_obs_tiles = nullptr;
+  std::vector<int> tz_obs_ptr;
   bool tz_col_ok = false, tz_col = false;
   // state storage: every level (ckpt = 0), or checkpoint pairs every ckpt
   // levels plus one segment that the adjoint recomputes
@@ -293,8 +296,14 @@ void adj_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int n
         if (!work) throw DevError{DD4DVAR_E_INVALID, "adjoint launch over an unknown tile range"};
       }
     }
+    const int32_t* otiles = nullptr;
+    int nobs = 0;
+    if (work) {
+      otiles = c->tz_obs_tiles + c->tz_obs_ptr[n];
+      nobs = c->tz_obs_ptr[n + 1] - c->tz_obs_ptr[n];
+    }
     launch_adj_tz<T>(D, n, tile_base, ntiles, mode, c->tz_p, c->tz_q, c->tz_alpha,
-                     c->plan.model.nlat, x, c->xb, forcing, out, work, nwork, st);
+                     c->plan.model.nlat, x, c->xb, forcing, out, work, nwork, otiles, nobs, st);
   } else {
     launch_adj<T>(D, n, tile_base, ntiles, mode, x, c->xb, forcing, out, st);
   }
@@ -873,6 +882,19 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
       }
       if (ok && !wl.empty()) {
         wb.back() = int(wl.size());
+        std::vector<int> otp(c->maxlev + 1, 0);
+        std::vector<int32_t> otl;
+        for (int n = 0; n < c->maxlev; ++n) {
+          otp[n] = int(otl.size());
+          for (const SubDev& S : c->subs)
+            for (int t = 0; t < S.ntile; ++t) {
+              const int64_t key = obs_key(S.tile0, S.ntile, c->maxlev, t, n);
+              if (optr[key + 1] > optr[key]) otl.push_back(S.tile0 + t);
+            }
+        }
+        otp[c->maxlev] = int(otl.size());
+        c->tz_obs_tiles = upload(c, otl, st);
+        c->tz_obs_ptr = otp;
         c->tz_work = upload(c, wl, st);
         c->tz_nwork = int(wl.size());
         c->tz_work_box = wb;

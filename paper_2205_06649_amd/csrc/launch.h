@@ -61,12 +61,14 @@ void launch_fwd_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int
 struct TzWork {
   int32_t box, c0, r0, r1, slot, zero0, zero1, pad_;
 };
-// work == nullptr: the gather kernel (one thread per cell, any p, q)
+// work == nullptr: the gather kernel (one thread per cell, any p, q);
+// otherwise the column walk over the nwork waves, and the observation
+// forcing over obs_tiles (the tiles with observation entries at level n)
 template <typename T>
 void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, int p, int q,
                    double alpha, int nlat, const double* x, const double* xb,
                    const double* forcing, double* out, const TzWork* work, int nwork,
-                   hipStream_t st);
+                   const int32_t* obs_tiles, int nobs_tiles, hipStream_t st);
 template <typename T>
 void launch_tlm_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
                    int nlat, hipStream_t st);

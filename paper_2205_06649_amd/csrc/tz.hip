@@ -821,10 +821,14 @@ __global__ __launch_bounds__(kColThreads, sizeof(T) == 4 ? 4 : 2) void k_adj_tz_
 // lambda^n, or at level 0 to the gradient / adj0; its share of J added to
 // the tile's accumulator.  A cell and field occur at most once per level.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kTile) void k_obs_tz(Dom<T> D, int n, int tile_base,
+__global__ __launch_bounds__(kTile) void k_obs_tz(Dom<T> D, int n, const int32_t* __restrict__ tiles,
+                                                  int tile_base, int ntiles,
                                                   double* __restrict__ out) {
   __shared__ double red[kTile / 64];
-  const int w = tile_base + xcd_tile(blockIdx.x, gridDim.x);
+  // one tile of the level's list (the tiles with entries at level n), if it
+  // belongs to the launched boxes
+  const int w = tiles[blockIdx.x];
+  if (w < tile_base || w >= tile_base + ntiles) return;
   const int2 wt = D.tiles[w];
   if (D.active && !D.active[wt.x]) return;
   const SubDev S = D.subs[wt.x];
@@ -866,9 +870,10 @@ template <typename T>
 void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, int p, int q,
                    double alpha, int nlat, const double* x, const double* xb,
                    const double* forcing, double* out, const TzWork* work, int nwork,
-                   hipStream_t st) {
+                   const int32_t* obs_tiles, int nobs_tiles, hipStream_t st) {
   if (work) {
-    // column walk (q = 2), then the observation forcing of the level
+    // column walk (q = 2), then the observation forcing of the level over
+    // the tiles that have entries there
     const int nb = (nwork + kColThreads / 64 - 1) / (kColThreads / 64);
     if (nb == 0) return;
     if (mode == 0)
@@ -883,12 +888,16 @@ void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, 
     else
       hipLaunchKernelGGL((k_adj_tz_col<T, 3>), dim3(nb), dim3(kColThreads), 0, st, D, n, work, nwork,
                          p, T(alpha), nlat, x, xb, forcing, out);
+    if (nobs_tiles == 0) return;
     if (mode == 0)
-      hipLaunchKernelGGL((k_obs_tz<T, 0>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, out);
+      hipLaunchKernelGGL((k_obs_tz<T, 0>), dim3(nobs_tiles), dim3(kTile), 0, st, D, n, obs_tiles,
+                         tile_base, ntiles, out);
     else if (mode == 2)
-      hipLaunchKernelGGL((k_obs_tz<T, 2>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, out);
+      hipLaunchKernelGGL((k_obs_tz<T, 2>), dim3(nobs_tiles), dim3(kTile), 0, st, D, n, obs_tiles,
+                         tile_base, ntiles, out);
     else if (mode == 3)
-      hipLaunchKernelGGL((k_obs_tz<T, 3>), dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, out);
+      hipLaunchKernelGGL((k_obs_tz<T, 3>), dim3(nobs_tiles), dim3(kTile), 0, st, D, n, obs_tiles,
+                         tile_base, ntiles, out);
     return;
   }
   if (mode == 0)
@@ -916,7 +925,7 @@ void launch_tlm_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int
                                  hipStream_t);                                                 \
   template void launch_adj_tz<T>(const Dom<T>&, int, int, int, int, int, int, double, int,     \
                                  const double*, const double*, const double*, double*,        \
-                                 const TzWork*, int, hipStream_t);                            \
+                                 const TzWork*, int, const int32_t*, int, hipStream_t);       \
   template void launch_tlm_tz<T>(const Dom<T>&, int, int, int, int, int, double, int,         \
                                  hipStream_t);
 DD4DVAR_INST(DD4DVAR_TZ_T)
