@@ -193,20 +193,21 @@ __global__ __launch_bounds__(kTile) void k_fwd_tz(Dom<T> D, int n, int tile_base
   const RowCoef<T> rc = D.rows[S.row0 + r];
   const RowCoef<T> rN = D.rows[P[7].grow], rS = D.rows[P[8].grow];
   const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
-  const T tp = T(p), tq = T(q);
+  // 1/p, 1/q: multiplying by them equals dividing when p, q are powers of two
+  const T itp = one / T(p), itq = one / T(q);
   const V3<T>& C = z.C;
   const T hh = h0 + C.h;
   const T U = -rc.a1 * C.u * (z.E.u - z.W.u) - st * C.v * (z.N.u - z.Sv.u) -
-              rc.a2 / tp * (z.Ep.h - z.Wp.h) +
+              rc.a2 * itp * (z.Ep.h - z.Wp.h) +
               ((one - al) * (rc.cf + rc.ct * C.u) * C.v + half * al * (rc.cf + rc.ct * z.Ep.u) * z.Ep.v +
                half * al * (rc.cf + rc.ct * z.Wp.u) * z.Wp.v);
   const T V = -rc.a1 * C.u * (z.E.v - z.W.v) - st * C.v * (z.N.v - z.Sv.v) -
-              stg / tq * (z.Nq.h - z.Sq.h) -
+              stg * itq * (z.Nq.h - z.Sq.h) -
               ((one - al) * (rc.cf + rc.ct * C.u) * C.u + half * al * (rN.cf + rN.ct * z.Nq.u) * z.Nq.u +
                half * al * (rS.cf + rS.ct * z.Sq.u) * z.Sq.u);
-  const T Dl = ((one - al) * (z.Ep.u - z.Wp.u) + half * al * (z.EN.u - z.WN.u + z.ES.u - z.WS.u)) / tp;
+  const T Dl = ((one - al) * (z.Ep.u - z.Wp.u) + half * al * (z.EN.u - z.WN.u + z.ES.u - z.WS.u)) * itp;
   const T Dt = ((one - al) * (z.Nq.v * rN.c - z.Sq.v * rS.c) + half * al * (z.EN.v * rN.c - z.ES.v * rS.c) +
-                half * al * (z.WN.v * rN.c - z.WS.v * rS.c)) / tq;
+                half * al * (z.WN.v * rN.c - z.WS.v * rS.c)) * itq;
   const T H = -rc.a1 * (C.u * (z.E.h - z.W.h) + hh * Dl) - (st * C.v * (z.N.h - z.Sv.h) + rc.a3 * hh * Dt);
   const T wgt = n == 0 ? T(0.5) : T(1);
   T* out = zlevel(D, S, n + 1);
@@ -242,26 +243,27 @@ __global__ __launch_bounds__(kTile) void k_tlm_tz(Dom<T> D, int n, int tile_base
   const RowCoef<T> rc = D.rows[S.row0 + r];
   const RowCoef<T> rN = D.rows[P[7].grow], rS = D.rows[P[8].grow];
   const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
-  const T tp = T(p), tq = T(q);
+  // 1/p, 1/q: multiplying by them equals dividing when p, q are powers of two
+  const T itp = one / T(p), itq = one / T(q);
   const V3<T>& C = z.C;
   const V3<T>& dC = d[0];
   const T hh = h0 + C.h;
   const T dU = -rc.a1 * (dC.u * (z.E.u - z.W.u) + C.u * (d[1].u - d[2].u)) -
-               st * (dC.v * (z.N.u - z.Sv.u) + C.v * (d[3].u - d[4].u)) - rc.a2 / tp * (d[5].h - d[6].h) +
+               st * (dC.v * (z.N.u - z.Sv.u) + C.v * (d[3].u - d[4].u)) - rc.a2 * itp * (d[5].h - d[6].h) +
                ((one - al) * (rc.ct * dC.u * C.v + (rc.cf + rc.ct * C.u) * dC.v) +
                 half * al * (rc.ct * d[5].u * z.Ep.v + (rc.cf + rc.ct * z.Ep.u) * d[5].v) +
                 half * al * (rc.ct * d[6].u * z.Wp.v + (rc.cf + rc.ct * z.Wp.u) * d[6].v));
   const T dV = -rc.a1 * (dC.u * (z.E.v - z.W.v) + C.u * (d[1].v - d[2].v)) -
-               st * (dC.v * (z.N.v - z.Sv.v) + C.v * (d[3].v - d[4].v)) - stg / tq * (d[7].h - d[8].h) -
+               st * (dC.v * (z.N.v - z.Sv.v) + C.v * (d[3].v - d[4].v)) - stg * itq * (d[7].h - d[8].h) -
                ((one - al) * (rc.cf + T(2) * rc.ct * C.u) * dC.u +
                 half * al * (rN.cf + T(2) * rN.ct * z.Nq.u) * d[7].u +
                 half * al * (rS.cf + T(2) * rS.ct * z.Sq.u) * d[8].u);
-  const T Dl = ((one - al) * (z.Ep.u - z.Wp.u) + half * al * (z.EN.u - z.WN.u + z.ES.u - z.WS.u)) / tp;
+  const T Dl = ((one - al) * (z.Ep.u - z.Wp.u) + half * al * (z.EN.u - z.WN.u + z.ES.u - z.WS.u)) * itp;
   const T Dt = ((one - al) * (z.Nq.v * rN.c - z.Sq.v * rS.c) + half * al * (z.EN.v * rN.c - z.ES.v * rS.c) +
-                half * al * (z.WN.v * rN.c - z.WS.v * rS.c)) / tq;
-  const T dDl = ((one - al) * (d[5].u - d[6].u) + half * al * (d[9].u - d[10].u + d[11].u - d[12].u)) / tp;
+                half * al * (z.WN.v * rN.c - z.WS.v * rS.c)) * itq;
+  const T dDl = ((one - al) * (d[5].u - d[6].u) + half * al * (d[9].u - d[10].u + d[11].u - d[12].u)) * itp;
   const T dDt = ((one - al) * (d[7].v * rN.c - d[8].v * rS.c) + half * al * (d[9].v * rN.c - d[11].v * rS.c) +
-                 half * al * (d[10].v * rN.c - d[12].v * rS.c)) / tq;
+                 half * al * (d[10].v * rN.c - d[12].v * rS.c)) * itq;
   const T dH = -rc.a1 * (dC.u * (z.E.h - z.W.h) + C.u * (d[1].h - d[2].h) + dC.h * Dl + hh * dDl) -
                (st * (dC.v * (z.N.h - z.Sv.h) + C.v * (d[3].h - d[4].h)) + rc.a3 * (dC.h * Dt + hh * dDt));
   const T wgt = n == 0 ? T(0.5) : T(1);
@@ -274,11 +276,12 @@ __global__ __launch_bounds__(kTile) void k_tlm_tz(Dom<T> D, int n, int tile_base
 // transposed contribution of reader k through offset o (1 .. 12) to the
 // point x it reads there: lk = lambda^{n+1}(k), hk, uk, vk its state (h as
 // the anomaly), K its row coefficients, X those of x's row, ux, vx the
-// values k reads at x (sign applied across a pole)
+// values k reads at x (sign applied across a pole); itp, itq = 1/p, 1/q
+// (a multiply instead of a division per term)
 template <typename T>
 __device__ __forceinline__ V3<T> reader_term(int o, const V3<T>& lk, T hk, T uk, T vk,
                                              const RowCoef<T>& K, const RowCoef<T>& X, T ux,
-                                             T vx, T st, T stg, T h0, T al, T tp, T tq) {
+                                             T vx, T st, T stg, T h0, T al, T itp, T itq) {
   const T one = T(1), half = T(0.5), hh = h0 + hk;
   switch (o) {
     case 1: case 2: {
@@ -291,16 +294,16 @@ __device__ __forceinline__ V3<T> reader_term(int o, const V3<T>& lk, T hk, T uk,
     }
     case 5: case 6: {
       const T sgn = o == 5 ? T(-1) : T(1);
-      return {sgn * lk.u * K.a2 / tp, lk.u * half * al * K.ct * vx + sgn * lk.h * (one - al) * K.a1 * hh / tp,
+      return {sgn * lk.u * K.a2 * itp, lk.u * half * al * K.ct * vx + sgn * lk.h * (one - al) * K.a1 * hh * itp,
               lk.u * half * al * (K.cf + K.ct * ux)};
     }
     case 7: case 8: {
       const T sgn = o == 7 ? T(-1) : T(1);
-      return {sgn * lk.v * stg / tq, -lk.v * half * al * (X.cf + T(2) * X.ct * ux),
-              sgn * lk.h * (one - al) * K.a3 * hh * X.c / tq};
+      return {sgn * lk.v * stg * itq, -lk.v * half * al * (X.cf + T(2) * X.ct * ux),
+              sgn * lk.h * (one - al) * K.a3 * hh * X.c * itq};
     }
     default: {
-      const T dn = half * al * K.a1 * hh / tp, cq = half * al * K.a3 * hh * X.c / tq;
+      const T dn = half * al * K.a1 * hh * itp, cq = half * al * K.a3 * hh * X.c * itq;
       const T su = (o == 9 || o == 11) ? T(-1) : T(1), sv = (o == 9 || o == 10) ? T(-1) : T(1);
       return {T(0), su * lk.h * dn, sv * lk.h * cq};
     }
@@ -349,13 +352,14 @@ __global__ __launch_bounds__(kTile) void k_adj_tz(Dom<T> D, int n, int tile_base
     const RowCoef<T> rc = D.rows[S.row0 + r];
     const RowCoef<T> rN = D.rows[P[7].grow], rS = D.rows[P[8].grow];
     const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
-    const T tp = T(p), tq = T(q);
+    // 1/p, 1/q: multiplying by them equals dividing when p, q are powers of two
+    const T itp = one / T(p), itq = one / T(q);
     const V3<T>& C = z.C;
     // the cell itself
     {
-      const T Dl = ((one - al) * (z.Ep.u - z.Wp.u) + half * al * (z.EN.u - z.WN.u + z.ES.u - z.WS.u)) / tp;
+      const T Dl = ((one - al) * (z.Ep.u - z.Wp.u) + half * al * (z.EN.u - z.WN.u + z.ES.u - z.WS.u)) * itp;
       const T Dt = ((one - al) * (z.Nq.v * rN.c - z.Sq.v * rS.c) + half * al * (z.EN.v * rN.c - z.ES.v * rS.c) +
-                    half * al * (z.WN.v * rN.c - z.WS.v * rS.c)) / tq;
+                    half * al * (z.WN.v * rN.c - z.WS.v * rS.c)) * itq;
       ah += double(-lam.h * (rc.a1 * Dl + rc.a3 * Dt));
       au += double(lam.u * (-rc.a1 * (z.E.u - z.W.u) + (one - al) * rc.ct * C.v) +
                    lam.v * (-rc.a1 * (z.E.v - z.W.v) - (one - al) * (rc.cf + T(2) * rc.ct * C.u)) -
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(kTile) void k_adj_tz(Dom<T> D, int n, int tile_base
       const int k = rk * S.nx + ck;
       const V3<T> lk = ld_box(L1, plane, k, T(1));
       const V3<T> t = reader_term(o, lk, Z[k], Z[plane + k], Z[2 * plane + k], D.rows[S.row0 + rk], rc,
-                                  C.u, C.v, st, stg, h0, al, tp, tq);
+                                  C.u, C.v, st, stg, h0, al, itp, itq);
       ah += double(t.h);
       au += double(t.u);
       av += double(t.v);
@@ -394,7 +398,7 @@ __global__ __launch_bounds__(kTile) void k_adj_tz(Dom<T> D, int n, int tile_base
         const int k = (gk - S.row0) * S.nx + ck;
         const V3<T> lk = ld_box(L1, plane, k, T(1));
         const V3<T> t = reader_term(o, lk, Z[k], Z[plane + k], Z[2 * plane + k], D.rows[gk], rc,
-                                    -C.u, -C.v, st, stg, h0, al, tp, tq);
+                                    -C.u, -C.v, st, stg, h0, al, itp, itq);
         ah += double(t.h);
         au -= double(t.u);
         av -= double(t.v);
@@ -648,7 +652,7 @@ __global__ __launch_bounds__(kColThreads, sizeof(T) == 4 ? 4 : 2) void k_adj_tz_
   const T* L1 = A + int64_t((n + 1) % 3) * 3 * plane;
   const T* L2 = A + int64_t((n + 2) % 3) * 3 * plane;
   const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
-  const T tp = T(p), tq = T(kColQ);
+  const T itp = one / T(p), itq = one / T(kColQ);
   const int q = kColQ;
   const int hl = D.half;
   const int lEp = min(lane + p, 63), lWp = max(lane - p, 0);
@@ -704,10 +708,10 @@ __global__ __launch_bounds__(kColThreads, sizeof(T) == 4 ? 4 : 2) void k_adj_tz_
     if (has1) {
       const V3<T> lam = w[2].l;
       {
-        const T Dl = ((one - al) * (Ep.z.u - Wp.z.u) + half * al * (EN.z.u - WN.z.u + ES.z.u - WS.z.u)) / tp;
+        const T Dl = ((one - al) * (Ep.z.u - Wp.z.u) + half * al * (EN.z.u - WN.z.u + ES.z.u - WS.z.u)) * itp;
         const T Dt = ((one - al) * (w[4].z.v * rN.c - w[0].z.v * rS.c) +
                       half * al * (EN.z.v * rN.c - ES.z.v * rS.c) +
-                      half * al * (WN.z.v * rN.c - WS.z.v * rS.c)) / tq;
+                      half * al * (WN.z.v * rN.c - WS.z.v * rS.c)) * itq;
         ah += double(-lam.h * (rc.a1 * Dl + rc.a3 * Dt));
         au += double(lam.u * (-rc.a1 * (E1.z.u - W1.z.u) + (one - al) * rc.ct * C.v) +
                      lam.v * (-rc.a1 * (E1.z.v - W1.z.v) - (one - al) * (rc.cf + T(2) * rc.ct * C.u)) -
@@ -722,7 +726,7 @@ __global__ __launch_bounds__(kColThreads, sizeof(T) == 4 ? 4 : 2) void k_adj_tz_
                            : o == 5 ? Wp : o == 6 ? Ep : o == 7 ? w[0] : o == 8 ? w[4]
                            : o == 9 ? WS : o == 10 ? ES : o == 11 ? WN : EN;
         const RowCoef<T>& K = (o == 7 || o == 9 || o == 10) ? rKs : (o == 8 || o == 11 || o == 12) ? rKn : rc;
-        const V3<T> t = reader_term(o, k.l, k.z.h, k.z.u, k.z.v, K, rc, C.u, C.v, st, stg, h0, al, tp, tq);
+        const V3<T> t = reader_term(o, k.l, k.z.h, k.z.u, k.z.v, K, rc, C.u, C.v, st, stg, h0, al, itp, itq);
         ah += double(t.h);
         au += double(t.u);
         av += double(t.v);
@@ -742,7 +746,7 @@ __global__ __launch_bounds__(kColThreads, sizeof(T) == 4 ? 4 : 2) void k_adj_tz_
           const int kk = (gk - S.row0) * nx + ck;
           const V3<T> lk = ld_box(L1, plane, kk, T(1));
           const V3<T> t = reader_term(o, lk, Z[kk], Z[plane + kk], Z[2 * plane + kk], D.rows[gk], rc,
-                                      -C.u, -C.v, st, stg, h0, al, tp, tq);
+                                      -C.u, -C.v, st, stg, h0, al, itp, itq);
           ah += double(t.h);
           au -= double(t.u);
           av -= double(t.v);
