@@ -322,21 +322,23 @@ dd4dvar_status dd4dvar_set_exec_mode(dd4dvar_ctx* ctx, int32_t mode);
  * plans; this call pins one, for tests and measurement. */
 dd4dvar_status dd4dvar_set_exec_plan(dd4dvar_ctx* ctx, int32_t mode, int32_t passes);
 
-/* Adjoint kernel of the Turkel-Zwas variant (Sec. 7 discrete U, V, H; the
- * adjoint definition of Sec. 2, eq. adjProd): kind 0 = gather form, one
- * thread per cell reading its 13-point neighbourhood and the state, adjoint
- * and row coefficients of its 12 readers (any p, q); kind 1 = column walk,
- * one wave per block of 64 - 2p columns walking a strip of rows with a
- * five-row window of state and adjoint per column in registers (q = 2 and
- * p <= 8 only; the default where it applies).  Both sum each cell's terms in
- * the same order in FP64; the column walk adds the observation forcing to
+/* Step kernels of the Turkel-Zwas variant (Sec. 7 discrete U, V, H; its
+ * adjoint by the definition of Sec. 2, eq. adjProd), forward and adjoint
+ * sweeps: kind 0 = gather form, one thread per cell reading its 13-point
+ * neighbourhood (and in the adjoint the state, adjoint and row coefficients
+ * of its 12 readers), any p, q; kind 1 = column walk, one wave per block of
+ * 64 - 2p columns walking a strip of rows with a five-row window of state
+ * (and adjoint) per column in registers, q = 2 and p <= 8 only, the default
+ * where it applies.  The global (whole-grid) forward runs always use kind 0.
+ * Both kinds evaluate the same expressions in the same order (the adjoint's
+ * per-cell sums in FP64); the column walk adds the observation forcing to
  * the adjoint state after it is rounded to the state precision (one more
  * rounding at observed cells) and keeps J's terms in other partial sums.
  * E_INVALID for another kind, or kind 1 where it does not apply. */
-dd4dvar_status dd4dvar_set_tz_adjoint(dd4dvar_ctx* ctx, int32_t kind);
+dd4dvar_status dd4dvar_set_tz_kernels(dd4dvar_ctx* ctx, int32_t kind);
 
-/* out[2] = {Turkel-Zwas adjoint kind in use, 1 if the column walk applies}. */
-dd4dvar_status dd4dvar_get_tz_adjoint(const dd4dvar_ctx* ctx, int32_t out[2]);
+/* out[2] = {Turkel-Zwas kernel kind in use, 1 if the column walk applies}. */
+dd4dvar_status dd4dvar_get_tz_kernels(const dd4dvar_ctx* ctx, int32_t out[2]);
 
 /* The plan in use: out[4] = {execution mode, pass count of the persistent
  * kernels (0 when they do not apply), rows per column strip of the mode-4

@@ -99,8 +99,8 @@ _SIGS = {
     "dd4dvar_set_exec_mode": (C.c_int, [_VP, C.c_int32]),
     "dd4dvar_set_exec_plan": (C.c_int, [_VP, C.c_int32, C.c_int32]),
     "dd4dvar_get_exec_plan": (C.c_int, [_VP, C.POINTER(C.c_int32)]),
-    "dd4dvar_set_tz_adjoint": (C.c_int, [_VP, C.c_int32]),
-    "dd4dvar_get_tz_adjoint": (C.c_int, [_VP, C.POINTER(C.c_int32)]),
+    "dd4dvar_set_tz_kernels": (C.c_int, [_VP, C.c_int32]),
+    "dd4dvar_get_tz_kernels": (C.c_int, [_VP, C.POINTER(C.c_int32)]),
     "dd4dvar_synchronize": (C.c_int, [_VP, _VP]),
     "dd4dvar_set_timing": (C.c_int, [_VP, C.c_int32]),
     "dd4dvar_set_graph": (C.c_int, [_VP, C.c_int32]),
@@ -264,13 +264,13 @@ def dd4dvar_get_exec_plan(ctx):
     return {"mode": out[0], "passes": out[1], "strip_rows": out[2], "persistent": bool(out[3])}
 
 
-def dd4dvar_set_tz_adjoint(ctx, kind):
-    check(lib().dd4dvar_set_tz_adjoint(ctx, kind), ctx)
+def dd4dvar_set_tz_kernels(ctx, kind):
+    check(lib().dd4dvar_set_tz_kernels(ctx, kind), ctx)
 
 
-def dd4dvar_get_tz_adjoint(ctx):
+def dd4dvar_get_tz_kernels(ctx):
     out = (C.c_int32 * 2)()
-    check(lib().dd4dvar_get_tz_adjoint(ctx, out), ctx)
+    check(lib().dd4dvar_get_tz_kernels(ctx, out), ctx)
     return {"kind": out[0], "column_walk_applies": bool(out[1])}
 
 

@@ -74,14 +74,14 @@ class Context:
         """{mode, passes, strip_rows, persistent} of the plan in use."""
         return L.dd4dvar_get_exec_plan(self.handle)
 
-    def set_tz_adjoint(self, kind):
-        """Turkel-Zwas adjoint kernel: 0 gather form, 1 column walk (q = 2,
-        p <= 8; the default where it applies)."""
-        L.dd4dvar_set_tz_adjoint(self.handle, kind)
+    def set_tz_kernels(self, kind):
+        """Turkel-Zwas forward and adjoint step kernels: 0 gather form,
+        1 column walk (q = 2, p <= 8; the default where it applies)."""
+        L.dd4dvar_set_tz_kernels(self.handle, kind)
 
-    def tz_adjoint(self):
-        """{kind, column_walk_applies} of the Turkel-Zwas adjoint."""
-        return L.dd4dvar_get_tz_adjoint(self.handle)
+    def tz_kernels(self):
+        """{kind, column_walk_applies} of the Turkel-Zwas step kernels."""
+        return L.dd4dvar_get_tz_kernels(self.handle)
 
     def synchronize(self):
         """Wait for the queued work; raises DD4DVarError (E_NONFINITE) if a

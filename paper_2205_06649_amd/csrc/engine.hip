@@ -264,38 +264,49 @@ void fill_rows(const dd4dvar_model_desc& m, std::vector<RowCoef<T>>& rows, std::
   cosx[m.nlat + 1] = T(c[m.nlat - 1]);
 }
 
+// The column-walk waves of the boxes whose tiles are [tile_base, tile_base +
+// ntiles) (a run of whole boxes: every box, one interval's, or one box);
+// none when the column walk is off
+void tz_work_range(const dd4dvar_ctx* c, int tile_base, int ntiles, const TzWork** work, int* nwork) {
+  *work = nullptr;
+  *nwork = 0;
+  if (!c->tz_col) return;
+  size_t s0 = c->subs.size(), s1 = c->subs.size();
+  for (size_t s = 0; s < c->subs.size(); ++s) {
+    if (c->subs[s].tile0 == tile_base) s0 = s;
+    if (c->subs[s].tile0 + c->subs[s].ntile == tile_base + ntiles) s1 = s;
+  }
+  if (s0 == c->subs.size() || s1 == c->subs.size() || s1 < s0)
+    throw DevError{DD4DVAR_E_INVALID, "sweep launch over a tile range that is not a run of boxes"};
+  *work = c->tz_work + c->tz_work_box[s0];
+  *nwork = c->tz_work_box[s1 + 1] - c->tz_work_box[s0];
+}
+
 // One forward and one adjoint step of the step kernels in the scheme that the
-// model selects (plain centred, or Turkel-Zwas)
+// model selects (plain centred, or Turkel-Zwas); global: the whole-grid run
+// (gather kernels only)
 template <typename T>
-void fwd_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int ntiles, hipStream_t st) {
-  if (c->tz_p > 0)
-    launch_fwd_tz<T>(D, n, tile_base, ntiles, c->tz_p, c->tz_q, c->tz_alpha, c->plan.model.nlat, st);
-  else
+void fwd_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int ntiles, hipStream_t st,
+              bool global = false) {
+  if (c->tz_p > 0) {
+    const TzWork* work = nullptr;
+    int nwork = 0;
+    if (!global) tz_work_range(c, tile_base, ntiles, &work, &nwork);
+    launch_fwd_tz<T>(D, n, tile_base, ntiles, c->tz_p, c->tz_q, c->tz_alpha, c->plan.model.nlat,
+                     work, nwork, st);
+  } else {
     launch_fwd<T>(D, n, tile_base, ntiles, st);
+  }
 }
 
 template <typename T>
 void adj_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int ntiles, int mode,
               const double* x, const double* forcing, double* out, hipStream_t st) {
   if (c->tz_p > 0) {
-    // the column-walk kernel takes the waves of the launched boxes: all of
-    // them, or those of the one box whose tiles these are
+    // the column-walk kernel takes the waves of the launched boxes
     const TzWork* work = nullptr;
     int nwork = 0;
-    if (c->tz_col) {
-      if (tile_base == 0 && ntiles == c->ntiles) {
-        work = c->tz_work;
-        nwork = c->tz_nwork;
-      } else {
-        for (size_t s = 0; s < c->subs.size(); ++s)
-          if (c->subs[s].tile0 == tile_base) {
-            work = c->tz_work + c->tz_work_box[s];
-            nwork = c->tz_work_box[s + 1] - c->tz_work_box[s];
-            break;
-          }
-        if (!work) throw DevError{DD4DVAR_E_INVALID, "adjoint launch over an unknown tile range"};
-      }
-    }
+    tz_work_range(c, tile_base, ntiles, &work, &nwork);
     const int32_t* otiles = nullptr;
     int nobs = 0;
     if (work) {
@@ -314,7 +325,7 @@ void adj_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int n
 void global_forward(dd4dvar_ctx* c, const double* x, double* traj, hipStream_t st) {
   Dom<double> G = global_dom(c, traj);
   launch_init<double>(G, x, 0, c->gtiles, st);
-  for (int n = 0; n < c->plan.model.nsteps; ++n) fwd_step<double>(c, G, n, 0, c->gtiles, st);
+  for (int n = 0; n < c->plan.model.nsteps; ++n) fwd_step<double>(c, G, n, 0, c->gtiles, st, true);
   chk(hipGetLastError(), "global forward launch");
 }
 
@@ -1053,16 +1064,16 @@ dd4dvar_status dd4dvar_set_exec_plan(dd4dvar_ctx* ctx, int32_t mode, int32_t pas
   return DD4DVAR_OK;
 }
 
-dd4dvar_status dd4dvar_set_tz_adjoint(dd4dvar_ctx* ctx, int32_t kind) {
-  if (!ctx || kind < 0 || kind > 1) return fail(ctx, DD4DVAR_E_INVALID, "bad Turkel-Zwas adjoint kind");
+dd4dvar_status dd4dvar_set_tz_kernels(dd4dvar_ctx* ctx, int32_t kind) {
+  if (!ctx || kind < 0 || kind > 1) return fail(ctx, DD4DVAR_E_INVALID, "bad Turkel-Zwas kernel kind");
   if (kind == 1 && !ctx->tz_col_ok)
     return fail(ctx, DD4DVAR_E_INVALID,
-                "the column-walk adjoint needs the Turkel-Zwas variant with q = 2 and p <= 8");
+                "the column-walk kernels need the Turkel-Zwas variant with q = 2 and p <= 8");
   ctx->tz_col = kind == 1;
   return DD4DVAR_OK;
 }
 
-dd4dvar_status dd4dvar_get_tz_adjoint(const dd4dvar_ctx* ctx, int32_t out[2]) {
+dd4dvar_status dd4dvar_get_tz_kernels(const dd4dvar_ctx* ctx, int32_t out[2]) {
   if (!ctx || !out) return fail(const_cast<dd4dvar_ctx*>(ctx), DD4DVAR_E_INVALID, "null argument");
   out[0] = ctx->tz_col ? 1 : 0;
   out[1] = ctx->tz_col_ok ? 1 : 0;

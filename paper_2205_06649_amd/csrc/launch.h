@@ -51,9 +51,7 @@ void launch_dz_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hipS
 
 // tz.hip: Turkel-Zwas step kernels (boxes with frozen pads q rows and p
 // columns wide)
-template <typename T>
-void launch_fwd_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
-                   int nlat, hipStream_t st);
+
 // one wave's share of the column-walk Turkel-Zwas adjoint (offset q = 2):
 // box, first column of its outputs' block (c0, lanes p .. 63 - p), rows
 // r0 .. r1 - 1, its J slot, and the box's J slots no wave writes
@@ -61,7 +59,12 @@ void launch_fwd_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int
 struct TzWork {
   int32_t box, c0, r0, r1, slot, zero0, zero1, pad_;
 };
-// work == nullptr: the gather kernel (one thread per cell, any p, q);
+// forward step: work == nullptr, the gather kernel (one thread per cell,
+// any p, q); otherwise the column walk over the nwork waves
+template <typename T>
+void launch_fwd_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
+                   int nlat, const TzWork* work, int nwork, hipStream_t st);
+// adjoint step: work == nullptr, the gather kernel (one thread per cell, any p, q);
 // otherwise the column walk over the nwork waves, and the observation
 // forcing over obs_tiles (the tiles with observation entries at level n)
 template <typename T>

@@ -820,6 +820,95 @@ __global__ __launch_bounds__(kColThreads, sizeof(T) == 4 ? 4 : 2) void k_adj_tz_
   }
 }
 
+// Column-walk forward step for the q = 2 offset: the waves of the adjoint's
+// column walk (same blocks of columns and strips of rows), each lane keeping
+// the state of the rows r - 2 .. r + 2 of its column as the 13-point stencil
+// reads them (box cells, frozen pad values, or box cells across a pole with
+// u, v negated), loading one new row per step, one step ahead, and taking
+// the other columns from the lanes 1 (DPP) and p (LDS crossbar) to either
+// side.  Arithmetic as in k_fwd_tz.
+template <typename T>
+__global__ __launch_bounds__(kColThreads) void k_fwd_tz_col(Dom<T> D, int n,
+                                                            const TzWork* __restrict__ work,
+                                                            int nwork, int p, T alpha, int nlat) {
+  const int wv = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * (kColThreads / 64) +
+                                                int(threadIdx.x >> 6));
+  if (wv >= nwork) return;                 // whole waves; no workgroup barrier below
+  const TzWork wk = work[wv];
+  if (D.active && !D.active[wk.box]) return;
+  const SubDev S = D.subs[wk.box];
+  if (n >= S.nlev - 1) return;
+  const int lane = int(threadIdx.x & 63);
+  const int nx = S.nx, ny = S.ny;
+  const int c = wk.c0 + lane - p;
+  const bool out_lane = lane >= p && lane < 64 - p && c < nx;
+  const bool col_ok = S.span || c < nx + p;
+  const int colw = S.span ? ((c % nx) + nx) % nx : c;
+  const int64_t plane = S.ncell;
+  const T* Z = zlevel(D, S, n);
+  const T* B0 = n >= 1 ? zlevel(D, S, n - 1) : Z;
+  const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
+  T* out = zlevel(D, S, n + 1);
+  const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
+  const T itp = one / T(p), itq = one / T(kColQ);
+  const int q = kColQ;
+  const int hl = D.half;
+  const int lEp = min(lane + p, 63), lWp = max(lane - p, 0);
+  const T wgt = n == 0 ? T(0.5) : T(1);
+  auto zload = [&](int rr) {
+    const Pt P = point(S, rr, col_ok ? colw : 0, 0, 0, p, kColQ, hl, nlat);
+    return ld_pt(Z, R, plane, S.nring, P);
+  };
+  V3<T> w[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) w[i] = zload(wk.r0 - 2 + i);
+  V3<T> pf;
+  for (int r = wk.r0; r < wk.r1; ++r) {
+    // coefficient rows first (the loads of a wave complete in order)
+    const RowCoef<T> rc = D.rows[__builtin_amdgcn_readfirstlane(S.row0 + r)];
+    const RowCoef<T> rN = D.rows[__builtin_amdgcn_readfirstlane(grow_of(S, r + q, nlat))];
+    const RowCoef<T> rS = D.rows[__builtin_amdgcn_readfirstlane(grow_of(S, r - q, nlat))];
+    if (r > wk.r0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[i] = w[i + 1];
+      w[4] = pf;
+    }
+    pf = zload(min(r + 3, ny + kColQ - 1));
+    const int m = out_lane ? r * nx + c : 0;
+    const V3<T> B = ld_box(B0, plane, m, T(1));
+    const V3<T> E = {lane_next(w[2].h), lane_next(w[2].u), lane_next(w[2].v)};
+    const V3<T> W = {lane_prev(w[2].h), lane_prev(w[2].u), lane_prev(w[2].v)};
+    const V3<T> Ep = {__shfl(w[2].h, lEp, 64), __shfl(w[2].u, lEp, 64), __shfl(w[2].v, lEp, 64)};
+    const V3<T> Wp = {__shfl(w[2].h, lWp, 64), __shfl(w[2].u, lWp, 64), __shfl(w[2].v, lWp, 64)};
+    const T ENu = __shfl(w[4].u, lEp, 64), ENv = __shfl(w[4].v, lEp, 64);
+    const T WNu = __shfl(w[4].u, lWp, 64), WNv = __shfl(w[4].v, lWp, 64);
+    const T ESu = __shfl(w[0].u, lEp, 64), ESv = __shfl(w[0].v, lEp, 64);
+    const T WSu = __shfl(w[0].u, lWp, 64), WSv = __shfl(w[0].v, lWp, 64);
+    if (!out_lane) continue;
+    const V3<T>& C = w[2];
+    const V3<T>& N = w[3];
+    const V3<T>& Sv = w[1];
+    const V3<T>& Nq = w[4];
+    const V3<T>& Sq = w[0];
+    const T hh = h0 + C.h;
+    const T U = -rc.a1 * C.u * (E.u - W.u) - st * C.v * (N.u - Sv.u) -
+                rc.a2 * itp * (Ep.h - Wp.h) +
+                ((one - al) * (rc.cf + rc.ct * C.u) * C.v + half * al * (rc.cf + rc.ct * Ep.u) * Ep.v +
+                 half * al * (rc.cf + rc.ct * Wp.u) * Wp.v);
+    const T V = -rc.a1 * C.u * (E.v - W.v) - st * C.v * (N.v - Sv.v) -
+                stg * itq * (Nq.h - Sq.h) -
+                ((one - al) * (rc.cf + rc.ct * C.u) * C.u + half * al * (rN.cf + rN.ct * Nq.u) * Nq.u +
+                 half * al * (rS.cf + rS.ct * Sq.u) * Sq.u);
+    const T Dl = ((one - al) * (Ep.u - Wp.u) + half * al * (ENu - WNu + ESu - WSu)) * itp;
+    const T Dt = ((one - al) * (Nq.v * rN.c - Sq.v * rS.c) + half * al * (ENv * rN.c - ESv * rS.c) +
+                  half * al * (WNv * rN.c - WSv * rS.c)) * itq;
+    const T H = -rc.a1 * (C.u * (E.h - W.h) + hh * Dl) - (st * C.v * (N.h - Sv.h) + rc.a3 * hh * Dt);
+    out[m] = B.h + wgt * H;
+    out[plane + m] = B.u + wgt * U;
+    out[2 * plane + m] = B.v + wgt * V;
+  }
+}
+
 // observation forcing of the column-walk adjoint at level n: for every entry
 // of a (tile, level) bin, q_o (Z - y) (or q_o dZ in mode 3) added to
 // lambda^n, or at level 0 to the gradient / adj0; its share of J added to
@@ -866,7 +955,14 @@ __global__ __launch_bounds__(kTile) void k_obs_tz(Dom<T> D, int n, const int32_t
 
 template <typename T>
 void launch_fwd_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
-                   int nlat, hipStream_t st) {
+                   int nlat, const TzWork* work, int nwork, hipStream_t st) {
+  if (work) {
+    const int nb = (nwork + kColThreads / 64 - 1) / (kColThreads / 64);
+    if (nb > 0)
+      hipLaunchKernelGGL(k_fwd_tz_col<T>, dim3(nb), dim3(kColThreads), 0, st, D, n, work, nwork, p,
+                         T(alpha), nlat);
+    return;
+  }
   hipLaunchKernelGGL(k_fwd_tz<T>, dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q, T(alpha),
                      nlat);
 }
@@ -926,7 +1022,7 @@ void launch_tlm_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int
 
 #define DD4DVAR_INST(T)                                                                        \
   template void launch_fwd_tz<T>(const Dom<T>&, int, int, int, int, int, double, int,         \
-                                 hipStream_t);                                                 \
+                                 const TzWork*, int, hipStream_t);                            \
   template void launch_adj_tz<T>(const Dom<T>&, int, int, int, int, int, int, double, int,     \
                                  const double*, const double*, const double*, double*,        \
                                  const TzWork*, int, const int32_t*, int, hipStream_t);       \

@@ -22,11 +22,11 @@ spanning bands whose pads reach across a pole partly into the box itself.
   (frozen pads unperturbed), and a DD solve with Gauss-Newton local solves;
 * the persistent execution modes, which the variant does not have, return
   E_INVALID;
-* the two adjoint kernels (gather form for any p, q; column walk for q = 2,
-  p <= 8, the default where it applies) against each other on the same
-  inputs: J and gradients, the adjoint of a caller forcing, the Gauss-Newton
-  product (every q = 2 case above also runs the column walk against the
-  oracle).
+* the two kinds of step kernels (gather form for any p, q; column walk for
+  q = 2, p <= 8, the default where it applies) against each other on the
+  same inputs: trajectories, J and gradients, the adjoint of a caller
+  forcing, the Gauss-Newton product (every q = 2 case above also runs the
+  column walk against the oracle).
 """
 import functools
 
@@ -295,18 +295,18 @@ def test_column_walk_applies_where_documented(which, tzv):
     p, maps, _, _ = _state(tzv, which)
     ctx = Context(p, "fp32")
     applies = tzv[1] == 2 and tzv[0] <= 8
-    assert ctx.tz_adjoint() == {"kind": int(applies), "column_walk_applies": applies}
-    ctx.set_tz_adjoint(0)
-    assert ctx.tz_adjoint()["kind"] == 0
+    assert ctx.tz_kernels() == {"kind": int(applies), "column_walk_applies": applies}
+    ctx.set_tz_kernels(0)
+    assert ctx.tz_kernels()["kind"] == 0
     if applies:
-        ctx.set_tz_adjoint(1)
-        assert ctx.tz_adjoint()["kind"] == 1
+        ctx.set_tz_kernels(1)
+        assert ctx.tz_kernels()["kind"] == 1
     else:
         with pytest.raises(L.DD4DVarError) as e:
-            ctx.set_tz_adjoint(1)
+            ctx.set_tz_kernels(1)
         assert e.value.status == L.DD4DVAR_E_INVALID
     with pytest.raises(L.DD4DVarError) as e:
-        ctx.set_tz_adjoint(2)
+        ctx.set_tz_kernels(2)
     assert e.value.status == L.DD4DVAR_E_INVALID
     ctx.close()
 
@@ -318,11 +318,12 @@ COLUMN_CASES = [("time", (2, 2, 0.5)), ("time", (3, 2, 0.25))] + \
 @pytest.mark.parametrize("which,tzv", COLUMN_CASES)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_column_walk_matches_gather(which, tzv, prec):
-    """Both adjoint kernels run the same terms in the same order; they differ
-    by the rounding of the observation forcing into the adjoint state (added
-    after it is rounded to the state precision in the column walk) and by
-    the partial sums of J: FP64 1e-13, FP32 1e-5 per field, J 1e-13 / 1e-6
-    relative."""
+    """Both kinds of step kernels evaluate the same expressions in the same
+    order; the adjoints differ by the rounding of the observation forcing
+    into the adjoint state (added after it is rounded to the state precision
+    in the column walk) and by the partial sums of J, and either may fuse
+    multiply-adds differently: FP64 1e-13, FP32 1e-5 per field, J 1e-13 /
+    1e-6 relative."""
     import torch
     from paper_2205_06649_amd.context import Context
     p, maps, trajs, rings = _state(tzv, which)
@@ -334,20 +335,22 @@ def test_column_walk_matches_gather(which, tzv, prec):
     xp, fp, dp = ctx.pack_ctrl(xs), ctx.pack_traj(forcing), ctx.pack_ctrl(dxs)
     res = {}
     for kind in (0, 1):
-        ctx.set_tz_adjoint(kind)
+        ctx.set_tz_kernels(kind)
         J, g = ctx.cost_grad(xp)
-        ctx.forward(xp, with_traj=False)
+        tr = ctx.unpack_traj(ctx.forward(xp))
         a = ctx.adjoint(fp)
         h = ctx.gn_hessvec(dp)
         ctx.synchronize()
-        res[kind] = (J.cpu().numpy(), [ctx.unpack_ctrl(v) for v in (g, a, h)])
+        res[kind] = (J.cpu().numpy(), [ctx.unpack_ctrl(v) for v in (g, a, h)], tr)
     ctx.close()
     tol = 1e-13 if prec == "fp64" else 1e-5
     tol_j = 1e-13 if prec == "fp64" else 1e-6
-    (J0, r0), (J1, r1) = res[0], res[1]
+    (J0, r0, t0), (J1, r1, t1) = res[0], res[1]
     ej = float(np.max(np.abs(J1 - J0) / np.abs(J0)))
     errs = [max(_field_err(r1[k][b.sub], r0[k][b.sub]) for b in maps.boxes) for k in range(3)]
-    print(f"tz {which} {tzv} {prec}: J {ej:.2e}, gradient {errs[0]:.2e}, adjoint {errs[1]:.2e}, "
-          f"Gauss-Newton product {errs[2]:.2e}", flush=True)
+    et = max(_field_err(_anom(t1[b.sub], p.h_ref), _anom(t0[b.sub], p.h_ref)) for b in maps.boxes)
+    print(f"tz {which} {tzv} {prec}: trajectories {et:.2e}, J {ej:.2e}, gradient {errs[0]:.2e}, "
+          f"adjoint {errs[1]:.2e}, Gauss-Newton product {errs[2]:.2e}", flush=True)
+    assert et <= tol
     assert ej <= tol_j
     assert max(errs) <= tol, errs
