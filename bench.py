@@ -487,6 +487,7 @@ def tz_leg(spec, reps=5):
     res = {}
     for prec, b in (("fp32", 4), ("fp64", 8)):
         ctx = Context(prob, prec)
+        out["step_kernels"] = ("column walk" if ctx.tz_kernels()["kind"] == 1 else "gather")
         gen = torch.Generator(device="cuda")
         gen.manual_seed(2205)
         sb = torch.tensor(prob.sigma_b, dtype=torch.float64, device="cuda")

@@ -90,6 +90,9 @@ struct dd4dvar_ctx {
   TzWork* tz_work = nullptr;
   int tz_nwork = 0;
   std::vector<int> tz_work_box;
+  // the forward's waves (shorter strips: no J slots; more waves in flight)
+  TzWork* tz_fwork = nullptr;
+  std::vector<int> tz_fwork_box;
   // per local level, the tiles with observation entries there (CSR)
   int32_t* tz_obs_tiles = nullptr;
   std::vector<int> tz_obs_ptr;
@@ -267,10 +270,13 @@ void fill_rows(const dd4dvar_model_desc& m, std::vector<RowCoef<T>>& rows, std::
 // The column-walk waves of the boxes whose tiles are [tile_base, tile_base +
 // ntiles) (a run of whole boxes: every box, one interval's, or one box);
 // none when the column walk is off
-void tz_work_range(const dd4dvar_ctx* c, int tile_base, int ntiles, const TzWork** work, int* nwork) {
+void tz_work_range(const dd4dvar_ctx* c, int tile_base, int ntiles, const TzWork** work, int* nwork,
+                   bool forward = false) {
   *work = nullptr;
   *nwork = 0;
   if (!c->tz_col) return;
+  const std::vector<int>& wb = forward ? c->tz_fwork_box : c->tz_work_box;
+  TzWork* base = forward ? c->tz_fwork : c->tz_work;
   size_t s0 = c->subs.size(), s1 = c->subs.size();
   for (size_t s = 0; s < c->subs.size(); ++s) {
     if (c->subs[s].tile0 == tile_base) s0 = s;
@@ -278,8 +284,8 @@ void tz_work_range(const dd4dvar_ctx* c, int tile_base, int ntiles, const TzWork
   }
   if (s0 == c->subs.size() || s1 == c->subs.size() || s1 < s0)
     throw DevError{DD4DVAR_E_INVALID, "sweep launch over a tile range that is not a run of boxes"};
-  *work = c->tz_work + c->tz_work_box[s0];
-  *nwork = c->tz_work_box[s1 + 1] - c->tz_work_box[s0];
+  *work = base + wb[s0];
+  *nwork = wb[s1 + 1] - wb[s0];
 }
 
 // One forward and one adjoint step of the step kernels in the scheme that the
@@ -291,7 +297,7 @@ void fwd_step(const dd4dvar_ctx* c, const Dom<T>& D, int n, int tile_base, int n
   if (c->tz_p > 0) {
     const TzWork* work = nullptr;
     int nwork = 0;
-    if (!global) tz_work_range(c, tile_base, ntiles, &work, &nwork);
+    if (!global) tz_work_range(c, tile_base, ntiles, &work, &nwork, true);
     launch_fwd_tz<T>(D, n, tile_base, ntiles, c->tz_p, c->tz_q, c->tz_alpha, c->plan.model.nlat,
                      work, nwork, st);
   } else {
@@ -855,44 +861,48 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
     c->tz_p = P.model.tz_p;
     c->tz_q = P.model.tz_q;
     c->tz_alpha = P.model.tz_alpha;
-    // column-walk adjoint (q = 2, p <= 8): each box in column blocks of
-    // 64 - 2p outputs and row strips of at least 16 rows, at most one wave
-    // per 256-cell tile of the box (each wave owns one J slot of the box)
+    // column-walk kernels (q = 2, p <= 8): each box in column blocks of
+    // 64 - 2p outputs and row strips (a strip reloads the four rows around
+    // it): at least 32 rows for the adjoint, with at most one wave per
+    // 256-cell tile of the box (each wave owns one J slot of the box), and
+    // at least 16 for the forward (more waves in flight)
     if (c->tz_q == 2 && c->tz_p <= 8) {
       const int cw = 64 - 2 * c->tz_p;
-      std::vector<TzWork> wl;
-      std::vector<int> wb(c->subs.size() + 1, 0);
-      bool ok = true;
-      for (size_t s = 0; s < c->subs.size() && ok; ++s) {
-        const SubDev& S = c->subs[s];
-        wb[s] = int(wl.size());
-        const int ncb = (S.nx + cw - 1) / cw;
-        if (ncb > S.ntile) {
-          ok = false;
-          break;
-        }
-        const int maxstrips = S.ntile / ncb;
-        const int R = std::max(16, (S.ny + maxstrips - 1) / maxstrips);
-        const int nstr = (S.ny + R - 1) / R;
-        int j = 0;
-        for (int cb = 0; cb < ncb; ++cb)
-          for (int k = 0; k < nstr; ++k, ++j) {
-            TzWork w{};
-            w.box = int32_t(s);
-            w.c0 = cb * cw;
-            w.r0 = k * R;
-            w.r1 = std::min(S.ny, (k + 1) * R);
-            w.slot = S.tile0 + j;
-            w.zero0 = w.zero1 = 0;
-            if (j == 0) {
-              w.zero0 = S.tile0 + ncb * nstr;
-              w.zero1 = S.tile0 + S.ntile;
+      // waves of every box with strips of at least rmin rows; false when some
+      // box has more column blocks than tiles
+      auto build_list = [&](int rmin, std::vector<TzWork>& wl, std::vector<int>& wb) {
+        wb.assign(c->subs.size() + 1, 0);
+        for (size_t s = 0; s < c->subs.size(); ++s) {
+          const SubDev& S = c->subs[s];
+          wb[s] = int(wl.size());
+          const int ncb = (S.nx + cw - 1) / cw;
+          if (ncb > S.ntile) return false;
+          const int maxstrips = S.ntile / ncb;
+          const int R = std::max(rmin, (S.ny + maxstrips - 1) / maxstrips);
+          const int nstr = (S.ny + R - 1) / R;
+          int j = 0;
+          for (int cb = 0; cb < ncb; ++cb)
+            for (int k = 0; k < nstr; ++k, ++j) {
+              TzWork w{};
+              w.box = int32_t(s);
+              w.c0 = cb * cw;
+              w.r0 = k * R;
+              w.r1 = std::min(S.ny, (k + 1) * R);
+              w.slot = S.tile0 + j;
+              w.zero0 = w.zero1 = 0;
+              if (j == 0) {
+                w.zero0 = S.tile0 + ncb * nstr;
+                w.zero1 = S.tile0 + S.ntile;
+              }
+              wl.push_back(w);
             }
-            wl.push_back(w);
-          }
-      }
-      if (ok && !wl.empty()) {
+        }
         wb.back() = int(wl.size());
+        return !wl.empty();
+      };
+      std::vector<TzWork> wl, fl;
+      std::vector<int> wb, fb;
+      if (build_list(32, wl, wb) && build_list(16, fl, fb)) {
         std::vector<int> otp(c->maxlev + 1, 0);
         std::vector<int32_t> otl;
         for (int n = 0; n < c->maxlev; ++n) {
@@ -909,6 +919,8 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
         c->tz_work = upload(c, wl, st);
         c->tz_nwork = int(wl.size());
         c->tz_work_box = wb;
+        c->tz_fwork = upload(c, fl, st);
+        c->tz_fwork_box = fb;
         c->tz_col_ok = c->tz_col = true;
       }
     }
