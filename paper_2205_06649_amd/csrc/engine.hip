@@ -434,9 +434,13 @@ void local_tlm(dd4dvar_ctx* c, const double* dx, hipStream_t st) {
   }
   auto sweep = [&](int tile_base, int ntiles, int nlev) {
     launch_tlm_init<T>(D, dx, tile_base, ntiles, st);
+    const TzWork* work = nullptr;
+    int nwork = 0;
+    if (c->tz_p > 0) tz_work_range(c, tile_base, ntiles, &work, &nwork, true);
     for (int n = 0; n + 1 < nlev; ++n) {
       if (c->tz_p > 0)
-        launch_tlm_tz<T>(D, n, tile_base, ntiles, c->tz_p, c->tz_q, c->tz_alpha, c->plan.model.nlat, st);
+        launch_tlm_tz<T>(D, n, tile_base, ntiles, c->tz_p, c->tz_q, c->tz_alpha, c->plan.model.nlat,
+                         work, nwork, st);
       else
         launch_tlm<T>(D, n, tile_base, ntiles, st);
     }

@@ -72,9 +72,11 @@ void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, 
                    double alpha, int nlat, const double* x, const double* xb,
                    const double* forcing, double* out, const TzWork* work, int nwork,
                    const int32_t* obs_tiles, int nobs_tiles, hipStream_t st);
+// tangent-linear step: work == nullptr, the gather kernel; otherwise the
+// column walk over the nwork waves
 template <typename T>
 void launch_tlm_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
-                   int nlat, hipStream_t st);
+                   int nlat, const TzWork* work, int nwork, hipStream_t st);
 
 // box.hip: persistent per-box sweeps (FP32 state)
 //

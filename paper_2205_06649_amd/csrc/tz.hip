@@ -909,6 +909,118 @@ __global__ __launch_bounds__(kColThreads) void k_fwd_tz_col(Dom<T> D, int n,
   }
 }
 
+// Column-walk tangent-linear step for the q = 2 offset (the TLM step of
+// Alg. 6 under the variant): the forward's waves, each lane keeping the
+// state and the perturbation of the rows r - 2 .. r + 2 of its column (the
+// perturbation zero at frozen pad positions, whose values do not depend on
+// the control, and negated in u, v across a pole), one new row per step.
+// Arithmetic as in k_tlm_tz.
+template <typename T>
+__global__ __launch_bounds__(kColThreads) void k_tlm_tz_col(Dom<T> D, int n,
+                                                            const TzWork* __restrict__ work,
+                                                            int nwork, int p, T alpha, int nlat) {
+  const int wv = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * (kColThreads / 64) +
+                                                int(threadIdx.x >> 6));
+  if (wv >= nwork) return;                 // whole waves; no workgroup barrier below
+  const TzWork wk = work[wv];
+  if (D.active && !D.active[wk.box]) return;
+  const SubDev S = D.subs[wk.box];
+  if (n >= S.nlev - 1) return;
+  const int lane = int(threadIdx.x & 63);
+  const int nx = S.nx, ny = S.ny;
+  const int c = wk.c0 + lane - p;
+  const bool out_lane = lane >= p && lane < 64 - p && c < nx;
+  const bool col_ok = S.span || c < nx + p;
+  const int colw = S.span ? ((c % nx) + nx) % nx : c;
+  const int64_t plane = S.ncell;
+  const T* Z = zlevel(D, S, n);
+  const T* R = D.ring + S.ring_off + int64_t(n) * 3 * S.nring;
+  const T* dZ = D.dz + S.zoff + int64_t(n) * 3 * plane;
+  const T* dB = n >= 1 ? D.dz + S.zoff + int64_t(n - 1) * 3 * plane : dZ;
+  T* out = D.dz + S.zoff + int64_t(n + 1) * 3 * plane;
+  const T st = D.st, stg = D.stg, h0 = D.h0, al = alpha, one = T(1), half = T(0.5);
+  const T itp = one / T(p), itq = one / T(kColQ);
+  const int q = kColQ;
+  const int hl = D.half;
+  const int lEp = min(lane + p, 63), lWp = max(lane - p, 0);
+  const T wgt = n == 0 ? T(0.5) : T(1);
+  // the state and the perturbation as loaded (no branch around the loads);
+  // the perturbation's pad flag and pole sign are applied when the row
+  // enters the window
+  struct TLoad {
+    V3<T> z, d;
+    bool din;
+    T sg;
+  };
+  auto issue = [&](int rr) {
+    const Pt P = point(S, rr, col_ok ? colw : 0, 0, 0, p, kColQ, hl, nlat);
+    TLoad t;
+    t.z = ld_pt(Z, R, plane, S.nring, P);
+    t.d = ld_box(dZ, plane, P.pad ? 0 : P.idx, T(1));
+    t.din = !P.pad;
+    t.sg = T(P.sg);
+    return t;
+  };
+  auto take = [&](const TLoad& t) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(t.din);
+    WinRow<T> w;
+    w.z = t.z;
+    w.l = {pick_lane(t.d.h, T(0), m), t.sg * pick_lane(t.d.u, T(0), m), t.sg * pick_lane(t.d.v, T(0), m)};
+    return w;
+  };
+  WinRow<T> w[5];                          // .z the state, .l the perturbation
+#pragma unroll
+  for (int i = 0; i < 5; ++i) w[i] = take(issue(wk.r0 - 2 + i));
+  TLoad pf;
+  for (int r = wk.r0; r < wk.r1; ++r) {
+    const RowCoef<T> rc = D.rows[__builtin_amdgcn_readfirstlane(S.row0 + r)];
+    const RowCoef<T> rN = D.rows[__builtin_amdgcn_readfirstlane(grow_of(S, r + q, nlat))];
+    const RowCoef<T> rS = D.rows[__builtin_amdgcn_readfirstlane(grow_of(S, r - q, nlat))];
+    if (r > wk.r0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[i] = w[i + 1];
+      w[4] = take(pf);
+    }
+    pf = issue(min(r + 3, ny + kColQ - 1));
+    const int m = out_lane ? r * nx + c : 0;
+    const V3<T> B = ld_box(dB, plane, m, T(1));
+    const WinRow<T> E1 = win_next(w[2]), W1 = win_prev(w[2]);
+    const WinRow<T> Ep = win_shfl(w[2], lEp), Wp = win_shfl(w[2], lWp);
+    const WinRow<T> EN = win_shfl(w[4], lEp), WN = win_shfl(w[4], lWp);
+    const WinRow<T> ES = win_shfl(w[0], lEp), WS = win_shfl(w[0], lWp);
+    if (!out_lane) continue;
+    const V3<T>& C = w[2].z;
+    const V3<T>& dC = w[2].l;
+    const T hh = h0 + C.h;
+    const T dU = -rc.a1 * (dC.u * (E1.z.u - W1.z.u) + C.u * (E1.l.u - W1.l.u)) -
+                 st * (dC.v * (w[3].z.u - w[1].z.u) + C.v * (w[3].l.u - w[1].l.u)) -
+                 rc.a2 * itp * (Ep.l.h - Wp.l.h) +
+                 ((one - al) * (rc.ct * dC.u * C.v + (rc.cf + rc.ct * C.u) * dC.v) +
+                  half * al * (rc.ct * Ep.l.u * Ep.z.v + (rc.cf + rc.ct * Ep.z.u) * Ep.l.v) +
+                  half * al * (rc.ct * Wp.l.u * Wp.z.v + (rc.cf + rc.ct * Wp.z.u) * Wp.l.v));
+    const T dV = -rc.a1 * (dC.u * (E1.z.v - W1.z.v) + C.u * (E1.l.v - W1.l.v)) -
+                 st * (dC.v * (w[3].z.v - w[1].z.v) + C.v * (w[3].l.v - w[1].l.v)) -
+                 stg * itq * (w[4].l.h - w[0].l.h) -
+                 ((one - al) * (rc.cf + T(2) * rc.ct * C.u) * dC.u +
+                  half * al * (rN.cf + T(2) * rN.ct * w[4].z.u) * w[4].l.u +
+                  half * al * (rS.cf + T(2) * rS.ct * w[0].z.u) * w[0].l.u);
+    const T Dl = ((one - al) * (Ep.z.u - Wp.z.u) + half * al * (EN.z.u - WN.z.u + ES.z.u - WS.z.u)) * itp;
+    const T Dt = ((one - al) * (w[4].z.v * rN.c - w[0].z.v * rS.c) +
+                  half * al * (EN.z.v * rN.c - ES.z.v * rS.c) +
+                  half * al * (WN.z.v * rN.c - WS.z.v * rS.c)) * itq;
+    const T dDl = ((one - al) * (Ep.l.u - Wp.l.u) + half * al * (EN.l.u - WN.l.u + ES.l.u - WS.l.u)) * itp;
+    const T dDt = ((one - al) * (w[4].l.v * rN.c - w[0].l.v * rS.c) +
+                   half * al * (EN.l.v * rN.c - ES.l.v * rS.c) +
+                   half * al * (WN.l.v * rN.c - WS.l.v * rS.c)) * itq;
+    const T dH = -rc.a1 * (dC.u * (E1.z.h - W1.z.h) + C.u * (E1.l.h - W1.l.h) + dC.h * Dl + hh * dDl) -
+                 (st * (dC.v * (w[3].z.h - w[1].z.h) + C.v * (w[3].l.h - w[1].l.h)) +
+                  rc.a3 * (dC.h * Dt + hh * dDt));
+    out[m] = B.h + wgt * dH;
+    out[plane + m] = B.u + wgt * dU;
+    out[2 * plane + m] = B.v + wgt * dV;
+  }
+}
+
 // observation forcing of the column-walk adjoint at level n: for every entry
 // of a (tile, level) bin, q_o (Z - y) (or q_o dZ in mode 3) added to
 // lambda^n, or at level 0 to the gradient / adj0; its share of J added to
@@ -1015,7 +1127,14 @@ void launch_adj_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, 
 }
 template <typename T>
 void launch_tlm_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int q, double alpha,
-                   int nlat, hipStream_t st) {
+                   int nlat, const TzWork* work, int nwork, hipStream_t st) {
+  if (work) {
+    const int nb = (nwork + kColThreads / 64 - 1) / (kColThreads / 64);
+    if (nb > 0)
+      hipLaunchKernelGGL(k_tlm_tz_col<T>, dim3(nb), dim3(kColThreads), 0, st, D, n, work, nwork, p,
+                         T(alpha), nlat);
+    return;
+  }
   hipLaunchKernelGGL(k_tlm_tz<T>, dim3(ntiles), dim3(kTile), 0, st, D, n, tile_base, p, q, T(alpha),
                      nlat);
 }
@@ -1027,7 +1146,7 @@ void launch_tlm_tz(const Dom<T>& D, int n, int tile_base, int ntiles, int p, int
                                  const double*, const double*, const double*, double*,        \
                                  const TzWork*, int, const int32_t*, int, hipStream_t);       \
   template void launch_tlm_tz<T>(const Dom<T>&, int, int, int, int, int, double, int,         \
-                                 hipStream_t);
+                                 const TzWork*, int, hipStream_t);
 DD4DVAR_INST(DD4DVAR_TZ_T)
 #undef DD4DVAR_INST
 

@@ -354,3 +354,42 @@ def test_column_walk_matches_gather(which, tzv, prec):
     assert et <= tol
     assert ej <= tol_j
     assert max(errs) <= tol, errs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_column_walk_without_observations(prec):
+    """No observation at any level: every level's list of tiles with entries
+    is empty and the column walk runs no observation kernel.  J and gradients
+    of every box against the oracle (FP64 against its extended-precision
+    pipeline, 1e-12; FP32 1e-4) and against the gather kernels."""
+    from paper_2205_06649_amd.context import Context
+    p = custom_problem(dict(TZ_SPACE_CFGS["c1"], tz=(2, 2, 0.5)))
+    p = p.replace(obs_step=p.obs_step[:0], obs_cell=p.obs_cell[:0], obs_field=p.obs_field[:0],
+                  obs_value=p.obs_value[:0], obs_sigma=p.obs_sigma[:0],
+                  obs_noise=p.obs_noise[:0])
+    assert p.nobs == 0
+    maps = ddmaps.build(p)
+    _, trajs = dd.background(p, maps)
+    xs = _controls(p, maps, trajs, seed=8)
+    ctx = Context(p, prec)
+    assert ctx.tz_kernels() == {"kind": 1, "column_walk_applies": True}
+    res = {}
+    for kind in (1, 0):
+        ctx.set_tz_kernels(kind)
+        J, g = ctx.cost_grad(ctx.pack_ctrl(xs))
+        ctx.synchronize()
+        res[kind] = (J.cpu().numpy(), ctx.unpack_ctrl(g))
+    ctx.close()
+    D = np.longdouble if prec == "fp64" else np.float64
+    _, rt = dd.background(p, maps, D)
+    rr, _ = dd.exchange(maps, rt)
+    J1, g1 = res[1]
+    J0, g0 = res[0]
+    for b in maps.boxes:
+        s = b.sub
+        Jr, gr = local.cost_grad(p, maps, s, xs[s], rt[s][0], rr[s], {k: rt[k] for k in maps.neighbors[s]},
+                                 dtype=D)
+        ej, eg = float(abs(J1[s] - Jr) / abs(Jr)), _rel(g1[s], gr)
+        print(f"tz no observations {prec} box {s}: J rel {ej:.2e}, grad rel {eg:.2e}", flush=True)
+        assert ej <= TOL[prec] and eg <= TOL_GRAD[prec], (s, ej, eg)
+        assert _field_err(g1[s], g0[s]) <= (1e-13 if prec == "fp64" else 1e-5)
