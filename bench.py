@@ -236,6 +236,45 @@ def solve_leg(prob, mode):
     return out
 
 
+def few_boxes_solve_leg(spec, reps=3):
+    """Local solves on a decomposition with few large boxes: the benchmark's
+    grid, window and observations as a time decomposition into 8 intervals,
+    each box the whole sphere (6.3 million control entries per box), FP32
+    state sweeps.  One outer iteration of Alg. 1 with 10 L-BFGS iterations,
+    and one with 2 Gauss-Newton updates of 6 CG products; the time of one
+    evaluation beside them, so that what the solver's own vector work costs
+    shows as the rest."""
+    import torch
+    import synth
+    from paper_2205_06649_amd.context import Context
+    tspec = spec.replace(band_lat_edges=np.array([0, spec.nlat], np.int32),
+                         band_npieces=np.array([1], np.int32),
+                         piece_lon_edges=np.array([0, spec.nlon], np.int32), overlap_cells=0)
+    prob = synth.finish_spec(tspec, gpu_truth_forward)
+    ctx = Context(prob, "fp32")
+    out = {"workload": f"{prob.nlat}x{prob.nlon}, {prob.nsteps} steps, "
+                       f"{len(prob.time_edges) - 1} intervals (boxes covering the sphere)",
+           "solver_parts": ctx.solver_parts()}
+    x = ctx.background_controls()
+    ms, _, _ = time_evals(ctx, x, reps, 1)
+    out["eval_ms"] = ms
+    for name, kw in (("lbfgs", dict(max_iter=10)),
+                     ("gauss_newton_cg", dict(max_iter=2, local_solver="gn", cg_max_iter=6))):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, rep, _, _ = ctx.solve(max_outer=1, outer_tol=0.0, **kw)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        out[name] = {"seconds": sec, "evaluations": int(rep.total_evals),
+                     "products": int(rep.gn_products)}
+        log(f"few-box {name} solve: {sec * 1e3:.0f} ms, {rep.total_evals} evaluations, "
+            f"{rep.gn_products} products")
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
 def differentiation_leg(config="c4"):
     """The local sweeps under torch.autograd on the 512 x 1024, 1000-step,
     8 x 8 x 10 decomposition (local windows of 103-106 steps): LocalSweep maps
@@ -899,6 +938,7 @@ def main():
 
     if not args.no_solve:
         result["solve"] = solve_leg(prob, mode)
+        result["solve"]["few_boxes"] = few_boxes_solve_leg(spec)
     if not args.no_gn:
         result["gauss_newton"] = gn_leg(prob, x, mode, passes, args.config,
                                         solves=not args.no_gn_solve)

@@ -340,6 +340,21 @@ dd4dvar_status dd4dvar_set_tz_kernels(dd4dvar_ctx* ctx, int32_t kind);
 /* out[2] = {Turkel-Zwas kernel kind in use, 1 if the column walk applies}. */
 dd4dvar_status dd4dvar_get_tz_kernels(const dd4dvar_ctx* ctx, int32_t out[2]);
 
+/* Vector work of the local solvers (the L-BFGS iteration of the remark
+ * after Alg. 5, the Gauss-Newton updates of Alg. 5 with CG or the Lanczos
+ * method of Alg. 7, and the background block of dd4dvar_gn_hessvec): every
+ * box's packed control is cut into parts of `entries` entries (the last
+ * part of a box shorter), one workgroup per part, and each per-box dot
+ * product is the sum of its parts' partial sums in part order
+ * (deterministic for a given part length; another length changes the
+ * rounding of the sums only).  Default 16384; E_INVALID outside
+ * [64, 2^24].  Waits for the device to be idle before it replaces the part
+ * map; not to be called while another call on this context is running. */
+dd4dvar_status dd4dvar_set_solver_parts(dd4dvar_ctx* ctx, int32_t entries);
+
+/* out[2] = {entries per part, number of parts over all boxes}. */
+dd4dvar_status dd4dvar_get_solver_parts(const dd4dvar_ctx* ctx, int32_t out[2]);
+
 /* The plan in use: out[4] = {execution mode, pass count of the persistent
  * kernels (0 when they do not apply), rows per column strip of the mode-4
  * adjoint (0 when it does not apply), 1 if the persistent modes apply}. */

@@ -101,6 +101,8 @@ _SIGS = {
     "dd4dvar_get_exec_plan": (C.c_int, [_VP, C.POINTER(C.c_int32)]),
     "dd4dvar_set_tz_kernels": (C.c_int, [_VP, C.c_int32]),
     "dd4dvar_get_tz_kernels": (C.c_int, [_VP, C.POINTER(C.c_int32)]),
+    "dd4dvar_set_solver_parts": (C.c_int, [_VP, C.c_int32]),
+    "dd4dvar_get_solver_parts": (C.c_int, [_VP, C.POINTER(C.c_int32)]),
     "dd4dvar_synchronize": (C.c_int, [_VP, _VP]),
     "dd4dvar_set_timing": (C.c_int, [_VP, C.c_int32]),
     "dd4dvar_set_graph": (C.c_int, [_VP, C.c_int32]),
@@ -272,6 +274,16 @@ def dd4dvar_get_tz_kernels(ctx):
     out = (C.c_int32 * 2)()
     check(lib().dd4dvar_get_tz_kernels(ctx, out), ctx)
     return {"kind": out[0], "column_walk_applies": bool(out[1])}
+
+
+def dd4dvar_set_solver_parts(ctx, entries):
+    check(lib().dd4dvar_set_solver_parts(ctx, entries), ctx)
+
+
+def dd4dvar_get_solver_parts(ctx):
+    out = (C.c_int32 * 2)()
+    check(lib().dd4dvar_get_solver_parts(ctx, out), ctx)
+    return {"entries": out[0], "parts": out[1]}
 
 
 def dd4dvar_synchronize(ctx, stream=None):

@@ -83,6 +83,14 @@ class Context:
         """{kind, column_walk_applies} of the Turkel-Zwas step kernels."""
         return L.dd4dvar_get_tz_kernels(self.handle)
 
+    def set_solver_parts(self, entries):
+        """Entries per part of the local solvers' vector work (default 16384)."""
+        L.dd4dvar_set_solver_parts(self.handle, entries)
+
+    def solver_parts(self):
+        """{entries, parts} of the local solvers' part map."""
+        return L.dd4dvar_get_solver_parts(self.handle)
+
     def synchronize(self):
         """Wait for the queued work; raises DD4DVarError (E_NONFINITE) if a
         cost or gradient computed since the last check was NaN or Inf."""

@@ -97,6 +97,10 @@ struct dd4dvar_ctx {
   int32_t* tz_obs_tiles = nullptr;
   std::vector<int> tz_obs_ptr;
   bool tz_col_ok = false, tz_col = false;
+  // the solvers' vector work: every box's control cut into parts of
+  // part_len entries
+  PartMap parts{};
+  int part_len = 0;
   // state storage: every level (ckpt = 0), or checkpoint pairs every ckpt
   // levels plus one segment that the adjoint recomputes
   int ckpt = 0;
@@ -186,6 +190,36 @@ P* upload(dd4dvar_ctx* c, const std::vector<P>& v, hipStream_t st) {
   P* d = dalloc<P>(c, v.size());
   if (!v.empty()) chk(hipMemcpyAsync(d, v.data(), v.size() * sizeof(P), hipMemcpyHostToDevice, st), "upload");
   return d;
+}
+
+// the solvers' part map: every box's control cut into parts of len entries
+// (the last part of a box ragged); replaces an earlier map, whose buffers are
+// released once the device is idle
+void build_parts(dd4dvar_ctx* c, int len, hipStream_t st) {
+  std::vector<Part> parts;
+  std::vector<int2> boxp(c->subs.size());
+  for (size_t s = 0; s < c->subs.size(); ++s) {
+    const SubDev& S = c->subs[s];
+    const int n = 3 * S.ncell;
+    boxp[s] = make_int2(int(parts.size()), (n + len - 1) / len);
+    for (int lo = 0; lo < n; lo += len)
+      parts.push_back(Part{S.ctrl_off, S.cell_off, int32_t(s), S.ncell, lo, std::min(lo + len, n)});
+  }
+  if (c->parts.part) {
+    chk(hipDeviceSynchronize(), "sync");
+    auto& owned = c->mem.owned;
+    for (void* q : {(void*)c->parts.part, (void*)c->parts.box, (void*)c->parts.acc}) {
+      owned.erase(std::remove(owned.begin(), owned.end(), q), owned.end());
+      chk(hipFree(q), "hipFree");
+    }
+  }
+  c->parts.part = upload(c, parts, st);
+  c->parts.box = upload(c, boxp, st);
+  c->parts.nparts = int(parts.size());
+  c->parts.acc = dalloc<double>(c, size_t(kPartSlots) * parts.size());
+  c->part_len = len;
+  // the host vectors are pageable: the copies complete before they go
+  chk(hipStreamSynchronize(st), "sync");
 }
 
 template <typename T>
@@ -812,6 +846,7 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
 
   // uploads
   c->d_subs = upload(c, c->subs, st);
+  build_parts(c, kPartLen, st);
   c->d_tiles = upload(c, c->tiles, st);
   c->d_order = upload(c, c->h_order, st);
   c->d_gsub = upload(c, std::vector<SubDev>{G}, st);
@@ -1093,6 +1128,22 @@ dd4dvar_status dd4dvar_get_tz_kernels(const dd4dvar_ctx* ctx, int32_t out[2]) {
   if (!ctx || !out) return fail(const_cast<dd4dvar_ctx*>(ctx), DD4DVAR_E_INVALID, "null argument");
   out[0] = ctx->tz_col ? 1 : 0;
   out[1] = ctx->tz_col_ok ? 1 : 0;
+  return DD4DVAR_OK;
+}
+
+dd4dvar_status dd4dvar_set_solver_parts(dd4dvar_ctx* ctx, int32_t entries) {
+  if (!ctx || entries < 64 || entries > (1 << 24))
+    return fail(ctx, DD4DVAR_E_INVALID, "entries per part must lie in [64, 2^24]");
+  API_GUARD(ctx, {
+    build_parts(ctx, entries, nullptr);
+    return DD4DVAR_OK;
+  })
+}
+
+dd4dvar_status dd4dvar_get_solver_parts(const dd4dvar_ctx* ctx, int32_t out[2]) {
+  if (!ctx || !out) return fail(const_cast<dd4dvar_ctx*>(ctx), DD4DVAR_E_INVALID, "null argument");
+  out[0] = ctx->part_len;
+  out[1] = ctx->parts.nparts;
   return DD4DVAR_OK;
 }
 
@@ -1420,8 +1471,8 @@ dd4dvar_status dd4dvar_gn_hessvec(dd4dvar_ctx* ctx, const double* dx_dev, double
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (ctx->prec == DD4DVAR_FP64) gn_product<double>(ctx, dx_dev, out_dev, st);
     else gn_product<float>(ctx, dx_dev, out_dev, st);
-    launch_add_bdiag(ctx->d_subs, ctx->nsub, ctx->cover, ctx->plan.model.weight_mode,
-                     ctx->plan.sigma_b.data(), dx_dev, out_dev, st);
+    launch_add_bdiag(ctx->parts, ctx->cover, ctx->plan.model.weight_mode, ctx->plan.sigma_b.data(),
+                     dx_dev, out_dev, st);
     chk(hipGetLastError(), "background block launch");
     return DD4DVAR_OK;
   })
@@ -1569,6 +1620,10 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
   L.trials = B.get<int32_t>(nsub);
   L.ls = B.get<uint8_t>(nsub);
   L.pending = B.get<int32_t>(1);
+  L.P = c->parts;
+  L.alph = B.get<double>(size_t(L.m) * nsub);
+  L.acc = B.get<uint8_t>(nsub);
+  L.wslot = B.get<int32_t>(nsub);
   // Gauss-Newton state: iterate, evaluation, norms and stop flags shared
   // with the L-BFGS state above, CG vectors of its own
   GnState G{};
@@ -1607,6 +1662,9 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
     G.gn_on = B.get<uint8_t>(nsub);
     G.cg_on = B.get<uint8_t>(nsub);
     G.pending = L.pending;
+    G.P = c->parts;
+    G.ca = B.get<double>(nsub);
+    G.cb = B.get<double>(nsub);
     G.krylov = o->krylov;
     if (o->krylov == 1) {
       // Lanczos basis (cg_max_iter vectors) and per-subdomain coefficients
@@ -1696,23 +1754,23 @@ dd4dvar_status solve_typed(dd4dvar_ctx* c, const dd4dvar_solve_opts* o, const do
         gn_after(G, st);
       }
     } else {
-    lb_start(L, st);
-    for (;;) {
-      chk(hipMemsetAsync(L.pending, 0, sizeof(int32_t), st), "memset");
-      lb_count(L, st);
-      if (read1(L.pending, st) == 0) break;
-      lb_direction(L, st);
+      lb_start(L, st);
       for (;;) {
-        lb_trial(L, st);
-        c->eval_mask = L.ls;
-        cost_grad_impl<T>(c, nullptr, L.xphys, L.Jt, L.gradx, st);
-        c->eval_mask = nullptr;
-        ++evals;
         chk(hipMemsetAsync(L.pending, 0, sizeof(int32_t), st), "memset");
-        lb_armijo(L, st);
+        lb_count(L, st);
         if (read1(L.pending, st) == 0) break;
+        lb_direction(L, st);
+        for (;;) {
+          lb_trial(L, st);
+          c->eval_mask = L.ls;
+          cost_grad_impl<T>(c, nullptr, L.xphys, L.Jt, L.gradx, st);
+          c->eval_mask = nullptr;
+          ++evals;
+          chk(hipMemsetAsync(L.pending, 0, sizeof(int32_t), st), "memset");
+          lb_armijo(L, st);
+          if (read1(L.pending, st) == 0) break;
+        }
       }
-    }
     }
     chk(hipMemcpyAsync(iters_h.data(), L.iters, nsub * sizeof(int32_t), hipMemcpyDeviceToHost, st),
         "read iters");

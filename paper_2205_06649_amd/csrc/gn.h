@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "parts.h"
 
 namespace dd4dvar {
 
@@ -32,6 +33,10 @@ struct GnState {
   int krylov;
   double *lv, *la, *lb, *ly, *ritz_lo, *ritz_hi;
   double *ld, *lz;          // per-subdomain scratch of the L D L^T solve
+  // vector work by parts; per box the step's scalars between the passes
+  // (CG: a and beta; Lanczos: alpha_j and beta_{j+1})
+  PartMap P;
+  double *ca, *cb;
 };
 
 void gn_to_x(const GnState& G, hipStream_t st);
@@ -47,9 +52,8 @@ void gn_lz_update(const GnState& G, hipStream_t st);
 void gn_lz_finish(const GnState& G, hipStream_t st);
 void gn_update(const GnState& G, hipStream_t st);
 void gn_after(const GnState& G, hipStream_t st);
-void gn_step(const GnState& G, hipStream_t st);
 // out += B_w^{-1} dx over every subdomain (w^b / sigma_b^2 per control entry)
-void launch_add_bdiag(const SubDev* subs, int nsub, const uint8_t* cover, int weight_mode,
-                      const double sb[3], const double* dx, double* out, hipStream_t st);
+void launch_add_bdiag(const PartMap& P, const uint8_t* cover, int weight_mode, const double sb[3],
+                      const double* dx, double* out, hipStream_t st);
 
 }  // namespace dd4dvar

@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "parts.h"
 
 namespace dd4dvar {
 
@@ -24,6 +25,13 @@ struct LbState {
   int32_t *npairs, *head, *status, *iters, *trials;
   uint8_t* ls;              // in the line search (also the evaluation mask)
   int32_t* pending;         // device counter
+  // vector work by parts; per box the recursion's a_k ([m][nsub]), the
+  // accepted trial of the current line-search round and the ring slot its
+  // pair went to (-1: not kept)
+  PartMap P;
+  double* alph;
+  uint8_t* acc;
+  int32_t* wslot;
 };
 
 void lb_to_x(const LbState& L, int use_trial, int sel, hipStream_t st);

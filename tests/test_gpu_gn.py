@@ -126,6 +126,21 @@ def test_gn_hessvec(which, prec):
     ctx.close()
 
 
+def test_gn_hessvec_by_small_parts():
+    """The background block of the normal-matrix product over parts of 64
+    entries: the same bits as with the default parts (an entrywise term)."""
+    p, maps, bg, trajs, rings = _oracle_state("mixed")
+    ctx = _ctx("mixed", "fp64")
+    xs, dxs = _controls(p, maps, trajs, seed=27)
+    ctx.forward(ctx.pack_ctrl(xs), with_traj=False)
+    h0 = ctx.gn_hessvec(ctx.pack_ctrl(dxs)).cpu().numpy()
+    ctx.set_solver_parts(64)
+    assert ctx.solver_parts()["parts"] > len(maps.boxes)
+    h1 = ctx.gn_hessvec(ctx.pack_ctrl(dxs)).cpu().numpy()
+    assert np.array_equal(h0, h1)
+    ctx.close()
+
+
 def test_gn_hessvec_symmetric_and_positive():
     """The normal matrix is symmetric positive definite: <u, A v> = <v, A u>
     and <v, A v> > 0 for every subdomain (FP64)."""
@@ -149,12 +164,17 @@ def test_gn_hessvec_symmetric_and_positive():
     ("c1", dict(max_outer=2, max_iter=2, cg_max_iter=25)),
     ("mixed", dict(max_outer=1, max_iter=2, cg_max_iter=20)),
 ])
-def test_gn_solve_matches_oracle(which, opts):
+@pytest.mark.parametrize("parts", [None, 100])
+def test_gn_solve_matches_oracle(which, opts, parts):
     """Alg. 1 with Gauss-Newton local solves (fixed update and CG counts) in
-    FP64 against the oracle's, on the analysis and on the local controls."""
+    FP64 against the oracle's, on the analysis and on the local controls;
+    also with the solver's vector work in parts of 100 entries (every box
+    of several parts, CG's per-box scalars between part launches)."""
     p, maps, bg, trajs, rings = _oracle_state(which)
     xa_ref, rep_ref = dd.solve(p, maps, outer_tol=0.0, local_solver="gn", cg_rtol=0.0, **opts)
     ctx = _ctx(which, "fp64")
+    if parts:
+        ctx.set_solver_parts(parts)
     xa, rep, st, xo = ctx.solve(outer_tol=0.0, local_solver="gn", cg_rtol=0.0,
                                 want_controls=True, **opts)
     inc = np.linalg.norm((xa_ref - p.xb0) / p.sigma_b[:, None, None])
@@ -176,16 +196,20 @@ def test_gn_solve_matches_oracle(which, opts):
     ("tiny2", dict(max_outer=2, max_iter=2, cg_max_iter=30)),
     ("c1", dict(max_outer=1, max_iter=2, cg_max_iter=20)),
 ])
-def test_gn_lanczos_solve_matches_oracle(which, opts):
+@pytest.mark.parametrize("parts", [None, 100])
+def test_gn_lanczos_solve_matches_oracle(which, opts, parts):
     """Gauss-Newton local solves whose normal equations are solved by the
     Lanczos method (Alg. 7), FP64, against the oracle's: analysis and local
     controls, product counts, the extreme Ritz values of the local
-    preconditioned normal matrices; and against the device CG solve."""
+    preconditioned normal matrices; and against the device CG solve; also
+    with the vector work in parts of 100 entries."""
     from paper_2205_06649_amd import _lib as L
     p, maps, bg, trajs, rings = _oracle_state(which)
     kw = dict(outer_tol=0.0, local_solver="gn", cg_rtol=0.0, **opts)
     xa_ref, rep_ref = dd.solve(p, maps, krylov="lanczos", **kw)
     ctx = _ctx(which, "fp64")
+    if parts:
+        ctx.set_solver_parts(parts)
     xa, rep, st, xo = ctx.solve(krylov="lanczos", want_controls=True, **kw)
     sb = p.sigma_b[:, None, None]
     inc = np.linalg.norm((xa_ref - p.xb0) / sb)

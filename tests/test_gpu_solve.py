@@ -59,6 +59,37 @@ def test_solve_matches_oracle(which, prec, tol):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-7), ("fp32", 1e-4)])
+@pytest.mark.parametrize("which", ["c1", "small"])
+def test_solve_by_small_parts(which, prec, tol):
+    """The solver's vector work cut into parts of 100 entries (every box of
+    several parts, the last one ragged): the per-box dot products summed
+    over parts, the two-loop recursion and the line search's pair update
+    across part launches; same bars against the oracle."""
+    from paper_2205_06649_amd import _lib as L
+    from paper_2205_06649_amd.context import Context
+    p = problem(which)
+    ref, rep = _oracle_solve(which)
+    ctx = Context(p, prec)
+    assert ctx.solver_parts()["entries"] == 16384
+    ctx.set_solver_parts(100)
+    pm = ctx.solver_parts()
+    sizes = [3 * int(i[1]) * int(i[3]) for i in ctx.info]
+    assert pm == {"entries": 100, "parts": sum((n + 99) // 100 for n in sizes)}
+    assert min(sizes) > 100 and any(n % 100 for n in sizes)
+    o = OPTS[which]
+    xa, grep, status, _ = ctx.solve(max_outer=o["max_outer"], max_iter=o["max_iter"], outer_tol=1e-12)
+    err = analysis_error(xa, ref)
+    print(f"{which} {prec} parts of 100: evals {grep.total_evals} analysis err {err:.2e}", flush=True)
+    assert np.all(np.isfinite(xa))
+    assert err <= tol, err
+    for bad in (63, (1 << 24) + 1):
+        with pytest.raises(L.DD4DVarError) as e:
+            ctx.set_solver_parts(bad)
+        assert e.value.status == L.DD4DVAR_E_INVALID
+    ctx.close()
+
+
 def test_solve_reports_and_options():
     from paper_2205_06649_amd import _lib as L
     from paper_2205_06649_amd.context import Context
