@@ -160,7 +160,7 @@ def gn_product_bytes(ctx, prec_bytes, persistent=False):
 # digest of the kernel sources they were measured on: a changed kernel (or
 # another workload) reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    "k_adj": ("sweep", "a3890750a10c1e04", 1158224896),
+    "k_adj": ("sweep", "ff254c10224ff0ba", 1158229105),
     "k_adj_box/10": ("box", "727178289b323131", 16096635494),
     "k_adj_box/11": ("box", "727178289b323131", 16092319027),
     "k_adj_strip/11": ("box", "727178289b323131", 16662557491),

@@ -250,14 +250,18 @@ __global__ __launch_bounds__(kTile) void k_targets_from_local(Dom<T> D, int leve
   if (threadIdx.x == 0) jc[w] = (n0 == 0) ? acc : jc[w] + acc;
 }
 
-__global__ void k_reduce_jconst(const SubDev* __restrict__ subs, int nsub, const double* __restrict__ jc,
-                                double half_mu, double* __restrict__ jconst) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsub) return;
+// one wave per box: lane l sums tiles l, l + 64, ... in order, then a
+// butterfly whose pairs add the same two values in either order
+__global__ __launch_bounds__(256) void k_reduce_jconst(const SubDev* __restrict__ subs, int nsub,
+                                                       const double* __restrict__ jc, double half_mu,
+                                                       double* __restrict__ jconst) {
+  const int s = int(blockIdx.x) * 4 + int(threadIdx.x >> 6);
+  if (s >= nsub) return;                    // uniform over the wave
   const SubDev S = subs[s];
   double acc = 0.0;
-  for (int t = 0; t < S.ntile; ++t) acc += jc[S.tile0 + t];
-  jconst[s] = half_mu * acc;
+  for (int t = int(threadIdx.x & 63); t < S.ntile; t += 64) acc += jc[S.tile0 + t];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) jconst[s] = half_mu * acc;
 }
 
 template <typename T>
@@ -328,8 +332,8 @@ void launch_targets_from_local(const Dom<T>& D, int level, int tile_base, int nt
 }
 void launch_reduce_jconst(const SubDev* subs, int nsub, const double* jc, double half_mu,
                           double* jconst, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_jconst, dim3((nsub + 255) / 256), dim3(256), 0, st, subs, nsub, jc,
-                     half_mu, jconst);
+  hipLaunchKernelGGL(k_reduce_jconst, dim3((nsub + 3) / 4), dim3(256), 0, st, subs, nsub, jc, half_mu,
+                     jconst);
 }
 template <typename T>
 void launch_gather(const Dom<T>& D, int nspace, int ntime, int level, int64_t ncell,

@@ -255,16 +255,24 @@ __global__ __launch_bounds__(kTile) void k_adj(Dom<T> D, int n, int tile_base,
 }
 
 #if DD4DVAR_SWEEP_PRIMARY
-// J[s] = sum of tile partials (fixed order) + constant overlap part
-__global__ void k_reduce_j(const SubDev* __restrict__ subs, int count, const int32_t* __restrict__ ids,
-                           const double* __restrict__ jpart, const double* __restrict__ jconst,
-                           double* __restrict__ J, uint32_t* __restrict__ nonfinite) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
+// J[s] = sum of tile partials + constant overlap part, one wave per box: lane
+// l sums tiles l, l + 64, ... in order, then a butterfly whose pairs add the
+// same two values in either order (a fixed order, whatever the box size: a
+// box of thousands of tiles is not left to one thread)
+__global__ __launch_bounds__(256) void k_reduce_j(const SubDev* __restrict__ subs, int count,
+                                                  const int32_t* __restrict__ ids,
+                                                  const double* __restrict__ jpart,
+                                                  const double* __restrict__ jconst,
+                                                  double* __restrict__ J,
+                                                  uint32_t* __restrict__ nonfinite) {
+  const int i = int(blockIdx.x) * 4 + int(threadIdx.x >> 6);
+  if (i >= count) return;                   // uniform over the wave
   const int s = ids ? ids[i] : i;
   const SubDev S = subs[s];
   double acc = 0.0;
-  for (int t = 0; t < S.ntile; ++t) acc += jpart[S.tile0 + t];
+  for (int t = int(threadIdx.x & 63); t < S.ntile; t += 64) acc += jpart[S.tile0 + t];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) != 0) return;
   acc += jconst[s];
   J[s] = acc;
   if (!isfinite(acc)) atomicOr(nonfinite, 1u);
@@ -318,8 +326,8 @@ void launch_adj(const Dom<T>& D, int n, int tile_base, int ntiles, int mode, con
 #if DD4DVAR_SWEEP_PRIMARY
 void launch_reduce_j(const SubDev* subs, int count, const int32_t* ids, const double* jpart,
                      const double* jconst, double* J, uint32_t* nonfinite, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_j, dim3((count + 255) / 256), dim3(256), 0, st, subs, count, ids,
-                     jpart, jconst, J, nonfinite);
+  hipLaunchKernelGGL(k_reduce_j, dim3((count + 3) / 4), dim3(256), 0, st, subs, count, ids, jpart,
+                     jconst, J, nonfinite);
 }
 #endif
 template <typename T>
