@@ -290,6 +290,47 @@ def test_fullsize_tz_sampled_subdomains(prec, tol):
         assert ej <= tol and eg <= tol, (s, ej, eg)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp64", 1e-12)])
+def test_fullsize_tz_gn_product_sampled_subdomains(prec, tol):
+    """The Gauss-Newton normal-matrix product (eq. line5and7) under the
+    Turkel-Zwas variant on the full-size decomposition, all 2048 boxes in
+    one call (the column-walk tangent-linear and adjoint steps, frozen pads
+    unperturbed), against the oracle's product on the sampled boxes (FP64
+    against the extended-precision pipeline)."""
+    from oracle import gn
+    from paper_2205_06649_amd.context import Context
+    p, maps, sample, bg = _fullsize_tz()
+    print(f"full-size turkel-zwas Gauss-Newton product {prec}: sample {sample}", flush=True)
+    ctx = Context(p, prec)
+    assert ctx.tz_kernels()["kind"] == 1
+    xb = ctx.background_controls()
+    rng = np.random.default_rng(14)
+    xs = [(local.restrict_global(maps, b.sub, bg)[0] if b.sub in sample else x) +
+          0.3 * p.sigma_b[:, None, None] * rng.standard_normal(x.shape)
+          for b, x in zip(maps.boxes, ctx.unpack_ctrl(xb))]
+    dxs = [p.sigma_b[:, None, None] * rng.standard_normal(x.shape) for x in xs]
+    ctx.forward(ctx.pack_ctrl(xs), with_traj=False)
+    hv = ctx.gn_hessvec(ctx.pack_ctrl(dxs)).cpu().numpy()
+    assert np.all(np.isfinite(hv))
+    hvs = ctx.unpack_ctrl(hv)
+    ctx.close()
+    D = np.longdouble if prec == "fp64" else np.float64
+    g = model.Grid.of(p, D)
+    trajs = {}
+    for s in sample:
+        need = {int(k) for k in maps.halo_src[s] if k >= 0} | {s}
+        for k in need:
+            if k not in trajs:
+                trajs[k] = local.restrict_global(maps, k, bg)
+        ring = local.ring_from_trajs(maps, s, {k: trajs[k] for k in need})
+        geo = local.LocalGeometry(g, maps, s)
+        lt = local.forward(geo, np.asarray(xs[s], D), ring)
+        ref = gn.hessvec(p, maps, s, lt, ring, np.asarray(dxs[s], D), dtype=D)
+        e = _rel(hvs[s], ref)
+        print(f"  subdomain {s}: product rel {e:.2e}", flush=True)
+        assert e <= tol, (s, e)
+
+
 @pytest.mark.parametrize("which", ["c2", "c3"])
 def test_gpu_gradient_finite_differences(which):
     """Centred differences of the GPU J (FP64) along a random direction agree
