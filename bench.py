@@ -938,7 +938,6 @@ def main():
 
     if not args.no_solve:
         result["solve"] = solve_leg(prob, mode)
-        result["solve"]["few_boxes"] = few_boxes_solve_leg(spec)
     if not args.no_gn:
         result["gauss_newton"] = gn_leg(prob, x, mode, passes, args.config,
                                         solves=not args.no_gn_solve)
@@ -946,6 +945,10 @@ def main():
         result["turkel_zwas"] = tz_leg(spec)
     if not args.no_diff:
         result["differentiation"] = differentiation_leg()
+    if not args.no_solve:
+        # last: its 8 large boxes leave the device memory in another state
+        # than the legs above expect for their own allocations
+        result["solve"]["few_boxes"] = few_boxes_solve_leg(spec)
 
     # the targets of this workload, stated beside what was measured
     frac = result["roofline"]["frac"]
