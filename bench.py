@@ -848,6 +848,15 @@ def main():
         b = a.clone()
         torch.cuda.synchronize()
         log(f"copy probe: {a.numel() * 4} bytes read and written by one clone")
+        # partial cache lines: the first 32 B, then the first 64 B, of every
+        # 128 B of the same 1 GiB, gathered into a packed copy (how the read
+        # counter scales when a kernel uses part of each line it touches)
+        for nb in (32, 64):
+            c = a.view(-1, 32)[:, :nb // 4].contiguous()
+            torch.cuda.synchronize()
+            log(f"partial-line probe: {c.numel() * 4} bytes read ({nb} B of every 128 B) "
+                f"and written packed")
+            del c
         del a, b
     del ctx
     torch.cuda.empty_cache()
