@@ -161,14 +161,14 @@ def gn_product_bytes(ctx, prec_bytes, persistent=False):
 # another workload) reports null until it is measured again.
 MEASURED_TRAFFIC = {
     "k_adj": ("sweep", "ff254c10224ff0ba", 1158229105),
-    "k_adj_box/10": ("box", "727178289b323131", 16096635494),
-    "k_adj_box/11": ("box", "727178289b323131", 16092319027),
-    "k_adj_strip/11": ("box", "727178289b323131", 16662557491),
-    "k_eval_box/10": ("box", "727178289b323131", 50178714931),
+    "k_adj_box/10": ("box", "d0a69a4840912446", 16093533656),
+    "k_adj_box/11": ("box", "d0a69a4840912446", 16089092536),
+    "k_adj_strip/11": ("box", "d0a69a4840912446", 16657258389),
+    "k_eval_box/10": ("box", "d0a69a4840912446", 29856191456),
     # Gauss-Newton normal-matrix product: tangent-linear sweep (10 passes)
     # and the adjoint with the Gauss-Newton forcing (column strips, 11 rows)
-    "k_tlm_box/10": ("box", "727178289b323131", 16795245773),
-    "k_adj_strip_gn/11": ("box", "727178289b323131", 15643503104),
+    "k_tlm_box/10": ("box", "d0a69a4840912446", 16788000987),
+    "k_adj_strip_gn/11": ("box", "d0a69a4840912446", 15650230395),
 }
 KERNEL_SOURCES = {"sweep": ("sweep.hip", "kernels.h", "stencil.h"),
                   "box": ("box.hip", "kernels.h", "stencil.h")}

@@ -239,11 +239,12 @@ __device__ __forceinline__ void fwd_box_body(const Dom<float>& D, const double* 
 
   // zr holds this thread's cells of Z^{n-1} on entry to step n >= 1 (the
   // level before the one in LDS), so the base of the leapfrog update never
-  // comes back from memory; the new level replaces it in place and is then
-  // swapped with the LDS copy.
-  float zr[3][K];
+  // comes back from memory; the new level replaces it in place and goes to
+  // LDS, and the thread's cells of level n, kept in cz from the step's own
+  // reads, become the next base (no second read of the frame).
+  float zr[3][K], cz[3][K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) zr[0][k] = zr[1][k] = zr[2][k] = 0.0f;
+  for (int k = 0; k < K; ++k) zr[0][k] = zr[1][k] = zr[2][k] = cz[0][k] = cz[1][k] = cz[2][k] = 0.0f;
   const Cell q0 = first_cell(nx);
   // this thread's frozen ring position, if any (decided once: a load that a
   // branch waits on at every step would hold up the thread's first pass)
@@ -263,30 +264,38 @@ __device__ __forceinline__ void fwd_box_body(const Dom<float>& D, const double* 
     asm volatile("" : "+v"(q.m), "+v"(q.r), "+v"(q.c));
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      if (k * kBoxThreads < ncell && q.m < ncell) {
-        const float* rw = rowtab + 8 * q.r;
+      if (k * kBoxThreads < ncell) {                   // uniform
+        // lanes past the box read a valid frame position and compute nothing
+        const bool act = q.m < ncell;
+        const int rr = act ? q.r : 0, cc = act ? q.c : 0;
+        const float* rw = rowtab + 8 * rr;
         const float a1 = rw[0], a2 = rw[1], a3 = rw[2], cf = rw[3], ct = rw[4], cN = rw[6], cS = rw[7];
-        const float* Pc = P + 3 * ((q.r + 1) * nxp + q.c + 1);
+        const float* Pc = P + 3 * ((rr + 1) * nxp + cc + 1);
         const V3<float> C = lds3(Pc, 0), E = lds3(Pc, 3), W = lds3(Pc, -3);
         const V3<float> N = lds3(Pc, n3), Sv = lds3(Pc, -n3);
-        const float cor = cf + ct * C.u;
-        const float U = -a1 * C.u * (E.u - W.u) - st * C.v * (N.u - Sv.u) - a2 * (E.h - W.h) + cor * C.v;
-        const float V = -a1 * C.u * (E.v - W.v) - st * C.v * (N.v - Sv.v) - stg * (N.h - Sv.h) - cor * C.u;
-        const float H = -a1 * (h0 * (E.u - W.u) + (E.h * E.u - W.h * W.u)) -
-                        a3 * (h0 * (N.v * cN - Sv.v * cS) + (N.h * N.v * cN - Sv.h * Sv.v * cS));
-        // Z^1 = Z^0 + F(Z^0)/2 (Euler start), else Z^{n+1} = Z^{n-1} + F(Z^n)
-        if (euler) {
-          zr[0][k] = C.h + 0.5f * H;
-          zr[1][k] = C.u + 0.5f * U;
-          zr[2][k] = C.v + 0.5f * V;
-        } else {
-          zr[0][k] += H;
-          zr[1][k] += U;
-          zr[2][k] += V;
+        cz[0][k] = C.h;
+        cz[1][k] = C.u;
+        cz[2][k] = C.v;
+        if (act) {
+          const float cor = cf + ct * C.u;
+          const float U = -a1 * C.u * (E.u - W.u) - st * C.v * (N.u - Sv.u) - a2 * (E.h - W.h) + cor * C.v;
+          const float V = -a1 * C.u * (E.v - W.v) - st * C.v * (N.v - Sv.v) - stg * (N.h - Sv.h) - cor * C.u;
+          const float H = -a1 * (h0 * (E.u - W.u) + (E.h * E.u - W.h * W.u)) -
+                          a3 * (h0 * (N.v * cN - Sv.v * cS) + (N.h * N.v * cN - Sv.h * Sv.v * cS));
+          // Z^1 = Z^0 + F(Z^0)/2 (Euler start), else Z^{n+1} = Z^{n-1} + F(Z^n)
+          if (euler) {
+            zr[0][k] = C.h + 0.5f * H;
+            zr[1][k] = C.u + 0.5f * U;
+            zr[2][k] = C.v + 0.5f * V;
+          } else {
+            zr[0][k] += H;
+            zr[1][k] += U;
+            zr[2][k] += V;
+          }
+          bstore(zrs, zr[0][k], q.m * 4, so);
+          bstore(zrs, zr[1][k], q.m * 4, so + fp);
+          bstore(zrs, zr[2][k], q.m * 4, so + 2 * fp);
         }
-        bstore(zrs, zr[0][k], q.m * 4, so);
-        bstore(zrs, zr[1][k], q.m * 4, so + fp);
-        bstore(zrs, zr[2][k], q.m * 4, so + 2 * fp);
       }
       // keep each pass's loads within its own iteration: hoisting them all
       // ahead of the unrolled loop exhausts the register file
@@ -294,16 +303,16 @@ __device__ __forceinline__ void fwd_box_body(const Dom<float>& D, const double* 
       next_cell(q, nx, dr, dc);
     }
     __syncthreads();                                    // every read of level n done
-    // level n+1 into LDS; level n into the registers (base of the next step)
+    // level n+1 into LDS; level n (kept from the reads above) into the
+    // registers, the base of the next step
     q = q0;
     asm volatile("" : "+v"(q.m), "+v"(q.r), "+v"(q.c));
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (q.m < ncell) {
         float* Pc = P + 3 * ((q.r + 1) * nxp + q.c + 1);
-        const float th = Pc[0], tu = Pc[1], tv = Pc[2];
         Pc[0] = zr[0][k]; Pc[1] = zr[1][k]; Pc[2] = zr[2][k];
-        zr[0][k] = th; zr[1][k] = tu; zr[2][k] = tv;
+        zr[0][k] = cz[0][k]; zr[1][k] = cz[1][k]; zr[2][k] = cz[2][k];
       }
       next_cell(q, nx, dr, dc);
     }
