@@ -5,7 +5,7 @@
 // Eq_matrixAV).  The vector work runs over parts of the boxes' controls (one
 // workgroup per part); per-box dot products are sums of the parts' partial
 // sums in a fixed order (deterministic), and the per-box scalar logic runs in
-// kernels of one wave per box between the vector passes.
+// kernels of one wave (or thread) per box between the vector passes.
 //
 // Per subdomain: two-loop recursion with the m newest pairs and initial
 // scaling gamma = s^T y / y^T y of the newest pair (1 without pairs);
