@@ -52,7 +52,17 @@ DENSE_CFG = dict(index=113, nlat=24, nlon=48, nsteps=24, bands=4, pieces=4, ntim
                  overlap_cells=5, overlap_steps=3, obs_frac=0.1, obs_every=2)
 
 
+# a time decomposition into two boxes covering the sphere, 112 x 256 cells:
+# 112 cost tiles per box (the per-box reduction's lanes sum more than one
+# tile each) and 86,016 control entries per box (six solver parts, the last
+# ragged)
+LARGE_CFG = dict(index=114, nlat=112, nlon=256, nsteps=8, bands=1, pieces=1, ntime=2,
+                 overlap_cells=0, overlap_steps=2, obs_frac=0.02, obs_every=2)
+
+
 def _prob(which):
+    if which == "large":
+        return custom_problem(LARGE_CFG)
     if which == "dense":
         return custom_problem(DENSE_CFG)
     if which == "span":
@@ -140,7 +150,7 @@ def test_local_forward(which, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("which", ["tiny1", "c1", "small", "span", "mixed", "c2"])
+@pytest.mark.parametrize("which", ["tiny1", "c1", "small", "span", "mixed", "c2", "large"])
 def test_local_cost_grad(which, prec):
     """J and gradient of every box; also per field, element-wise (largest
     error over the field's largest reference value)."""

@@ -90,6 +90,36 @@ def test_solve_by_small_parts(which, prec, tol):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-7), ("fp32", 1e-4)])
+def test_solve_large_boxes(prec, tol):
+    """Two boxes covering the sphere (112 x 256 cells each): the solver's
+    default parts of 16384 entries split each box's control in six, the
+    last ragged; against the oracle's solve."""
+    from conftest import custom_problem
+    from paper_2205_06649_amd.context import Context
+    from test_gpu_parity import LARGE_CFG
+    p = custom_problem(LARGE_CFG)
+    ref, _ = _oracle_large()
+    ctx = Context(p, prec)
+    sizes = [3 * int(i[1]) * int(i[3]) for i in ctx.info]
+    assert ctx.solver_parts() == {"entries": 16384,
+                                  "parts": sum((n + 16383) // 16384 for n in sizes)}
+    assert min(sizes) > 5 * 16384 and all(n % 16384 for n in sizes)
+    xa, rep, status, _ = ctx.solve(max_outer=1, max_iter=8, outer_tol=1e-12)
+    err = analysis_error(xa, ref)
+    print(f"large boxes {prec}: evals {rep.total_evals} analysis err {err:.2e}", flush=True)
+    assert np.all(np.isfinite(xa))
+    assert err <= tol, err
+    ctx.close()
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_large():
+    from conftest import custom_problem
+    from test_gpu_parity import LARGE_CFG
+    return dd.solve(custom_problem(LARGE_CFG), max_outer=1, outer_tol=1e-12, max_iter=8)
+
+
 def test_solve_reports_and_options():
     from paper_2205_06649_amd import _lib as L
     from paper_2205_06649_amd.context import Context
