@@ -526,7 +526,8 @@ def tz_leg(spec, reps=5):
     res = {}
     for prec, b in (("fp32", 4), ("fp64", 8)):
         ctx = Context(prob, prec)
-        out["step_kernels"] = ("column walk" if ctx.tz_kernels()["kind"] == 1 else "gather")
+        out[f"step_kernels_{prec}"] = {0: "gather", 1: "column walk",
+                                       2: "column walk, persistent forward"}[ctx.tz_kernels()["kind"]]
         gen = torch.Generator(device="cuda")
         gen.manual_seed(2205)
         sb = torch.tensor(prob.sigma_b, dtype=torch.float64, device="cuda")
@@ -587,7 +588,10 @@ def tz_leg(spec, reps=5):
     out["spatial_fp32"] = {"subdomains": ctx.nsub, "ms_per_eval": ms,
                            "local_point_steps_per_s": pts / (ms * 1e-3),
                            "pad_positions_per_box": int(ctx.info[0][9]),
-                           "exchange_ms": e0.elapsed_time(e1) / reps}
+                           "exchange_ms": e0.elapsed_time(e1) / reps,
+                           "step_kernels": {0: "gather", 1: "column walk",
+                                            2: "column walk, persistent forward"}[
+                                                ctx.tz_kernels()["kind"]]}
     log(f"turkel-zwas on {ctx.nsub} boxes, fp32: {ms:.2f} ms/eval, exchange "
         f"{out['spatial_fp32']['exchange_ms']:.2f} ms")
     ctx.close()

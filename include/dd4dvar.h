@@ -328,8 +328,13 @@ dd4dvar_status dd4dvar_set_exec_plan(dd4dvar_ctx* ctx, int32_t mode, int32_t pas
  * neighbourhood (and in the adjoint the state, adjoint and row coefficients
  * of its 12 readers), any p, q; kind 1 = column walk, one wave per block of
  * 64 - 2p columns walking a strip of rows with a five-row window of state
- * (and adjoint) per column in registers, q = 2 and p <= 8 only, the default
- * where it applies.  The global (whole-grid) forward runs always use kind 0.
+ * (and adjoint) per column in registers, q = 2 and p <= 8 only; kind 2 =
+ * the column walk with the forward sweep as one persistent launch (one
+ * workgroup per box for the whole interval, the level and its frozen pad
+ * in LDS), FP32 state, every level stored (no checkpoints: with them the
+ * context turns to kind 1), no box spanning the circle, every box's frame
+ * within the LDS.  The default is the highest kind that applies.  The
+ * global (whole-grid) forward runs always use kind 0.
  * Both kinds evaluate the same expressions in the same order (the adjoint's
  * per-cell sums in FP64); the column walk adds the observation forcing to
  * the adjoint state after it is rounded to the state precision (one more
@@ -337,7 +342,8 @@ dd4dvar_status dd4dvar_set_exec_plan(dd4dvar_ctx* ctx, int32_t mode, int32_t pas
  * E_INVALID for another kind, or kind 1 where it does not apply. */
 dd4dvar_status dd4dvar_set_tz_kernels(dd4dvar_ctx* ctx, int32_t kind);
 
-/* out[2] = {Turkel-Zwas kernel kind in use, 1 if the column walk applies}. */
+/* out[2] = {Turkel-Zwas kernel kind in use, the highest kind that applies
+ * (0 if the column walk does not)}. */
 dd4dvar_status dd4dvar_get_tz_kernels(const dd4dvar_ctx* ctx, int32_t out[2]);
 
 /* Vector work of the local solvers (the L-BFGS iteration of the remark

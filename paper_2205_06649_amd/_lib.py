@@ -273,7 +273,7 @@ def dd4dvar_set_tz_kernels(ctx, kind):
 def dd4dvar_get_tz_kernels(ctx):
     out = (C.c_int32 * 2)()
     check(lib().dd4dvar_get_tz_kernels(ctx, out), ctx)
-    return {"kind": out[0], "column_walk_applies": bool(out[1])}
+    return {"kind": out[0], "column_walk_applies": out[1] >= 1, "max_kind": out[1]}
 
 
 def dd4dvar_set_solver_parts(ctx, entries):

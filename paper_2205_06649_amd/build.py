@@ -30,6 +30,7 @@ HIP_UNITS = [
     ("tlm.hip", "tlm_f64.o", ["-DDD4DVAR_TLM_T=double", "-ffp-contract=off"]),
     ("tz.hip", "tz_f32.o", ["-DDD4DVAR_TZ_T=float"]),
     ("tz.hip", "tz_f64.o", ["-DDD4DVAR_TZ_T=double", "-ffp-contract=off"]),
+    ("tzbox.hip", "tzbox.o", []),
     ("gn.hip", "gn.o", []),
     ("exchange.hip", "exchange.o", []),
     ("box.hip", "box.o", []),

@@ -76,11 +76,14 @@ class Context:
 
     def set_tz_kernels(self, kind):
         """Turkel-Zwas forward and adjoint step kernels: 0 gather form,
-        1 column walk (q = 2, p <= 8; the default where it applies)."""
+        1 column walk (q = 2, p <= 8; the default where it applies), 2 the
+        column walk with the persistent FP32 forward sweep (no box spanning
+        the circle)."""
         L.dd4dvar_set_tz_kernels(self.handle, kind)
 
     def tz_kernels(self):
-        """{kind, column_walk_applies} of the Turkel-Zwas step kernels."""
+        """{kind, column_walk_applies, max_kind} of the Turkel-Zwas step
+        kernels (max_kind: the highest kind that applies)."""
         return L.dd4dvar_get_tz_kernels(self.handle)
 
     def set_solver_parts(self, entries):

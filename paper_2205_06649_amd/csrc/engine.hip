@@ -97,6 +97,12 @@ struct dd4dvar_ctx {
   int32_t* tz_obs_tiles = nullptr;
   std::vector<int> tz_obs_ptr;
   bool tz_col_ok = false, tz_col = false;
+  // persistent forward of the variant (FP32, no box spanning the circle):
+  // available / in use, LDS bytes of the largest frame, cells of the
+  // largest box
+  bool tz_box_ok = false, tz_box = false;
+  size_t tz_box_lds = 0;
+  int tz_box_cells = 0;
   // the solvers' vector work: every box's control cut into parts of
   // part_len entries
   PartMap parts{};
@@ -375,6 +381,14 @@ template <typename T>
 void local_forward(dd4dvar_ctx* c, const double* x, hipStream_t st, double* traj_out = nullptr) {
   Dom<T> D = local_dom<T>(c);
   if constexpr (std::is_same<T, float>::value) {
+    if (c->tz_p > 0 && c->tz_box && c->ckpt == 0) {
+      chk(launch_fwd_tz_box(D, x, c->d_order, c->nsub, c->tz_box_lds, c->tz_box_cells, c->tz_p,
+                            c->tz_q, c->tz_alpha, c->plan.model.nlat, st),
+          "persistent Turkel-Zwas forward launch");
+      if (traj_out) launch_traj_out<T>(D, traj_out, 0, c->ntiles, -1, st);
+      c->have_forward = true;
+      return;
+    }
     if (c->exec_mode >= 2) {
       chk(launch_fwd_box(D, x, c->d_order, c->nsub, c->box_lds, c->box_k, c->box_span, st),
           "persistent forward launch");
@@ -963,6 +977,28 @@ void build_device(dd4dvar_ctx* c, hipStream_t st) {
         c->tz_col_ok = c->tz_col = true;
       }
     }
+    if (c->prec == DD4DVAR_FP32_STATE) {
+      bool ok = !c->subs.empty();
+      size_t lds = 0;
+      int cells = 0;
+      for (const SubDev& S : c->subs) {
+        const size_t b = tz_box_lds_bytes(S.nx, S.ny, c->tz_p, c->tz_q);
+        // the pad layout the frame fill assumes: q rows of nx + 2p above and
+        // below the box, p columns either side of each box row
+        const int pads = 2 * c->tz_q * (S.nx + 2 * c->tz_p) + 2 * S.ny * c->tz_p;
+        ok = ok && !S.span && S.nring == pads && tz_box_fits(S.ncell, S.nring, b);
+        lds = std::max(lds, b);
+        cells = std::max(cells, S.ncell);
+      }
+      if (ok) {
+        chk(prepare_fwd_tz_box(), "persistent Turkel-Zwas forward set-up");
+        // the default with the column walk
+        c->tz_box_ok = true;
+        c->tz_box = c->tz_col;
+        c->tz_box_lds = lds;
+        c->tz_box_cells = cells;
+      }
+    }
   }
   chk(hipMemsetAsync(c->ring, 0, size_t(std::max<int64_t>(ring_off, 1)) * tsz, st), "memset ring");
   chk(hipMemsetAsync(c->targ, 0, size_t(P.traj_total) * tsz, st), "memset targets");
@@ -1116,18 +1152,23 @@ dd4dvar_status dd4dvar_set_exec_plan(dd4dvar_ctx* ctx, int32_t mode, int32_t pas
 }
 
 dd4dvar_status dd4dvar_set_tz_kernels(dd4dvar_ctx* ctx, int32_t kind) {
-  if (!ctx || kind < 0 || kind > 1) return fail(ctx, DD4DVAR_E_INVALID, "bad Turkel-Zwas kernel kind");
-  if (kind == 1 && !ctx->tz_col_ok)
+  if (!ctx || kind < 0 || kind > 2) return fail(ctx, DD4DVAR_E_INVALID, "bad Turkel-Zwas kernel kind");
+  if (kind >= 1 && !ctx->tz_col_ok)
     return fail(ctx, DD4DVAR_E_INVALID,
                 "the column-walk kernels need the Turkel-Zwas variant with q = 2 and p <= 8");
-  ctx->tz_col = kind == 1;
+  if (kind == 2 && (!ctx->tz_box_ok || ctx->ckpt))
+    return fail(ctx, DD4DVAR_E_INVALID,
+                "the persistent Turkel-Zwas forward needs FP32 state, every level stored, no box "
+                "spanning the circle and every box's frame within the LDS");
+  ctx->tz_col = kind >= 1;
+  ctx->tz_box = kind == 2;
   return DD4DVAR_OK;
 }
 
 dd4dvar_status dd4dvar_get_tz_kernels(const dd4dvar_ctx* ctx, int32_t out[2]) {
   if (!ctx || !out) return fail(const_cast<dd4dvar_ctx*>(ctx), DD4DVAR_E_INVALID, "null argument");
-  out[0] = ctx->tz_col ? 1 : 0;
-  out[1] = ctx->tz_col_ok ? 1 : 0;
+  out[0] = ctx->tz_box ? 2 : (ctx->tz_col ? 1 : 0);
+  out[1] = ctx->tz_col_ok ? (ctx->tz_box_ok && !ctx->ckpt ? 2 : 1) : 0;
   return DD4DVAR_OK;
 }
 
@@ -1323,6 +1364,9 @@ dd4dvar_status dd4dvar_set_checkpointing(dd4dvar_ctx* ctx, int32_t stride, int64
         "upload subdomains");
     ctx->subs = subs;
     ctx->ckpt = stride;
+    // the persistent Turkel-Zwas forward stores every level: with
+    // checkpoints the column walk's forward steps run (kind 1)
+    if (stride != 0) ctx->tz_box = false;
     ctx->nslot = nslot;
     ctx->have_forward = false;
     if (state_bytes) *state_bytes = int64_t(bytes);

@@ -59,6 +59,17 @@ void launch_dz_out(const Dom<T>& D, double* out, int tile_base, int ntiles, hipS
 struct TzWork {
   int32_t box, c0, r0, r1, slot, zero0, zero1, pad_;
 };
+// persistent Turkel-Zwas forward sweep (FP32): one workgroup per box for the
+// whole interval, the level and its pad in an LDS frame; boxes that span the
+// circle are not taken.  LDS bytes of a box's frame and row table, whether
+// a box fits (cells, pad positions, LDS), and the launch over the nboxes
+// boxes of order (max_cells: the largest box)
+size_t tz_box_lds_bytes(int nx, int ny, int p, int q);
+bool tz_box_fits(int ncell, int nring, size_t lds_bytes);
+hipError_t prepare_fwd_tz_box();          // once, before any launch: the LDS allowance
+hipError_t launch_fwd_tz_box(const Dom<float>& D, const double* x, const int32_t* order, int nboxes,
+                             size_t lds_bytes, int max_cells, int p, int q, double alpha, int nlat,
+                             hipStream_t st);
 // forward step: work == nullptr, the gather kernel (one thread per cell,
 // any p, q); otherwise the column walk over the nwork waves
 template <typename T>

@@ -252,15 +252,19 @@ def _fullsize_tz():
     return p, maps, sample, bg
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp64", 1e-12)])
-def test_fullsize_tz_sampled_subdomains(prec, tol):
+@pytest.mark.parametrize("prec,tol,kind", [("fp32", 1e-4, None), ("fp32", 1e-4, 2),
+                                           ("fp64", 1e-12, None)])
+def test_fullsize_tz_sampled_subdomains(prec, tol, kind):
     """Sampled boxes of the full-size decomposition under the Turkel-Zwas
     variant, in the launch configuration the benchmark times (all 2048 boxes
-    per call, step kernels), against the oracle."""
+    per call, step kernels; kind 2: the persistent FP32 forward sweep),
+    against the oracle."""
     from paper_2205_06649_amd.context import Context
     p, maps, sample, bg = _fullsize_tz()
-    print(f"full-size turkel-zwas parity {prec}: sample {sample}", flush=True)
+    print(f"full-size turkel-zwas parity {prec} kind {kind}: sample {sample}", flush=True)
     ctx = Context(p, prec)
+    if kind is not None:
+        ctx.set_tz_kernels(kind)
     xb = ctx.background_controls()
     rng = np.random.default_rng(12)
     # sampled boxes start from the oracle's background; the others (not
@@ -302,7 +306,8 @@ def test_fullsize_tz_gn_product_sampled_subdomains(prec, tol):
     p, maps, sample, bg = _fullsize_tz()
     print(f"full-size turkel-zwas Gauss-Newton product {prec}: sample {sample}", flush=True)
     ctx = Context(p, prec)
-    assert ctx.tz_kernels()["kind"] == 1
+    # the column walk, in FP32 with the persistent forward sweep
+    assert ctx.tz_kernels()["kind"] == (2 if prec == "fp32" else 1)
     xb = ctx.background_controls()
     rng = np.random.default_rng(14)
     xs = [(local.restrict_global(maps, b.sub, bg)[0] if b.sub in sample else x) +

@@ -295,18 +295,22 @@ def test_column_walk_applies_where_documented(which, tzv):
     p, maps, _, _ = _state(tzv, which)
     ctx = Context(p, "fp32")
     applies = tzv[1] == 2 and tzv[0] <= 8
-    assert ctx.tz_kernels() == {"kind": int(applies), "column_walk_applies": applies}
+    # the persistent forward (kind 2) with the column walk where no box spans
+    # the circle (FP32)
+    top = (2 if not any(b.nx == p.nlon for b in maps.boxes) else 1) if applies else 0
+    assert ctx.tz_kernels() == {"kind": top, "column_walk_applies": applies, "max_kind": top}
     ctx.set_tz_kernels(0)
     assert ctx.tz_kernels()["kind"] == 0
-    if applies:
-        ctx.set_tz_kernels(1)
-        assert ctx.tz_kernels()["kind"] == 1
-    else:
-        with pytest.raises(L.DD4DVarError) as e:
-            ctx.set_tz_kernels(1)
-        assert e.value.status == L.DD4DVAR_E_INVALID
+    for kind in (1, 2):
+        if kind <= top:
+            ctx.set_tz_kernels(kind)
+            assert ctx.tz_kernels()["kind"] == kind
+        else:
+            with pytest.raises(L.DD4DVarError) as e:
+                ctx.set_tz_kernels(kind)
+            assert e.value.status == L.DD4DVAR_E_INVALID
     with pytest.raises(L.DD4DVarError) as e:
-        ctx.set_tz_kernels(2)
+        ctx.set_tz_kernels(3)
     assert e.value.status == L.DD4DVAR_E_INVALID
     ctx.close()
 
@@ -372,9 +376,10 @@ def test_column_walk_without_observations(prec):
     _, trajs = dd.background(p, maps)
     xs = _controls(p, maps, trajs, seed=8)
     ctx = Context(p, prec)
-    assert ctx.tz_kernels() == {"kind": 1, "column_walk_applies": True}
+    top = 2 if prec == "fp32" else 1
+    assert ctx.tz_kernels() == {"kind": top, "column_walk_applies": True, "max_kind": top}
     res = {}
-    for kind in (1, 0):
+    for kind in (top, 0):
         ctx.set_tz_kernels(kind)
         J, g = ctx.cost_grad(ctx.pack_ctrl(xs))
         ctx.synchronize()
@@ -383,7 +388,7 @@ def test_column_walk_without_observations(prec):
     D = np.longdouble if prec == "fp64" else np.float64
     _, rt = dd.background(p, maps, D)
     rr, _ = dd.exchange(maps, rt)
-    J1, g1 = res[1]
+    J1, g1 = res[top]
     J0, g0 = res[0]
     for b in maps.boxes:
         s = b.sub
@@ -393,3 +398,63 @@ def test_column_walk_without_observations(prec):
         print(f"tz no observations {prec} box {s}: J rel {ej:.2e}, grad rel {eg:.2e}", flush=True)
         assert ej <= TOL[prec] and eg <= TOL_GRAD[prec], (s, ej, eg)
         assert _field_err(g1[s], g0[s]) <= (1e-13 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("which", ["c1", "mixed", "span", "time"])
+def test_persistent_forward(which):
+    """The persistent FP32 forward sweep of the variant (kind 2: one
+    workgroup per box for the whole interval, the level and its pad in LDS)
+    where no box spans the circle: J and gradients against the oracle (FP32
+    1e-4), and trajectories, J, gradients, the adjoint of a caller forcing
+    and the Gauss-Newton product against the column walk (kind 1: the same
+    expressions in the same order, FP32 1e-5 per field, J 1e-6); refused
+    (E_INVALID) with a box spanning the circle and in FP64."""
+    from paper_2205_06649_amd import _lib as L
+    from paper_2205_06649_amd.context import Context
+    tzv = (2, 2, 0.5)
+    p, maps, trajs, rings = _state(tzv, which)
+    span = any(b.nx == p.nlon for b in maps.boxes)
+    c64 = Context(p, "fp64")
+    assert c64.tz_kernels()["max_kind"] == 1
+    with pytest.raises(L.DD4DVarError) as e:
+        c64.set_tz_kernels(2)
+    assert e.value.status == L.DD4DVAR_E_INVALID
+    c64.close()
+    ctx = Context(p, "fp32")
+    if span:
+        assert ctx.tz_kernels()["max_kind"] == 1
+        with pytest.raises(L.DD4DVarError) as e:
+            ctx.set_tz_kernels(2)
+        assert e.value.status == L.DD4DVAR_E_INVALID
+        ctx.close()
+        return
+    assert ctx.tz_kernels()["max_kind"] == 2
+    xs = _controls(p, maps, trajs, seed=7)
+    rng = np.random.default_rng(8)
+    forcing = [rng.standard_normal((b.nlev, 3, b.ny, b.nx)) for b in maps.boxes]
+    dxs = [p.sigma_b[:, None, None] * rng.standard_normal(x.shape) for x in xs]
+    xp, fp, dp = ctx.pack_ctrl(xs), ctx.pack_traj(forcing), ctx.pack_ctrl(dxs)
+    res = {}
+    for kind in (1, 2):
+        ctx.set_tz_kernels(kind)
+        assert ctx.tz_kernels()["kind"] == kind
+        J, g = ctx.cost_grad(xp)
+        tr = ctx.unpack_traj(ctx.forward(xp))
+        a = ctx.adjoint(fp)
+        h = ctx.gn_hessvec(dp)
+        ctx.synchronize()
+        res[kind] = (J.cpu().numpy(), [ctx.unpack_ctrl(v) for v in (g, a, h)], tr)
+    ctx.close()
+    (J1, r1, t1), (J2, r2, t2) = res[1], res[2]
+    ej = float(np.max(np.abs(J2 - J1) / np.abs(J1)))
+    errs = [max(_field_err(r2[k][b.sub], r1[k][b.sub]) for b in maps.boxes) for k in range(3)]
+    et = max(_field_err(_anom(t2[b.sub], p.h_ref), _anom(t1[b.sub], p.h_ref)) for b in maps.boxes)
+    print(f"tz {which} persistent forward: trajectories {et:.2e}, J {ej:.2e}, gradient "
+          f"{errs[0]:.2e}, adjoint {errs[1]:.2e}, Gauss-Newton product {errs[2]:.2e}", flush=True)
+    assert et <= 1e-5 and ej <= 1e-6 and max(errs) <= 1e-5, (et, ej, errs)
+    for b in maps.boxes:
+        s = b.sub
+        Jr, gr = local.cost_grad(p, maps, s, xs[s], trajs[s][0], rings[s],
+                                 {k: trajs[k] for k in maps.neighbors[s]})
+        ejr, egr = float(abs(J2[s] - Jr) / abs(Jr)), _rel(r2[0][s], gr)
+        assert ejr <= TOL["fp32"] and egr <= TOL_GRAD["fp32"], (s, ejr, egr)
